@@ -1,0 +1,44 @@
+"""Seeded random small circuits for the tests (no method arithmetic)."""
+import numpy as np
+
+from workloads.circuit import Circuit
+
+
+def random_circuit(rng, n, length, p_noise=0.3, allow_reset=True):
+    c = Circuit(n)
+    for _ in range(length):
+        r = rng.random()
+        if r < 0.25:
+            c.append(str(rng.choice(["H", "S", "S_DAG", "X", "Y", "Z"])), [int(rng.integers(n))])
+        elif r < 0.4 and n >= 2:
+            a, b = rng.choice(n, 2, replace=False)
+            c.append(str(rng.choice(["CX", "CZ", "SWAP"])), [int(a), int(b)])
+        elif r < 0.55:
+            w = int(rng.integers(1, min(n, 4) + 1))
+            qs = rng.choice(n, w, replace=False)
+            c.rot([(int(q), str(rng.choice(list("XYZ")))) for q in qs], float(rng.uniform(-np.pi, np.pi)),
+                  negate=bool(rng.random() < 0.3))
+        elif r < 0.72:
+            w = int(rng.integers(1, min(n, 4) + 1))
+            qs = rng.choice(n, w, replace=False)
+            c.mpp([(int(q), str(rng.choice(list("XYZ")))) for q in qs], negate=bool(rng.random() < 0.3))
+            if rng.random() < 0.5:
+                qs2 = rng.choice(n, int(rng.integers(1, min(n, 2) + 1)), replace=False)
+                nr = c.num_records
+                recs = sorted(set(int(x) for x in rng.choice(nr, int(rng.integers(1, min(nr, 2) + 1)), replace=False)))
+                c.feedback([(int(q), str(rng.choice(list("XYZ")))) for q in qs2], recs)
+        elif r < 0.8:
+            names = ["M", "MR", "R"] if allow_reset else ["M"]
+            c.append(str(rng.choice(names)), [int(rng.integers(n))])
+        elif r < 0.9:
+            c.append("DEPOLARIZE1", [int(rng.integers(n))], arg=p_noise)
+        elif r < 0.95 and n >= 2:
+            a, b = rng.choice(n, 2, replace=False)
+            c.append("DEPOLARIZE2", [int(a), int(b)], arg=p_noise)
+        else:
+            c.append("X_ERROR", [int(rng.integers(n))], arg=p_noise)
+    if c.num_records >= 2 and rng.random() < 0.7:
+        c.detector([0, c.num_records - 1])
+    if c.num_records >= 1:
+        c.observable(0, [c.num_records - 1])
+    return c
