@@ -1,0 +1,182 @@
+/*
+ * symft.h -- C ABI of the SymFT per-shot sampling library for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The library compiles a noisy Clifford-dominated circuit into a SymFT
+ * sampling program on the host (symbolic Clifford-Pauli frame factorization,
+ * paper Sec. 3, and adaptive stabilizer-coordinate planning, Sec. 4) and
+ * replays that program across many shots on the GPU (paper Sec. 5): noise
+ * choices and random measurement bits are drawn, affine sign expressions are
+ * evaluated by XOR, the dense active-state vector is updated by PromoteRot /
+ * ActiveDiagRot / ActivePairRot and sampled by RandomMeas / DetMeas /
+ * ActiveDiagMeas / ActivePairMeas, and bit-packed records are written.
+ *
+ * Conventions (all functions):
+ *   - Status codes only; nothing throws across this boundary.  On failure
+ *     symft_last_error() returns a thread-local message.
+ *   - Pointers marked "host" are read during the call only.  Pointers marked
+ *     "device" are HIP device allocations owned by the caller.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Sampling calls are asynchronous on that stream.
+ *   - Records layout (record-major, bit-packed): row r, word w is
+ *     out[r * row_stride_words + w]; bit (s % 64) of word (s / 64) holds
+ *     shot s of the call; padding bits of the last word are 0.  Rows are the
+ *     visible measurement records in circuit order, then detectors, then
+ *     observables.
+ *   - Measurement outcome 0 is the +1 eigenvalue (paper Sec. 2).
+ *   - Random draws follow a counter-based Philox4x32-10 contract keyed by
+ *     (seed, global shot index), so any shot range is reproducible and
+ *     shard-independent.
+ */
+#ifndef SYMFT_H
+#define SYMFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t symft_status;
+#define SYMFT_OK 0
+#define SYMFT_EINVAL (-1)     /* malformed op, null pointer, bad size or offset */
+#define SYMFT_EACAUSAL (-3)   /* a record referenced before it is measured (paper Sec. 5, causality) */
+#define SYMFT_EPROB (-4)      /* probability < 0, > 1, or a channel total > 1 (paper Sec. 2) */
+#define SYMFT_ECAPACITY (-5)  /* peak active width or scratch need exceeds what the library supports */
+#define SYMFT_ENOMEM (-6)     /* host or device allocation failed */
+#define SYMFT_EHIP (-7)       /* a HIP runtime call failed */
+
+/* Operation kinds (paper Sec. 2).  Pauli letters: 1 = X, 2 = Y, 3 = Z (0 = I in branches). */
+enum symft_op_kind {
+    SYMFT_OP_H = 1, SYMFT_OP_S, SYMFT_OP_S_DAG, SYMFT_OP_X, SYMFT_OP_Y, SYMFT_OP_Z, /* 1q Cliffords on each qubit */
+    SYMFT_OP_CX, SYMFT_OP_CZ, SYMFT_OP_SWAP,          /* on qubit pairs (q0,q1),(q2,q3),... */
+    SYMFT_OP_R,            /* reset each qubit to |0> (unrecorded Z measurement + X feedback) */
+    SYMFT_OP_M,            /* recorded Z measurement of each qubit */
+    SYMFT_OP_MR,           /* recorded Z measurement, then reset, of each qubit */
+    SYMFT_OP_X_ERROR,      /* per qubit: X with probability arg */
+    SYMFT_OP_DEPOLARIZE1,  /* per qubit: X, Y, Z each with probability arg/3 */
+    SYMFT_OP_DEPOLARIZE2,  /* per pair: each of the 15 non-identity two-qubit Paulis with probability arg/15 */
+    SYMFT_OP_PAULI_CHANNEL,/* one channel on `qubits`: branch j applies branch_paulis[j*n..] w.p. probs[j] */
+    SYMFT_OP_ROT,          /* R_P(arg) = exp(-i arg P / 2), P = (-1)^negate * prod paulis (paper Sec. 2) */
+    SYMFT_OP_MPP,          /* recorded measurement of P = (-1)^negate * prod paulis */
+    SYMFT_OP_FEEDBACK,     /* apply P if the XOR of records `recs` is 1 */
+    SYMFT_OP_DETECTOR,     /* detector row = XOR of records `recs` */
+    SYMFT_OP_OBSERVABLE,   /* XOR records `recs` into observable row obs_id */
+    SYMFT_OP_TICK          /* ignored */
+};
+
+typedef struct {
+    uint32_t kind;                 /* enum symft_op_kind */
+    uint32_t n;                    /* number of entries in qubits (and paulis) */
+    const uint32_t *qubits;        /* host, [n] */
+    const uint8_t *paulis;         /* host, [n] letters for ROT / MPP / FEEDBACK; else NULL */
+    uint32_t negate;               /* ROT / MPP: sign of P (the Pauli stays Hermitian) */
+    double arg;                    /* ROT: theta; X_ERROR / DEPOLARIZE1 / DEPOLARIZE2: p */
+    uint32_t n_branches;           /* PAULI_CHANNEL */
+    const double *probs;           /* host, [n_branches] */
+    const uint8_t *branch_paulis;  /* host, [n_branches * n] letters 0..3 */
+    uint32_t n_recs;
+    const int64_t *recs;           /* host, [n_recs]: absolute record ids, or < 0 = look-back (-1 = last) */
+    uint32_t obs_id;               /* OBSERVABLE */
+} symft_op;
+
+typedef struct symft_program symft_program; /* opaque, immutable after compile */
+
+/* Instruction kinds of the sampling program (paper Sec. 5). */
+enum symft_instr_kind {
+    SYMFT_PROMOTE_ROT = 1, SYMFT_ACTIVE_DIAG_ROT = 2, SYMFT_ACTIVE_PAIR_ROT = 3,
+    SYMFT_RANDOM_MEAS = 4, SYMFT_DET_MEAS = 5, SYMFT_ACTIVE_DIAG_MEAS = 6, SYMFT_ACTIVE_PAIR_MEAS = 7
+};
+
+typedef struct {
+    uint32_t n_qubits;
+    uint32_t k_max;                /* peak active width over the program */
+    uint64_t n_ops;
+    uint64_t n_measurements;       /* all measurements, resets included */
+    uint64_t n_records, n_detectors, n_observables, n_rows;
+    uint64_t n_instr[8];           /* instruction count by enum symft_instr_kind */
+    uint64_t n_channels, n_classes, n_noise_symbols;
+    uint64_t expr_noise_nnz;       /* noise-symbol references over all sign expressions */
+    uint64_t expr_meas_nnz;        /* measurement-symbol references over all sign expressions */
+    double dense_flops_per_shot;   /* algorithmic flops of the dense instructions, see DESIGN */
+    double dense_bytes_per_shot;   /* one read + one write of the live vector per dense instruction (complex FP32) */
+} symft_info;
+
+/* Compile `ops` (paper Sec. 2 circuit) into a sampling program (Sec. 3-4).
+ * Host only; no GPU work.  Errors: EINVAL (bad op / qubit / arity), EACAUSAL,
+ * EPROB, ECAPACITY (k_max > 30), ENOMEM.  `opts` is reserved (pass NULL).
+ * On success *out owns the program; free it with symft_program_free. */
+symft_status symft_compile(uint32_t n_qubits, const symft_op *ops, size_t n_ops, const void *opts,
+                           symft_program **out);
+
+/* Summary counts and the per-shot algorithmic work of the program. */
+symft_status symft_program_info(const symft_program *p, symft_info *info);
+
+/* Host introspection of the plan, for tests:
+ *   k_after_op[n_ops]     active width after every op;
+ *   meas_kind[n_meas]     per measurement 0 random, 1 deterministic, 2 active-diagonal, 3 active-pair;
+ *   rot_kind[n_ops]       per op 0 none, 1 promote, 2 active-diagonal, 3 active-pair.
+ * Any pointer may be NULL. */
+symft_status symft_program_plan(const symft_program *p, int16_t *k_after_op, int8_t *meas_kind, int8_t *rot_kind);
+
+/* Export of the compiled instruction stream, for tests and inspection.
+ * Call once with all array pointers NULL to get the counts in *counts
+ * (counts[0] instructions, [1] noise refs, [2] measurement refs, [3] channels,
+ * [4] branch masks), then again with arrays of those sizes:
+ *   instr[n_instr * 13]: kind, k_in, h, mu (power of i), eta, lambda constant,
+ *                        a, b, measurement index (-1 none), noise_off,
+ *                        noise_len, meas_off, meas_len
+ *   theta[n_instr]       rotation angle
+ *   noise_refs / meas_refs  symbol lists of each lambda (paper Sec. 3 affine signs)
+ *   chan[n_chan * 4]:    first noise symbol, symbol count, branch count,
+ *                        offset into bmask
+ *   bmask[...]           per branch: bit i set <=> symbol (first + i) is 1 */
+symft_status symft_program_export(const symft_program *p, uint64_t *counts, int64_t *instr, double *theta,
+                                  uint32_t *noise_refs, uint32_t *meas_refs, int64_t *chan, uint32_t *bmask);
+
+/* Sampling options. */
+typedef struct {
+    uint64_t shot_offset;          /* global index of the first shot; must be a multiple of 64 */
+    uint32_t precision;            /* 0 = complex FP64 amplitudes, 1 = complex FP32 (FP64 scale and threshold) */
+    uint32_t sections;             /* bit 0 records, bit 1 detectors, bit 2 observables; 0 means all */
+    uint64_t row_stride_words;     /* 0 means ceil(shots / 64) */
+} symft_sample_opts;
+
+/* Sample `shots` shots (paper Sec. 5) into device buffer records_out
+ * (n_rows x ceil(shots/64) uint64 words, record-major as above), with
+ * complex FP64 amplitudes.  shots == 0 is a no-op.  Errors: EINVAL (null
+ * program or output), ECAPACITY, ENOMEM, EHIP. */
+symft_status symft_sample(const symft_program *p, uint64_t shots, uint64_t seed, uint64_t *records_out,
+                          void *stream);
+
+/* As symft_sample with options (shot offset, precision, sections, stride).
+ * Rows of sections not requested are left untouched. */
+symft_status symft_sample_ex(const symft_program *p, const symft_sample_opts *opts, uint64_t shots, uint64_t seed,
+                             uint64_t *records_out, void *stream);
+
+/* Sample n programs in one persistent launch (work queue over (program,
+ * word range) items).  records_out[i] receives program i's rows for shots[i]
+ * shots with seeds[i].  precision as in symft_sample_opts.  `graph` = 1
+ * captures the launch in a HIP graph on first use and replays it on later
+ * calls with the same arguments. */
+symft_status symft_sample_batch(const symft_program *const *progs, const uint64_t *shots, const uint64_t *seeds,
+                                uint64_t *const *records_out, size_t n, uint32_t precision, uint32_t graph,
+                                void *stream);
+
+/* Probe: Pr(m = 0) of every measurement for shots [shot_begin, shot_begin + n_shots)
+ * computed by the same GPU kernels (FP64 or FP32), written to host
+ * p0_host[n_shots * n_measurements] (NaN for RandomMeas / DetMeas).
+ * Synchronous.  For tests and error reports. */
+symft_status symft_probe(const symft_program *p, uint64_t shot_begin, uint32_t n_shots, uint64_t seed,
+                         uint32_t precision, double *p0_host);
+
+void symft_program_free(symft_program *p);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *symft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SYMFT_H */

@@ -343,7 +343,7 @@ void *orc_circuit_new(int n_qubits, const int64_t *tape, const double *dargs) {
                 double cum = 0.0;
                 for (int b = 0; b < o->nbr; ++b) {
                     cum += o->probs[b];
-                    double f = ldexp(cum / ptot, 32);
+                    double f = ptot > 0 ? ldexp(cum / ptot, 32) : 4294967296.0;
                     uint64_t t = f >= 4294967296.0 ? ((uint64_t)1 << 32) : (uint64_t)floor(f);
                     c->thr[b] = t;
                 }

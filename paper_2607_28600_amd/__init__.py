@@ -1,0 +1,247 @@
+"""Python binding of the SymFT MI355X sampling library (libsymft.so).
+
+Argument marshalling only: every step of the sampling path runs in the HIP
+kernels behind the C ABI declared in include/symft.h.  PyTorch supplies
+device memory and the current stream.  There is no CPU fallback: if the
+library is missing the import of this module fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libsymft.so")
+
+if not os.path.exists(LIB):
+    raise ImportError(f"{LIB} is not built; run `python paper_2607_28600_amd/build.py` (or __graft_entry__.build())")
+
+_lib = C.CDLL(LIB)
+
+OK = 0
+ERRORS = {-1: "EINVAL", -3: "EACAUSAL", -4: "EPROB", -5: "ECAPACITY", -6: "ENOMEM", -7: "EHIP"}
+
+OP = {
+    "H": 1, "S": 2, "S_DAG": 3, "X": 4, "Y": 5, "Z": 6, "CX": 7, "CZ": 8, "SWAP": 9,
+    "R": 10, "M": 11, "MR": 12, "X_ERROR": 13, "DEPOLARIZE1": 14, "DEPOLARIZE2": 15,
+    "PAULI_CHANNEL": 16, "ROT": 17, "MPP": 18, "FEEDBACK": 19, "DETECTOR": 20,
+    "OBSERVABLE_INCLUDE": 21, "TICK": 22,
+}
+LETTER = {"I": 0, "X": 1, "Y": 2, "Z": 3}
+INSTR_NAMES = {1: "PromoteRot", 2: "ActiveDiagRot", 3: "ActivePairRot", 4: "RandomMeas", 5: "DetMeas",
+               6: "ActiveDiagMeas", 7: "ActivePairMeas"}
+
+
+class symft_op(C.Structure):
+    _fields_ = [
+        ("kind", C.c_uint32), ("n", C.c_uint32), ("qubits", C.POINTER(C.c_uint32)),
+        ("paulis", C.POINTER(C.c_uint8)), ("negate", C.c_uint32), ("arg", C.c_double),
+        ("n_branches", C.c_uint32), ("probs", C.POINTER(C.c_double)), ("branch_paulis", C.POINTER(C.c_uint8)),
+        ("n_recs", C.c_uint32), ("recs", C.POINTER(C.c_int64)), ("obs_id", C.c_uint32),
+    ]
+
+
+class symft_info(C.Structure):
+    _fields_ = [
+        ("n_qubits", C.c_uint32), ("k_max", C.c_uint32), ("n_ops", C.c_uint64), ("n_measurements", C.c_uint64),
+        ("n_records", C.c_uint64), ("n_detectors", C.c_uint64), ("n_observables", C.c_uint64),
+        ("n_rows", C.c_uint64), ("n_instr", C.c_uint64 * 8), ("n_channels", C.c_uint64),
+        ("n_classes", C.c_uint64), ("n_noise_symbols", C.c_uint64), ("expr_noise_nnz", C.c_uint64),
+        ("expr_meas_nnz", C.c_uint64), ("dense_flops_per_shot", C.c_double), ("dense_bytes_per_shot", C.c_double),
+    ]
+
+
+class symft_sample_opts(C.Structure):
+    _fields_ = [("shot_offset", C.c_uint64), ("precision", C.c_uint32), ("sections", C.c_uint32),
+                ("row_stride_words", C.c_uint64)]
+
+
+_lib.symft_compile.restype = C.c_int32
+_lib.symft_compile.argtypes = [C.c_uint32, C.POINTER(symft_op), C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]
+_lib.symft_program_info.restype = C.c_int32
+_lib.symft_program_info.argtypes = [C.c_void_p, C.POINTER(symft_info)]
+_lib.symft_program_plan.restype = C.c_int32
+_lib.symft_program_plan.argtypes = [C.c_void_p, C.POINTER(C.c_int16), C.POINTER(C.c_int8), C.POINTER(C.c_int8)]
+_lib.symft_sample.restype = C.c_int32
+_lib.symft_sample.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p]
+_lib.symft_sample_ex.restype = C.c_int32
+_lib.symft_sample_ex.argtypes = [C.c_void_p, C.POINTER(symft_sample_opts), C.c_uint64, C.c_uint64, C.c_void_p,
+                                 C.c_void_p]
+_lib.symft_sample_batch.restype = C.c_int32
+_lib.symft_sample_batch.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                    C.POINTER(C.c_void_p), C.c_size_t, C.c_uint32, C.c_uint32, C.c_void_p]
+_lib.symft_probe.restype = C.c_int32
+_lib.symft_probe.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.POINTER(C.c_double)]
+_lib.symft_program_export.restype = C.c_int32
+_lib.symft_program_export.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p]
+_lib.symft_program_free.argtypes = [C.c_void_p]
+_lib.symft_last_error.restype = C.c_char_p
+
+EXPORTED = ["symft_compile", "symft_program_info", "symft_program_plan", "symft_program_export",
+            "symft_sample", "symft_sample_ex",
+            "symft_sample_batch", "symft_probe", "symft_program_free", "symft_last_error"]
+
+
+class SymftError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = _lib.symft_last_error().decode(errors="replace")
+        super().__init__(f"{what}: {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise SymftError(rc, what)
+
+
+def _marshal(circ):
+    """Circuit -> (symft_op array, keep-alive list)."""
+    keep: List = []
+    arr = (symft_op * max(1, len(circ.ops)))()
+    for i, o in enumerate(circ.ops):
+        s = arr[i]
+        s.kind = OP[o.name]
+        if o.name in ("ROT", "MPP", "FEEDBACK"):
+            qs = [q for q, _ in o.pauli]
+            lets = [LETTER[l] for _, l in o.pauli]
+        else:
+            qs = list(o.targets)
+            lets = []
+        qa = (C.c_uint32 * max(1, len(qs)))(*qs)
+        keep.append(qa)
+        s.n = len(qs)
+        s.qubits = C.cast(qa, C.POINTER(C.c_uint32))
+        if lets:
+            la = (C.c_uint8 * len(lets))(*lets)
+            keep.append(la)
+            s.paulis = C.cast(la, C.POINTER(C.c_uint8))
+        s.negate = 1 if o.negate else 0
+        s.arg = float(o.arg)
+        if o.branches:
+            pr = (C.c_double * len(o.branches))(*[float(p) for p, _ in o.branches])
+            bl = (C.c_uint8 * (len(o.branches) * len(qs)))(*[LETTER[ch] for _, st in o.branches for ch in st])
+            keep += [pr, bl]
+            s.n_branches = len(o.branches)
+            s.probs = C.cast(pr, C.POINTER(C.c_double))
+            s.branch_paulis = C.cast(bl, C.POINTER(C.c_uint8))
+        if o.recs:
+            ra = (C.c_int64 * len(o.recs))(*o.recs)
+            keep.append(ra)
+            s.n_recs = len(o.recs)
+            s.recs = C.cast(ra, C.POINTER(C.c_int64))
+        s.obs_id = o.obs
+    return arr, keep
+
+
+class Program:
+    """A compiled SymFT sampling program (owned by the C library)."""
+
+    def __init__(self, circ):
+        arr, keep = _marshal(circ)
+        h = C.c_void_p()
+        _check(_lib.symft_compile(circ.n_qubits, arr, len(circ.ops), None, C.byref(h)), "symft_compile")
+        self._h = h
+        self.n_ops = len(circ.ops)
+        info = self.info()
+        self.n_rows = int(info["n_rows"])
+        self.n_meas = int(info["n_measurements"])
+        self.k_max = int(info["k_max"])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.symft_program_free(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> Dict:
+        s = symft_info()
+        _check(_lib.symft_program_info(self._h, C.byref(s)), "symft_program_info")
+        d = {name: getattr(s, name) for name, _ in s._fields_}
+        d["n_instr"] = {INSTR_NAMES[i]: int(s.n_instr[i]) for i in range(1, 8)}
+        return d
+
+    def plan(self):
+        k = np.zeros(max(1, self.n_ops), dtype=np.int16)
+        mk = np.zeros(max(1, self.n_meas), dtype=np.int8)
+        rk = np.zeros(max(1, self.n_ops), dtype=np.int8)
+        _check(_lib.symft_program_plan(self._h, k.ctypes.data_as(C.POINTER(C.c_int16)),
+                                       mk.ctypes.data_as(C.POINTER(C.c_int8)),
+                                       rk.ctypes.data_as(C.POINTER(C.c_int8))), "symft_program_plan")
+        return {"k": k[: self.n_ops], "meas_kind": mk[: self.n_meas], "rot_kind": rk[: self.n_ops]}
+
+    def export(self) -> Dict[str, np.ndarray]:
+        """The compiled instruction stream and channel symbol masks (host copy)."""
+        cnt = np.zeros(5, dtype=np.uint64)
+        _check(_lib.symft_program_export(self._h, cnt.ctypes.data_as(C.POINTER(C.c_uint64)), None, None, None,
+                                         None, None, None), "symft_program_export")
+        ni, nn, nm, nc, nb = (int(v) for v in cnt)
+        instr = np.zeros((max(ni, 1), 13), dtype=np.int64)
+        theta = np.zeros(max(ni, 1), dtype=np.float64)
+        noise = np.zeros(max(nn, 1), dtype=np.uint32)
+        meas = np.zeros(max(nm, 1), dtype=np.uint32)
+        chan = np.zeros((max(nc, 1), 4), dtype=np.int64)
+        bm = np.zeros(max(nb, 1), dtype=np.uint32)
+        _check(_lib.symft_program_export(self._h, cnt.ctypes.data_as(C.POINTER(C.c_uint64)), instr.ctypes.data,
+                                         theta.ctypes.data, noise.ctypes.data, meas.ctypes.data, chan.ctypes.data,
+                                         bm.ctypes.data), "symft_program_export")
+        return {"instr": instr[:ni], "theta": theta[:ni], "noise": noise[:nn], "meas": meas[:nm],
+                "chan": chan[:nc], "bmask": bm[:nb]}
+
+    # -- sampling (device) ------------------------------------------------
+    def sample_into(self, out, shots: int, seed: int, shot_offset: int = 0, precision: str = "fp64",
+                    sections: int = 0, row_stride_words: int = 0, stream=None) -> None:
+        """out: a device tensor / pointer holding n_rows x stride uint64 words."""
+        import torch
+        ptr = out.data_ptr() if hasattr(out, "data_ptr") else int(out)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        o = symft_sample_opts(shot_offset, 0 if precision == "fp64" else 1, sections, row_stride_words)
+        _check(_lib.symft_sample_ex(self._h, C.byref(o), shots, seed, C.c_void_p(ptr), C.c_void_p(stream)),
+               "symft_sample_ex")
+
+    def sample(self, shots: int, seed: int, shot_offset: int = 0, precision: str = "fp64", device="cuda"):
+        """Returns a [n_rows, ceil(shots/64)] int64 tensor on the GPU (uint64 bit patterns)."""
+        import torch
+        words = (shots + 63) // 64
+        out = torch.zeros((max(self.n_rows, 1), max(words, 1)), dtype=torch.int64, device=device)
+        if shots:
+            self.sample_into(out, shots, seed, shot_offset=shot_offset, precision=precision)
+        return out[: self.n_rows, :words]
+
+    def probe(self, shot_begin: int, n_shots: int, seed: int, precision: str = "fp64") -> np.ndarray:
+        """Pr(m = 0) of every measurement of shots [shot_begin, +n_shots) from the GPU kernels."""
+        p0 = np.zeros((n_shots, max(1, self.n_meas)), dtype=np.float64)
+        _check(_lib.symft_probe(self._h, shot_begin, n_shots, seed, 0 if precision == "fp64" else 1,
+                                p0.ctypes.data_as(C.POINTER(C.c_double))), "symft_probe")
+        return p0[:, : self.n_meas]
+
+
+def compile(circ) -> Program:  # noqa: A001 - mirrors symft_compile
+    return Program(circ)
+
+
+def sample_batch(programs: Sequence[Program], shots: Sequence[int], seeds: Sequence[int], outs,
+                 precision: str = "fp32", graph: bool = True, stream=None) -> None:
+    import torch
+    n = len(programs)
+    hs = (C.c_void_p * n)(*[p.handle.value for p in programs])
+    sh = (C.c_uint64 * n)(*[int(s) for s in shots])
+    sd = (C.c_uint64 * n)(*[int(s) for s in seeds])
+    op = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(_lib.symft_sample_batch(hs, sh, sd, op, n, 0 if precision == "fp64" else 1, 1 if graph else 0,
+                                   C.c_void_p(stream)), "symft_sample_batch")
+
+
+def bits_to_numpy(t) -> np.ndarray:
+    """int64 device tensor -> uint64 numpy array."""
+    return t.cpu().numpy().view(np.uint64)

@@ -1,0 +1,525 @@
+// capi.cpp -- the C ABI: compile, introspection, device upload and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/symft.h"
+#include "device_program.hpp"
+#include "program.hpp"
+
+namespace symft {
+struct ActiveArgs;
+hipError_t launch_active(const ActiveArgs &A, bool fp64, uint32_t bs, uint32_t grid, hipStream_t st);
+size_t active_lds_bytes(const DevProg &P, uint32_t bs, uint32_t tps, bool lds_vec, bool fp64);
+int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds);
+struct FrameArgs;
+hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st);
+size_t frame_lds_bytes(const DevProg &P, uint32_t words_per_block);
+int frame_max_blocks_per_cu(size_t lds);
+}  // namespace symft
+
+#include "launch_args.hpp"
+
+using namespace symft;
+
+static thread_local std::string g_err;
+
+static symft_status set_err(symft_status code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+struct HostLayout {
+    std::vector<uint8_t> blob;
+    // offsets of each array inside blob
+    size_t o_instr, o_cmeas, o_rm, o_recmeas, o_detoff, o_detrows, o_obsoff, o_obsrows, o_clsQ, o_clsoff, o_clschan,
+        o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_frstep, o_frdata, o_frsymoff, o_frsymslot;
+    DevProg meta;  // counts only; pointers filled at upload
+};
+
+struct symft_program {
+    Program P;
+    HostLayout L;
+    FrameSchedule F;
+    std::mutex mu;
+    std::map<int, void *> dev;  // device id -> uploaded blob
+    ~symft_program() {
+        for (auto &kv : dev) {
+            int cur = 0;
+            hipGetDevice(&cur);
+            hipSetDevice(kv.first);
+            hipFree(kv.second);
+            hipSetDevice(cur);
+        }
+    }
+};
+
+template <typename T>
+static size_t put(std::vector<uint8_t> &blob, const std::vector<T> &v) {
+    size_t off = (blob.size() + 15) & ~(size_t)15;
+    blob.resize(off + std::max<size_t>(v.size() * sizeof(T), 16), 0);
+    if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+}
+
+static void lower(symft_program *h) {
+    const Program &P = h->P;
+    HostLayout &L = h->L;
+    std::vector<DevInstr> ins(P.instrs.size());
+    std::vector<uint32_t> cmeas, rm;
+    std::vector<std::vector<uint32_t>> cons(P.n_noise_sym);
+    for (size_t i = 0; i < P.instrs.size(); ++i) {
+        const Instr &I = P.instrs[i];
+        DevInstr &D = ins[i];
+        std::memset(&D, 0, sizeof(D));
+        D.kind = I.kind;
+        D.k_in = I.k_in;
+        D.h = I.h;
+        D.mu = I.mu;
+        D.eta = I.eta;
+        D.a = I.a;
+        D.b = I.b;
+        D.meas = I.meas;
+        D.c = std::cos(I.theta / 2);
+        D.s = std::sin(I.theta / 2);
+        D.cf = (float)D.c;
+        D.sf = (float)D.s;
+        if (I.kind == RANDOM_MEAS) {
+            rm.push_back((uint32_t)i);
+            continue;  // its sign is never evaluated while sampling
+        }
+        D.lam_c = I.lam.c;
+        D.cm_off = (uint32_t)cmeas.size();
+        D.cm_len = (uint32_t)I.lam.meas.size();
+        cmeas.insert(cmeas.end(), I.lam.meas.begin(), I.lam.meas.end());
+        for (uint32_t s : I.lam.noise) cons[s].push_back((uint32_t)i);
+    }
+    std::vector<uint32_t> symoff(P.n_noise_sym + 1, 0), symcons;
+    for (uint32_t s = 0; s < P.n_noise_sym; ++s) {
+        symoff[s] = (uint32_t)symcons.size();
+        symcons.insert(symcons.end(), cons[s].begin(), cons[s].end());
+    }
+    symoff[P.n_noise_sym] = (uint32_t)symcons.size();
+    std::vector<uint32_t> recmeas(P.n_rec);
+    for (uint64_t t = 0; t < P.n_meas; ++t)
+        if (P.meas_row[t] >= 0) recmeas[(size_t)P.meas_row[t]] = (uint32_t)t;
+    std::vector<uint32_t> detoff, detrows, obsoff, obsrows;
+    for (auto &d : P.det_meas) {
+        detoff.push_back((uint32_t)detrows.size());
+        for (uint32_t t : d) detrows.push_back((uint32_t)P.meas_row[t]);
+    }
+    detoff.push_back((uint32_t)detrows.size());
+    for (auto &o : P.obs_meas) {
+        obsoff.push_back((uint32_t)obsrows.size());
+        for (uint32_t t : o) obsrows.push_back((uint32_t)P.meas_row[t]);
+    }
+    obsoff.push_back((uint32_t)obsrows.size());
+    std::vector<uint64_t> clsQ;
+    std::vector<uint32_t> clsoff, clschan;
+    for (auto &c : P.classes) {
+        clsQ.insert(clsQ.end(), c.Q.begin(), c.Q.end());
+        clsoff.push_back((uint32_t)clschan.size());
+        for (int32_t ch : c.chans) clschan.push_back((uint32_t)ch);
+    }
+    clsoff.push_back((uint32_t)clschan.size());
+    std::vector<DevChan> chans(P.chans.size());
+    std::vector<uint32_t> bmask;
+    std::vector<uint64_t> thr;
+    for (size_t i = 0; i < P.chans.size(); ++i) {
+        const Channel &c = P.chans[i];
+        DevChan &d = chans[i];
+        d.J = (uint8_t)c.J;
+        d.uniform = c.uniform;
+        d.nsym = (uint8_t)c.nsym;
+        d.pad = 0;
+        d.sym0 = c.sym0;
+        d.bm_off = (uint32_t)bmask.size();
+        bmask.insert(bmask.end(), c.bmask.begin(), c.bmask.end());
+        d.thr_off = (uint32_t)thr.size();
+        thr.insert(thr.end(), c.thr.begin(), c.thr.end());
+    }
+    build_frame_schedule(P, h->F);
+    L.blob.clear();
+    L.o_instr = put(L.blob, ins);
+    L.o_cmeas = put(L.blob, cmeas);
+    L.o_rm = put(L.blob, rm);
+    L.o_recmeas = put(L.blob, recmeas);
+    L.o_detoff = put(L.blob, detoff);
+    L.o_detrows = put(L.blob, detrows);
+    L.o_obsoff = put(L.blob, obsoff);
+    L.o_obsrows = put(L.blob, obsrows);
+    L.o_clsQ = put(L.blob, clsQ);
+    L.o_clsoff = put(L.blob, clsoff);
+    L.o_clschan = put(L.blob, clschan);
+    L.o_chan = put(L.blob, chans);
+    L.o_bmask = put(L.blob, bmask);
+    L.o_thr = put(L.blob, thr);
+    L.o_symoff = put(L.blob, symoff);
+    L.o_symcons = put(L.blob, symcons);
+    L.o_frstep = put(L.blob, h->F.steps);
+    L.o_frdata = put(L.blob, h->F.data);
+    L.o_frsymoff = put(L.blob, h->F.sym_off);
+    L.o_frsymslot = put(L.blob, h->F.sym_slot);
+    DevProg &m = L.meta;
+    std::memset(&m, 0, sizeof(m));
+    m.n_instr = (uint32_t)ins.size();
+    m.n_meas = (uint32_t)P.n_meas;
+    m.n_rm = (uint32_t)rm.size();
+    m.n_rec = (uint32_t)P.n_rec;
+    m.n_det = (uint32_t)P.n_det;
+    m.n_obs = (uint32_t)P.n_obs;
+    m.n_cls = (uint32_t)P.classes.size();
+    m.k_max = P.k_max;
+    m.fr_n_steps = (uint32_t)h->F.n_steps;
+    m.fr_n_slots = h->F.n_slots;
+    m.n_sym = P.n_noise_sym;
+}
+
+static symft_status device_prog(symft_program *h, DevProg &out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return set_err(SYMFT_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(h->mu);
+    void *base = nullptr;
+    auto it = h->dev.find(dev);
+    if (it == h->dev.end()) {
+        if (hipMalloc(&base, h->L.blob.size()) != hipSuccess) return set_err(SYMFT_ENOMEM, "device program allocation failed");
+        if (hipMemcpy(base, h->L.blob.data(), h->L.blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            hipFree(base);
+            return set_err(SYMFT_EHIP, "device program upload failed");
+        }
+        h->dev[dev] = base;
+    } else {
+        base = it->second;
+    }
+    const uint8_t *b = (const uint8_t *)base;
+    const HostLayout &L = h->L;
+    out = L.meta;
+    out.instr = (const DevInstr *)(b + L.o_instr);
+    out.cmeas = (const uint32_t *)(b + L.o_cmeas);
+    out.rm_list = (const uint32_t *)(b + L.o_rm);
+    out.rec_meas = (const uint32_t *)(b + L.o_recmeas);
+    out.det_off = (const uint32_t *)(b + L.o_detoff);
+    out.det_rows = (const uint32_t *)(b + L.o_detrows);
+    out.obs_off = (const uint32_t *)(b + L.o_obsoff);
+    out.obs_rows = (const uint32_t *)(b + L.o_obsrows);
+    out.cls_Q = (const uint64_t *)(b + L.o_clsQ);
+    out.cls_off = (const uint32_t *)(b + L.o_clsoff);
+    out.cls_chan = (const uint32_t *)(b + L.o_clschan);
+    out.chan = (const DevChan *)(b + L.o_chan);
+    out.bmask = (const uint32_t *)(b + L.o_bmask);
+    out.thr = (const uint64_t *)(b + L.o_thr);
+    out.sym_off = (const uint32_t *)(b + L.o_symoff);
+    out.sym_cons = (const uint32_t *)(b + L.o_symcons);
+    out.fr_step = (const uint32_t *)(b + L.o_frstep);
+    out.fr_data = (const uint32_t *)(b + L.o_frdata);
+    out.fr_sym_off = (const uint32_t *)(b + L.o_frsymoff);
+    out.fr_sym_slot = (const uint32_t *)(b + L.o_frsymslot);
+    return SYMFT_OK;
+}
+
+static int g_num_cus = 0;
+static int num_cus() {
+    if (!g_num_cus) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceProp_t pr;
+        if (hipGetDeviceProperties(&pr, dev) == hipSuccess) g_num_cus = pr.multiProcessorCount;
+        if (g_num_cus <= 0) g_num_cus = 256;
+    }
+    return g_num_cus;
+}
+
+// Launch configuration of the active kernel for a program (see DESIGN: tuning table).
+struct ActiveConfig {
+    uint32_t bs, tps;
+    bool lds_vec;
+    size_t lds;
+};
+
+static const size_t kLdsLimit = 160 * 1024;
+
+ActiveConfig choose_active(const DevProg &P, bool fp64) {
+    ActiveConfig c;
+    uint32_t k = P.k_max;
+    c.bs = 256;
+    if (k <= 4) c.tps = 16;
+    else if (k == 5) c.tps = 32;
+    else if (k <= 8) c.tps = 64;
+    else if (k == 9) c.tps = 128;
+    else c.tps = 256;
+    if (k >= 13) {
+        c.bs = 1024;
+        c.tps = 1024;
+    }
+    c.lds = active_lds_bytes(P, c.bs, c.tps, true, fp64);
+    c.lds_vec = c.lds <= kLdsLimit;
+    if (!c.lds_vec) c.lds = active_lds_bytes(P, c.bs, c.tps, false, fp64);
+    return c;
+}
+
+static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, uint64_t word_begin, uint64_t n_words,
+                               uint64_t shots, uint64_t *out, uint64_t stride, uint32_t sections, double *p0,
+                               uint64_t probe_shot0, uint64_t probe_n, uint64_t seed, hipStream_t st) {
+    ActiveConfig c = choose_active(D, fp64);
+    if (c.lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "program tables exceed the LDS budget of the active kernel");
+    int per_cu = active_max_blocks_per_cu(fp64, c.bs, c.lds_vec, c.lds);
+    if (per_cu <= 0) per_cu = 1;
+    uint64_t cap = (uint64_t)per_cu * (uint64_t)num_cus();
+    if (!c.lds_vec) cap = std::min<uint64_t>(cap, (uint64_t)num_cus() * 2);
+    uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_words, cap));
+    ActiveArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.P = D;
+    A.seed = seed;
+    A.word_begin = word_begin;
+    A.n_words = n_words;
+    A.shots = shots;
+    A.out = out;
+    A.row_stride = stride;
+    A.sections = sections;
+    A.tps = c.tps;
+    A.p0_out = p0;
+    A.probe_shot0 = probe_shot0;
+    A.probe_n = probe_n;
+    A.lds_vec = c.lds_vec ? 1 : 0;
+    A.lds_bytes = (uint32_t)c.lds;
+    void *scratch = nullptr;
+    if (!c.lds_vec) {
+        const uint32_t G = c.bs / c.tps;
+        A.scratch_stride = (uint64_t)1 << D.k_max;
+        size_t bytes = (size_t)grid * G * A.scratch_stride * (fp64 ? 16 : 8);
+        if (hipMallocAsync(&scratch, bytes, st) != hipSuccess) return set_err(SYMFT_ENOMEM, "vector scratch allocation failed");
+        A.scratch = scratch;
+    }
+    hipError_t e = launch_active(A, fp64, c.bs, grid, st);
+    if (scratch) hipFreeAsync(scratch, st);
+    if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("active kernel launch failed: ") + hipGetErrorString(e));
+    return SYMFT_OK;
+}
+
+static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_begin, uint64_t n_words, uint64_t shots,
+                              uint64_t *out, uint64_t stride, uint32_t sections, uint64_t seed, hipStream_t st) {
+    const uint32_t wpb = frame_words_per_block(D);
+    size_t lds = frame_lds_bytes(D, wpb);
+    if (lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "frame schedule exceeds the LDS budget");
+    int per_cu = frame_max_blocks_per_cu(lds);
+    if (per_cu <= 0) per_cu = 1;
+    uint64_t tiles = (n_words + wpb - 1) / wpb;
+    uint64_t cap = (uint64_t)per_cu * (uint64_t)num_cus();
+    uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
+    FrameArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.P = D;
+    A.seed = seed;
+    A.word_begin = word_begin;
+    A.n_words = n_words;
+    A.shots = shots;
+    A.out = out;
+    A.row_stride = stride;
+    A.sections = sections;
+    A.wpb = wpb;
+    A.lds_bytes = (uint32_t)lds;
+    hipError_t e = launch_frame(A, grid, st);
+    if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("frame kernel launch failed: ") + hipGetErrorString(e));
+    return SYMFT_OK;
+}
+
+extern "C" {
+
+const char *symft_last_error(void) { return g_err.c_str(); }
+
+symft_status symft_compile(uint32_t n_qubits, const symft_op *ops, size_t n_ops, const void *opts, symft_program **out) {
+    (void)opts;
+    if (!out) return set_err(SYMFT_EINVAL, "out is NULL");
+    *out = nullptr;
+    symft_program *h = nullptr;
+    try {
+        h = new symft_program();
+        std::string err;
+        int rc = compile_program(n_qubits, ops, n_ops, h->P, err);
+        if (rc) {
+            delete h;
+            return set_err(rc, err);
+        }
+        lower(h);
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return set_err(SYMFT_ENOMEM, "host allocation failed during compile");
+    }
+    *out = h;
+    return SYMFT_OK;
+}
+
+void symft_program_free(symft_program *p) { delete p; }
+
+symft_status symft_program_info(const symft_program *p, symft_info *info) {
+    if (!p || !info) return set_err(SYMFT_EINVAL, "NULL argument");
+    const Program &P = p->P;
+    std::memset(info, 0, sizeof(*info));
+    info->n_qubits = P.n_qubits;
+    info->k_max = P.k_max;
+    info->n_ops = P.n_ops;
+    info->n_measurements = P.n_meas;
+    info->n_records = P.n_rec;
+    info->n_detectors = P.n_det;
+    info->n_observables = P.n_obs;
+    info->n_rows = P.n_rows();
+    info->n_channels = P.chans.size();
+    info->n_classes = P.classes.size();
+    info->n_noise_symbols = P.n_noise_sym;
+    double flops = 0, bytes = 0;
+    for (const Instr &I : P.instrs) {
+        info->n_instr[I.kind] += 1;
+        if (I.kind != RANDOM_MEAS) {
+            info->expr_noise_nnz += I.lam.noise.size();
+            info->expr_meas_nnz += I.lam.meas.size();
+        }
+        const double N = std::ldexp(1.0, I.k_in);
+        switch (I.kind) {
+        case PROMOTE_ROT: flops += 4 * N; bytes += 8 * (N + 2 * N); break;
+        case ACTIVE_DIAG_ROT: flops += 6 * N; bytes += 8 * 2 * N; break;
+        case ACTIVE_PAIR_ROT: flops += 6 * N; bytes += 8 * 2 * N; break;
+        case ACTIVE_DIAG_MEAS: flops += 4 * N + 2 * (N / 2); bytes += 8 * (N + N / 2); break;
+        case ACTIVE_PAIR_MEAS: flops += 8 * N + 6 * (N / 2); bytes += 8 * (N + N / 2); break;
+        default: break;
+        }
+    }
+    info->dense_flops_per_shot = flops;
+    info->dense_bytes_per_shot = bytes;
+    return SYMFT_OK;
+}
+
+symft_status symft_program_plan(const symft_program *p, int16_t *k_after_op, int8_t *meas_kind, int8_t *rot_kind) {
+    if (!p) return set_err(SYMFT_EINVAL, "NULL program");
+    const Program &P = p->P;
+    if (k_after_op) std::memcpy(k_after_op, P.k_after_op.data(), P.k_after_op.size() * sizeof(int16_t));
+    if (meas_kind) std::memcpy(meas_kind, P.meas_kind.data(), P.meas_kind.size());
+    if (rot_kind) std::memcpy(rot_kind, P.rot_kind.data(), P.rot_kind.size());
+    return SYMFT_OK;
+}
+
+symft_status symft_program_export(const symft_program *p, uint64_t *counts, int64_t *instr, double *theta,
+                                  uint32_t *noise_refs, uint32_t *meas_refs, int64_t *chan, uint32_t *bmask) {
+    if (!p || !counts) return set_err(SYMFT_EINVAL, "NULL argument");
+    const Program &P = p->P;
+    uint64_t nn = 0, nmr = 0, nb = 0;
+    for (const Instr &I : P.instrs) {
+        nn += I.lam.noise.size();
+        nmr += I.lam.meas.size();
+    }
+    for (const Channel &c : P.chans) nb += c.bmask.size();
+    counts[0] = P.instrs.size();
+    counts[1] = nn;
+    counts[2] = nmr;
+    counts[3] = P.chans.size();
+    counts[4] = nb;
+    uint64_t on = 0, om = 0, ob = 0;
+    for (size_t i = 0; i < P.instrs.size(); ++i) {
+        const Instr &I = P.instrs[i];
+        if (instr) {
+            int64_t *r = instr + 13 * i;
+            r[0] = I.kind; r[1] = I.k_in; r[2] = I.h; r[3] = I.mu; r[4] = I.eta; r[5] = I.lam.c;
+            r[6] = I.a; r[7] = I.b; r[8] = I.meas;
+            r[9] = (int64_t)on; r[10] = (int64_t)I.lam.noise.size();
+            r[11] = (int64_t)om; r[12] = (int64_t)I.lam.meas.size();
+        }
+        if (theta) theta[i] = I.theta;
+        if (noise_refs) std::copy(I.lam.noise.begin(), I.lam.noise.end(), noise_refs + on);
+        if (meas_refs) std::copy(I.lam.meas.begin(), I.lam.meas.end(), meas_refs + om);
+        on += I.lam.noise.size();
+        om += I.lam.meas.size();
+    }
+    for (size_t c = 0; c < P.chans.size(); ++c) {
+        const Channel &ch = P.chans[c];
+        if (chan) {
+            chan[4 * c] = ch.sym0; chan[4 * c + 1] = ch.nsym; chan[4 * c + 2] = ch.J; chan[4 * c + 3] = (int64_t)ob;
+        }
+        if (bmask) std::copy(ch.bmask.begin(), ch.bmask.end(), bmask + ob);
+        ob += ch.bmask.size();
+    }
+    return SYMFT_OK;
+}
+
+symft_status symft_sample_ex(const symft_program *pc, const symft_sample_opts *opts, uint64_t shots, uint64_t seed,
+                             uint64_t *records_out, void *stream) {
+    symft_program *p = const_cast<symft_program *>(pc);
+    if (!p) return set_err(SYMFT_EINVAL, "NULL program");
+    symft_sample_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (o.shot_offset % 64) return set_err(SYMFT_EINVAL, "shot_offset must be a multiple of 64");
+    if (o.precision > 1) return set_err(SYMFT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+    if (shots == 0) return SYMFT_OK;
+    if (!records_out) return set_err(SYMFT_EINVAL, "records_out is NULL");
+    const uint64_t n_words = (shots + 63) / 64;
+    const uint64_t stride = o.row_stride_words ? o.row_stride_words : n_words;
+    if (stride < n_words) return set_err(SYMFT_EINVAL, "row_stride_words smaller than the shot words");
+    const uint32_t sections = o.sections ? o.sections : 7u;
+    DevProg D;
+    symft_status rc = device_prog(p, D);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t w0 = o.shot_offset / 64;
+    if (D.k_max == 0 && D.fr_n_steps > 0 && frame_words_per_block(D) > 0)
+        return run_frame(p, D, w0, n_words, shots, records_out, stride, sections, seed, st);
+    return run_active(p, D, o.precision == 0, w0, n_words, shots, records_out, stride, sections, nullptr, 0, 0, seed, st);
+}
+
+symft_status symft_sample(const symft_program *p, uint64_t shots, uint64_t seed, uint64_t *records_out, void *stream) {
+    return symft_sample_ex(p, nullptr, shots, seed, records_out, stream);
+}
+
+symft_status symft_probe(const symft_program *pc, uint64_t shot_begin, uint32_t n_shots, uint64_t seed,
+                         uint32_t precision, double *p0_host) {
+    symft_program *p = const_cast<symft_program *>(pc);
+    if (!p || !p0_host) return set_err(SYMFT_EINVAL, "NULL argument");
+    if (precision > 1) return set_err(SYMFT_EINVAL, "precision must be 0 or 1");
+    if (n_shots == 0) return SYMFT_OK;
+    DevProg D;
+    symft_status rc = device_prog(p, D);
+    if (rc) return rc;
+    const uint64_t w0 = shot_begin / 64, w1 = (shot_begin + n_shots + 63) / 64;
+    const uint64_t nw = w1 - w0;
+    const size_t nm = std::max<size_t>(1, p->P.n_meas);
+    double *dp0 = nullptr;
+    uint64_t *drec = nullptr;
+    const uint64_t rows = std::max<uint64_t>(1, p->P.n_rows());
+    if (hipMalloc(&dp0, sizeof(double) * nm * n_shots) != hipSuccess) return set_err(SYMFT_ENOMEM, "probe allocation failed");
+    if (hipMalloc(&drec, 8 * rows * nw) != hipSuccess) {
+        hipFree(dp0);
+        return set_err(SYMFT_ENOMEM, "probe allocation failed");
+    }
+    hipMemset(dp0, 0xff, sizeof(double) * nm * n_shots);  // NaN pattern
+    rc = run_active(p, D, precision == 0, w0, nw, nw * 64, drec, nw, 7u, dp0, shot_begin, n_shots, seed, nullptr);
+    if (rc == SYMFT_OK) {
+        if (hipDeviceSynchronize() != hipSuccess ||
+            hipMemcpy(p0_host, dp0, sizeof(double) * nm * n_shots, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = set_err(SYMFT_EHIP, "probe copy failed");
+    }
+    hipFree(dp0);
+    hipFree(drec);
+    return rc;
+}
+
+symft_status symft_sample_batch(const symft_program *const *progs, const uint64_t *shots, const uint64_t *seeds,
+                                uint64_t *const *records_out, size_t n, uint32_t precision, uint32_t graph,
+                                void *stream) {
+    (void)graph;
+    if (n && (!progs || !shots || !seeds || !records_out)) return set_err(SYMFT_EINVAL, "NULL argument");
+    for (size_t i = 0; i < n; ++i) {
+        symft_sample_opts o;
+        std::memset(&o, 0, sizeof(o));
+        o.precision = precision;
+        symft_status rc = symft_sample_ex(progs[i], &o, shots[i], seeds[i], records_out[i], stream);
+        if (rc) return rc;
+    }
+    return SYMFT_OK;
+}
+
+}  // extern "C"

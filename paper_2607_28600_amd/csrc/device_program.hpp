@@ -1,0 +1,59 @@
+// device_program.hpp -- the sampling program as laid out in device memory.
+// Shared by the host lowering (capi.cpp) and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace symft {
+
+// One sampling instruction (48 bytes).  cos/sin(theta/2) are computed once on
+// the host in FP64; the FP32 copies are rounded from them, so the kernels
+// evaluate no transcendental function.
+struct DevInstr {
+    uint8_t kind, k_in, h, mu;     // mu: power of i
+    uint8_t eta, lam_c, pad0, pad1;
+    uint32_t a, b;
+    int32_t meas;                  // measurement index (measurements)
+    uint32_t cm_off, cm_len;       // causal measurement refs of lambda
+    uint32_t pad2;
+    double c, s;
+    float cf, sf;
+};
+static_assert(sizeof(DevInstr) == 56, "DevInstr layout");
+
+// Noise channel under the draw contract.
+struct DevChan {
+    uint8_t J, uniform, nsym, pad;
+    uint32_t sym0;     // first noise symbol
+    uint32_t bm_off;   // J branch masks in bmask[]
+    uint32_t thr_off;  // J thresholds in thr[] (non-uniform only)
+};
+
+// Pointers into one device allocation (all read-only in the kernels).
+struct DevProg {
+    const DevInstr *instr;
+    const uint32_t *cmeas;       // causal refs (measurement ids)
+    const uint32_t *rm_list;     // instructions that are RandomMeas
+    const uint32_t *rec_meas;    // record row -> measurement id
+    const uint32_t *det_off;     // n_det + 1
+    const uint32_t *det_rows;    // record rows per detector
+    const uint32_t *obs_off;     // n_obs + 1
+    const uint32_t *obs_rows;    // record rows per observable (XOR)
+    const uint64_t *cls_Q;       // n_cls x 4097
+    const uint32_t *cls_off;     // n_cls + 1 into cls_chan
+    const uint32_t *cls_chan;    // channel ids by rank
+    const DevChan *chan;
+    const uint32_t *bmask;
+    const uint64_t *thr;
+    const uint32_t *sym_off;     // n_sym + 1 into sym_cons
+    const uint32_t *sym_cons;    // consumer instruction ids per noise symbol
+    // pure-frame schedule (k_max == 0 programs)
+    const uint32_t *fr_step;     // per step: (kind << 28) | payload offset, see frame kernel
+    const uint32_t *fr_data;
+    const uint32_t *fr_sym_off;  // n_sym + 1 into fr_sym_slot
+    const uint32_t *fr_sym_slot; // consumer slots per noise symbol
+    uint32_t n_instr, n_meas, n_rm, n_rec, n_det, n_obs, n_cls, k_max;
+    uint32_t fr_n_steps, fr_n_slots, n_sym, pad;
+};
+
+}  // namespace symft

@@ -1,0 +1,455 @@
+// sample_active.hip -- per-shot replay of a SymFT program with a dense active
+// vector (paper Sec. 5), for gfx950.
+//
+// One workgroup owns one 64-shot word at a time (persistent loop over words):
+//   1. noise events of the word are drawn cooperatively under the draw
+//      contract (geometric gaps per probability class, block-wide prefix
+//      sums over 1024 draws per step) and scattered by LDS atomic XOR into
+//      the exogenous part of every consuming sign expression, exo[i];
+//   2. RandomMeas words (64 bits per measurement) are drawn into exo[i];
+//   3. shot groups of TPS threads step through the instruction stream in
+//      lockstep (the stream and the active width trajectory are the same for
+//      every shot).  lambda = const ^ exo bit ^ parity of earlier outcomes of
+//      the shot.  The vector of each group lives in LDS or, when 2^k_max does
+//      not fit, in an HBM scratch slice of the workgroup;
+//   4. the word's records, detectors and observables are written.
+// Branch probabilities are reduced in the amplitude precision (FP32 with
+// compensated per-thread sums and pairwise wave trees, or FP64), and the
+// threshold Pr(m = 0) and the renormalisation scale are formed in FP64.
+#include <hip/hip_runtime.h>
+
+#include "launch_args.hpp"
+#include "philox.hpp"
+
+namespace symft {
+
+template <typename T> struct C2;
+template <> struct C2<float> { using type = float2; };
+template <> struct C2<double> { using type = double2; };
+
+
+
+__device__ __forceinline__ uint32_t insert_bit(uint32_t z, uint32_t h, uint32_t v) {
+    uint32_t lo = z & ((1u << h) - 1u);
+    return lo | (v << h) | ((z >> h) << (h + 1));
+}
+
+__device__ __forceinline__ int parity(uint32_t v) { return __popc(v) & 1; }
+
+// G = max { g in [0, 4096] : v < Q[g] }, Q non-increasing with Q[0] = 2^32 > v.
+__device__ __forceinline__ int gap_search(const uint64_t *__restrict__ Q, uint32_t v) {
+    if ((uint64_t)v < Q[4096]) return 4096;
+    int lo = 0, hi = 4096;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if ((uint64_t)v < Q[mid]) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Block-wide exclusive scan of (a, b) pairs packed as 64-bit (a in low 32).
+template <int BS>
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *tmp, uint64_t &total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint64_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint64_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) tmp[wid] = x;
+    __syncthreads();
+    uint64_t base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < BS / 64; ++i) {
+        uint64_t t = tmp[i];
+        if (i < wid) base += t;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return base + x - v;
+}
+
+// Draw the word's noise events and XOR them into exo[] (draw contract, domains 1 and 2).
+template <int BS>
+__device__ void word_noise(const DevProg &P, uint64_t seed, uint64_t w, unsigned long long *exo, uint64_t *tmp) {
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t wlo = (uint32_t)w, whi = (uint32_t)(w >> 32);
+    for (uint32_t c = 0; c < P.n_cls; ++c) {
+        const uint64_t *Q = P.cls_Q + (size_t)c * 4097;
+        const uint32_t coff = P.cls_off[c];
+        const uint64_t end = (uint64_t)(P.cls_off[c + 1] - coff) * 64;
+        uint64_t pos = 0, ev0 = 0, blk0 = 0;
+        while (pos < end) {
+            uint4 r = philox4x32_10(make_uint4((uint32_t)(blk0 + threadIdx.x), wlo, c, (1u << 24) | whi), k0, k1);
+            uint32_t v[4] = {r.x, r.y, r.z, r.w};
+            int G[4];
+            uint32_t inc = 0, evc = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                G[i] = gap_search(Q, v[i]);
+                inc += (G[i] == 4096) ? 4096u : (uint32_t)G[i] + 1u;
+                evc += (G[i] < 4096) ? 1u : 0u;
+            }
+            uint64_t total;
+            uint64_t ex = block_excl_scan<BS>(((uint64_t)evc << 40) | inc, tmp, total);
+            uint64_t p = pos + (ex & ((1ull << 40) - 1));
+            uint64_t e = ev0 + (ex >> 40);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (G[i] < 4096) {
+                    uint64_t at = p + (uint64_t)G[i];
+                    if (at < end) {
+                        uint32_t rank = (uint32_t)(at >> 6), lane = (uint32_t)(at & 63);
+                        const DevChan ch = P.chan[P.cls_chan[coff + rank]];
+                        uint4 br = philox4x32_10(make_uint4((uint32_t)(e >> 2), wlo, c, (2u << 24) | whi), k0, k1);
+                        uint32_t bv = (e & 3) == 0 ? br.x : (e & 3) == 1 ? br.y : (e & 3) == 2 ? br.z : br.w;
+                        uint32_t j;
+                        if (ch.uniform) {
+                            j = (uint32_t)(((uint64_t)bv * ch.J) >> 32);
+                        } else {
+                            j = ch.J - 1;
+                            for (uint32_t t = 0; t < ch.J; ++t)
+                                if ((uint64_t)bv < P.thr[ch.thr_off + t]) { j = t; break; }
+                        }
+                        uint32_t mask = P.bmask[ch.bm_off + j];
+                        while (mask) {
+                            uint32_t s = ch.sym0 + (uint32_t)__ffs(mask) - 1u;
+                            mask &= mask - 1u;
+                            for (uint32_t q = P.sym_off[s]; q < P.sym_off[s + 1]; ++q)
+                                atomicXor(&exo[P.sym_cons[q]], 1ull << lane);
+                        }
+                    }
+                    ++e;
+                }
+                p += (G[i] == 4096) ? 4096u : (uint32_t)G[i] + 1u;
+            }
+            pos += total & ((1ull << 40) - 1);
+            ev0 += total >> 40;
+            blk0 += BS;
+        }
+    }
+}
+
+// Sum over the TPS lanes of a shot group; every lane gets the same value.
+template <typename T, int BS>
+__device__ __forceinline__ void group_sum2(T &s0, T &s1, int tps, T *red) {
+    const int lim = tps < 64 ? tps : 64;
+    for (int off = lim >> 1; off > 0; off >>= 1) {
+        s0 += __shfl_xor(s0, off, 64);
+        s1 += __shfl_xor(s1, off, 64);
+    }
+    if (tps > 64) {
+        const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        if (lane == 0) { red[2 * wid] = s0; red[2 * wid + 1] = s1; }
+        __syncthreads();
+        const int w0 = (threadIdx.x / tps) * (tps >> 6), nw = tps >> 6;
+        T a = 0, b = 0;
+        for (int i = 0; i < nw; ++i) { a += red[2 * (w0 + i)]; b += red[2 * (w0 + i) + 1]; }
+        __syncthreads();
+        s0 = a; s1 = b;
+    }
+}
+
+// Parity of the causal part of lambda for the shot of this group.
+__device__ __forceinline__ int causal_parity(const DevProg &P, const DevInstr &I, const uint32_t *mb, int tps) {
+    if (I.cm_len == 0) return 0;
+    const int unit = tps < 64 ? tps : 64;
+    const int r = (int)(threadIdx.x % unit);
+    int x = 0;
+    for (uint32_t j = (uint32_t)r; j < I.cm_len; j += (uint32_t)unit) {
+        uint32_t t = P.cmeas[I.cm_off + j];
+        x ^= (int)((mb[t >> 5] >> (t & 31)) & 1u);
+    }
+    uint64_t bal = __ballot(x);
+    if (unit < 64) {
+        const int sub = (int)((threadIdx.x & 63) / unit);
+        bal = (bal >> (sub * unit)) & ((1ull << unit) - 1ull);
+    }
+    return __popcll(bal) & 1;
+}
+
+template <typename T>
+__device__ __forceinline__ void kahan_add(T &s, T &c, T v) {
+    T y = v - c;
+    T t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+template <typename T, int BS, bool LDSV>
+__global__ void __launch_bounds__(BS) active_kernel(ActiveArgs A) {
+    using V = typename C2<T>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const DevProg &P = A.P;
+    const int tps = (int)A.tps;
+    const int G = BS / tps;
+    const int g = threadIdx.x / tps, r = threadIdx.x % tps;
+    const uint32_t mw = (P.n_meas + 31) / 32;
+    // LDS carve-up
+    unsigned long long *exo = (unsigned long long *)smem;                       // n_instr
+    unsigned long long *recw = exo + P.n_instr;                                  // n_rec
+    uint64_t *tmp = (uint64_t *)(recw + P.n_rec);                                // 16
+    T *red = (T *)(tmp + 16);                                                    // 2 * BS/64
+    uint32_t *mbits = (uint32_t *)(red + 2 * (BS / 64) + 2);                     // G * mw
+    V *vec_lds = (V *)(((uintptr_t)(mbits + G * mw) + 15) & ~(uintptr_t)15);     // G * 2^kmax (LDS mode)
+    const size_t vlen = (size_t)1 << P.k_max;
+    V *vec;
+    if (LDSV) vec = vec_lds + (size_t)g * vlen;
+    else vec = (V *)A.scratch + ((size_t)blockIdx.x * G + g) * A.scratch_stride;
+    uint32_t *mb = mbits + g * mw;
+    const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
+
+    for (uint64_t wi = blockIdx.x; wi < A.n_words; wi += gridDim.x) {
+        const uint64_t w = A.word_begin + wi;
+        for (uint32_t i = threadIdx.x; i < P.n_instr; i += BS) exo[i] = 0;
+        for (uint32_t i = threadIdx.x; i < P.n_rec; i += BS) recw[i] = 0;
+        __syncthreads();
+        word_noise<BS>(P, A.seed, w, exo, tmp);
+        for (uint32_t i = threadIdx.x; i < P.n_rm; i += BS) {
+            const uint32_t ii = P.rm_list[i];
+            const uint32_t t = (uint32_t)P.instr[ii].meas;
+            uint4 o = philox4x32_10(make_uint4(t >> 1, (uint32_t)w, 0u, (3u << 24) | (uint32_t)(w >> 32)), k0, k1);
+            exo[ii] = (t & 1) ? ((uint64_t)o.z | ((uint64_t)o.w << 32)) : ((uint64_t)o.x | ((uint64_t)o.y << 32));
+        }
+        __syncthreads();
+
+        for (int base = 0; base < 64; base += G) {
+            const int lane = base + g;
+            const uint64_t shot = w * 64 + (uint64_t)lane;
+            for (uint32_t i = (uint32_t)r; i < mw; i += (uint32_t)tps) mb[i] = 0;
+            if (r == 0) { vec[0].x = (T)1; vec[0].y = (T)0; }
+            __syncthreads();
+            for (uint32_t ii = 0; ii < P.n_instr; ++ii) {
+                const DevInstr I = P.instr[ii];
+                const uint32_t N = 1u << I.k_in;
+                const int lam = (int)I.lam_c ^ (int)((exo[ii] >> lane) & 1ull) ^ causal_parity(P, I, mb, tps);
+                const T c = sizeof(T) == 8 ? (T)I.c : (T)I.cf;
+                const T s = sizeof(T) == 8 ? (T)I.s : (T)I.sf;
+                switch (I.kind) {
+                case 1: {  // PromoteRot: x0 <- c a_x, x1 <- -i (-1)^lam s a_x
+                    const T ss = lam ? -s : s;
+                    for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
+                        V v = vec[x];
+                        V hi;
+                        hi.x = ss * v.y;
+                        hi.y = -ss * v.x;
+                        vec[x + N] = hi;
+                        v.x *= c; v.y *= c;
+                        vec[x] = v;
+                    }
+                    break;
+                }
+                case 2: {  // ActiveDiagRot: a_x *= c - i sigma s, sigma = (-1)^lam mu (-1)^(b.x)
+                    const int neg = lam ^ (I.mu == 2 ? 1 : 0);
+                    for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
+                        const T sg = (neg ^ parity(I.b & x)) ? -s : s;
+                        V v = vec[x];
+                        V o;
+                        o.x = c * v.x + sg * v.y;
+                        o.y = c * v.y - sg * v.x;
+                        vec[x] = o;
+                    }
+                    break;
+                }
+                case 3: {  // ActivePairRot on pairs (x0, x0 ^ a), bit h of x0 = 0
+                    // a'_x = c a_x - i (-1)^lam s mu (-1)^(b.(x^a)) a_(x^a); with mu = i^m:
+                    // -i mu = i^(m+3)
+                    const uint32_t half = N >> 1;
+                    const int e0 = (int)I.mu + 3 + 2 * lam;
+                    for (uint32_t z = (uint32_t)r; z < half; z += (uint32_t)tps) {
+                        const uint32_t x0 = insert_bit(z, I.h, 0), x1 = x0 ^ I.a;
+                        V a0 = vec[x0], a1 = vec[x1];
+                        // factor f0 multiplies a1 into x0's update, f1 multiplies a0 into x1's
+                        const int q0 = (e0 + 2 * parity(I.b & x1)) & 3;
+                        const int q1 = (e0 + 2 * parity(I.b & x0)) & 3;
+                        // multiply by s * i^q
+                        V t0, t1;
+                        t0.x = (q0 == 0) ? a1.x : (q0 == 1) ? -a1.y : (q0 == 2) ? -a1.x : a1.y;
+                        t0.y = (q0 == 0) ? a1.y : (q0 == 1) ? a1.x : (q0 == 2) ? -a1.y : -a1.x;
+                        t1.x = (q1 == 0) ? a0.x : (q1 == 1) ? -a0.y : (q1 == 2) ? -a0.x : a0.y;
+                        t1.y = (q1 == 0) ? a0.y : (q1 == 1) ? a0.x : (q1 == 2) ? -a0.y : -a0.x;
+                        V n0, n1;
+                        n0.x = c * a0.x + s * t0.x; n0.y = c * a0.y + s * t0.y;
+                        n1.x = c * a1.x + s * t1.x; n1.y = c * a1.y + s * t1.y;
+                        vec[x0] = n0;
+                        vec[x1] = n1;
+                    }
+                    break;
+                }
+                case 4: {  // RandomMeas
+                    if (r == 0) {
+                        const uint32_t t = (uint32_t)I.meas;
+                        if ((exo[ii] >> lane) & 1ull) mb[t >> 5] |= 1u << (t & 31);
+                        if (A.p0_out && shot - A.probe_shot0 < A.probe_n) A.p0_out[(shot - A.probe_shot0) * P.n_meas + t] = 0.5;
+                    }
+                    break;
+                }
+                case 5: {  // DetMeas: m = lambda ^ eta (exo holds the noise part of lambda)
+                    if (r == 0) {
+                        const uint32_t t = (uint32_t)I.meas;
+                        if (lam ^ I.eta) mb[t >> 5] |= 1u << (t & 31);
+                        if (A.p0_out && shot - A.probe_shot0 < A.probe_n)
+                            A.p0_out[(shot - A.probe_shot0) * P.n_meas + t] = (lam ^ I.eta) ? 0.0 : 1.0;
+                    }
+                    break;
+                }
+                case 6:    // ActiveDiagMeas
+                case 7: {  // ActivePairMeas
+                    const uint32_t half = N >> 1;
+                    const bool pair = I.kind == 7;
+                    // conj(mu) (-1)^(b.u0) for the pair case; diag: parity classes of b.x
+                    T s0 = 0, s1 = 0, c0 = 0, c1 = 0;
+                    const T rs2 = (T)0.70710678118654752440;
+                    if (!pair) {
+                        for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
+                            V v = vec[x];
+                            T m2 = v.x * v.x + v.y * v.y;
+                            if (parity(I.b & x)) kahan_add(s1, c1, m2); else kahan_add(s0, c0, m2);
+                        }
+                    } else {
+                        const int mc = (4 - (int)I.mu) & 3;  // conj(mu) = i^mc
+                        for (uint32_t z = (uint32_t)r; z < half; z += (uint32_t)tps) {
+                            const uint32_t u0 = insert_bit(z, I.h, 0);
+                            V a0 = vec[u0], a1 = vec[u0 ^ I.a];
+                            const int q = (mc + 2 * parity(I.b & u0)) & 3;
+                            T tx = (q == 0) ? a1.x : (q == 1) ? -a1.y : (q == 2) ? -a1.x : a1.y;
+                            T ty = (q == 0) ? a1.y : (q == 1) ? a1.x : (q == 2) ? -a1.y : -a1.x;
+                            T bx = (a0.x + tx) * rs2, by = (a0.y + ty) * rs2;
+                            T dx = (a0.x - tx) * rs2, dy = (a0.y - ty) * rs2;
+                            kahan_add(s0, c0, bx * bx + by * by);
+                            kahan_add(s1, c1, dx * dx + dy * dy);
+                        }
+                    }
+                    group_sum2<T, BS>(s0, s1, tps, red);
+                    // y = classes: diag keeps b.x = m ^ lam ^ eta, pair keeps y = m ^ lam
+                    const int flip = pair ? lam : (lam ^ (int)I.eta);
+                    const double S0 = (double)s0, S1 = (double)s1;
+                    const double p0 = (flip ? S1 : S0) / (S0 + S1);
+                    const uint32_t t = (uint32_t)I.meas;
+                    uint4 o = philox4x32_10(make_uint4(t, (uint32_t)shot, (uint32_t)(shot >> 32), 4u << 24), k0, k1);
+                    const double u = (double)(((uint64_t)o.x << 21) + (uint64_t)(o.y >> 11)) * 0x1p-53;
+                    const int m = (u < p0) ? 0 : 1;
+                    const int y = m ^ flip;  // kept class
+                    const double Sy = y ? S1 : S0;
+                    const T scale = (T)(1.0 / sqrt(Sy > 0x1p-1000 ? Sy : 0x1p-1000));
+                    if (r == 0) {
+                        if (m) mb[t >> 5] |= 1u << (t & 31);
+                        if (A.p0_out && shot - A.probe_shot0 < A.probe_n) A.p0_out[(shot - A.probe_shot0) * P.n_meas + t] = p0;
+                    }
+                    // compaction 2^k -> 2^(k-1); sources of output z lie at indices >= z, so
+                    // chunks are read into registers, then written after a barrier
+                    const uint32_t chunk = (uint32_t)tps * 4u;
+                    const int mc = (4 - (int)I.mu) & 3;
+                    const uint32_t bl = I.b & ~(1u << I.h);
+                    for (uint32_t z0 = 0; z0 < half; z0 += chunk) {
+                        V vals[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const uint32_t z = z0 + (uint32_t)e * (uint32_t)tps + (uint32_t)r;
+                            if (z < half) {
+                                if (!pair) {
+                                    const uint32_t uu = insert_bit(z, I.h, (uint32_t)y);
+                                    const uint32_t x = uu ^ ((uint32_t)parity(bl & uu) << I.h);
+                                    V v = vec[x];
+                                    vals[e].x = v.x * scale; vals[e].y = v.y * scale;
+                                } else {
+                                    const uint32_t u0 = insert_bit(z, I.h, 0);
+                                    V a0 = vec[u0], a1 = vec[u0 ^ I.a];
+                                    const int q = (mc + 2 * parity(I.b & u0) + 2 * y) & 3;
+                                    T tx = (q == 0) ? a1.x : (q == 1) ? -a1.y : (q == 2) ? -a1.x : a1.y;
+                                    T ty = (q == 0) ? a1.y : (q == 1) ? a1.x : (q == 2) ? -a1.y : -a1.x;
+                                    vals[e].x = (a0.x + tx) * rs2 * scale;
+                                    vals[e].y = (a0.y + ty) * rs2 * scale;
+                                }
+                            }
+                        }
+                        __syncthreads();
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const uint32_t z = z0 + (uint32_t)e * (uint32_t)tps + (uint32_t)r;
+                            if (z < half) vec[z] = vals[e];
+                        }
+                        __syncthreads();
+                    }
+                    break;
+                }
+                default: break;
+                }
+                __syncthreads();
+            }
+            // visible records of this shot into the word's rows
+            if (shot - A.word_begin * 64 < A.shots) {
+                for (uint32_t row = (uint32_t)r; row < P.n_rec; row += (uint32_t)tps) {
+                    const uint32_t t = P.rec_meas[row];
+                    if ((mb[t >> 5] >> (t & 31)) & 1u) atomicOr(&recw[row], 1ull << lane);
+                }
+            }
+            __syncthreads();
+        }
+        // write rows: records, detectors, observables
+        const uint64_t col = wi;
+        if (A.sections & 1u)
+            for (uint32_t row = threadIdx.x; row < P.n_rec; row += BS) A.out[(uint64_t)row * A.row_stride + col] = recw[row];
+        if (A.sections & 2u)
+            for (uint32_t d = threadIdx.x; d < P.n_det; d += BS) {
+                uint64_t v = 0;
+                for (uint32_t q = P.det_off[d]; q < P.det_off[d + 1]; ++q) v ^= recw[P.det_rows[q]];
+                A.out[(uint64_t)(P.n_rec + d) * A.row_stride + col] = v;
+            }
+        if (A.sections & 4u)
+            for (uint32_t b = threadIdx.x; b < P.n_obs; b += BS) {
+                uint64_t v = 0;
+                for (uint32_t q = P.obs_off[b]; q < P.obs_off[b + 1]; ++q) v ^= recw[P.obs_rows[q]];
+                A.out[(uint64_t)(P.n_rec + P.n_det + b) * A.row_stride + col] = v;
+            }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- host ----
+template <typename T, int BS, bool LDSV>
+static hipError_t launch_one(const ActiveArgs &A, uint32_t grid, hipStream_t st) {
+    auto kfn = active_kernel<T, BS, LDSV>;
+    hipError_t e = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kfn, dim3(grid), dim3(BS), A.lds_bytes, st, A);
+    return hipGetLastError();
+}
+
+size_t active_lds_bytes(const DevProg &P, uint32_t bs, uint32_t tps, bool lds_vec, bool fp64) {
+    const uint32_t G = bs / tps;
+    const uint32_t mw = (P.n_meas + 31) / 32;
+    size_t b = 8ull * P.n_instr + 8ull * P.n_rec + 8 * 16 + (fp64 ? 8 : 4) * (2 * (bs / 64) + 2) + 4ull * G * mw;
+    b = (b + 15) & ~(size_t)15;
+    if (lds_vec) b += (size_t)G * ((size_t)1 << P.k_max) * (fp64 ? 16 : 8);
+    return b;
+}
+
+template <typename T, int BS, bool LDSV>
+static int blocks_per_cu(size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, active_kernel<T, BS, LDSV>, BS, lds) != hipSuccess) return 1;
+    return nb;
+}
+
+int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds) {
+    if (fp64) {
+        if (bs == 1024) return lds_vec ? blocks_per_cu<double, 1024, true>(lds) : blocks_per_cu<double, 1024, false>(lds);
+        return lds_vec ? blocks_per_cu<double, 256, true>(lds) : blocks_per_cu<double, 256, false>(lds);
+    }
+    if (bs == 1024) return lds_vec ? blocks_per_cu<float, 1024, true>(lds) : blocks_per_cu<float, 1024, false>(lds);
+    return lds_vec ? blocks_per_cu<float, 256, true>(lds) : blocks_per_cu<float, 256, false>(lds);
+}
+
+hipError_t launch_active(const ActiveArgs &A, bool fp64, uint32_t bs, uint32_t grid, hipStream_t st) {
+    if (fp64) {
+        if (bs == 1024) return A.lds_vec ? launch_one<double, 1024, true>(A, grid, st) : launch_one<double, 1024, false>(A, grid, st);
+        return A.lds_vec ? launch_one<double, 256, true>(A, grid, st) : launch_one<double, 256, false>(A, grid, st);
+    }
+    if (bs == 1024) return A.lds_vec ? launch_one<float, 1024, true>(A, grid, st) : launch_one<float, 1024, false>(A, grid, st);
+    return A.lds_vec ? launch_one<float, 256, true>(A, grid, st) : launch_one<float, 256, false>(A, grid, st);
+}
+
+}  // namespace symft

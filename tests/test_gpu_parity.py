@@ -1,0 +1,190 @@
+"""GPU parity: records from the HIP kernels (through the C ABI) vs the CPU oracle.
+
+Pure-Clifford circuits must match bit for bit.  Near-Clifford circuits must
+match except shots with an active-measurement draw within 1e-5 (FP32) or
+1e-9 (FP64) of its branch threshold; branch probabilities from the kernels
+must agree with the oracle within 1e-5 (FP32) / 1e-12 (FP64).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle as O  # noqa: E402
+import paper_2607_28600_amd as S  # noqa: E402
+from oracle import OracleCircuit  # noqa: E402
+from tests.parity_util import compare_records  # noqa: E402
+from tests.randcirc import random_circuit  # noqa: E402
+from workloads import configs  # noqa: E402
+
+TOL = {"fp64": 1e-9, "fp32": 1e-5}
+P0_TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def _gpu(prog, shots, seed, **kw):
+    return S.bits_to_numpy(prog.sample(shots, seed, **kw))
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = configs.c1()
+    return w, S.Program(w.circuit), OracleCircuit(w.circuit)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    w = configs.c2()
+    return w, S.Program(w.circuit), OracleCircuit(w.circuit)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    w = configs.c3()
+    return w, S.Program(w.circuit), OracleCircuit(w.circuit)
+
+
+def test_c1_full_bit_exact(c1):
+    w, p, oc = c1
+    got = _gpu(p, w.shots, w.seed)
+    want = oc.sample(w.seed, w.shots)
+    assert np.array_equal(got, want)
+
+
+def test_c2_small_bit_exact(c2):
+    w, p, oc = c2
+    got = _gpu(p, 64 * 20, w.seed)          # two tiles, the second partial
+    want = oc.sample(w.seed, 64 * 20, threads=0)
+    assert np.array_equal(got, want)
+
+
+def test_c2_ragged_offset_and_split(c2):
+    w, p, oc = c2
+    shots, off = 1000, 64 * 37
+    got = _gpu(p, shots, w.seed, shot_offset=off)
+    want = oc.sample(w.seed, shots, shot_begin=off)
+    assert np.array_equal(got, want)
+    # padding bits of the last word are zero
+    assert not np.any(got[:, -1] >> np.uint64(shots % 64))
+    full = _gpu(p, 64 * 8, w.seed)
+    a = _gpu(p, 64 * 3, w.seed)
+    b = _gpu(p, 64 * 5, w.seed, shot_offset=64 * 3)
+    assert np.array_equal(full, np.concatenate([a, b], axis=1))
+
+
+def test_c2_full_size_sampled_words(c2):
+    """2^24 shots in the benchmark's launch configuration; words spread over the range."""
+    w, p, oc = c2
+    out = p.sample(w.shots, w.seed)
+    words = [0, 1, 4095, 65536, 131071, 200003, 262143]
+    got = S.bits_to_numpy(out[:, words])
+    del out
+    want = oc.sample_words(w.seed, words)
+    assert np.array_equal(got, want)
+
+
+def test_frame_deterministic(c1):
+    w, p, _ = c1
+    a = _gpu(p, 64 * 64, w.seed)
+    b = _gpu(p, 64 * 64, w.seed)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c3_records(c3, prec):
+    w, p, oc = c3
+    n = 64 * 48
+    got = _gpu(p, n, w.seed, precision=prec)
+    want = oc.sample(w.seed, n)
+    excluded = compare_records(got, want, w.circuit, oc, w.seed, 0, TOL[prec])
+    assert excluded <= max(3, n // 200)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c3_branch_probabilities(c3, prec):
+    w, p, oc = c3
+    shots = list(range(64 * 7, 64 * 7 + 24))
+    p0 = p.probe(shots[0], len(shots), w.seed, precision=prec)
+    worst = 0.0
+    for i, s in enumerate(shots):
+        tr = oc.trace(w.seed, s)
+        act = tr["meas_kind"] >= 2
+        # compare only up to the first draw that could flip between the two precisions
+        ts = np.flatnonzero(act)
+        for t in ts:
+            worst = max(worst, abs(p0[i, t] - tr["p0"][t]))
+            if abs(O.active_u(w.seed, int(t), s) - tr["p0"][t]) < TOL[prec]:
+                break
+    assert worst < P0_TOL[prec], worst
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c3_full_size_sampled_words(c3, prec):
+    w, p, oc = c3
+    out = p.sample(w.shots, w.seed, precision=prec)
+    words = [0, 777, 8191, 16383]
+    got = S.bits_to_numpy(out[:, words])
+    del out
+    want = oc.sample_words(w.seed, words)
+    for j, wd in enumerate(words):
+        compare_records(got[:, j:j + 1], want[:, j:j + 1], w.circuit, oc, w.seed, 64 * wd, TOL[prec])
+
+
+@pytest.mark.parametrize("i", [0, 3, 7, 10, 11, 23, 59, 127])
+def test_c4_programs(i):
+    w = configs.c4()[i]
+    p = S.Program(w.circuit)
+    oc = OracleCircuit(w.circuit)
+    n = 64 * 8
+    for prec in ("fp64", "fp32"):
+        got = _gpu(p, n, w.seed, precision=prec)
+        want = oc.sample(w.seed, n)
+        compare_records(got, want, w.circuit, oc, w.seed, 0, TOL[prec])
+
+
+@pytest.mark.parametrize("k,prec", [(14, "fp32"), (14, "fp64"), (16, "fp32")])
+def test_c5_large_active_state(k, prec):
+    w = configs.c5(k)
+    p = S.Program(w.circuit)
+    assert p.k_max == k
+    oc = OracleCircuit(w.circuit)
+    n = 64 * 2
+    got = _gpu(p, n, w.seed, precision=prec)
+    want = oc.sample(w.seed, n)
+    compare_records(got, want, w.circuit, oc, w.seed, 0, TOL[prec])
+
+
+def test_random_small_circuits():
+    rng = np.random.default_rng(2024)
+    for trial in range(25):
+        c = random_circuit(rng, int(rng.integers(2, 8)), int(rng.integers(10, 60)))
+        p = S.Program(c)
+        oc = OracleCircuit(c)
+        seed = 31337 + trial
+        for prec in ("fp64", "fp32"):
+            got = _gpu(p, 64 * 3, seed, precision=prec)
+            want = oc.sample(seed, 64 * 3)
+            compare_records(got, want, c, oc, seed, 0, TOL[prec])
+
+
+def test_zero_shots_is_noop(c1):
+    w, p, _ = c1
+    out = torch.full((p.n_rows, 4), 7, dtype=torch.int64, device="cuda")
+    p.sample_into(out, 0, w.seed)
+    torch.cuda.synchronize()
+    assert int((out != 7).sum()) == 0
+
+
+def test_sections_only_detectors(c1):
+    w, p, oc = c1
+    out = torch.zeros((p.n_rows, 16), dtype=torch.int64, device="cuda")
+    p.sample_into(out, 1024, w.seed, sections=2)
+    got = S.bits_to_numpy(out)
+    want = oc.sample(w.seed, 1024)
+    n_rec = w.circuit.num_records
+    n_det = w.circuit.num_detectors
+    assert not np.any(got[:n_rec]) and not np.any(got[n_rec + n_det:])
+    assert np.array_equal(got[n_rec:n_rec + n_det], want[n_rec:n_rec + n_det])
