@@ -1,0 +1,172 @@
+"""Benchmark: SymFT per-shot sampling throughput on one MI355X.
+
+Default workload (N=1): rotated surface-code Z-memory, distance 11, 11 rounds,
+p = 1e-3 (241 qubits, 1441 records, 1320 detectors, 1 observable), 2^24 shots
+per step on the pure-frame path.  One step = one symft_sample call that
+writes all 2762 bit-packed rows for 2^24 shots, inputs (the compiled program)
+already resident in HBM.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c1|c3|c3fp64|c4|c5]
+
+Prints one JSON line.  `roofline` prices the dominant kernel against HBM
+bandwidth (record bytes written per launch / average launch time, measured
+with HIP events on the launch stream); `cpu_baseline` times the CPU oracle
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "shots/s on 1 MI355X (batched FP32 vs plain FP64) + % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def _time_launches(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for i in range(steps):
+        starts[i].record(stream)
+        fn()
+        ends[i].record(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    per = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return t0.elapsed_time(t1) / steps, sum(per) / len(per), wall
+
+
+def _cpu_baseline(circ, seed, words, threads):
+    from oracle import OracleCircuit
+    oc = OracleCircuit(circ)
+    t = time.perf_counter()
+    oc.sample_words(seed, words, threads=threads)
+    dt = time.perf_counter() - t
+    return len(words) * 64 / dt, dt
+
+
+def run(args):
+    import torch
+    import paper_2607_28600_amd as S
+    from workloads import configs
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    cores = os.cpu_count() or 1
+    extra = {}
+    wl = args.workload
+    if wl in ("c1", "c2", "c3", "c3fp64", "c5"):
+        w = {"c1": configs.c1, "c2": configs.c2, "c3": configs.c3, "c3fp64": configs.c3,
+             "c5": lambda: configs.c5(14)}[wl]()
+        prec = "fp64" if wl in ("c1", "c3fp64") else ("fp32" if wl in ("c3", "c5") else "fp64")
+        prog = S.Program(w.circuit)
+        info = prog.info()
+        words = (w.shots + 63) // 64
+        out = torch.empty((prog.n_rows, words), dtype=torch.int64, device="cuda")
+
+        def step():
+            prog.sample_into(out, w.shots, w.seed, precision=prec, stream=stream.cuda_stream)
+
+        ms_step, ms_kernel, wall = _time_launches(step, args.steps, args.warmup, stream)
+        value = w.shots / (ms_step / 1e3)
+        rec_bytes = prog.n_rows * words * 8
+        if info["k_max"] == 0:
+            achieved = rec_bytes / (ms_kernel / 1e3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "frame_kernel", "bytes_per_launch": rec_bytes}
+            dtype = "u64"
+        else:
+            flops = info["dense_flops_per_shot"] * w.shots
+            achieved = flops / (ms_kernel / 1e3) / 1e12
+            peak = FP32_PEAK_TFLOPS if prec == "fp32" else FP64_PEAK_TFLOPS
+            roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 4), "traffic": None, "kernel": "active_kernel",
+                    "flops_per_launch": flops}
+            dtype = "f32" if prec == "fp32" else "f64"
+        config = {"workload": w.name, "shots": w.shots, "rows": prog.n_rows, "k_max": info["k_max"],
+                  "precision": prec if info["k_max"] else "n/a (integer path)"}
+        n_cpu_words = {"c1": 256, "c2": 24, "c3": 64, "c3fp64": 64, "c5": 8}[wl]
+        sample_words = [int(i * words / n_cpu_words) for i in range(n_cpu_words)]
+        circ, seed = w.circuit, w.seed
+    elif wl == "c4":
+        ws = configs.c4()
+        progs = [S.Program(x.circuit) for x in ws]
+        outs = [torch.empty((p.n_rows, (x.shots + 63) // 64), dtype=torch.int64, device="cuda")
+                for p, x in zip(progs, ws)]
+        shots = [x.shots for x in ws]
+        seeds = [x.seed for x in ws]
+        prec = args.precision
+
+        def step():
+            S.sample_batch(progs, shots, seeds, outs, precision=prec, graph=True, stream=stream.cuda_stream)
+
+        ms_step, ms_kernel, wall = _time_launches(step, args.steps, args.warmup, stream)
+        total = sum(shots)
+        value = total / (ms_step / 1e3)
+        flops = sum(p.info()["dense_flops_per_shot"] * s for p, s in zip(progs, shots))
+        achieved = flops / (ms_kernel / 1e3) / 1e12
+        peak = FP32_PEAK_TFLOPS if prec == "fp32" else FP64_PEAK_TFLOPS
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None, "kernel": "active_kernel"}
+        dtype = "f32" if prec == "fp32" else "f64"
+        config = {"workload": "batch_128_near_clifford", "shots": total, "programs": len(ws), "precision": prec}
+        circ, seed = ws[0].circuit, ws[0].seed
+        sample_words = list(range(16))
+    else:
+        raise SystemExit(f"unknown workload {wl}")
+
+    if args.cpu_baseline:
+        cpu_value, cpu_dt = _cpu_baseline(circ, seed, sample_words, threads=cores)
+        cpu = {"value": round(cpu_value, 2), "unit": "shots/s", "cores": cores, "kind": "oracle",
+               "sample": f"{len(sample_words)} 64-shot words spread over the workload's shot range "
+                         f"({len(sample_words) * 64} shots, {cpu_dt:.1f} s)"}
+    else:
+        cpu = None
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    line["kernel_ms_avg"] = round(ms_kernel, 4)
+    if extra:
+        line["extra"] = extra
+    print(json.dumps(line), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build samples on one GPU; shots shard by 64-shot word ranges, "
+                                   "so N GPUs would each run this same kernel on 1/N of the words"}))
+        raise SystemExit(2)
+    run(args)
+
+
+if __name__ == "__main__":
+    main()
