@@ -26,6 +26,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "shots/s on 1 MI355X (batched FP32 vs plain FP64) + % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+# Measured HBM bytes per launch of the pure-frame kernel on this workload (profiles/
+# frame_kernel_surface_d11_r11_2e24.md): FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the scales
+# read off a 1 GiB device copy.  None once the kernel changes without a new measurement.
+FRAME_TRAFFIC_BYTES = {"surface_d11_r11_p1e-3": 2.58e9 + 6.71e9}
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
@@ -89,8 +93,10 @@ def run(args):
         rec_bytes = prog.n_rows * words * 8
         if info["k_max"] == 0:
             achieved = rec_bytes / (ms_kernel / 1e3) / 1e9
+            traffic = FRAME_TRAFFIC_BYTES.get(w.name) if w.shots == 1 << 24 else None
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": round(traffic / 1e9, 3) if traffic else None, "traffic_unit": "GB/launch",
                     "kernel": "frame_kernel", "bytes_per_launch": rec_bytes}
             dtype = "u64"
         else:

@@ -57,7 +57,7 @@ enum symft_op_kind {
     SYMFT_OP_X_ERROR,      /* per qubit: X with probability arg */
     SYMFT_OP_DEPOLARIZE1,  /* per qubit: X, Y, Z each with probability arg/3 */
     SYMFT_OP_DEPOLARIZE2,  /* per pair: each of the 15 non-identity two-qubit Paulis with probability arg/15 */
-    SYMFT_OP_PAULI_CHANNEL,/* one channel on `qubits`: branch j applies branch_paulis[j*n..] w.p. probs[j] */
+    SYMFT_OP_PAULI_CHANNEL,/* one channel on `qubits` (<= 16): branch j (< 64) applies branch_paulis[j*n..] w.p. probs[j] */
     SYMFT_OP_ROT,          /* R_P(arg) = exp(-i arg P / 2), P = (-1)^negate * prod paulis (paper Sec. 2) */
     SYMFT_OP_MPP,          /* recorded measurement of P = (-1)^negate * prod paulis */
     SYMFT_OP_FEEDBACK,     /* apply P if the XOR of records `recs` is 1 */
@@ -101,6 +101,12 @@ typedef struct {
     uint64_t expr_meas_nnz;        /* measurement-symbol references over all sign expressions */
     double dense_flops_per_shot;   /* algorithmic flops of the dense instructions, see DESIGN */
     double dense_bytes_per_shot;   /* one read + one write of the live vector per dense instruction (complex FP32) */
+    uint64_t frame_steps;          /* pure-frame schedule: steps (0 when the program needs the active kernel) */
+    uint64_t frame_noise_steps;    /* of which noise steps */
+    uint64_t frame_slots;          /* live accumulator rows of the schedule */
+    uint64_t frame_max_level;      /* largest emit level */
+    uint64_t frame_pushes;         /* record-to-consumer XORs over the schedule */
+    uint64_t frame_noise_consumers;/* noise-symbol-to-consumer XORs, summed over symbols */
 } symft_info;
 
 /* Compile `ops` (paper Sec. 2 circuit) into a sampling program (Sec. 3-4).

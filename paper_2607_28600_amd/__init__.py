@@ -51,6 +51,8 @@ class symft_info(C.Structure):
         ("n_rows", C.c_uint64), ("n_instr", C.c_uint64 * 8), ("n_channels", C.c_uint64),
         ("n_classes", C.c_uint64), ("n_noise_symbols", C.c_uint64), ("expr_noise_nnz", C.c_uint64),
         ("expr_meas_nnz", C.c_uint64), ("dense_flops_per_shot", C.c_double), ("dense_bytes_per_shot", C.c_double),
+        ("frame_steps", C.c_uint64), ("frame_noise_steps", C.c_uint64), ("frame_slots", C.c_uint64),
+        ("frame_max_level", C.c_uint64), ("frame_pushes", C.c_uint64), ("frame_noise_consumers", C.c_uint64),
     ]
 
 

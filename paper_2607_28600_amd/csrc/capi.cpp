@@ -39,7 +39,8 @@ struct HostLayout {
     std::vector<uint8_t> blob;
     // offsets of each array inside blob
     size_t o_instr, o_cmeas, o_rm, o_recmeas, o_detoff, o_detrows, o_obsoff, o_obsrows, o_clsQ, o_clsoff, o_clschan,
-        o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_frstep, o_frdata, o_frsymoff, o_frsymslot;
+        o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_invlog, o_frstep, o_frdata, o_frnodes, o_frpush, o_frchinfo,
+        o_frfltab, o_frflslots;
     DevProg meta;  // counts only; pointers filled at upload
 };
 
@@ -122,7 +123,10 @@ static void lower(symft_program *h) {
     obsoff.push_back((uint32_t)obsrows.size());
     std::vector<uint64_t> clsQ;
     std::vector<uint32_t> clsoff, clschan;
+    std::vector<float> invlog;
     for (auto &c : P.classes) {
+        const double q = 1.0 - std::ldexp((double)c.p32, -32);
+        invlog.push_back(q > 0 ? (float)(1.0 / std::log2(q)) : -0.0f);
         clsQ.insert(clsQ.end(), c.Q.begin(), c.Q.end());
         clsoff.push_back((uint32_t)clschan.size());
         for (int32_t ch : c.chans) clschan.push_back((uint32_t)ch);
@@ -162,10 +166,14 @@ static void lower(symft_program *h) {
     L.o_thr = put(L.blob, thr);
     L.o_symoff = put(L.blob, symoff);
     L.o_symcons = put(L.blob, symcons);
+    L.o_invlog = put(L.blob, invlog);
     L.o_frstep = put(L.blob, h->F.steps);
     L.o_frdata = put(L.blob, h->F.data);
-    L.o_frsymoff = put(L.blob, h->F.sym_off);
-    L.o_frsymslot = put(L.blob, h->F.sym_slot);
+    L.o_frnodes = put(L.blob, h->F.nodes);
+    L.o_frpush = put(L.blob, h->F.push);
+    L.o_frchinfo = put(L.blob, h->F.chinfo);
+    L.o_frfltab = put(L.blob, h->F.fltab);
+    L.o_frflslots = put(L.blob, h->F.flslots);
     DevProg &m = L.meta;
     std::memset(&m, 0, sizeof(m));
     m.n_instr = (uint32_t)ins.size();
@@ -178,6 +186,7 @@ static void lower(symft_program *h) {
     m.k_max = P.k_max;
     m.fr_n_steps = (uint32_t)h->F.n_steps;
     m.fr_n_slots = h->F.n_slots;
+    m.fr_cap = frame_event_capacity(h->F.events_per_word);
     m.n_sym = P.n_noise_sym;
 }
 
@@ -216,10 +225,14 @@ static symft_status device_prog(symft_program *h, DevProg &out) {
     out.thr = (const uint64_t *)(b + L.o_thr);
     out.sym_off = (const uint32_t *)(b + L.o_symoff);
     out.sym_cons = (const uint32_t *)(b + L.o_symcons);
+    out.cls_invlog2q = (const float *)(b + L.o_invlog);
     out.fr_step = (const uint32_t *)(b + L.o_frstep);
     out.fr_data = (const uint32_t *)(b + L.o_frdata);
-    out.fr_sym_off = (const uint32_t *)(b + L.o_frsymoff);
-    out.fr_sym_slot = (const uint32_t *)(b + L.o_frsymslot);
+    out.fr_nodes = (const uint32_t *)(b + L.o_frnodes);
+    out.fr_push = (const uint32_t *)(b + L.o_frpush);
+    out.fr_chinfo = (const uint64_t *)(b + L.o_frchinfo);
+    out.fr_fltab = (const uint64_t *)(b + L.o_frfltab);
+    out.fr_flslots = (const uint32_t *)(b + L.o_frflslots);
     return SYMFT_OK;
 }
 
@@ -310,7 +323,7 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
     if (lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "frame schedule exceeds the LDS budget");
     int per_cu = frame_max_blocks_per_cu(lds);
     if (per_cu <= 0) per_cu = 1;
-    uint64_t tiles = (n_words + wpb - 1) / wpb;
+    uint64_t tiles = (n_words + wpb - 1) / wpb;  // word groups, one wave each
     uint64_t cap = (uint64_t)per_cu * (uint64_t)num_cus();
     uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
     FrameArgs A;
@@ -392,6 +405,13 @@ symft_status symft_program_info(const symft_program *p, symft_info *info) {
     }
     info->dense_flops_per_shot = flops;
     info->dense_bytes_per_shot = bytes;
+    info->frame_steps = p->F.n_steps;
+    info->frame_slots = p->F.n_slots;
+    info->frame_max_level = p->F.max_level;
+    info->frame_noise_consumers = p->F.flslots.size();
+    info->frame_pushes = p->F.n_pushes;
+    for (uint32_t st : p->F.steps)
+        if ((st >> 28) == FR_NOISE) info->frame_noise_steps += 1;
     return SYMFT_OK;
 }
 

@@ -95,6 +95,7 @@ struct Compiler {
             Zb[q].z[q >> 6] |= uint64_t(1) << (q & 63);
             Xb[q].x[q >> 6] |= uint64_t(1) << (q & 63);
         }
+        rel_of.assign(S, {});
         EX.resize(n);
         EZ.resize(n);
         for (uint32_t q = 0; q < n; ++q) {
@@ -207,6 +208,75 @@ struct Compiler {
         }
     }
 
+    // ------------------------------------- relative sign expressions -----
+    // Every deterministic measurement t gives the identity
+    //     lambda_t ^ m_t ^ eta_t = 0
+    // over the symbols, so XOR-ing it into a later sign expression leaves the
+    // expression's value unchanged.  A greedy pass rewrites each new sign
+    // relative to earlier records this way while that lowers its weight, which
+    // keeps signs local (paper Sec. 6: exogenous/causal split and shared
+    // partial expressions).
+    std::vector<std::vector<uint32_t>> rel;     // symbol ids of each identity (0 = constant)
+    std::vector<std::vector<uint32_t>> rel_of;  // symbol id -> identities containing it
+    std::vector<int> cnt;
+    std::vector<uint32_t> touched;
+
+    void add_relation(const Bits &lam, uint32_t t, int eta) {
+        std::vector<uint32_t> ids;
+        for (size_t i = 0; i < lam.w.size(); ++i) {
+            uint64_t v = lam.w[i];
+            while (v) {
+                ids.push_back(uint32_t(i * 64 + __builtin_ctzll(v)));
+                v &= v - 1;
+            }
+        }
+        auto toggle = [&](uint32_t id) {
+            auto it = std::lower_bound(ids.begin(), ids.end(), id);
+            if (it != ids.end() && *it == id) ids.erase(it);
+            else ids.insert(it, id);
+        };
+        toggle(sym_meas(t));
+        if (eta) toggle(0);
+        const uint32_t r = (uint32_t)rel.size();
+        for (uint32_t id : ids)
+            if (id) rel_of[id].push_back(r);
+        rel.push_back(std::move(ids));
+        cnt.push_back(0);
+    }
+
+    void reduce(Bits &lam) {
+        auto has = [&](uint32_t id) { return (lam.w[id >> 6] >> (id & 63)) & 1u; };
+        int w = 0;
+        for (size_t i = 0; i < lam.w.size(); ++i) w += popc(lam.w[i]);
+        w -= (int)has(0);
+        for (int iter = 0; iter < 256; ++iter) {
+            touched.clear();
+            for (size_t i = 0; i < lam.w.size(); ++i) {
+                uint64_t v = lam.w[i];
+                while (v) {
+                    uint32_t id = uint32_t(i * 64 + __builtin_ctzll(v));
+                    v &= v - 1;
+                    if (!id) continue;
+                    for (uint32_t r : rel_of[id]) {
+                        if (cnt[r]++ == 0) touched.push_back(r);
+                    }
+                }
+            }
+            int best = -1, best_w = w;
+            for (uint32_t r : touched) {
+                int len = (int)rel[r].size() - (rel[r][0] == 0 ? 1 : 0);
+                int nw = w + len - 2 * cnt[r];
+                if (nw < best_w || (nw == best_w && best >= 0 && r > (uint32_t)best)) {
+                    if (nw < w) { best = (int)r; best_w = nw; }
+                }
+            }
+            for (uint32_t r : touched) cnt[r] = 0;
+            if (best < 0) break;
+            for (uint32_t id : rel[best]) lam.flip(id);
+            w = best_w;
+        }
+    }
+
     // ------------------------------------------------------- planner ----
     struct Dec {
         std::vector<uint8_t> zc, xc;  // omega with Zbar_j, Xbar_j
@@ -264,7 +334,8 @@ struct Compiler {
 
     void emit(Instr in) { P->instrs.push_back(std::move(in)); }
 
-    void plan_rotation(const PauliV &Q, const Bits &lam, double theta, int op) {
+    void plan_rotation(const PauliV &Q, Bits &lam, double theta, int op) {
+        reduce(lam);
         Dec D = decompose(Q);
         Instr in;
         in.theta = theta;
@@ -303,6 +374,8 @@ struct Compiler {
 
     // measurement t of pulled-back Q with sign expression lam
     void plan_measurement(const PauliV &Q, Bits &lam, uint32_t t, int op) {
+        Bits raw = lam;
+        reduce(lam);
         Dec D = decompose(Q);
         Instr in;
         in.k_in = (uint8_t)k;
@@ -325,6 +398,7 @@ struct Compiler {
             in.kind = DET_MEAS;
             in.eta = (uint8_t)(D.mu == 0 ? 0 : 1);
             P->meas_kind[t] = 1;
+            add_relation(raw, t, in.eta);
         } else if (D.a == 0) {
             int h = 31 - __builtin_clz(D.b);
             in.kind = ACTIVE_DIAG_MEAS;
@@ -432,6 +506,7 @@ int compile_program(uint32_t n_qubits, const void *ops_v, size_t n_ops, Program 
             }
             if (tot > 1.0 + 1e-12) return fail(err, SYMFT_EPROB, "op " + std::to_string(i) + ": channel total exceeds 1");
             if (o.n > 16) return fail(err, SYMFT_EINVAL, "op " + std::to_string(i) + ": channel support above 16 qubits");
+            if (o.n_branches > 64) return fail(err, SYMFT_EINVAL, "op " + std::to_string(i) + ": more than 64 branches");
             nsym += 2 * o.n;
             break;
         }

@@ -47,13 +47,17 @@ struct DevProg {
     const uint64_t *thr;
     const uint32_t *sym_off;     // n_sym + 1 into sym_cons
     const uint32_t *sym_cons;    // consumer instruction ids per noise symbol
-    // pure-frame schedule (k_max == 0 programs)
-    const uint32_t *fr_step;     // per step: (kind << 28) | payload offset, see frame kernel
-    const uint32_t *fr_data;
-    const uint32_t *fr_sym_off;  // n_sym + 1 into fr_sym_slot
-    const uint32_t *fr_sym_slot; // consumer slots per noise symbol
+    const float *cls_invlog2q;   // per class 1 / log2(1 - P32 / 2^32): initial guess of a geometric gap
+    // pure-frame schedule (k_max == 0 programs), see sample_frame.hip
+    const uint32_t *fr_step;     // per step: (kind << 28) | payload offset into fr_data
+    const uint32_t *fr_data;     // NOISE: class, rank_begin, rank_end; EMIT: first node, node count
+    const uint32_t *fr_nodes;    // 4 words per node (+ sentinel): slot | flags << 24, row, meas, push offset
+    const uint32_t *fr_push;     // successor slots
+    const uint64_t *fr_chinfo;   // per (class, rank): flip-table offset | J << 32 | uniform << 40 | thr_off << 41
+    const uint64_t *fr_fltab;    // per (channel, branch): first flip << 24 | flip count
+    const uint32_t *fr_flslots;  // slots flipped by each (channel, branch)
     uint32_t n_instr, n_meas, n_rm, n_rec, n_det, n_obs, n_cls, k_max;
-    uint32_t fr_n_steps, fr_n_slots, n_sym, pad;
+    uint32_t fr_n_steps, fr_n_slots, n_sym, fr_cap;
 };
 
 }  // namespace symft

@@ -12,6 +12,7 @@
 // step that emits it; slots are interval-coloured, and a slot is reused only
 // by an interval that starts strictly after the previous one ended.
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <queue>
 
@@ -20,10 +21,29 @@
 
 namespace symft {
 
+// A flip-table entry: count in bits 0..7; up to two slots inline in bits
+// 8..35 and 36..63, otherwise bits 8..35 index the slot list (count 255 means
+// the list starts with its own length).
+static uint64_t pack_flips(const std::vector<uint32_t> &fl, std::vector<uint32_t> &store) {
+    const uint64_t n = fl.size();
+    if (n <= 2) {
+        uint64_t e = n;
+        if (n > 0) e |= (uint64_t)fl[0] << 8;
+        if (n > 1) e |= (uint64_t)fl[1] << 36;
+        return e;
+    }
+    const uint64_t off = store.size();
+    if (n >= 255) store.push_back((uint32_t)n);
+    store.insert(store.end(), fl.begin(), fl.end());
+    return (n >= 255 ? 255 : n) | (off << 8);
+}
+
 void build_frame_schedule(const Program &P, FrameSchedule &F) {
     F = FrameSchedule();
-    F.sym_off.assign(P.n_noise_sym + 1, 0);
     if (P.k_max != 0) return;
+    uint64_t fl_total = 0;
+    for (const Channel &ch : P.chans) fl_total += ch.J;
+    if (fl_total >= (1u << 26)) return;  // event records hold 26-bit flip-table indices
     const uint32_t M = (uint32_t)P.n_meas, D = (uint32_t)P.n_det, B = (uint32_t)P.n_obs;
     const uint32_t NN = M + D + B;
     struct Node {
@@ -181,49 +201,89 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
         busy.push({nd[i].emit, s});
     }
     F.n_slots = n_slots;
-    // symbol -> consumer slots
+    // noise symbol -> consumer slots; (channel, branch) -> slots flipped
     std::vector<std::vector<uint32_t>> cons(P.n_noise_sym);
     for (uint32_t i = 0; i < NN; ++i)
         for (uint32_t s : nd[i].noise) cons[s].push_back((uint32_t)nd[i].slot);
-    for (uint32_t s = 0; s < P.n_noise_sym; ++s) {
-        F.sym_off[s] = (uint32_t)F.sym_slot.size();
-        F.sym_slot.insert(F.sym_slot.end(), cons[s].begin(), cons[s].end());
+    std::vector<uint64_t> chan_fl(P.chans.size(), 0), chan_thr(P.chans.size(), 0);
+    uint64_t thr_off = 0;
+    for (size_t c = 0; c < P.chans.size(); ++c) {
+        const Channel &ch = P.chans[c];
+        chan_thr[c] = thr_off;
+        thr_off += ch.thr.size();
+        chan_fl[c] = F.fltab.size();
+        for (uint32_t j = 0; j < ch.J; ++j) {
+            std::map<uint32_t, int> par;
+            for (uint32_t i = 0; i < ch.nsym; ++i)
+                if ((ch.bmask[j] >> i) & 1u)
+                    for (uint32_t sl : cons[ch.sym0 + i]) par[sl] ^= 1;
+            std::vector<uint32_t> fl;
+            for (auto &kv : par)
+                if (kv.second) fl.push_back(kv.first);
+            F.fltab.push_back(pack_flips(fl, F.flslots));
+        }
     }
-    F.sym_off[P.n_noise_sym] = (uint32_t)F.sym_slot.size();
-    // encode
+    for (const NoiseClass &nc : P.classes) {
+        for (int32_t c : nc.chans) {
+            const Channel &ch = P.chans[(size_t)c];
+            F.chinfo.push_back((chan_fl[(size_t)c] & 0xFFFFFFFFull) | ((uint64_t)(ch.J & 0xFF) << 32) |
+                               ((uint64_t)ch.uniform << 40) | (chan_thr[(size_t)c] << 41));
+        }
+        F.events_per_word += (double)nc.chans.size() * 64.0 * std::ldexp((double)nc.p32, -32);
+    }
+    // encode steps and node records
+    std::vector<uint64_t> cls_first(P.classes.size() + 1, 0);
     for (const Step &s : steps) {
         F.steps.push_back((s.kind << 28) | (uint32_t)F.data.size());
         if (s.kind == FR_NOISE) {
+            const NoiseClass &nc = P.classes[s.cls];
+            // flip-table index of the first channel past this step (events are kept as flip-table indices)
+            const uint64_t bound = s.r1 < nc.chans.size() ? chan_fl[(size_t)nc.chans[s.r1]] : UINT64_C(0xFFFFFFFF);
             F.data.push_back(s.cls);
             F.data.push_back(s.r0);
             F.data.push_back(s.r1);
+            F.data.push_back((uint32_t)std::min<uint64_t>(bound, 0xFFFFFFFFull));
             continue;
         }
-        const size_t base = F.data.size();
+        F.data.push_back((uint32_t)(F.nodes.size() / 8));
         F.data.push_back((uint32_t)s.nodes.size());
-        for (size_t i = 0; i < s.nodes.size(); ++i) F.data.push_back(0);
-        for (size_t i = 0; i < s.nodes.size(); ++i) {
-            const Node &v = nd[s.nodes[i]];
-            F.data[base + 1 + i] = (uint32_t)F.data.size();
+        for (uint32_t id : s.nodes) {
+            const Node &v = nd[id];
             uint32_t flags = (v.cst ? 1u : 0u) | (v.slot >= 0 ? 2u : 0u) | (v.rm ? 4u : 0u) | ((uint32_t)v.sec << 4);
-            F.data.push_back(flags);
-            F.data.push_back(v.slot >= 0 ? (uint32_t)v.slot : 0u);
-            F.data.push_back(v.meas);
-            F.data.push_back(v.row);
-            F.data.push_back((uint32_t)v.succs.size());
-            for (uint32_t u : v.succs) F.data.push_back((uint32_t)nd[u].slot);
+            const uint32_t np = (uint32_t)v.succs.size();
+            F.nodes.push_back((v.slot >= 0 ? (uint32_t)v.slot : 0u) | (flags << 24));
+            F.nodes.push_back(v.row);
+            F.nodes.push_back(v.meas);
+            F.nodes.push_back(np);
+            F.nodes.push_back(np > 0 ? (uint32_t)nd[v.succs[0]].slot : 0u);
+            F.nodes.push_back(np > 1 ? (uint32_t)nd[v.succs[1]].slot : 0u);
+            F.nodes.push_back((uint32_t)F.push.size());  // pushes beyond the first two
+            F.nodes.push_back(0);
+            for (uint32_t k = 2; k < np; ++k) F.push.push_back((uint32_t)nd[v.succs[k]].slot);
         }
     }
+    F.n_pushes = 0;
+    for (uint32_t i = 0; i < NN; ++i) F.n_pushes += nd[i].succs.size();
     F.n_steps = steps.size();
 }
 
+// Events buffered per word: the expected count plus 8 standard deviations
+// (the count is Poisson), rounded up; a word that draws more streams the rest.
+uint32_t frame_event_capacity(double events_per_word) {
+    double cap = events_per_word + 8.0 * std::sqrt(events_per_word + 1.0) + 64.0;
+    uint32_t c = (uint32_t)std::ceil(cap / 64.0) * 64u;
+    return std::max<uint32_t>(64u, std::min<uint32_t>(c, 4096u));
+}
+
 uint32_t frame_words_per_block(const DevProg &P) {
-    // W words per workgroup, TPW = 256 / W threads per word must fit one wave
-    for (uint32_t w : {16u, 8u, 4u}) {
-        const size_t bytes = (size_t)P.fr_n_slots * w * 8 + (size_t)P.n_cls * w * 16;
-        if (bytes <= 96 * 1024) return w;
+    // words per wave: its slots and one batch of events per word, sized for
+    // at least eight waves per CU
+    for (uint32_t w : {4u, 2u, 1u}) {
+        const size_t bytes = (size_t)w * ((size_t)P.fr_n_slots * 8 + (size_t)P.n_cls * 32 + 256 * 4) + 16;
+        if (bytes <= 20 * 1024) return w;
     }
-    return 0;  // too many live slots: the active kernel runs the program instead
+    const size_t one = (size_t)P.fr_n_slots * 8 + (size_t)P.n_cls * 32 + 256 * 4 + 16;
+    return one <= 64 * 1024 ? 1u : 0u;  // 0: the active kernel runs the program instead
 }
 
 }  // namespace symft

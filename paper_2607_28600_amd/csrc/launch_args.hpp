@@ -42,32 +42,40 @@ struct FrameArgs {
     uint32_t pad;
 };
 
-// Pure-frame schedule (programs with peak active width 0).  Steps run in
+// Pure-frame schedule (programs with peak active width 0); steps run in
 // order, separated by workgroup barriers:
-//   NOISE  data = [class, rank_begin, rank_end]: draw the events of those
-//          channels for every word of the tile and XOR each event's symbols
-//          into the accumulator slots of the nodes that consume them;
-//   EMIT   data = [n, off_0 .. off_{n-1}, node descriptors ...]: every node of
-//          the level reads (and clears) its slot, adds its constant or its
-//          RandomMeas word, writes its output row and XORs its value into the
-//          slots of its successors.
-// Node descriptor: [flags, slot, meas, row, n_push, push slots ...] with
-// flags bit0 const, bit1 has slot, bit2 RandomMeas, bits 4..5 section
-// (1 record, 2 detector, 3 observable, 0 hidden).
+//   NOISE  data = [class, rank_begin, rank_end, flip-table bound]: apply the
+//          noise events of those channels (drawn once per word at the start
+//          of the tile and kept as flip-table indices, so the bound is the
+//          first index past the step) by XOR-ing each event's lane bit into
+//          the slots of its consumers;
+//   EMIT   data = [first node, node count]: every node of the level reads
+//          (and clears) its slot, adds its constant or its RandomMeas word,
+//          writes its output row and XORs its value into its successors' slots.
+// Node record (8 x uint32): slot | flags << 24 (flags bit0 const, bit1 has
+// slot, bit2 RandomMeas, bits 4..5 section: 1 record, 2 detector,
+// 3 observable, 0 hidden), output row, measurement index, push count, first
+// two successor slots, offset of further successors in the push list, 0.
 enum FrameStepKind : uint32_t { FR_NOISE = 1, FR_EMIT = 2 };
 static const uint32_t FR_NO_ROW = 0xFFFFFFFFu;
 
 struct FrameSchedule {
-    std::vector<uint32_t> steps;     // (kind << 28) | data offset
+    std::vector<uint32_t> steps;
     std::vector<uint32_t> data;
-    std::vector<uint32_t> sym_off;   // n_sym + 1
-    std::vector<uint32_t> sym_slot;  // consumer slots per noise symbol
+    std::vector<uint32_t> nodes;    // 4 per node, plus a sentinel
+    std::vector<uint32_t> push;
+    std::vector<uint64_t> chinfo;   // indexed by class offset + rank
+    std::vector<uint64_t> fltab;
+    std::vector<uint32_t> flslots;
     uint32_t n_slots = 0;
     size_t n_steps = 0;
     uint32_t max_level = 0;
+    uint64_t n_pushes = 0;
+    double events_per_word = 0;     // expected noise events of one 64-shot word
 };
 
 void build_frame_schedule(const Program &P, FrameSchedule &F);
 uint32_t frame_words_per_block(const DevProg &P);
+uint32_t frame_event_capacity(double events_per_word);
 
 }  // namespace symft

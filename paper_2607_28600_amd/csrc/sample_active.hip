@@ -36,17 +36,6 @@ __device__ __forceinline__ uint32_t insert_bit(uint32_t z, uint32_t h, uint32_t 
 
 __device__ __forceinline__ int parity(uint32_t v) { return __popc(v) & 1; }
 
-// G = max { g in [0, 4096] : v < Q[g] }, Q non-increasing with Q[0] = 2^32 > v.
-__device__ __forceinline__ int gap_search(const uint64_t *__restrict__ Q, uint32_t v) {
-    if ((uint64_t)v < Q[4096]) return 4096;
-    int lo = 0, hi = 4096;
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if ((uint64_t)v < Q[mid]) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 // Block-wide exclusive scan of (a, b) pairs packed as 64-bit (a in low 32).
 template <int BS>
 __device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *tmp, uint64_t &total) {
@@ -78,6 +67,7 @@ __device__ void word_noise(const DevProg &P, uint64_t seed, uint64_t w, unsigned
     const uint32_t wlo = (uint32_t)w, whi = (uint32_t)(w >> 32);
     for (uint32_t c = 0; c < P.n_cls; ++c) {
         const uint64_t *Q = P.cls_Q + (size_t)c * 4097;
+        const float il = P.cls_invlog2q[c];
         const uint32_t coff = P.cls_off[c];
         const uint64_t end = (uint64_t)(P.cls_off[c + 1] - coff) * 64;
         uint64_t pos = 0, ev0 = 0, blk0 = 0;
@@ -88,7 +78,7 @@ __device__ void word_noise(const DevProg &P, uint64_t seed, uint64_t w, unsigned
             uint32_t inc = 0, evc = 0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                G[i] = gap_search(Q, v[i]);
+                G[i] = gap_of(Q, il, v[i]);
                 inc += (G[i] == 4096) ? 4096u : (uint32_t)G[i] + 1u;
                 evc += (G[i] < 4096) ? 1u : 0u;
             }
