@@ -161,14 +161,29 @@ symft_status symft_sample(const symft_program *p, uint64_t shots, uint64_t seed,
 symft_status symft_sample_ex(const symft_program *p, const symft_sample_opts *opts, uint64_t shots, uint64_t seed,
                              uint64_t *records_out, void *stream);
 
-/* Sample n programs in one persistent launch (work queue over (program,
- * word range) items).  records_out[i] receives program i's rows for shots[i]
- * shots with seeds[i].  precision as in symft_sample_opts.  `graph` = 1
- * captures the launch in a HIP graph on first use and replays it on later
- * calls with the same arguments. */
+/* Sample n programs in one persistent launch (paper Sec. 6 batching across
+ * shots, here also across programs): a work queue over (program, word range)
+ * items ordered by decreasing cost.  records_out[i] (device, n_rows(i) x
+ * ceil(shots[i]/64) words) receives program i's rows for shots[i] shots with
+ * seeds[i]; precision as in symft_sample_opts.  Threads per shot come from
+ * the autotuner (run on first use of each (k_max, precision)).  `graph` = 1
+ * captures the launch (a counter-reset kernel and the persistent kernel) in
+ * a HIP graph on first use and replays it on later calls with identical
+ * arguments.  Programs that need their own kernel (pure frame, or vectors
+ * that do not fit LDS) are sampled by ordinary launches on the same stream.
+ * Calls with the same plan must not overlap on the device (they share the
+ * queue counter). */
 symft_status symft_sample_batch(const symft_program *const *progs, const uint64_t *shots, const uint64_t *seeds,
                                 uint64_t *const *records_out, size_t n, uint32_t precision, uint32_t graph,
                                 void *stream);
+
+/* Autotuner: times each threads-per-shot configuration of the active-state
+ * kernel that fits LDS on 256 words of this program and keeps the fastest
+ * for the program's (peak active width, precision); later launches with that
+ * key use it (sample calls and batches alike).  Records do not depend on the
+ * choice.  Synchronous; allocates a scratch output.  *tps_out (nullable)
+ * receives the choice (0 for pure-frame programs, which have one kernel). */
+symft_status symft_autotune(const symft_program *p, uint32_t precision, uint32_t *tps_out);
 
 /* Probe: Pr(m = 0) of every measurement for shots [shot_begin, shot_begin + n_shots)
  * computed by the same GPU kernels (FP64 or FP32), written to host

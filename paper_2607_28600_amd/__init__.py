@@ -75,6 +75,8 @@ _lib.symft_sample_ex.argtypes = [C.c_void_p, C.POINTER(symft_sample_opts), C.c_u
 _lib.symft_sample_batch.restype = C.c_int32
 _lib.symft_sample_batch.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                     C.POINTER(C.c_void_p), C.c_size_t, C.c_uint32, C.c_uint32, C.c_void_p]
+_lib.symft_autotune.restype = C.c_int32
+_lib.symft_autotune.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32)]
 _lib.symft_probe.restype = C.c_int32
 _lib.symft_probe.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.POINTER(C.c_double)]
 _lib.symft_program_export.restype = C.c_int32
@@ -85,7 +87,7 @@ _lib.symft_last_error.restype = C.c_char_p
 
 EXPORTED = ["symft_compile", "symft_program_info", "symft_program_plan", "symft_program_export",
             "symft_sample", "symft_sample_ex",
-            "symft_sample_batch", "symft_probe", "symft_program_free", "symft_last_error"]
+            "symft_sample_batch", "symft_autotune", "symft_probe", "symft_program_free", "symft_last_error"]
 
 
 class SymftError(RuntimeError):
@@ -217,6 +219,12 @@ class Program:
         if shots:
             self.sample_into(out, shots, seed, shot_offset=shot_offset, precision=precision)
         return out[: self.n_rows, :words]
+
+    def autotune(self, precision: str = "fp32") -> int:
+        """Run the autotuner for this program's (k_max, precision); returns threads per shot."""
+        v = C.c_uint32(0)
+        _check(_lib.symft_autotune(self._h, 0 if precision == "fp64" else 1, C.byref(v)), "symft_autotune")
+        return int(v.value)
 
     def probe(self, shot_begin: int, n_shots: int, seed: int, precision: str = "fp64") -> np.ndarray:
         """Pr(m = 0) of every measurement of shots [shot_begin, +n_shots) from the GPU kernels."""

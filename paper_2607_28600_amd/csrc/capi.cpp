@@ -20,6 +20,9 @@ size_t active_lds_bytes(const DevProg &P, uint32_t bs, uint32_t tps, bool lds_ve
 int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds);
 struct FrameArgs;
 hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st);
+struct BatchArgs;
+hipError_t launch_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t lds, hipStream_t st);
+int batch_max_blocks_per_cu(bool fp64, size_t lds);
 size_t frame_lds_bytes(const DevProg &P, uint32_t words_per_block);
 int frame_max_blocks_per_cu(size_t lds);
 }  // namespace symft
@@ -257,15 +260,29 @@ struct ActiveConfig {
 
 static const size_t kLdsLimit = 160 * 1024;
 
-ActiveConfig choose_active(const DevProg &P, bool fp64) {
+// Threads per shot chosen by the autotuner, per (peak active width, precision).
+static std::mutex g_tune_mu;
+static std::map<std::pair<uint32_t, bool>, uint32_t> g_tune;
+
+static uint32_t default_tps(uint32_t k) {
+    if (k <= 4) return 16;
+    if (k == 5) return 32;
+    if (k <= 8) return 64;
+    if (k == 9) return 128;
+    return 256;
+}
+
+ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0) {
     ActiveConfig c;
     uint32_t k = P.k_max;
     c.bs = 256;
-    if (k <= 4) c.tps = 16;
-    else if (k == 5) c.tps = 32;
-    else if (k <= 8) c.tps = 64;
-    else if (k == 9) c.tps = 128;
-    else c.tps = 256;
+    c.tps = default_tps(k);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find({k, fp64});
+        if (it != g_tune.end()) c.tps = it->second;
+    }
+    if (force_tps) c.tps = force_tps;
     if (k >= 13) {
         c.bs = 1024;
         c.tps = 1024;
@@ -278,8 +295,9 @@ ActiveConfig choose_active(const DevProg &P, bool fp64) {
 
 static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, uint64_t word_begin, uint64_t n_words,
                                uint64_t shots, uint64_t *out, uint64_t stride, uint32_t sections, double *p0,
-                               uint64_t probe_shot0, uint64_t probe_n, uint64_t seed, hipStream_t st) {
-    ActiveConfig c = choose_active(D, fp64);
+                               uint64_t probe_shot0, uint64_t probe_n, uint64_t seed, hipStream_t st,
+                               uint32_t force_tps = 0) {
+    ActiveConfig c = choose_active(D, fp64, force_tps);
     if (c.lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "program tables exceed the LDS budget of the active kernel");
     int per_cu = active_max_blocks_per_cu(fp64, c.bs, c.lds_vec, c.lds);
     if (per_cu <= 0) per_cu = 1;
@@ -527,12 +545,261 @@ symft_status symft_probe(const symft_program *pc, uint64_t shot_begin, uint32_t 
     return rc;
 }
 
+// ------------------------------------------------------------ autotune ----
+// Times every threads-per-shot candidate that fits LDS on `words` words of
+// the program and keeps the fastest for (k_max, precision).  Records do not
+// depend on the choice; only branch-probability rounding does.
+static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, uint32_t *tps_out) {
+    if (D.k_max >= 13 || (D.k_max == 0 && D.fr_n_steps > 0 && frame_words_per_block(D) > 0)) {
+        if (tps_out) *tps_out = D.k_max >= 13 ? 1024 : 0;
+        return SYMFT_OK;
+    }
+    const uint64_t words = 256;
+    uint64_t *out = nullptr;
+    const uint64_t rows = std::max<uint64_t>(1, p->P.n_rows());
+    if (hipMalloc(&out, 8 * rows * words) != hipSuccess) return set_err(SYMFT_ENOMEM, "autotune buffer allocation failed");
+    hipStream_t st;
+    if (hipStreamCreate(&st) != hipSuccess) {
+        hipFree(out);
+        return set_err(SYMFT_EHIP, "stream creation failed");
+    }
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best = 1e30f;
+    uint32_t best_tps = default_tps(D.k_max);
+    symft_status rc = SYMFT_OK;
+    for (uint32_t tps : {16u, 32u, 64u, 128u, 256u}) {
+        if (((uint32_t)1 << D.k_max) < tps / 4 && tps > 16) continue;  // most lanes would idle
+        if (active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
+        float ms = 0;
+        for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
+            hipEventRecord(e0, st);
+            rc = run_active(p, D, fp64, 0, words, words * 64, out, words, 7u, nullptr, 0, 0, 0x7E57ull, st, tps);
+            hipEventRecord(e1, st);
+            hipEventSynchronize(e1);
+            hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (rc) break;
+        if (ms < best) {
+            best = ms;
+            best_tps = tps;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamDestroy(st);
+    hipFree(out);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[{D.k_max, fp64}] = best_tps;
+    }
+    if (tps_out) *tps_out = best_tps;
+    return SYMFT_OK;
+}
+
+symft_status symft_autotune(const symft_program *pc, uint32_t precision, uint32_t *tps_out) {
+    symft_program *p = const_cast<symft_program *>(pc);
+    if (!p) return set_err(SYMFT_EINVAL, "NULL program");
+    if (precision > 1) return set_err(SYMFT_EINVAL, "precision must be 0 or 1");
+    DevProg D;
+    symft_status rc = device_prog(p, D);
+    if (rc) return rc;
+    return tune_program(p, D, precision == 0, tps_out);
+}
+
+// ------------------------------------------------------------- batching ----
+struct BatchPlan {
+    std::vector<const symft_program *> progs;
+    std::vector<uint64_t> shots, seeds;
+    std::vector<uint64_t *> outs;
+    uint32_t precision = 0;
+    int device = 0;
+    ActiveArgs *d_calls = nullptr;
+    BatchItem *d_items = nullptr;
+    uint32_t *d_counter = nullptr;
+    BatchArgs args;
+    uint32_t grid = 0, lds = 0;
+    std::vector<size_t> others;  // programs sampled by their own launches
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    bool same(const symft_program *const *p, const uint64_t *sh, const uint64_t *sd, uint64_t *const *o, size_t n,
+              uint32_t prec, int dev) const {
+        if (n != progs.size() || prec != precision || dev != device) return false;
+        for (size_t i = 0; i < n; ++i)
+            if (p[i] != progs[i] || sh[i] != shots[i] || sd[i] != seeds[i] || o[i] != outs[i]) return false;
+        return true;
+    }
+    void release() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        hipFree(d_calls);
+        hipFree(d_items);
+        hipFree(d_counter);
+        exec = nullptr;
+        graph = nullptr;
+        d_calls = nullptr;
+        d_items = nullptr;
+        d_counter = nullptr;
+    }
+};
+
+static std::mutex g_batch_mu;
+static std::vector<BatchPlan *> g_plans;  // most recent first, a few kept
+
+static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, const uint64_t *shots,
+                               const uint64_t *seeds, uint64_t *const *outs, size_t n, uint32_t precision) {
+    const bool fp64 = precision == 0;
+    B.progs.assign(progs, progs + n);
+    B.shots.assign(shots, shots + n);
+    B.seeds.assign(seeds, seeds + n);
+    B.outs.assign(outs, outs + n);
+    B.precision = precision;
+    hipGetDevice(&B.device);
+    std::vector<ActiveArgs> calls;
+    std::vector<double> cost;
+    std::vector<uint64_t> words_of;
+    size_t lds = 0;
+    for (size_t i = 0; i < n; ++i) {
+        symft_program *p = const_cast<symft_program *>(progs[i]);
+        if (!p || (shots[i] && !outs[i])) return set_err(SYMFT_EINVAL, "NULL program or output in batch");
+        DevProg D;
+        symft_status rc = device_prog(p, D);
+        if (rc) return rc;
+        bool mine = shots[i] > 0 && !(D.k_max == 0 && D.fr_n_steps > 0 && frame_words_per_block(D) > 0);
+        ActiveConfig c;
+        if (mine) {
+            bool tuned;
+            {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                tuned = g_tune.count({D.k_max, fp64}) > 0;
+            }
+            if (!tuned && D.k_max < 13) {
+                rc = tune_program(p, D, fp64, nullptr);
+                if (rc) return rc;
+            }
+            c = choose_active(D, fp64);
+            mine = c.bs == 256 && c.lds_vec;
+        }
+        if (!mine) {
+            if (shots[i]) B.others.push_back(i);
+            continue;
+        }
+        ActiveArgs A;
+        std::memset(&A, 0, sizeof(A));
+        A.P = D;
+        A.seed = seeds[i];
+        A.word_begin = 0;
+        A.n_words = (shots[i] + 63) / 64;
+        A.shots = shots[i];
+        A.out = outs[i];
+        A.row_stride = A.n_words;
+        A.sections = 7u;
+        A.tps = c.tps;
+        A.lds_vec = 1;
+        A.lds_bytes = (uint32_t)c.lds;
+        lds = std::max(lds, c.lds);
+        calls.push_back(A);
+        words_of.push_back(A.n_words);
+        symft_info info;
+        symft_program_info(p, &info);
+        cost.push_back(info.dense_flops_per_shot + 200.0 * (double)info.n_instr[0] + 64.0);
+    }
+    std::vector<BatchItem> items;
+    if (!calls.empty()) {
+        int per_cu = std::max(1, batch_max_blocks_per_cu(fp64, lds));
+        B.grid = (uint32_t)(per_cu * num_cus());
+        uint64_t total_words = 0;
+        for (uint64_t w : words_of) total_words += w;
+        // about eight items per workgroup; an item never splits a word
+        const uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(64, total_words / ((uint64_t)B.grid * 8) + 1));
+        std::vector<std::pair<double, BatchItem>> tmp;
+        for (size_t ci = 0; ci < calls.size(); ++ci)
+            for (uint64_t w0 = 0; w0 < words_of[ci]; w0 += chunk) {
+                BatchItem it;
+                it.call = (uint32_t)ci;
+                it.pad = 0;
+                it.w0 = w0;
+                it.w1 = std::min(words_of[ci], w0 + chunk);
+                tmp.push_back({cost[ci] * (double)(it.w1 - it.w0), it});
+            }
+        std::stable_sort(tmp.begin(), tmp.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+        for (auto &x : tmp) items.push_back(x.second);
+        B.grid = (uint32_t)std::min<uint64_t>(B.grid, items.size());
+        B.lds = (uint32_t)lds;
+        if (hipMalloc(&B.d_calls, sizeof(ActiveArgs) * calls.size()) != hipSuccess ||
+            hipMalloc(&B.d_items, sizeof(BatchItem) * items.size()) != hipSuccess ||
+            hipMalloc(&B.d_counter, 256) != hipSuccess)
+            return set_err(SYMFT_ENOMEM, "batch metadata allocation failed");
+        if (hipMemcpy(B.d_calls, calls.data(), sizeof(ActiveArgs) * calls.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(B.d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return set_err(SYMFT_EHIP, "batch metadata upload failed");
+    }
+    B.args.calls = B.d_calls;
+    B.args.items = B.d_items;
+    B.args.counter = B.d_counter;
+    B.args.n_items = (uint32_t)items.size();
+    B.args.pad = 0;
+    return SYMFT_OK;
+}
+
 symft_status symft_sample_batch(const symft_program *const *progs, const uint64_t *shots, const uint64_t *seeds,
                                 uint64_t *const *records_out, size_t n, uint32_t precision, uint32_t graph,
                                 void *stream) {
-    (void)graph;
-    if (n && (!progs || !shots || !seeds || !records_out)) return set_err(SYMFT_EINVAL, "NULL argument");
-    for (size_t i = 0; i < n; ++i) {
+    if (n == 0) return SYMFT_OK;
+    if (!progs || !shots || !seeds || !records_out) return set_err(SYMFT_EINVAL, "NULL argument");
+    if (precision > 1) return set_err(SYMFT_EINVAL, "precision must be 0 or 1");
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchPlan *B = nullptr;
+    for (size_t i = 0; i < g_plans.size(); ++i)
+        if (g_plans[i]->same(progs, shots, seeds, records_out, n, precision, dev)) {
+            B = g_plans[i];
+            break;
+        }
+    if (!B) {
+        B = new BatchPlan();
+        symft_status rc = build_plan(*B, progs, shots, seeds, records_out, n, precision);
+        if (rc) {
+            B->release();
+            delete B;
+            return rc;
+        }
+        g_plans.insert(g_plans.begin(), B);
+        while (g_plans.size() > 4) {
+            g_plans.back()->release();
+            delete g_plans.back();
+            g_plans.pop_back();
+        }
+    }
+    const bool fp64 = precision == 0;
+    if (B->args.n_items) {
+        if (graph) {
+            if (!B->exec) {
+                // capture [counter reset, persistent kernel] once on a private stream
+                hipStream_t cs;
+                if (hipStreamCreate(&cs) != hipSuccess) return set_err(SYMFT_EHIP, "stream creation failed");
+                hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) e = launch_batch(B->args, fp64, B->grid, B->lds, cs);
+                hipGraph_t g = nullptr;
+                hipError_t e2 = hipStreamEndCapture(cs, &g);
+                if (e == hipSuccess) e = e2;
+                if (e == hipSuccess) e = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
+                B->graph = g;
+                hipStreamDestroy(cs);
+                if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("batch graph capture failed: ") + hipGetErrorString(e));
+            }
+            hipError_t e = hipGraphLaunch(B->exec, st);
+            if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("batch graph launch failed: ") + hipGetErrorString(e));
+        } else {
+            hipError_t e = launch_batch(B->args, fp64, B->grid, B->lds, st);
+            if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("batch kernel launch failed: ") + hipGetErrorString(e));
+        }
+    }
+    for (size_t i : B->others) {
         symft_sample_opts o;
         std::memset(&o, 0, sizeof(o));
         o.precision = precision;

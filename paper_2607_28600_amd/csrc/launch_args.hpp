@@ -28,6 +28,19 @@ struct ActiveArgs {
     uint32_t lds_bytes;
 };
 
+// One item of the batched work queue: words [w0, w1) of call `call`.
+struct BatchItem {
+    uint32_t call, pad;
+    uint64_t w0, w1;
+};
+
+struct BatchArgs {
+    const ActiveArgs *calls;   // device array, one per program of the batch
+    const BatchItem *items;    // device array, decreasing estimated cost
+    uint32_t *counter;         // next item (reset by a one-thread kernel before each launch)
+    uint32_t n_items, pad;
+};
+
 struct FrameArgs {
     DevProg P;
     uint64_t seed;

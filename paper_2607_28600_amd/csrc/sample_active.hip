@@ -168,10 +168,13 @@ __device__ __forceinline__ void kahan_add(T &s, T &c, T v) {
     s = t;
 }
 
+// Words [wi_begin, wi_end) (step wi_step, call-relative) of the call described
+// by A, run by this workgroup.  `slice` picks the HBM vector slice when the
+// vectors do not fit LDS.
 template <typename T, int BS, bool LDSV>
-__global__ void __launch_bounds__(BS) active_kernel(ActiveArgs A) {
+__device__ void run_active_words(const ActiveArgs &A, uint64_t wi_begin, uint64_t wi_end, uint64_t wi_step,
+                                 uint32_t slice, unsigned char *smem) {
     using V = typename C2<T>::type;
-    extern __shared__ __align__(16) unsigned char smem[];
     const DevProg &P = A.P;
     const int tps = (int)A.tps;
     const int G = BS / tps;
@@ -187,11 +190,11 @@ __global__ void __launch_bounds__(BS) active_kernel(ActiveArgs A) {
     const size_t vlen = (size_t)1 << P.k_max;
     V *vec;
     if (LDSV) vec = vec_lds + (size_t)g * vlen;
-    else vec = (V *)A.scratch + ((size_t)blockIdx.x * G + g) * A.scratch_stride;
+    else vec = (V *)A.scratch + ((size_t)slice * G + g) * A.scratch_stride;
     uint32_t *mb = mbits + g * mw;
     const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
 
-    for (uint64_t wi = blockIdx.x; wi < A.n_words; wi += gridDim.x) {
+    for (uint64_t wi = wi_begin; wi < wi_end; wi += wi_step) {
         const uint64_t w = A.word_begin + wi;
         for (uint32_t i = threadIdx.x; i < P.n_instr; i += BS) exo[i] = 0;
         for (uint32_t i = threadIdx.x; i < P.n_rec; i += BS) recw[i] = 0;
@@ -398,6 +401,32 @@ __global__ void __launch_bounds__(BS) active_kernel(ActiveArgs A) {
     }
 }
 
+template <typename T, int BS, bool LDSV>
+__global__ void __launch_bounds__(BS) active_kernel(ActiveArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    run_active_words<T, BS, LDSV>(A, blockIdx.x, A.n_words, gridDim.x, blockIdx.x, smem);
+}
+
+// Persistent work queue over (program, word range) items: every workgroup
+// takes the next item index with a global atomic until the list is exhausted,
+// so every wave reaches the exit.  Items are ordered by decreasing cost.
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) batch_kernel(BatchArgs B) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_idx;
+    while (true) {
+        if (threadIdx.x == 0) s_idx = atomicAdd(B.counter, 1u);
+        __syncthreads();
+        const uint32_t idx = __builtin_amdgcn_readfirstlane(s_idx);
+        __syncthreads();
+        if (idx >= B.n_items) break;
+        const BatchItem it = B.items[idx];
+        run_active_words<T, BS, true>(B.calls[it.call], it.w0, it.w1, 1, blockIdx.x, smem);
+    }
+}
+
+__global__ void reset_counter_kernel(uint32_t *counter) { counter[threadIdx.x] = 0u; }
+
 // ---------------------------------------------------------------- host ----
 template <typename T, int BS, bool LDSV>
 static hipError_t launch_one(const ActiveArgs &A, uint32_t grid, hipStream_t st) {
@@ -431,6 +460,27 @@ int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds) {
     }
     if (bs == 1024) return lds_vec ? blocks_per_cu<float, 1024, true>(lds) : blocks_per_cu<float, 1024, false>(lds);
     return lds_vec ? blocks_per_cu<float, 256, true>(lds) : blocks_per_cu<float, 256, false>(lds);
+}
+
+template <typename T>
+static hipError_t launch_batch_t(const BatchArgs &B, uint32_t grid, uint32_t lds, hipStream_t st) {
+    auto kfn = batch_kernel<T, 256>;
+    hipError_t e = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, B.counter);
+    hipLaunchKernelGGL(kfn, dim3(grid), dim3(256), lds, st, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t lds, hipStream_t st) {
+    return fp64 ? launch_batch_t<double>(B, grid, lds, st) : launch_batch_t<float>(B, grid, lds, st);
+}
+
+int batch_max_blocks_per_cu(bool fp64, size_t lds) {
+    int nb = 0;
+    hipError_t e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<double, 256>, 256, lds)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<float, 256>, 256, lds);
+    return e == hipSuccess ? nb : 1;
 }
 
 hipError_t launch_active(const ActiveArgs &A, bool fp64, uint32_t bs, uint32_t grid, hipStream_t st) {

@@ -188,3 +188,53 @@ def test_sections_only_detectors(c1):
     n_det = w.circuit.num_detectors
     assert not np.any(got[:n_rec]) and not np.any(got[n_rec + n_det:])
     assert np.array_equal(got[n_rec:n_rec + n_det], want[n_rec:n_rec + n_det])
+
+
+def test_batch_graph_replays_match_single_launches_and_oracle():
+    ws = configs.c4()[:24]
+    progs = [S.Program(w.circuit) for w in ws]
+    shots = [64 * (3 + i % 5) + (i * 7) % 64 for i in range(len(ws))]  # ragged last words
+    seeds = [w.seed for w in ws]
+    outs = [torch.zeros((p.n_rows, (s + 63) // 64), dtype=torch.int64, device="cuda") for p, s in zip(progs, shots)]
+    first = None
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-1)                      # eager work between replays
+        torch.cuda.synchronize()
+        S.sample_batch(progs, shots, seeds, outs, precision="fp32", graph=True)
+        torch.cuda.synchronize()
+        got = [S.bits_to_numpy(o) for o in outs]
+        if first is None:
+            first = got
+        for a, b in zip(first, got):
+            assert np.array_equal(a, b), "graph replay differs"
+    for i, (p, s, sd) in enumerate(zip(progs, shots, seeds)):
+        single = _gpu(p, s, sd, precision="fp32")
+        assert np.array_equal(single, first[i]), f"program {i}: batch differs from its own launch"
+        if i % 4 == 0:
+            oc = OracleCircuit(ws[i].circuit)
+            compare_records(first[i], oc.sample(sd, s), ws[i].circuit, oc, sd, 0, TOL["fp32"])
+
+
+def test_batch_without_graph_and_fp64():
+    ws = configs.c4()[24:40]
+    progs = [S.Program(w.circuit) for w in ws]
+    shots = [256 + 64 * (i % 3) for i in range(len(ws))]
+    seeds = [w.seed for w in ws]
+    outs = [torch.zeros((p.n_rows, (s + 63) // 64), dtype=torch.int64, device="cuda") for p, s in zip(progs, shots)]
+    S.sample_batch(progs, shots, seeds, outs, precision="fp64", graph=False)
+    torch.cuda.synchronize()
+    for i in (0, 5, 11):
+        oc = OracleCircuit(ws[i].circuit)
+        compare_records(S.bits_to_numpy(outs[i]), oc.sample(seeds[i], shots[i]), ws[i].circuit, oc, seeds[i], 0,
+                        TOL["fp64"])
+
+
+def test_autotune_choice_keeps_records():
+    w = configs.c3(shots=64 * 16)
+    p = S.Program(w.circuit)
+    oc = OracleCircuit(w.circuit)
+    tps = p.autotune("fp32")
+    assert tps in (16, 32, 64, 128, 256)
+    got = _gpu(p, w.shots, w.seed, precision="fp32")
+    compare_records(got, oc.sample(w.seed, w.shots), w.circuit, oc, w.seed, 0, TOL["fp32"])
