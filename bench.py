@@ -26,10 +26,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "shots/s on 1 MI355X (batched FP32 vs plain FP64) + % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-# Measured HBM bytes per launch of the pure-frame kernel on this workload (profiles/
-# frame_kernel_surface_d11_r11_2e24.md): FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the scales
-# read off a 1 GiB device copy.  None once the kernel changes without a new measurement.
-FRAME_TRAFFIC_BYTES = {"surface_d11_r11_p1e-3": 2.58e9 + 6.71e9}
+# Measured HBM bytes per launch of the pure-frame kernel on a workload (FETCH_SIZE x 2.000 +
+# WRITE_SIZE x 1.000, the scales read off a 1 GiB device copy), kept only while the kernel is
+# the one the counters were taken on.
+FRAME_TRAFFIC_BYTES = {}
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 

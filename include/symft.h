@@ -192,6 +192,14 @@ symft_status symft_autotune(const symft_program *p, uint32_t precision, uint32_t
 symft_status symft_probe(const symft_program *p, uint64_t shot_begin, uint32_t n_shots, uint64_t seed,
                          uint32_t precision, double *p0_host);
 
+/* Gap check: the geometric gap G = max { g <= 4096 : v < Q[g] } of the
+ * noise draw contract (Q the exact table of a class with per-draw firing
+ * probability p32 / 2^32, 0 < p32 <= 2^32) for n draws v (device array),
+ * decided exactly as the sampling kernels decide it (table-free margins,
+ * else the table), written to device array g_out.  Synchronous.  For tests
+ * of the gap decision at table boundaries.  Errors: EINVAL, ENOMEM, EHIP. */
+symft_status symft_gap_check(uint64_t p32, const uint32_t *v, int32_t *g_out, uint64_t n, void *stream);
+
 void symft_program_free(symft_program *p);
 
 /* Thread-local message of the last failing call on this thread. */

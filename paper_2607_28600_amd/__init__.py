@@ -77,6 +77,8 @@ _lib.symft_sample_batch.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64)
                                     C.POINTER(C.c_void_p), C.c_size_t, C.c_uint32, C.c_uint32, C.c_void_p]
 _lib.symft_autotune.restype = C.c_int32
 _lib.symft_autotune.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32)]
+_lib.symft_gap_check.restype = C.c_int32
+_lib.symft_gap_check.argtypes = [C.c_uint64, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p]
 _lib.symft_probe.restype = C.c_int32
 _lib.symft_probe.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.POINTER(C.c_double)]
 _lib.symft_program_export.restype = C.c_int32
@@ -87,7 +89,8 @@ _lib.symft_last_error.restype = C.c_char_p
 
 EXPORTED = ["symft_compile", "symft_program_info", "symft_program_plan", "symft_program_export",
             "symft_sample", "symft_sample_ex",
-            "symft_sample_batch", "symft_autotune", "symft_probe", "symft_program_free", "symft_last_error"]
+            "symft_sample_batch", "symft_autotune", "symft_probe", "symft_gap_check", "symft_program_free",
+            "symft_last_error"]
 
 
 class SymftError(RuntimeError):
@@ -236,6 +239,18 @@ class Program:
 
 def compile(circ) -> Program:  # noqa: A001 - mirrors symft_compile
     return Program(circ)
+
+
+def gap_check(p32: int, v, stream=None):
+    """Geometric gaps of the noise draw contract for uint32 draws `v` (a CUDA int32 tensor
+    holding the bit patterns), decided as the sampling kernels decide them."""
+    import torch
+    g = torch.empty_like(v)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(_lib.symft_gap_check(int(p32), C.c_void_p(v.data_ptr()), C.c_void_p(g.data_ptr()), v.numel(),
+                                C.c_void_p(stream)), "symft_gap_check")
+    return g
 
 
 def sample_batch(programs: Sequence[Program], shots: Sequence[int], seeds: Sequence[int], outs,

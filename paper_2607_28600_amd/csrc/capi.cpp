@@ -23,13 +23,45 @@ hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st);
 struct BatchArgs;
 hipError_t launch_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t lds, hipStream_t st);
 int batch_max_blocks_per_cu(bool fp64, size_t lds);
-size_t frame_lds_bytes(const DevProg &P, uint32_t words_per_block);
-int frame_max_blocks_per_cu(size_t lds);
+size_t frame_lds_bytes(const DevProg &P, bool buffered, uint32_t nw);
+int frame_max_blocks_per_cu(size_t lds, uint32_t nw);
+hipError_t launch_gap_check(const GapFast &F, const uint64_t *Q, const uint32_t *v, int32_t *g, uint64_t n,
+                            hipStream_t st);
 }  // namespace symft
 
 #include "launch_args.hpp"
 
 using namespace symft;
+
+static const size_t kLdsLimit = 160 * 1024;  // LDS of one gfx950 CU
+
+// Margins of the table-free gap decision for one probability class (the
+// derivation is with GapFast).  The FP32 error of t = log2(v / 2^32) / log2 q
+// is bounded from: rounding v to float (2^-24 relative), the hardware log2
+// (taken as 2^-21 |log2 x| + 2^-22 absolute, several ulp), and rounding of
+// 1 / log2 q and of the product (2^-24 relative each, t < 4097); eps doubles
+// that sum.
+static GapFast gap_fast_constants(uint64_t p32, const uint64_t *Q) {
+    GapFast f;
+    std::memset(&f, 0, sizeof(f));
+    f.qW = Q[4096];
+    if (p32 == 0 || p32 >= (uint64_t(1) << 32)) {
+        f.invlog2q = -0.0f;
+        f.vmin = UINT64_MAX;  // P32 = 0: every draw is below Q[4096]; P32 = 2^32: table only
+        return f;
+    }
+    const double q = 1.0 - std::ldexp((double)p32, -32);
+    const double l = -std::log2(q);  // |log2 q|
+    const double D = std::ldexp(1.0, 32) / (double)p32;
+    const double Lmax = 33.0;       // |log2 x| for x = v / 2^32 >= 2^-32
+    const double err_log = std::ldexp(1.0, -24) / std::log(2.0) + std::ldexp(1.0, -21) * Lmax + std::ldexp(1.0, -22);
+    const double err_t = err_log / l * (1.0 + std::ldexp(1.0, -20)) + 4097.0 * std::ldexp(1.0, -23);
+    f.invlog2q = (float)(-1.0 / l);
+    f.A = (float)(1.25 * D / (std::log(2.0) * l));
+    f.eps = (float)(2.0 * err_t);
+    f.vmin = 1;
+    return f;
+}
 
 static thread_local std::string g_err;
 
@@ -42,7 +74,7 @@ struct HostLayout {
     std::vector<uint8_t> blob;
     // offsets of each array inside blob
     size_t o_instr, o_cmeas, o_rm, o_recmeas, o_detoff, o_detrows, o_obsoff, o_obsrows, o_clsQ, o_clsoff, o_clschan,
-        o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_invlog, o_frstep, o_frdata, o_frnodes, o_frpush, o_frchinfo,
+        o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_invlog, o_clsfast, o_frstep, o_frdata, o_frnodes, o_frpush, o_frchinfo,
         o_frfltab, o_frflslots;
     DevProg meta;  // counts only; pointers filled at upload
 };
@@ -127,9 +159,11 @@ static void lower(symft_program *h) {
     std::vector<uint64_t> clsQ;
     std::vector<uint32_t> clsoff, clschan;
     std::vector<float> invlog;
+    std::vector<GapFast> clsfast;
     for (auto &c : P.classes) {
         const double q = 1.0 - std::ldexp((double)c.p32, -32);
         invlog.push_back(q > 0 ? (float)(1.0 / std::log2(q)) : -0.0f);
+        clsfast.push_back(gap_fast_constants(c.p32, c.Q.data()));
         clsQ.insert(clsQ.end(), c.Q.begin(), c.Q.end());
         clsoff.push_back((uint32_t)clschan.size());
         for (int32_t ch : c.chans) clschan.push_back((uint32_t)ch);
@@ -170,6 +204,7 @@ static void lower(symft_program *h) {
     L.o_symoff = put(L.blob, symoff);
     L.o_symcons = put(L.blob, symcons);
     L.o_invlog = put(L.blob, invlog);
+    L.o_clsfast = put(L.blob, clsfast);
     L.o_frstep = put(L.blob, h->F.steps);
     L.o_frdata = put(L.blob, h->F.data);
     L.o_frnodes = put(L.blob, h->F.nodes);
@@ -189,7 +224,7 @@ static void lower(symft_program *h) {
     m.k_max = P.k_max;
     m.fr_n_steps = (uint32_t)h->F.n_steps;
     m.fr_n_slots = h->F.n_slots;
-    m.fr_cap = frame_event_capacity(h->F.events_per_word);
+    m.fr_ok = h->F.ok && frame_lds_bytes(m, false, 4) <= kLdsLimit ? 1u : 0u;
     m.n_sym = P.n_noise_sym;
 }
 
@@ -229,6 +264,7 @@ static symft_status device_prog(symft_program *h, DevProg &out) {
     out.sym_off = (const uint32_t *)(b + L.o_symoff);
     out.sym_cons = (const uint32_t *)(b + L.o_symcons);
     out.cls_invlog2q = (const float *)(b + L.o_invlog);
+    out.cls_fast = (const GapFast *)(b + L.o_clsfast);
     out.fr_step = (const uint32_t *)(b + L.o_frstep);
     out.fr_data = (const uint32_t *)(b + L.o_frdata);
     out.fr_nodes = (const uint32_t *)(b + L.o_frnodes);
@@ -251,14 +287,12 @@ static int num_cus() {
     return g_num_cus;
 }
 
-// Launch configuration of the active kernel for a program (see DESIGN: tuning table).
+// Launch configuration of the active kernel for a program.
 struct ActiveConfig {
     uint32_t bs, tps;
     bool lds_vec;
     size_t lds;
 };
-
-static const size_t kLdsLimit = 160 * 1024;
 
 // Threads per shot chosen by the autotuner, per (peak active width, precision).
 static std::mutex g_tune_mu;
@@ -334,14 +368,21 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
     return SYMFT_OK;
 }
 
+// Waves per workgroup of the frame kernel (4 or 8; 8 measured faster on the
+// d = 11 surface-code memory: 10.8 vs 15.0 ms per 2^24 shots).
+static uint32_t g_frame_waves = 8;
+
 static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_begin, uint64_t n_words, uint64_t shots,
                               uint64_t *out, uint64_t stride, uint32_t sections, uint64_t seed, hipStream_t st) {
-    const uint32_t wpb = frame_words_per_block(D);
-    size_t lds = frame_lds_bytes(D, wpb);
+    // Per-(word, class) event buffers when they fit beside the slots; else each
+    // NOISE step walks its stream afresh.
+    const uint32_t nw = g_frame_waves;
+    bool buffered = frame_lds_bytes(D, true, nw) <= kLdsLimit;
+    size_t lds = frame_lds_bytes(D, buffered, nw);
     if (lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "frame schedule exceeds the LDS budget");
-    int per_cu = frame_max_blocks_per_cu(lds);
+    int per_cu = frame_max_blocks_per_cu(lds, nw);
     if (per_cu <= 0) per_cu = 1;
-    uint64_t tiles = (n_words + wpb - 1) / wpb;  // word groups, one wave each
+    uint64_t tiles = (n_words + 15) / 16;  // 16-word tiles
     uint64_t cap = (uint64_t)per_cu * (uint64_t)num_cus();
     uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
     FrameArgs A;
@@ -354,7 +395,9 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
     A.out = out;
     A.row_stride = stride;
     A.sections = sections;
-    A.wpb = wpb;
+    A.buffered = buffered ? 1u : 0u;
+    A.nwave = nw;
+    A.store16 = (((uintptr_t)out & 15u) == 0 && (stride & 1u) == 0) ? 1u : 0u;
     A.lds_bytes = (uint32_t)lds;
     hipError_t e = launch_frame(A, grid, st);
     if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("frame kernel launch failed: ") + hipGetErrorString(e));
@@ -426,7 +469,7 @@ symft_status symft_program_info(const symft_program *p, symft_info *info) {
     info->frame_steps = p->F.n_steps;
     info->frame_slots = p->F.n_slots;
     info->frame_max_level = p->F.max_level;
-    info->frame_noise_consumers = p->F.flslots.size();
+    info->frame_noise_consumers = p->F.n_flips;
     info->frame_pushes = p->F.n_pushes;
     for (uint32_t st : p->F.steps)
         if ((st >> 28) == FR_NOISE) info->frame_noise_steps += 1;
@@ -504,7 +547,7 @@ symft_status symft_sample_ex(const symft_program *pc, const symft_sample_opts *o
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     const uint64_t w0 = o.shot_offset / 64;
-    if (D.k_max == 0 && D.fr_n_steps > 0 && frame_words_per_block(D) > 0)
+    if (D.fr_ok)
         return run_frame(p, D, w0, n_words, shots, records_out, stride, sections, seed, st);
     return run_active(p, D, o.precision == 0, w0, n_words, shots, records_out, stride, sections, nullptr, 0, 0, seed, st);
 }
@@ -545,12 +588,30 @@ symft_status symft_probe(const symft_program *pc, uint64_t shot_begin, uint32_t 
     return rc;
 }
 
+symft_status symft_gap_check(uint64_t p32, const uint32_t *v, int32_t *g_out, uint64_t n, void *stream) {
+    if (p32 == 0 || p32 > (uint64_t(1) << 32)) return set_err(SYMFT_EINVAL, "p32 must be in (0, 2^32]");
+    if (n == 0) return SYMFT_OK;
+    if (!v || !g_out) return set_err(SYMFT_EINVAL, "NULL argument");
+    std::vector<uint64_t> Q(4097);
+    gap_table(p32, Q.data());
+    const GapFast F = gap_fast_constants(p32, Q.data());
+    uint64_t *dQ = nullptr;
+    if (hipMalloc(&dQ, Q.size() * 8) != hipSuccess) return set_err(SYMFT_ENOMEM, "gap table allocation failed");
+    hipStream_t st = (hipStream_t)stream;
+    symft_status rc = SYMFT_OK;
+    if (hipMemcpy(dQ, Q.data(), Q.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        launch_gap_check(F, dQ, v, g_out, n, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+        rc = set_err(SYMFT_EHIP, "gap check failed");
+    hipFree(dQ);
+    return rc;
+}
+
 // ------------------------------------------------------------ autotune ----
 // Times every threads-per-shot candidate that fits LDS on `words` words of
 // the program and keeps the fastest for (k_max, precision).  Records do not
 // depend on the choice; only branch-probability rounding does.
 static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, uint32_t *tps_out) {
-    if (D.k_max >= 13 || (D.k_max == 0 && D.fr_n_steps > 0 && frame_words_per_block(D) > 0)) {
+    if (D.k_max >= 13 || D.fr_ok) {
         if (tps_out) *tps_out = D.k_max >= 13 ? 1024 : 0;
         return SYMFT_OK;
     }
@@ -667,7 +728,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         DevProg D;
         symft_status rc = device_prog(p, D);
         if (rc) return rc;
-        bool mine = shots[i] > 0 && !(D.k_max == 0 && D.fr_n_steps > 0 && frame_words_per_block(D) > 0);
+        bool mine = shots[i] > 0 && !D.fr_ok;
         ActiveConfig c;
         if (mine) {
             bool tuned;

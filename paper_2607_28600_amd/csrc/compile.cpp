@@ -751,13 +751,17 @@ int compile_program(uint32_t n_qubits, const void *ops_v, size_t n_ops, Program 
     }
     for (auto &nc : P.classes) {
         nc.Q.resize(4097);
-        nc.Q[0] = uint64_t(1) << 32;
-        for (int g = 0; g < 4096; ++g) {
-            unsigned __int128 prod = (unsigned __int128)nc.Q[g] * ((uint64_t(1) << 32) - nc.p32);
-            nc.Q[g + 1] = (uint64_t)(prod >> 32);
-        }
+        gap_table(nc.p32, nc.Q.data());
     }
     return 0;
+}
+
+void gap_table(uint64_t p32, uint64_t *Q) {
+    Q[0] = uint64_t(1) << 32;
+    for (int g = 0; g < 4096; ++g) {
+        unsigned __int128 prod = (unsigned __int128)Q[g] * ((uint64_t(1) << 32) - p32);
+        Q[g + 1] = (uint64_t)(prod >> 32);
+    }
 }
 
 }  // namespace symft

@@ -29,6 +29,25 @@ struct DevChan {
     uint32_t thr_off;  // J thresholds in thr[] (non-uniform only)
 };
 
+// Per-class constants of the table-free gap decision.  With q = 1 - P32/2^32
+// and R[g] = 2^32 q^g, the integer table obeys R[g] - D < Q[g] <= R[g] with
+// D = 2^32 / P32 (each floor loses less than one, shrunk by q at every later
+// step).  For v >= Q[4096] let t = log2(v / 2^32) / log2(q); then v < R[g]
+// exactly when g < t, so v >= R[floor(t) + 1] >= Q[floor(t) + 1], and
+// v < Q[floor(t)] is guaranteed once v + D < R[floor(t)], i.e. once
+// frac(t) > log2(1 + D/v) / |log2 q|, which frac(t) >= A / v with
+// A >= D / (ln 2 |log2 q|) implies.  Then G = floor(t).  eps bounds the FP32
+// error of t; draws outside these margins take the exact table search.
+struct GapFast {
+    float invlog2q;   // 1 / log2(q)
+    float A;          // margin numerator (inflated)
+    float eps;        // bound on |t computed - t|
+    uint32_t pad;
+    uint64_t qW;      // Q[4096]: v < qW means G = 4096
+    uint64_t vmin;    // fast path only for v >= vmin (1, or never when P32 = 2^32)
+};
+static_assert(sizeof(GapFast) == 32, "GapFast layout");
+
 // Pointers into one device allocation (all read-only in the kernels).
 struct DevProg {
     const DevInstr *instr;
@@ -48,16 +67,17 @@ struct DevProg {
     const uint32_t *sym_off;     // n_sym + 1 into sym_cons
     const uint32_t *sym_cons;    // consumer instruction ids per noise symbol
     const float *cls_invlog2q;   // per class 1 / log2(1 - P32 / 2^32): initial guess of a geometric gap
+    const GapFast *cls_fast;     // per class: table-free gap decision margins
     // pure-frame schedule (k_max == 0 programs), see sample_frame.hip
     const uint32_t *fr_step;     // per step: (kind << 28) | payload offset into fr_data
     const uint32_t *fr_data;     // NOISE: class, rank_begin, rank_end; EMIT: first node, node count
-    const uint32_t *fr_nodes;    // 4 words per node (+ sentinel): slot | flags << 24, row, meas, push offset
+    const uint32_t *fr_nodes;    // 8 words per node: slot | flags << 24, row, meas, push count, two successor slots, push offset, 0
     const uint32_t *fr_push;     // successor slots
     const uint64_t *fr_chinfo;   // per (class, rank): flip-table offset | J << 32 | uniform << 40 | thr_off << 41
-    const uint64_t *fr_fltab;    // per (channel, branch): first flip << 24 | flip count
+    const uint64_t *fr_fltab;    // per (channel, branch): flip count | inline slots or slot-list offset
     const uint32_t *fr_flslots;  // slots flipped by each (channel, branch)
     uint32_t n_instr, n_meas, n_rm, n_rec, n_det, n_obs, n_cls, k_max;
-    uint32_t fr_n_steps, fr_n_slots, n_sym, fr_cap;
+    uint32_t fr_n_steps, fr_n_slots, n_sym, fr_ok;   // fr_ok: the pure-frame kernel can run the program
 };
 
 }  // namespace symft

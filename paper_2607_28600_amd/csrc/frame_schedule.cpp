@@ -44,6 +44,8 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
     uint64_t fl_total = 0;
     for (const Channel &ch : P.chans) fl_total += ch.J;
     if (fl_total >= (1u << 26)) return;  // event records hold 26-bit flip-table indices
+    for (const NoiseClass &nc : P.classes)
+        if (nc.chans.size() > (1u << 25)) return;  // class stream positions are 32-bit
     const uint32_t M = (uint32_t)P.n_meas, D = (uint32_t)P.n_det, B = (uint32_t)P.n_obs;
     const uint32_t NN = M + D + B;
     struct Node {
@@ -220,6 +222,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             std::vector<uint32_t> fl;
             for (auto &kv : par)
                 if (kv.second) fl.push_back(kv.first);
+            F.n_flips += fl.size();
             F.fltab.push_back(pack_flips(fl, F.flslots));
         }
     }
@@ -265,25 +268,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
     F.n_pushes = 0;
     for (uint32_t i = 0; i < NN; ++i) F.n_pushes += nd[i].succs.size();
     F.n_steps = steps.size();
-}
-
-// Events buffered per word: the expected count plus 8 standard deviations
-// (the count is Poisson), rounded up; a word that draws more streams the rest.
-uint32_t frame_event_capacity(double events_per_word) {
-    double cap = events_per_word + 8.0 * std::sqrt(events_per_word + 1.0) + 64.0;
-    uint32_t c = (uint32_t)std::ceil(cap / 64.0) * 64u;
-    return std::max<uint32_t>(64u, std::min<uint32_t>(c, 4096u));
-}
-
-uint32_t frame_words_per_block(const DevProg &P) {
-    // words per wave: its slots and one batch of events per word, sized for
-    // at least eight waves per CU
-    for (uint32_t w : {4u, 2u, 1u}) {
-        const size_t bytes = (size_t)w * ((size_t)P.fr_n_slots * 8 + (size_t)P.n_cls * 32 + 256 * 4) + 16;
-        if (bytes <= 20 * 1024) return w;
-    }
-    const size_t one = (size_t)P.fr_n_slots * 8 + (size_t)P.n_cls * 32 + 256 * 4 + 16;
-    return one <= 64 * 1024 ? 1u : 0u;  // 0: the active kernel runs the program instead
+    F.ok = F.n_steps > 0;
 }
 
 }  // namespace symft

@@ -50,7 +50,9 @@ struct FrameArgs {
     uint64_t *out;
     uint64_t row_stride;
     uint32_t sections;
-    uint32_t wpb;             // 64-shot words per workgroup
+    uint32_t buffered;        // 1: per-(word, class) event buffers; 0: walk each step afresh
+    uint32_t nwave;           // waves per workgroup (4 or 8)
+    uint32_t store16;         // output rows may be stored 16 bytes at a time
     uint32_t lds_bytes;
     uint32_t pad;
 };
@@ -58,10 +60,10 @@ struct FrameArgs {
 // Pure-frame schedule (programs with peak active width 0); steps run in
 // order, separated by workgroup barriers:
 //   NOISE  data = [class, rank_begin, rank_end, flip-table bound]: apply the
-//          noise events of those channels (drawn once per word at the start
-//          of the tile and kept as flip-table indices, so the bound is the
-//          first index past the step) by XOR-ing each event's lane bit into
-//          the slots of its consumers;
+//          noise events of those channels of the class by XOR-ing each
+//          event's lane bit into the slots of its consumers (events are kept
+//          as flip-table indices, increasing along a class stream, so the
+//          bound is the first index past the step);
 //   EMIT   data = [first node, node count]: every node of the level reads
 //          (and clears) its slot, adds its constant or its RandomMeas word,
 //          writes its output row and XORs its value into its successors' slots.
@@ -75,7 +77,7 @@ static const uint32_t FR_NO_ROW = 0xFFFFFFFFu;
 struct FrameSchedule {
     std::vector<uint32_t> steps;
     std::vector<uint32_t> data;
-    std::vector<uint32_t> nodes;    // 4 per node, plus a sentinel
+    std::vector<uint32_t> nodes;    // 8 per node
     std::vector<uint32_t> push;
     std::vector<uint64_t> chinfo;   // indexed by class offset + rank
     std::vector<uint64_t> fltab;
@@ -84,11 +86,11 @@ struct FrameSchedule {
     size_t n_steps = 0;
     uint32_t max_level = 0;
     uint64_t n_pushes = 0;
+    uint64_t n_flips = 0;           // slot flips over all (channel, branch) entries
     double events_per_word = 0;     // expected noise events of one 64-shot word
+    bool ok = false;                // the pure-frame kernel can run the program
 };
 
 void build_frame_schedule(const Program &P, FrameSchedule &F);
-uint32_t frame_words_per_block(const DevProg &P);
-uint32_t frame_event_capacity(double events_per_word);
 
 }  // namespace symft

@@ -1,4 +1,5 @@
-// philox.hpp -- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) for gfx950.
+// philox.hpp -- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) for gfx950,
+// and the geometric-gap search of the draw contract.
 // Ten rounds of two 32x32->64 multiplies with the published multipliers and
 // Weyl key increments.  Used by the draw contract: key = (seed lo, seed hi),
 // counter top byte = draw domain (1 gap, 2 branch, 3 random measurement,
@@ -7,14 +8,16 @@
 
 #include <hip/hip_runtime.h>
 
+#include "device_program.hpp"
+
 namespace symft {
 
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // one v_mad_u64_u32 per product gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -40,6 +43,20 @@ __device__ __forceinline__ int gap_of(const uint64_t *__restrict__ Q, float invl
         if ((uint64_t)v < Q[mid]) lo = mid; else hi = mid;
     }
     return lo;
+}
+
+__device__ __forceinline__ bool gap_fast(const GapFast &F, uint32_t v, int &G) {
+    if ((uint64_t)v < F.qW) {
+        G = 4096;
+        return true;
+    }
+    if ((uint64_t)v < F.vmin) return false;
+    const float vf = (float)v;
+    const float t = __log2f(vf * 2.3283064365386963e-10f) * F.invlog2q;
+    const int g0 = (int)t;
+    const float fr = t - (float)g0;
+    G = g0;
+    return g0 < 4096 && fr >= F.A * __builtin_amdgcn_rcpf(vf) + F.eps && fr < 1.0f - F.eps;
 }
 
 }  // namespace symft

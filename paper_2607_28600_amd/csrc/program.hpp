@@ -51,6 +51,10 @@ struct Channel {
     std::vector<uint32_t> bmask;  // per branch: bit i <=> symbol sym0 + i is 1
 };
 
+// Exact geometric table of the draw contract: Q[0] = 2^32,
+// Q[g + 1] = floor(Q[g] (2^32 - p32) / 2^32), g < 4096 (4097 entries).
+void gap_table(uint64_t p32, uint64_t *Q);
+
 struct NoiseClass {
     uint64_t p32 = 0;
     std::vector<int32_t> chans;  // channel ids by rank

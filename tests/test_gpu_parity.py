@@ -238,3 +238,59 @@ def test_autotune_choice_keeps_records():
     assert tps in (16, 32, 64, 128, 256)
     got = _gpu(p, w.shots, w.seed, precision="fp32")
     compare_records(got, oc.sample(w.seed, w.shots), w.circuit, oc, w.seed, 0, TOL["fp32"])
+
+
+def _multiclass_surface(d, rounds, k):
+    """Surface-code memory whose channels carry k different probabilities (k classes, interleaved
+    along the circuit), and one non-uniform general channel."""
+    import dataclasses
+    from workloads.surface import rotated_memory_z
+    c = rotated_memory_z(d, rounds, 1e-3)
+    ops, swapped = [], False
+    for op in c.ops:
+        if op.name in ("X_ERROR", "DEPOLARIZE1", "DEPOLARIZE2"):
+            if op.name == "DEPOLARIZE1" and not swapped:
+                for q in op.targets:
+                    ops.append(dataclasses.replace(op, name="PAULI_CHANNEL", targets=(q,), arg=0.0,
+                                                   branches=((0.002, "X"), (0.0005, "Y"), (0.001, "Z"))))
+                swapped = True
+                continue
+            width = 2 if op.name == "DEPOLARIZE2" else 1
+            for i in range(0, len(op.targets), width):
+                t = op.targets[i:i + width]
+                ops.append(dataclasses.replace(op, targets=t, arg=op.arg * (1.0 + (t[0] % k) / 10.0)))
+        else:
+            ops.append(op)
+    c.ops = ops
+    return c
+
+
+@pytest.mark.parametrize("k", [3, 12])
+def test_frame_multiclass_bit_exact(k):
+    c = _multiclass_surface(5, 4, k)
+    p = S.Program(c)
+    info = p.info()
+    assert info["k_max"] == 0 and info["n_classes"] >= k
+    # k = 3 keeps per-(word, class) event buffers; k = 12 cannot, and walks every step afresh
+    buffered_lds = info["frame_slots"] * 128 + 16 * info["n_classes"] * (24 + 1024)
+    assert (buffered_lds <= 160 * 1024) == (k == 3)
+    oc = OracleCircuit(c)
+    seed = 0xC1A55 + k
+    n = 64 * 40 + 17
+    assert np.array_equal(_gpu(p, n, seed), oc.sample(seed, n))
+    off = 64 * 21
+    assert np.array_equal(_gpu(p, 700, seed, shot_offset=off), oc.sample(seed, 700, shot_begin=off))
+
+
+@pytest.mark.parametrize("p32", [1, 4295, 429497, 4294967, 85899346, 1288490189, 2147483648, 4294967295, 4294967296])
+def test_gap_decision_at_table_boundaries(p32):
+    Q = O.gap_table(p32).astype(np.int64)
+    rng = np.random.default_rng(p32 % 1000003)
+    q = Q[1:]
+    cand = np.concatenate([q - 2, q - 1, q, q + 1, rng.integers(0, 1 << 32, 1 << 20), [0, (1 << 32) - 1]])
+    cand = cand[(cand >= 0) & (cand < (1 << 32))]
+    want = np.searchsorted(-Q, -cand, side="left") - 1  # G = #{g : v < Q[g]} - 1 (Q non-increasing)
+    v = torch.from_numpy(cand.astype(np.uint32).view(np.int32)).cuda()
+    got = S.gap_check(p32, v).cpu().numpy()
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, (p32, cand[bad[:5]], got[bad[:5]], want[bad[:5]])
