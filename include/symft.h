@@ -147,6 +147,11 @@ typedef struct {
     uint32_t precision;            /* 0 = complex FP64 amplitudes, 1 = complex FP32 (FP64 scale and threshold) */
     uint32_t sections;             /* bit 0 records, bit 1 detectors, bit 2 observables; 0 means all */
     uint64_t row_stride_words;     /* 0 means ceil(shots / 64) */
+    uint32_t frame_entry_cap;      /* pure-frame programs: 0 = automatic; otherwise the number of flip entries
+                                      kept per (64-shot word, probability class) before that word falls back to
+                                      drawing its events again at every step (records are unchanged; for tests
+                                      of that fallback) */
+    uint32_t reserved;             /* 0 */
 } symft_sample_opts;
 
 /* Sample `shots` shots (paper Sec. 5) into device buffer records_out

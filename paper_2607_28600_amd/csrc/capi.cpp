@@ -23,8 +23,9 @@ hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st);
 struct BatchArgs;
 hipError_t launch_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t lds, hipStream_t st);
 int batch_max_blocks_per_cu(bool fp64, size_t lds);
-size_t frame_lds_bytes(const DevProg &P, bool buffered, uint32_t nw);
-int frame_max_blocks_per_cu(size_t lds, uint32_t nw);
+size_t frame_lds_bytes(const DevProg &P);
+size_t frame_scratch_words(uint32_t word_entries);
+int frame_max_blocks_per_cu(size_t lds);
 hipError_t launch_gap_check(const GapFast &F, const uint64_t *Q, const uint32_t *v, int32_t *g, uint64_t n,
                             hipStream_t st);
 }  // namespace symft
@@ -74,8 +75,9 @@ struct HostLayout {
     std::vector<uint8_t> blob;
     // offsets of each array inside blob
     size_t o_instr, o_cmeas, o_rm, o_recmeas, o_detoff, o_detrows, o_obsoff, o_obsrows, o_clsQ, o_clsoff, o_clschan,
-        o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_invlog, o_clsfast, o_frstep, o_frdata, o_frnodes, o_frpush, o_frchinfo,
-        o_frfltab, o_frflslots;
+        o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_invlog, o_clsfast, o_frstep, o_frnodes, o_frpush, o_frchinfo,
+        o_frfltab, o_frfl3, o_frcap, o_frcapoff;
+    uint32_t word_entries = 0;  // flip entries per word over all classes (frame kernel scratch)
     DevProg meta;  // counts only; pointers filled at upload
 };
 
@@ -206,12 +208,18 @@ static void lower(symft_program *h) {
     L.o_invlog = put(L.blob, invlog);
     L.o_clsfast = put(L.blob, clsfast);
     L.o_frstep = put(L.blob, h->F.steps);
-    L.o_frdata = put(L.blob, h->F.data);
     L.o_frnodes = put(L.blob, h->F.nodes);
     L.o_frpush = put(L.blob, h->F.push);
     L.o_frchinfo = put(L.blob, h->F.chinfo);
     L.o_frfltab = put(L.blob, h->F.fltab);
-    L.o_frflslots = put(L.blob, h->F.flslots);
+    L.o_frfl3 = put(L.blob, h->F.fl3);
+    {
+        std::vector<uint32_t> capoff(1, 0);
+        for (uint32_t c : h->F.cls_cap) capoff.push_back(capoff.back() + c);
+        L.o_frcap = put(L.blob, h->F.cls_cap);
+        L.o_frcapoff = put(L.blob, capoff);
+        L.word_entries = capoff.back();
+    }
     DevProg &m = L.meta;
     std::memset(&m, 0, sizeof(m));
     m.n_instr = (uint32_t)ins.size();
@@ -224,7 +232,10 @@ static void lower(symft_program *h) {
     m.k_max = P.k_max;
     m.fr_n_steps = (uint32_t)h->F.n_steps;
     m.fr_n_slots = h->F.n_slots;
-    m.fr_ok = h->F.ok && frame_lds_bytes(m, false, 4) <= kLdsLimit ? 1u : 0u;
+    m.fr_first_emit = h->F.first_emit[0];
+    m.fr_first_emit_n = h->F.first_emit[1];
+    m.fr_first_noise_cls = h->F.first_noise_cls;
+    m.fr_ok = h->F.ok && frame_lds_bytes(m) <= kLdsLimit ? 1u : 0u;
     m.n_sym = P.n_noise_sym;
 }
 
@@ -266,13 +277,46 @@ static symft_status device_prog(symft_program *h, DevProg &out) {
     out.cls_invlog2q = (const float *)(b + L.o_invlog);
     out.cls_fast = (const GapFast *)(b + L.o_clsfast);
     out.fr_step = (const uint32_t *)(b + L.o_frstep);
-    out.fr_data = (const uint32_t *)(b + L.o_frdata);
     out.fr_nodes = (const uint32_t *)(b + L.o_frnodes);
     out.fr_push = (const uint32_t *)(b + L.o_frpush);
     out.fr_chinfo = (const uint64_t *)(b + L.o_frchinfo);
     out.fr_fltab = (const uint64_t *)(b + L.o_frfltab);
-    out.fr_flslots = (const uint32_t *)(b + L.o_frflslots);
+    out.fr_fl3 = (const uint64_t *)(b + L.o_frfl3);
+    out.fr_cap = (const uint32_t *)(b + L.o_frcap);
+    out.fr_capoff = (const uint32_t *)(b + L.o_frcapoff);
     return SYMFT_OK;
+}
+
+// Stream-ordered scratch from one library-owned pool per device, which keeps
+// its memory between calls (release threshold at its maximum), so repeated
+// launches of the same size do not go back to the driver.
+static std::mutex g_pool_mu;
+static std::map<int, hipMemPool_t> g_pools;
+
+static hipError_t pool_alloc(void **p, size_t bytes, hipStream_t st) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    hipMemPool_t pool;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        auto it = g_pools.find(dev);
+        if (it == g_pools.end()) {
+            hipMemPoolProps pr;
+            std::memset(&pr, 0, sizeof(pr));
+            pr.allocType = hipMemAllocationTypePinned;
+            pr.location.type = hipMemLocationTypeDevice;
+            pr.location.id = dev;
+            e = hipMemPoolCreate(&pool, &pr);
+            if (e != hipSuccess) return e;
+            uint64_t thr = UINT64_MAX;
+            hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+            g_pools[dev] = pool;
+        } else {
+            pool = it->second;
+        }
+    }
+    return hipMallocFromPoolAsync(p, std::max<size_t>(bytes, 256), pool, st);
 }
 
 static int g_num_cus = 0;
@@ -359,7 +403,7 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
         const uint32_t G = c.bs / c.tps;
         A.scratch_stride = (uint64_t)1 << D.k_max;
         size_t bytes = (size_t)grid * G * A.scratch_stride * (fp64 ? 16 : 8);
-        if (hipMallocAsync(&scratch, bytes, st) != hipSuccess) return set_err(SYMFT_ENOMEM, "vector scratch allocation failed");
+        if (pool_alloc(&scratch, bytes, st) != hipSuccess) return set_err(SYMFT_ENOMEM, "vector scratch allocation failed");
         A.scratch = scratch;
     }
     hipError_t e = launch_active(A, fp64, c.bs, grid, st);
@@ -368,25 +412,27 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
     return SYMFT_OK;
 }
 
-// Waves per workgroup of the frame kernel (4 or 8; 8 measured faster on the
-// d = 11 surface-code memory: 10.8 vs 15.0 ms per 2^24 shots).
-static uint32_t g_frame_waves = 8;
-
 static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_begin, uint64_t n_words, uint64_t shots,
-                              uint64_t *out, uint64_t stride, uint32_t sections, uint64_t seed, hipStream_t st) {
-    // Per-(word, class) event buffers when they fit beside the slots; else each
-    // NOISE step walks its stream afresh.
-    const uint32_t nw = g_frame_waves;
-    bool buffered = frame_lds_bytes(D, true, nw) <= kLdsLimit;
-    size_t lds = frame_lds_bytes(D, buffered, nw);
+                              uint64_t *out, uint64_t stride, uint32_t sections, uint64_t seed, uint32_t cap_override,
+                              hipStream_t st) {
+    size_t lds = frame_lds_bytes(D);
     if (lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "frame schedule exceeds the LDS budget");
-    int per_cu = frame_max_blocks_per_cu(lds, nw);
+    int per_cu = frame_max_blocks_per_cu(lds);
     if (per_cu <= 0) per_cu = 1;
     uint64_t tiles = (n_words + 15) / 16;  // 16-word tiles
     uint64_t cap = (uint64_t)per_cu * (uint64_t)num_cus();
     uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
     FrameArgs A;
     std::memset(&A, 0, sizeof(A));
+    A.word_entries = cap_override ? cap_override * D.n_cls : h->L.word_entries;
+    A.cap_override = cap_override;
+    A.cap = D.fr_cap;
+    A.cap_off = D.fr_capoff;
+    const size_t scratch_bytes = (size_t)grid * frame_scratch_words(A.word_entries) * 8;
+    void *scratch = nullptr;
+    if (pool_alloc(&scratch, scratch_bytes, st) != hipSuccess)
+        return set_err(SYMFT_ENOMEM, "frame scratch allocation failed");
+    A.scratch = (uint64_t *)scratch;
     A.P = D;
     A.seed = seed;
     A.word_begin = word_begin;
@@ -395,11 +441,10 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
     A.out = out;
     A.row_stride = stride;
     A.sections = sections;
-    A.buffered = buffered ? 1u : 0u;
-    A.nwave = nw;
     A.store16 = (((uintptr_t)out & 15u) == 0 && (stride & 1u) == 0) ? 1u : 0u;
     A.lds_bytes = (uint32_t)lds;
     hipError_t e = launch_frame(A, grid, st);
+    hipFreeAsync(scratch, st);
     if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("frame kernel launch failed: ") + hipGetErrorString(e));
     return SYMFT_OK;
 }
@@ -471,8 +516,8 @@ symft_status symft_program_info(const symft_program *p, symft_info *info) {
     info->frame_max_level = p->F.max_level;
     info->frame_noise_consumers = p->F.n_flips;
     info->frame_pushes = p->F.n_pushes;
-    for (uint32_t st : p->F.steps)
-        if ((st >> 28) == FR_NOISE) info->frame_noise_steps += 1;
+    for (size_t i = 0; i < p->F.steps.size(); i += FR_STEP_WORDS)
+        if (p->F.steps[i] == FR_NOISE) info->frame_noise_steps += 1;
     return SYMFT_OK;
 }
 
@@ -548,7 +593,7 @@ symft_status symft_sample_ex(const symft_program *pc, const symft_sample_opts *o
     hipStream_t st = (hipStream_t)stream;
     const uint64_t w0 = o.shot_offset / 64;
     if (D.fr_ok)
-        return run_frame(p, D, w0, n_words, shots, records_out, stride, sections, seed, st);
+        return run_frame(p, D, w0, n_words, shots, records_out, stride, sections, seed, o.frame_entry_cap, st);
     return run_active(p, D, o.precision == 0, w0, n_words, shots, records_out, stride, sections, nullptr, 0, 0, seed, st);
 }
 

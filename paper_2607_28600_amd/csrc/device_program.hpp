@@ -69,15 +69,17 @@ struct DevProg {
     const float *cls_invlog2q;   // per class 1 / log2(1 - P32 / 2^32): initial guess of a geometric gap
     const GapFast *cls_fast;     // per class: table-free gap decision margins
     // pure-frame schedule (k_max == 0 programs), see sample_frame.hip
-    const uint32_t *fr_step;     // per step: (kind << 28) | payload offset into fr_data
-    const uint32_t *fr_data;     // NOISE: class, rank_begin, rank_end; EMIT: first node, node count
+    const uint32_t *fr_step;     // 8 words per step (launch_args.hpp)
     const uint32_t *fr_nodes;    // 8 words per node: slot | flags << 24, row, meas, push count, two successor slots, push offset, 0
     const uint32_t *fr_push;     // successor slots
-    const uint64_t *fr_chinfo;   // per (class, rank): flip-table offset | J << 32 | uniform << 40 | thr_off << 41
-    const uint64_t *fr_fltab;    // per (channel, branch): flip count | inline slots or slot-list offset
-    const uint32_t *fr_flslots;  // slots flipped by each (channel, branch)
+    const uint64_t *fr_chinfo;   // per (class, rank): flip-table offset | J << 26 | uniform << 32 | step << 33 | thr_off << 41
+    const uint64_t *fr_fltab;    // per (channel, branch): flip-entry count | first entry << 8
+    const uint64_t *fr_fl3;      // flip entries: cnt << 6 | up to three 16-bit slots from bit 16
+    const uint32_t *fr_cap;      // per class: flip entries kept per (word, class)
+    const uint32_t *fr_capoff;   // per class + 1: prefix of fr_cap
     uint32_t n_instr, n_meas, n_rm, n_rec, n_det, n_obs, n_cls, k_max;
     uint32_t fr_n_steps, fr_n_slots, n_sym, fr_ok;   // fr_ok: the pure-frame kernel can run the program
+    uint32_t fr_first_emit, fr_first_emit_n, fr_first_noise_cls, pad;
 };
 
 }  // namespace symft

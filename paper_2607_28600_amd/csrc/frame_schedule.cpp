@@ -11,6 +11,11 @@
 // owns an accumulator slot from the step of its first contribution to the
 // step that emits it; slots are interval-coloured, and a slot is reused only
 // by an interval that starts strictly after the previous one ended.
+//
+// The slots flipped by each (channel, branch) are pre-packed as flip entries
+// of up to three 16-bit slots each (the kernel ORs in the shot lane and the
+// step), and every channel carries the index of its NOISE step within its
+// class, so a drawn event becomes its entries without further lookups.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -21,21 +26,18 @@
 
 namespace symft {
 
-// A flip-table entry: count in bits 0..7; up to two slots inline in bits
-// 8..35 and 36..63, otherwise bits 8..35 index the slot list (count 255 means
-// the list starts with its own length).
-static uint64_t pack_flips(const std::vector<uint32_t> &fl, std::vector<uint32_t> &store) {
-    const uint64_t n = fl.size();
-    if (n <= 2) {
-        uint64_t e = n;
-        if (n > 0) e |= (uint64_t)fl[0] << 8;
-        if (n > 1) e |= (uint64_t)fl[1] << 36;
-        return e;
+// Flip entries of one (channel, branch): ceil(n / 3) entries
+// cnt << 6 | s0 << 16 | s1 << 32 | s2 << 48 (cnt = slots in the entry, 1..3);
+// returns the flip-table word: entry count | first entry << 8.
+static uint64_t pack_flips(const std::vector<uint32_t> &fl, std::vector<uint64_t> &fl3) {
+    const uint64_t off = fl3.size(), k = (fl.size() + 2) / 3;
+    for (size_t i = 0; i < fl.size(); i += 3) {
+        const size_t cnt = std::min<size_t>(3, fl.size() - i);
+        uint64_t e = (uint64_t)cnt << 6;
+        for (size_t q = 0; q < cnt; ++q) e |= (uint64_t)fl[i + q] << (16 + 16 * q);
+        fl3.push_back(e);
     }
-    const uint64_t off = store.size();
-    if (n >= 255) store.push_back((uint32_t)n);
-    store.insert(store.end(), fl.begin(), fl.end());
-    return (n >= 255 ? 255 : n) | (off << 8);
+    return k | (off << 8);
 }
 
 void build_frame_schedule(const Program &P, FrameSchedule &F) {
@@ -46,6 +48,9 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
     if (fl_total >= (1u << 26)) return;  // event records hold 26-bit flip-table indices
     for (const NoiseClass &nc : P.classes)
         if (nc.chans.size() > (1u << 25)) return;  // class stream positions are 32-bit
+    uint64_t thr_total = 0;
+    for (const Channel &ch : P.chans) thr_total += ch.thr.size();
+    if (thr_total >= (1u << 23)) return;  // channel records hold 23-bit threshold offsets
     const uint32_t M = (uint32_t)P.n_meas, D = (uint32_t)P.n_det, B = (uint32_t)P.n_obs;
     const uint32_t NN = M + D + B;
     struct Node {
@@ -132,16 +137,19 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
         seg.clear();
         seg_chans.clear();
     };
+    // a level of independent nodes is emitted in chunks of at most FR_LEVEL_MAX
     auto flush_level = [&]() {
         if (level.empty()) return;
-        Step s;
-        s.kind = FR_EMIT;
-        s.cls = s.r0 = s.r1 = 0;
-        s.nodes = level;
-        steps.push_back(s);
-        for (uint32_t v : level) {
-            nd[v].emit = (int)steps.size() - 1;
-            in_level[v] = 0;
+        for (size_t i0 = 0; i0 < level.size(); i0 += FR_LEVEL_MAX) {
+            Step s;
+            s.kind = FR_EMIT;
+            s.cls = s.r0 = s.r1 = 0;
+            s.nodes.assign(level.begin() + i0, level.begin() + std::min(level.size(), i0 + FR_LEVEL_MAX));
+            steps.push_back(s);
+            for (uint32_t v : s.nodes) {
+                nd[v].emit = (int)steps.size() - 1;
+                in_level[v] = 0;
+            }
         }
         F.max_level = std::max<uint32_t>(F.max_level, (uint32_t)level.size());
         level.clear();
@@ -203,11 +211,13 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
         busy.push({nd[i].emit, s});
     }
     F.n_slots = n_slots;
+    if (n_slots >= (1u << 16)) return;  // flip entries hold 16-bit slots
     // noise symbol -> consumer slots; (channel, branch) -> slots flipped
     std::vector<std::vector<uint32_t>> cons(P.n_noise_sym);
     for (uint32_t i = 0; i < NN; ++i)
         for (uint32_t s : nd[i].noise) cons[s].push_back((uint32_t)nd[i].slot);
     std::vector<uint64_t> chan_fl(P.chans.size(), 0), chan_thr(P.chans.size(), 0);
+    std::vector<double> chan_k1(P.chans.size(), 0), chan_k2(P.chans.size(), 0);  // E[entries], E[entries^2] per event
     uint64_t thr_off = 0;
     for (size_t c = 0; c < P.chans.size(); ++c) {
         const Channel &ch = P.chans[c];
@@ -223,33 +233,83 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             for (auto &kv : par)
                 if (kv.second) fl.push_back(kv.first);
             F.n_flips += fl.size();
-            F.fltab.push_back(pack_flips(fl, F.flslots));
+            if ((fl.size() + 2) / 3 > 255) return;  // flip-table words hold 8-bit entry counts
+            F.fltab.push_back(pack_flips(fl, F.fl3));
+            // branch probability under the draw contract
+            double pj = 1.0 / ch.J;
+            if (!ch.uniform) {
+                const double lo = j ? (double)ch.thr[j - 1] : 0.0;
+                pj = ((double)ch.thr[j] - lo) / 4294967296.0;
+            }
+            const double k = (double)((fl.size() + 2) / 3);
+            chan_k1[c] += pj * k;
+            chan_k2[c] += pj * k * k;
         }
     }
+    // step index of every channel within its class
+    std::vector<uint32_t> chan_step_local(P.chans.size(), 0);
+    {
+        std::vector<uint32_t> next_local(P.classes.size(), 0);
+        for (const Step &st : steps) {
+            if (st.kind != FR_NOISE) continue;
+            const uint32_t sl = next_local[st.cls]++;
+            if (sl > 255) return;  // flip entries hold 8-bit step indices
+            for (uint32_t r = st.r0; r < st.r1; ++r) chan_step_local[(size_t)P.classes[st.cls].chans[r]] = sl;
+        }
+    }
+    // channel record per (class, rank): flip-table offset | J << 26 | uniform << 32 |
+    // step index << 33 | threshold offset << 41; per-class flip-entry capacity per
+    // word: the expected count plus 8 standard deviations (compound Poisson) plus 64
     for (const NoiseClass &nc : P.classes) {
+        double m1 = 0, m2 = 0;
+        const double p = std::ldexp((double)nc.p32, -32);
         for (int32_t c : nc.chans) {
             const Channel &ch = P.chans[(size_t)c];
-            F.chinfo.push_back((chan_fl[(size_t)c] & 0xFFFFFFFFull) | ((uint64_t)(ch.J & 0xFF) << 32) |
-                               ((uint64_t)ch.uniform << 40) | (chan_thr[(size_t)c] << 41));
+            F.chinfo.push_back(chan_fl[(size_t)c] | ((uint64_t)ch.J << 26) | ((uint64_t)ch.uniform << 32) |
+                               ((uint64_t)chan_step_local[(size_t)c] << 33) | (chan_thr[(size_t)c] << 41));
+            m1 += 64.0 * p * chan_k1[(size_t)c];
+            m2 += 64.0 * p * chan_k2[(size_t)c];
         }
-        F.events_per_word += (double)nc.chans.size() * 64.0 * std::ldexp((double)nc.p32, -32);
+        F.events_per_word += (double)nc.chans.size() * 64.0 * p;
+        const double cap = std::ceil((m1 + 8.0 * std::sqrt(m2) + 64.0) / 64.0) * 64.0;
+        F.cls_cap.push_back((uint32_t)std::min(cap, 16777216.0));
     }
-    // encode steps and node records
-    std::vector<uint64_t> cls_first(P.classes.size() + 1, 0);
-    for (const Step &s : steps) {
-        F.steps.push_back((s.kind << 28) | (uint32_t)F.data.size());
+    // encode steps (FR_STEP_WORDS per step, see launch_args.hpp) and node records
+    std::vector<uint32_t> first_node(steps.size(), 0);
+    uint32_t nodes_so_far = 0;
+    for (size_t i = 0; i < steps.size(); ++i) {
+        first_node[i] = nodes_so_far;
+        if (steps[i].kind == FR_EMIT) nodes_so_far += (uint32_t)steps[i].nodes.size();
+    }
+    uint32_t ne_first = 0, ne_n = 0, nn_cls = FR_NONE;  // next EMIT / NOISE step after the current one
+    std::vector<uint32_t> rec(steps.size() * FR_STEP_WORDS, 0);
+    for (size_t i = steps.size(); i-- > 0;) {
+        const Step &s = steps[i];
+        uint32_t *r = &rec[i * FR_STEP_WORDS];
+        r[0] = s.kind;
         if (s.kind == FR_NOISE) {
-            const NoiseClass &nc = P.classes[s.cls];
-            // flip-table index of the first channel past this step (events are kept as flip-table indices)
-            const uint64_t bound = s.r1 < nc.chans.size() ? chan_fl[(size_t)nc.chans[s.r1]] : UINT64_C(0xFFFFFFFF);
-            F.data.push_back(s.cls);
-            F.data.push_back(s.r0);
-            F.data.push_back(s.r1);
-            F.data.push_back((uint32_t)std::min<uint64_t>(bound, 0xFFFFFFFFull));
-            continue;
+            r[1] = s.cls;
+            r[2] = s.r1;
+            r[3] = s.r0 < s.r1 ? chan_step_local[(size_t)P.classes[s.cls].chans[s.r0]] : 0u;
+        } else {
+            r[1] = first_node[i];
+            r[2] = (uint32_t)s.nodes.size();
         }
-        F.data.push_back((uint32_t)(F.nodes.size() / 8));
-        F.data.push_back((uint32_t)s.nodes.size());
+        r[5] = ne_first;
+        r[6] = ne_n;
+        r[7] = nn_cls;
+        if (s.kind == FR_EMIT) {
+            ne_first = first_node[i];
+            ne_n = (uint32_t)s.nodes.size();
+        } else {
+            nn_cls = s.cls;
+        }
+    }
+    F.steps = rec;
+    F.first_emit = {ne_first, ne_n};
+    F.first_noise_cls = nn_cls;
+    for (const Step &s : steps) {
+        if (s.kind != FR_EMIT) continue;
         for (uint32_t id : s.nodes) {
             const Node &v = nd[id];
             uint32_t flags = (v.cst ? 1u : 0u) | (v.slot >= 0 ? 2u : 0u) | (v.rm ? 4u : 0u) | ((uint32_t)v.sec << 4);

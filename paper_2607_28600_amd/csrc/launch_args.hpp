@@ -49,39 +49,49 @@ struct FrameArgs {
     uint64_t shots;
     uint64_t *out;
     uint64_t row_stride;
+    uint64_t *scratch;        // per workgroup: flip entries [16 words][sum of class capacities], fallback walk positions
+    const uint32_t *cap;      // per class: flip entries kept per word (device)
+    const uint32_t *cap_off;  // per class: offset of the class within a word's region (device)
+    uint32_t word_entries;    // sum of class capacities
+    uint32_t cap_override;    // nonzero: every class keeps this many entries (offsets c * cap_override)
     uint32_t sections;
-    uint32_t buffered;        // 1: per-(word, class) event buffers; 0: walk each step afresh
-    uint32_t nwave;           // waves per workgroup (4 or 8)
     uint32_t store16;         // output rows may be stored 16 bytes at a time
     uint32_t lds_bytes;
     uint32_t pad;
 };
 
 // Pure-frame schedule (programs with peak active width 0); steps run in
-// order, separated by workgroup barriers:
-//   NOISE  data = [class, rank_begin, rank_end, flip-table bound]: apply the
+// order, separated by workgroup barriers.  Each step is FR_STEP_WORDS words:
+//   [kind, a, b, c, 0, next EMIT first node, next EMIT node count, next NOISE class]
+//   NOISE  a = class, b = rank end, c = step index within the class: apply the
 //          noise events of those channels of the class by XOR-ing each
-//          event's lane bit into the slots of its consumers (events are kept
-//          as flip-table indices, increasing along a class stream, so the
-//          bound is the first index past the step);
-//   EMIT   data = [first node, node count]: every node of the level reads
-//          (and clears) its slot, adds its constant or its RandomMeas word,
-//          writes its output row and XORs its value into its successors' slots.
+//          event's lane bit into the slots of its consumers;
+//   EMIT   a = first node, b = node count <= FR_LEVEL_MAX: every node of the
+//          level reads (and clears) its slot, adds its constant or its
+//          RandomMeas word, writes its output row and XORs its value into its
+//          successors' slots.
+// The "next" fields (node count 0 / class FR_NONE when there is none) let the
+// kernel fetch a step's data ahead of the step.
 // Node record (8 x uint32): slot | flags << 24 (flags bit0 const, bit1 has
 // slot, bit2 RandomMeas, bits 4..5 section: 1 record, 2 detector,
 // 3 observable, 0 hidden), output row, measurement index, push count, first
 // two successor slots, offset of further successors in the push list, 0.
 enum FrameStepKind : uint32_t { FR_NOISE = 1, FR_EMIT = 2 };
 static const uint32_t FR_NO_ROW = 0xFFFFFFFFu;
+static const uint32_t FR_LEVEL_MAX = 64;  // nodes per EMIT step: one (node, word pair) per thread of 8 waves
+static const uint32_t FR_STEP_WORDS = 8;
+static const uint32_t FR_NONE = 0xFFFFFFFFu;
 
 struct FrameSchedule {
-    std::vector<uint32_t> steps;
-    std::vector<uint32_t> data;
+    std::vector<uint32_t> steps;      // FR_STEP_WORDS per step
+    std::vector<uint32_t> first_emit = {0, 0};  // first EMIT step: first node, node count
+    uint32_t first_noise_cls = 0xFFFFFFFFu;     // class of the first NOISE step
     std::vector<uint32_t> nodes;    // 8 per node
     std::vector<uint32_t> push;
     std::vector<uint64_t> chinfo;   // indexed by class offset + rank
-    std::vector<uint64_t> fltab;
-    std::vector<uint32_t> flslots;
+    std::vector<uint64_t> fltab;    // per (channel, branch): entry count | first flip entry << 8
+    std::vector<uint64_t> fl3;      // flip entries: cnt << 6 | three 16-bit slots from bit 16
+    std::vector<uint32_t> cls_cap;  // flip entries kept per (word, class)
     uint32_t n_slots = 0;
     size_t n_steps = 0;
     uint32_t max_level = 0;

@@ -2,63 +2,83 @@
 //
 // A workgroup owns a tile of 16 consecutive 64-shot words.  One uint64 holds
 // one row of one word's 64 shots, so a row of a tile is one aligned 128-byte
-// line of the record-major output.  The workgroup runs the push-based
-// schedule (launch_args.hpp) over its tile, with a barrier after every step:
-//  * NOISE steps: the waves share out the tile's words; for each word a wave
-//    applies the noise events of the step's channels, XOR-ing each event's
-//    lane bit into the slots its (channel, branch) flips.  Events come from
-//    the draw contract one walk at a time: 64 lanes x 4 gap draws decided
-//    without the table except near a boundary, a 32-bit wave scan turning
-//    gaps into positions, and one branch-draw Philox block per lane.  A walk's
-//    events are kept in a per-(word, class) buffer of (flip index << 6 | lane)
-//    entries until their step comes; a program with too many probability
-//    classes for those buffers walks each step afresh and applies at once;
-//  * EMIT levels: lanes take (node, pair of words): read and clear the node's
-//    two slot words, add its constant or its RandomMeas words, store 16 bytes
-//    of its output row and XOR the values into its successors' slots.
+// line of the record-major output.  Per tile:
+//  * phase G (no barriers): the waves share out the tile's words and draw
+//    every noise event of each (word, probability class) stream under the
+//    draw contract -- walks of 64 lanes x 4 gap draws decided without the
+//    table except near a boundary, a 32-bit wave scan turning gaps into
+//    positions, one branch-draw Philox block per lane -- and turn each event
+//    into its pre-packed flip entries (shot lane, NOISE step, up to three
+//    slots), written in stream order to the workgroup's scratch, which stays
+//    in L2 / the Infinity Cache;
+//  * phase S: the push-based schedule (launch_args.hpp), a barrier after
+//    every step.  NOISE: each wave streams its words' entries of the step and
+//    XORs the lane bits into the slots.  EMIT: lanes take (node, pair of
+//    words), read and clear the node's two slot words, add its constant or
+//    RandomMeas words, store 16 bytes of its row and XOR the values into its
+//    successors' slots.
+// A (word, class) stream with more entries than its capacity (8 standard
+// deviations above the mean) is instead walked afresh at every NOISE step
+// and applied at once, so records never depend on the capacity.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "launch_args.hpp"
 #include "philox.hpp"
 
 namespace symft {
 
-constexpr uint32_t TW = 16;    // words per tile
-constexpr uint32_t EVB = 256;  // event entries per buffer: one walk
+constexpr uint32_t TW = 16;  // words per tile
+
+// Program data read with wave-uniform indices goes through the constant
+// address space, so it is fetched by scalar loads: those are counted apart
+// from vector memory, and never wait behind the row stores in flight.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ cptr<T> uniform(const T *p) {
+    return (cptr<T>)p;
+}
+
+__device__ __forceinline__ GapFast load_fast(const GapFast *p, uint32_t c) {
+    const cptr<uint32_t> q = uniform((const uint32_t *)(p + c));
+    GapFast f;
+    f.invlog2q = __uint_as_float(q[0]);
+    f.A = __uint_as_float(q[1]);
+    f.eps = __uint_as_float(q[2]);
+    f.pad = 0;
+    f.qW = (uint64_t)q[4] | ((uint64_t)q[5] << 32);
+    f.vmin = (uint64_t)q[6] | ((uint64_t)q[7] << 32);
+    return f;
+}
 
 struct FrWord {
-    uint32_t pos, j, e;  // class stream: next position, next draw, next event index
-    uint32_t bi, nb;     // buffered events [bi, nb) of the last walk
-    uint32_t done;       // no events left in the stream
+    uint32_t pos, j, e, pad;  // class stream state: next position, draw, event index
 };
 
 __device__ __forceinline__ uint32_t pick4(uint4 r, uint32_t i) {
     return i == 0 ? r.x : i == 1 ? r.y : i == 2 ? r.z : r.w;
 }
 
+// Channel record: flip-table offset | J << 26 | uniform << 32 | step << 33 | thr_off << 41.
 __device__ __forceinline__ uint32_t branch_of(const DevProg &P, uint64_t info, uint32_t bv) {
-    const uint32_t J = (uint32_t)(info >> 32) & 0xFFu;
-    if ((info >> 40) & 1u) return (uint32_t)(((uint64_t)bv * J) >> 32);
+    const uint32_t J = (uint32_t)(info >> 26) & 0x3Fu;
+    if ((info >> 32) & 1u) return (uint32_t)(((uint64_t)bv * J) >> 32);
     const uint64_t t0 = info >> 41;
     for (uint32_t t = 0; t < J; ++t)
         if ((uint64_t)bv < P.thr[t0 + t]) return t;
     return J - 1;
 }
 
-// XOR lane bit `ln` into every slot flipped by flip-table entry `fi`; `col`
-// is the word's column of the slot array (slot s at col[s * TW]).
-__device__ __forceinline__ void apply_flips(const DevProg &P, uint32_t fi, uint32_t ln, unsigned long long *col) {
-    const uint64_t e = P.fr_fltab[fi];
-    const uint32_t n = (uint32_t)(e & 0xFFu);
-    const unsigned long long bit = 1ull << ln;
-    if (n <= 2) {
-        if (n > 0) atomicXor(&col[(size_t)((e >> 8) & 0xFFFFFFFu) * TW], bit);
-        if (n > 1) atomicXor(&col[(size_t)(e >> 36) * TW], bit);
-        return;
-    }
-    uint32_t off = (uint32_t)((e >> 8) & 0xFFFFFFFu), cnt = n;
-    if (n == 255) cnt = P.fr_flslots[off++];
-    for (uint32_t q = 0; q < cnt; ++q) atomicXor(&col[(size_t)P.fr_flslots[off + q] * TW], bit);
+// Flip entry: lane | cnt << 6 | step << 8 | s0 << 16 | s1 << 32 | s2 << 48.
+// `col` is the word's column of the slot array (slot s at col[s * TW]).
+__device__ __forceinline__ void apply_entry(uint64_t e, unsigned long long *col) {
+    const unsigned long long bit = 1ull << (e & 63u);
+    const uint32_t cnt = (uint32_t)(e >> 6) & 3u;
+    atomicXor(&col[(size_t)((e >> 16) & 0xFFFFu) * TW], bit);
+    if (cnt > 1) atomicXor(&col[(size_t)((e >> 32) & 0xFFFFu) * TW], bit);
+    if (cnt > 2) atomicXor(&col[(size_t)(e >> 48) * TW], bit);
 }
 
 struct Walk {
@@ -68,13 +88,15 @@ struct Walk {
 // One walk of the stream (class c, word w): the 256 gap draws from st.j
 // (aligned down to a Philox block), cut before the first event at a position
 // >= R or with an index past the 64 branch blocks that start at st.e & ~3.
-// Event st.e + k goes to buf[(st.e & 3) + k] as fi << 6 | lane (STORE) or is
-// applied to the word's slot column.  Returns the event count; cutR reports a
-// cut at R.  buf also holds the event positions between the two phases.
-template <bool STORE>
-__device__ uint32_t walk(const DevProg &P, const GapFast &F, const uint64_t *Q, uint32_t c, uint32_t coff, uint32_t wlo,
-                         uint32_t whi, Walk &st, uint32_t R, uint32_t *buf, unsigned long long *col, uint32_t k0,
-                         uint32_t k1, bool &cutR) {
+// tmp (256 words, private to the wave) carries event positions between the
+// two phases.  Each event becomes its flip entries: GEN appends them to
+// out[*n_out ...] (those past `cap` are dropped, *n_out still counts them);
+// otherwise they are applied to the word's slot column.  Returns whether the
+// walk stopped at R.
+template <bool GEN>
+__device__ bool walk(const DevProg &P, const GapFast &F, const uint64_t *Q, uint32_t c, uint32_t coff, uint32_t wlo,
+                     uint32_t whi, Walk &st, uint32_t R, uint32_t *tmp, uint64_t *out, uint32_t cap,
+                     uint32_t *n_out, unsigned long long *col, uint32_t k0, uint32_t k1) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t jal = st.j & ~3u;
     const uint4 rr = philox4x32_10(make_uint4((jal >> 2) + lane, wlo, c, (1u << 24) | whi), k0, k1);
@@ -153,6 +175,7 @@ __device__ uint32_t walk(const DevProg &P, const GapFast &F, const uint64_t *Q, 
     const uint64_t bal = __ballot(cut_i < 4);
     const uint32_t cut_lane = bal ? (uint32_t)(__ffsll((long long)bal) - 1) : 64u;
     uint32_t n_pos, n_e, n_j;
+    bool cutR;
     if (cut_lane < 64) {
         n_pos = __shfl(cut_p, (int)cut_lane, 64);
         n_e = __shfl(cut_e, (int)cut_lane, 64);
@@ -171,7 +194,7 @@ __device__ uint32_t walk(const DevProg &P, const GapFast &F, const uint64_t *Q, 
         for (int i = 0; i < 4; ++i) {
             if (G[i] >= 0) {
                 const bool before = lane < cut_lane || (lane == cut_lane && i < cut_i);
-                if (before && G[i] < 4096) buf[ee - eb] = pp + (uint32_t)G[i];
+                if (before && G[i] < 4096) tmp[ee - eb] = pp + (uint32_t)G[i];
                 if (G[i] < 4096) ++ee;
                 pp += G[i] == 4096 ? 4096u : (uint32_t)G[i] + 1u;
             }
@@ -182,82 +205,66 @@ __device__ uint32_t walk(const DevProg &P, const GapFast &F, const uint64_t *Q, 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // branch draws: lane l owns events eb + 4l .. eb + 4l + 3, one Philox block
     const uint4 bb = philox4x32_10(make_uint4((eb >> 2) + lane, wlo, c, (2u << 24) | whi), k0, k1);
+    uint64_t fw[4], tag[4];
+    uint32_t k_lane = 0;
 #pragma unroll
     for (uint32_t i = 0; i < 4; ++i) {
-        const uint32_t idx = 4 * lane + i, ev = eb + idx;
+        const uint32_t ev = eb + 4 * lane + i;
+        fw[i] = 0;
+        tag[i] = 0;
         if (ev >= st.e && ev < n_e) {
-            const uint32_t at = buf[idx];
+            const uint32_t at = tmp[4 * lane + i];
             const uint64_t info = P.fr_chinfo[coff + (at >> 6)];
-            const uint32_t fi = (uint32_t)info + branch_of(P, info, pick4(bb, i));
-            if (STORE) buf[idx] = (fi << 6) | (at & 63u);
-            else apply_flips(P, fi, at & 63u, col);
+            const uint32_t fi = (uint32_t)(info & 0x3FFFFFFu) + branch_of(P, info, pick4(bb, i));
+            fw[i] = P.fr_fltab[fi];
+            tag[i] = (uint64_t)(at & 63u) | (((info >> 33) & 0xFFu) << 8);
+            k_lane += (uint32_t)(fw[i] & 0xFFu);
         }
     }
-    const uint32_t n = n_e - st.e;
+    if (GEN) {
+        // entries of this lane's events go after those of the lanes below it
+        uint32_t xs = k_lane;
+#pragma unroll
+        for (uint32_t off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(xs, off, 64);
+            if (lane >= off) xs += y;
+        }
+        const uint32_t ktot = __shfl(xs, 63, 64);
+        uint32_t o = *n_out + xs - k_lane;
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+            const uint32_t k = (uint32_t)(fw[i] & 0xFFu);
+            const uint64_t f0 = fw[i] >> 8;
+            for (uint32_t q = 0; q < k; ++q, ++o)
+                if (o < cap) out[o] = P.fr_fl3[f0 + q] | tag[i];
+        }
+        *n_out += ktot;
+    } else {
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+            const uint32_t k = (uint32_t)(fw[i] & 0xFFu);
+            const uint64_t f0 = fw[i] >> 8;
+            for (uint32_t q = 0; q < k; ++q) apply_entry(P.fr_fl3[f0 + q] | tag[i], col);
+        }
+    }
     st.pos = n_pos;
     st.e = n_e;
     st.j = n_j;
-    return n;
+    return cutR;
 }
 
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Apply the word's buffered events of this step (flip index below `bound`),
-// walking on whenever the buffer runs out.
-__device__ void noise_buffered(const DevProg &P, const GapFast &F, const uint64_t *Q, uint32_t c, uint32_t coff,
-                               uint32_t cend, uint32_t bound, uint64_t w, FrWord *S, uint32_t *buf,
-                               unsigned long long *col, uint32_t k0, uint32_t k1) {
-    const uint32_t lane = threadIdx.x & 63u;
-    uint32_t bi = rfl(S->bi), nb = rfl(S->nb), done = rfl(S->done);
-    Walk st = {rfl(S->pos), rfl(S->j), rfl(S->e)};
-    bool walked = false;
-    while (true) {
-        while (bi < nb) {
-            const uint32_t idx = bi + lane;
-            const uint32_t ev = idx < nb ? buf[idx] : 0u;
-            const bool take = idx < nb && (ev >> 6) < bound;
-            if (take) apply_flips(P, ev >> 6, ev & 63u, col);
-            const uint32_t nd = (uint32_t)__popcll(__ballot(take));
-            bi += nd;
-            if (nd < 64) break;
-        }
-        if (bi < nb || done) break;  // the next buffered event belongs to a later step
-        const uint32_t e0 = st.e;
-        uint32_t n;
-        bool cutR;
-        do {
-            n = walk<true>(P, F, Q, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st, cend, buf, col, k0, k1, cutR);
-        } while (n == 0 && !cutR && st.pos < cend);
-        walked = true;
-        if (n == 0) {
-            done = 1;
-            break;
-        }
-        bi = e0 & 3u;
-        nb = bi + n;
-    }
-    if (lane == 0) {
-        S->bi = bi;
-        S->nb = nb;
-        S->done = done;
-        if (walked) {
-            S->pos = st.pos;
-            S->j = st.j;
-            S->e = st.e;
-        }
-    }
-}
-
-// Walk the word's stream up to the end R of this step, applying events at once.
+// Walk the word's class stream up to the end R of this step, applying events at once.
 __device__ void noise_direct(const DevProg &P, const GapFast &F, const uint64_t *Q, uint32_t c, uint32_t coff,
                              uint32_t R, uint64_t w, FrWord *S, uint32_t *tmp, unsigned long long *col, uint32_t k0,
                              uint32_t k1) {
     Walk st = {rfl(S->pos), rfl(S->j), rfl(S->e)};
     if (st.pos >= R) return;
-    bool cutR;
-    do {
-        walk<false>(P, F, Q, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st, R, tmp, col, k0, k1, cutR);
-    } while (!cutR && st.pos < R);
+    while (!walk<false>(P, F, Q, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st, R, tmp, nullptr, 0, nullptr, col,
+                        k0, k1) &&
+           st.pos < R) {
+    }
     if ((threadIdx.x & 63u) == 0) {
         S->pos = st.pos;
         S->j = st.j;
@@ -277,102 +284,225 @@ __device__ __forceinline__ unsigned long long rm_word(uint32_t t, uint64_t w, ui
     return (t & 1) ? ((uint64_t)o.z | ((uint64_t)o.w << 32)) : ((uint64_t)o.x | ((uint64_t)o.y << 32));
 }
 
-// One EMIT level over the tile whose first word (within the call) is wt.
-__device__ __forceinline__ void emit_level(const DevProg &P, const FrameArgs &A, uint32_t first, uint32_t n,
-                                           uint64_t wt, unsigned long long *slots, uint32_t tid, uint32_t nthr,
-                                           uint32_t k0, uint32_t k1) {
-    for (uint32_t q = tid; q < n * (TW / 2); q += nthr) {
-        const uint32_t v = first + q / (TW / 2), wl = 2 * (q % (TW / 2));
-        const uint4 *rec = (const uint4 *)(P.fr_nodes + 8 * (size_t)v);
-        const uint4 ra = rec[0], rb = rec[1];
-        const uint32_t flags = ra.x >> 24;
-        unsigned long long v0 = (flags & 1u) ? ~0ull : 0ull, v1 = v0;
-        if (flags & 2u) {
-            ulonglong2 *sp = (ulonglong2 *)&slots[(size_t)(ra.x & 0xFFFFFFu) * TW + wl];
-            const ulonglong2 s = *sp;
-            v0 ^= s.x;
-            v1 ^= s.y;
-            *sp = make_ulonglong2(0ull, 0ull);
-        }
-        const uint64_t wi = wt + wl;
-        if (flags & 4u) {
-            const uint64_t w = A.word_begin + wi;
-            v0 ^= rm_word(ra.z, w, k0, k1);
-            v1 ^= rm_word(ra.z, w + 1, k0, k1);
-        }
+// One (node, word pair) of an EMIT step: the pair's two slot words are read
+// and cleared, the node's constant and RandomMeas words added, the values
+// staged for the store wave (with the node's row, or FR_NO_ROW when the row
+// is not written) and XOR-ed into the successors' slots.
+__device__ __forceinline__ void emit_pair(const DevProg &P, const FrameArgs &A, uint4 ra, uint4 rb, uint32_t q,
+                                          uint64_t wt, unsigned long long *slots, unsigned long long *stg,
+                                          uint32_t *rows, uint32_t k0, uint32_t k1) {
+    const uint32_t vi = q >> 3, wl = 2 * (q & 7u);
+    const uint32_t flags = ra.x >> 24;
+    unsigned long long v0 = (flags & 1u) ? ~0ull : 0ull, v1 = v0;
+    if (flags & 2u) {
+        ulonglong2 *sp = (ulonglong2 *)&slots[(size_t)(ra.x & 0xFFFFFFu) * TW + wl];
+        const ulonglong2 sv = *sp;
+        v0 ^= sv.x;
+        v1 ^= sv.y;
+        *sp = make_ulonglong2(0ull, 0ull);
+    }
+    if (flags & 4u) {
+        const uint64_t w = A.word_begin + wt + wl;
+        v0 ^= rm_word(ra.z, w, k0, k1);
+        v1 ^= rm_word(ra.z, w + 1, k0, k1);
+    }
+    *(ulonglong2 *)&stg[vi * TW + wl] = make_ulonglong2(v0, v1);
+    if (wl == 0) {
         const uint32_t sec = (flags >> 4) & 3u;
-        if (ra.y != FR_NO_ROW && sec && ((A.sections >> (sec - 1)) & 1u) && wi < A.n_words) {
-            unsigned long long *dst = (unsigned long long *)A.out + (uint64_t)ra.y * A.row_stride + wi;
-            const unsigned long long o0 = v0 & word_mask(wi, A.shots), o1 = v1 & word_mask(wi + 1, A.shots);
-            if (A.store16 && wi + 1 < A.n_words) {
-                *(ulonglong2 *)dst = make_ulonglong2(o0, o1);
-            } else {
-                dst[0] = o0;
-                if (wi + 1 < A.n_words) dst[1] = o1;
-            }
-        }
-        const uint32_t np = ra.w;
-        if (np > 0) {
-            unsigned long long *d = &slots[(size_t)rb.x * TW + wl];
-            atomicXor(d, v0);
-            atomicXor(d + 1, v1);
-        }
-        if (np > 1) {
-            unsigned long long *d = &slots[(size_t)rb.y * TW + wl];
-            atomicXor(d, v0);
-            atomicXor(d + 1, v1);
-        }
-        for (uint32_t k = 2; k < np; ++k) {
-            unsigned long long *d = &slots[(size_t)P.fr_push[rb.z + k - 2] * TW + wl];
-            atomicXor(d, v0);
-            atomicXor(d + 1, v1);
-        }
+        rows[vi] = (ra.y != FR_NO_ROW && sec && ((A.sections >> (sec - 1)) & 1u)) ? ra.y : FR_NO_ROW;
+    }
+    const uint32_t np = ra.w;
+    if (np > 0) {
+        unsigned long long *d = &slots[(size_t)rb.x * TW + wl];
+        atomicXor(d, v0);
+        atomicXor(d + 1, v1);
+    }
+    if (np > 1) {
+        unsigned long long *d = &slots[(size_t)rb.y * TW + wl];
+        atomicXor(d, v0);
+        atomicXor(d + 1, v1);
+    }
+    for (uint32_t k = 2; k < np; ++k) {
+        unsigned long long *d = &slots[(size_t)P.fr_push[rb.z + k - 2] * TW + wl];
+        atomicXor(d, v0);
+        atomicXor(d + 1, v1);
     }
 }
 
-// LDS: slots [NS][TW] u64 | word states [TW][NC] | event buffers
-// ([TW][NC][EVB] buffered, [NW][EVB] direct).  Every slot is zero between
-// tiles: each one that receives a contribution is read and cleared by the
-// node that owns it, and every node is emitted.
-template <uint32_t NW>
-__global__ void __launch_bounds__(NW * 64) frame_kernel(FrameArgs A) {
+// One 16-byte chunk (node q / 8, words 2 (q % 8), +1) of the rows staged by
+// an EMIT step of n nodes.
+__device__ __forceinline__ void store_chunk(const FrameArgs &A, const unsigned long long *stg, const uint32_t *rows,
+                                            uint32_t q, uint64_t wt) {
+    const uint32_t v = q >> 3, pw = 2 * (q & 7u);
+    const uint32_t row = rows[v];
+    const uint64_t wi = wt + pw;
+    if (row == FR_NO_ROW || wi >= A.n_words) return;
+    const ulonglong2 val = *(const ulonglong2 *)&stg[v * TW + pw];
+    const unsigned long long m0 = word_mask(wi, A.shots), m1 = word_mask(wi + 1, A.shots);
+    unsigned long long *dst = (unsigned long long *)A.out + (uint64_t)row * A.row_stride + wi;
+    if (A.store16 && wi + 1 < A.n_words) {
+        *(ulonglong2 *)dst = make_ulonglong2(val.x & m0, val.y & m1);
+    } else {
+        dst[0] = val.x & m0;
+        if (wi + 1 < A.n_words) dst[1] = val.y & m1;
+    }
+}
+
+constexpr uint32_t NWC = 8;                        // waves; FR_LEVEL_MAX * TW / 2 = NWC * 64
+constexpr uint32_t STG_WORDS = FR_LEVEL_MAX * TW;  // staged u64 per buffer
+constexpr uint32_t WPW = TW / NWC;                 // words per wave in NOISE steps
+
+// Workgroup: 8 waves.  LDS: slots [NS][TW] u64 | stream states [TW][NC] |
+// entry cursors and counts [TW][NC] | overflow flags [TW] | one region used by
+// phase G as walk positions [NWC][256] and by phase S as two staging buffers
+// ([FR_LEVEL_MAX][TW] u64 + [FR_LEVEL_MAX] rows).
+// Phase S orders each step so that nothing it waits for was issued in the
+// same step: the rows staged by the previous EMIT step are stored first (one
+// 16-byte chunk per thread), node records were fetched one EMIT step ahead
+// and the first flip entries of a NOISE step right after the previous NOISE
+// step; a step record (one scalar load) names what the next steps need.  (Vector loads and stores share one completion counter, so a load
+// issued behind fresh stores would wait for them.)  Every slot is zero
+// between tiles: each one that receives a contribution is read and cleared by
+// the node that owns it, and every node is emitted.
+__global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4))) frame_kernel(FrameArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const DevProg &P = A.P;
-    const uint32_t NC = P.n_cls, NS = P.fr_n_slots;
-    const uint32_t tid = threadIdx.x, wave = tid >> 6;
+    const uint32_t NC = P.n_cls, NS = P.fr_n_slots, n_steps = P.fr_n_steps;
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     unsigned long long *slots = (unsigned long long *)smem;
     FrWord *wst = (FrWord *)(slots + (size_t)NS * TW);
-    uint32_t *evb = (uint32_t *)(wst + (size_t)TW * NC);
+    uint32_t *cur = (uint32_t *)(wst + (size_t)TW * NC);
+    uint32_t *cnt = cur + (size_t)TW * NC;
+    uint32_t *ovf = cnt + (size_t)TW * NC;
+    unsigned char *region = (unsigned char *)(((uintptr_t)(ovf + TW) + 15) & ~(uintptr_t)15);
+    uint32_t *tmp = (uint32_t *)region + (size_t)wave * 256;
+    unsigned long long *stg = (unsigned long long *)region;         // [2][STG_WORDS]
+    uint32_t *rows = (uint32_t *)(stg + 2 * STG_WORDS);              // [2][FR_LEVEL_MAX]
     const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
     const uint64_t n_tiles = (A.n_words + TW - 1) / TW;
-    for (uint32_t i = tid; i < NS * TW; i += NW * 64) slots[i] = 0ull;
+    uint64_t *scr = A.scratch + (size_t)blockIdx.x * (TW * A.word_entries + NWC * 128);
+    uint32_t *gtmp = (uint32_t *)(scr + (size_t)TW * A.word_entries) + (size_t)wave * 256;  // fallback walks
+    for (uint32_t i = tid; i < NS * TW; i += NWC * 64) slots[i] = 0ull;
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t wt = tile * TW;
-        for (uint32_t i = tid; i < TW * NC; i += NW * 64) wst[i] = FrWord{0, 0, 0, 0, 0, 0};
+        for (uint32_t i = tid; i < TW * NC; i += NWC * 64) {
+            wst[i] = FrWord{0, 0, 0, 0};
+            cur[i] = 0;
+        }
+        if (tid < TW) ovf[tid] = 0;
         __syncthreads();
-        for (uint32_t step = 0; step < P.fr_n_steps; ++step) {
-            const uint32_t code = P.fr_step[step];
-            const uint32_t *d = P.fr_data + (code & 0x0FFFFFFFu);
-            if ((code >> 28) == FR_NOISE) {
-                const uint32_t c = d[0], r1 = d[2], bound = d[3];
-                const uint32_t coff = P.cls_off[c];
-                const uint32_t cend = (P.cls_off[c + 1] - coff) * 64u;
-                const GapFast F = P.cls_fast[c];
-                const uint64_t *Q = P.cls_Q + (size_t)c * 4097;
-                for (uint32_t wl = wave; wl < TW && wt + wl < A.n_words; wl += NW) {
-                    const uint64_t w = A.word_begin + wt + wl;
-                    FrWord *S = &wst[wl * NC + c];
-                    if (A.buffered)
-                        noise_buffered(P, F, Q, c, coff, cend, bound, w, S, evb + ((size_t)wl * NC + c) * EVB,
-                                       slots + wl, k0, k1);
-                    else
-                        noise_direct(P, F, Q, c, coff, r1 * 64u, w, S, evb + (size_t)wave * EVB, slots + wl, k0, k1);
+        // phase G: every event of every (word, class) stream of the tile
+        for (uint32_t wl = wave; wl < TW && wt + wl < A.n_words; wl += NWC) {
+            const uint64_t w = A.word_begin + wt + wl;
+            bool over = false;
+            for (uint32_t c = 0; c < NC && !over; ++c) {
+                const uint32_t coff = uniform(P.cls_off)[c], cend = (uniform(P.cls_off)[c + 1] - coff) * 64u;
+                const GapFast F = load_fast(P.cls_fast, c);
+                const uint32_t cap = A.cap_override ? A.cap_override : uniform(A.cap)[c];
+                uint64_t *out =
+                    scr + (size_t)wl * A.word_entries + (A.cap_override ? c * A.cap_override : uniform(A.cap_off)[c]);
+                Walk st = {0, 0, 0};
+                uint32_t n = 0;
+                while (!walk<true>(P, F, P.cls_Q + (size_t)c * 4097, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st,
+                                   cend, tmp, out, cap, &n, nullptr, k0, k1) &&
+                       st.pos < cend && n <= cap) {
                 }
+                over = n > cap;
+                if (lane == 0) cnt[wl * NC + c] = n;
+            }
+            if (lane == 0 && over) ovf[wl] = 1;
+        }
+        // each wave reads back only the entries it wrote (through other lanes); a
+        // workgroup-scope fence orders them, all waves of a workgroup sharing one L1
+        __threadfence_block();
+        __syncthreads();
+        // phase S
+        const cptr<uint32_t> stp = uniform(P.fr_step);
+        uint32_t e_idx = 0, pend_n = 0;
+        uint4 pa = make_uint4(0, 0, 0, 0), pb = pa;
+        uint64_t pe[WPW];
+        uint32_t pk[WPW];
+        auto fetch_records = [&](uint32_t first, uint32_t n) {
+            if (tid < n * (TW / 2)) {
+                const uint4 *rec = (const uint4 *)(P.fr_nodes + 8 * (size_t)(first + (tid >> 3)));
+                pa = rec[0];
+                pb = rec[1];
+            }
+        };
+        auto fetch_entries = [&](uint32_t c) {
+#pragma unroll
+            for (uint32_t i = 0; i < WPW; ++i) {
+                pe[i] = 0;
+                pk[i] = FR_NONE;
+            }
+            if (c == FR_NONE) return;
+            const uint32_t coff = A.cap_override ? c * A.cap_override : uniform(A.cap_off)[c];
+#pragma unroll
+            for (uint32_t i = 0; i < WPW; ++i) {
+                const uint32_t wl = wave + i * NWC;
+                if (wt + wl >= A.n_words || rfl(ovf[wl])) continue;
+                const uint32_t k = rfl(cur[wl * NC + c]), kend = rfl(cnt[wl * NC + c]);
+                pk[i] = k;
+                if (k + lane < kend) pe[i] = scr[(size_t)wl * A.word_entries + coff + k + lane];
+            }
+        };
+        fetch_records(P.fr_first_emit, P.fr_first_emit_n);
+        fetch_entries(P.fr_first_noise_cls);
+        for (uint32_t step = 0; step < n_steps; ++step) {
+            const cptr<uint32_t> r = stp + (size_t)step * FR_STEP_WORDS;
+            const bool is_emit = r[0] == FR_EMIT;
+            // rows staged by the previous step (if it was an EMIT step)
+            if (tid < pend_n * (TW / 2))
+                store_chunk(A, stg + (size_t)((e_idx - 1) & 1u) * STG_WORDS, rows + ((e_idx - 1) & 1u) * FR_LEVEL_MAX,
+                            tid, wt);
+            if (!is_emit) {
+                const uint32_t c = r[1], r1 = r[2], sl = r[3];
+                const uint32_t coff = A.cap_override ? c * A.cap_override : uniform(A.cap_off)[c];
+#pragma unroll
+                for (uint32_t i = 0; i < WPW; ++i) {
+                    const uint32_t wl = wave + i * NWC;
+                    if (wt + wl >= A.n_words) continue;
+                    unsigned long long *col = slots + wl;
+                    if (rfl(ovf[wl])) {
+                        noise_direct(P, load_fast(P.cls_fast, c), P.cls_Q + (size_t)c * 4097, c,
+                                     uniform(P.cls_off)[c], r1 * 64u, A.word_begin + wt + wl, &wst[wl * NC + c],
+                                     gtmp, col, k0, k1);
+                        continue;
+                    }
+                    const uint64_t *src = scr + (size_t)wl * A.word_entries + coff;
+                    uint32_t k = rfl(cur[wl * NC + c]);
+                    const uint32_t kend = rfl(cnt[wl * NC + c]);
+                    bool first = pk[i] == k;
+                    while (k < kend) {
+                        const uint32_t idx = k + lane;
+                        const uint64_t e = first ? pe[i] : (idx < kend ? src[idx] : 0ull);
+                        first = false;
+                        const bool take = idx < kend && ((uint32_t)(e >> 8) & 0xFFu) == sl;
+                        if (take) apply_entry(e, col);
+                        const uint32_t nd = (uint32_t)__popcll(__ballot(take));
+                        k += nd;
+                        if (nd < 64) break;
+                    }
+                    if (lane == 0) cur[wl * NC + c] = k;
+                }
+                fetch_entries(r[7]);
+                pend_n = 0;
             } else {
-                emit_level(P, A, d[0], d[1], wt, slots, tid, NW * 64, k0, k1);
+                const uint4 ra = pa, rb = pb;
+                const uint32_t n = r[2];
+                fetch_records(r[5], r[6]);
+                if (tid < n * (TW / 2))
+                    emit_pair(P, A, ra, rb, tid, wt, slots, stg + (size_t)(e_idx & 1u) * STG_WORDS,
+                              rows + (e_idx & 1u) * FR_LEVEL_MAX, k0, k1);
+                pend_n = n;
+                ++e_idx;
             }
             __syncthreads();
         }
+        if (tid < pend_n * (TW / 2))
+            store_chunk(A, stg + (size_t)((e_idx - 1) & 1u) * STG_WORDS, rows + ((e_idx - 1) & 1u) * FR_LEVEL_MAX,
+                        tid, wt);
+        __syncthreads();
     }
 }
 
@@ -385,26 +515,28 @@ __global__ void gap_check_kernel(GapFast F, const uint64_t *Q, const uint32_t *v
     g[i] = G;
 }
 
-size_t frame_lds_bytes(const DevProg &P, bool buffered, uint32_t nw) {
-    return (size_t)P.fr_n_slots * TW * 8 + (size_t)TW * P.n_cls * sizeof(FrWord) +
-           (buffered ? (size_t)TW * P.n_cls * EVB * 4 : (size_t)nw * EVB * 4) + 16;
+size_t frame_lds_bytes(const DevProg &P) {
+    // slots | stream states | cursors and counts | overflow flags | (walk positions or staging)
+    const size_t head = (size_t)P.fr_n_slots * TW * 8 + (size_t)TW * P.n_cls * (sizeof(FrWord) + 8) + TW * 4;
+    const size_t region = std::max<size_t>((size_t)NWC * 256 * 4, 2 * (STG_WORDS * 8 + FR_LEVEL_MAX * 4));
+    return ((head + 15) & ~(size_t)15) + region;
 }
 
-int frame_max_blocks_per_cu(size_t lds, uint32_t nw) {
+// Scratch per workgroup, in u64: flip entries of 16 words plus the fallback walks' positions.
+size_t frame_scratch_words(uint32_t word_entries) { return (size_t)TW * word_entries + NWC * 128; }
+
+uint32_t frame_threads() { return NWC * 64; }
+
+int frame_max_blocks_per_cu(size_t lds) {
     int nb = 0;
-    const void *f = nw == 8 ? (const void *)frame_kernel<8> : (const void *)frame_kernel<4>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, (int)nw * 64, lds) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, frame_kernel, (int)frame_threads(), lds) != hipSuccess) return 1;
     return nb;
 }
 
 hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st) {
-    const void *f = A.nwave == 8 ? (const void *)frame_kernel<8> : (const void *)frame_kernel<4>;
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds_bytes);
+    hipError_t e = hipFuncSetAttribute((const void *)frame_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds_bytes);
     if (e != hipSuccess) return e;
-    if (A.nwave == 8)
-        hipLaunchKernelGGL(frame_kernel<8>, dim3(grid), dim3(512), A.lds_bytes, st, A);
-    else
-        hipLaunchKernelGGL(frame_kernel<4>, dim3(grid), dim3(256), A.lds_bytes, st, A);
+    hipLaunchKernelGGL(frame_kernel, dim3(grid), dim3(frame_threads()), A.lds_bytes, st, A);
     return hipGetLastError();
 }
 

@@ -266,20 +266,28 @@ def _multiclass_surface(d, rounds, k):
 
 
 @pytest.mark.parametrize("k", [3, 12])
-def test_frame_multiclass_bit_exact(k):
+@pytest.mark.parametrize("cap", [0, 8])
+def test_frame_multiclass_bit_exact(k, cap):
+    """cap = 8 flip entries per (word, class) sends nearly every word down the fallback that
+    draws its events again at every NOISE step."""
     c = _multiclass_surface(5, 4, k)
     p = S.Program(c)
     info = p.info()
     assert info["k_max"] == 0 and info["n_classes"] >= k
-    # k = 3 keeps per-(word, class) event buffers; k = 12 cannot, and walks every step afresh
-    buffered_lds = info["frame_slots"] * 128 + 16 * info["n_classes"] * (24 + 1024)
-    assert (buffered_lds <= 160 * 1024) == (k == 3)
     oc = OracleCircuit(c)
     seed = 0xC1A55 + k
     n = 64 * 40 + 17
-    assert np.array_equal(_gpu(p, n, seed), oc.sample(seed, n))
+    assert np.array_equal(_gpu(p, n, seed, frame_entry_cap=cap), oc.sample(seed, n))
     off = 64 * 21
-    assert np.array_equal(_gpu(p, 700, seed, shot_offset=off), oc.sample(seed, 700, shot_begin=off))
+    assert np.array_equal(_gpu(p, 700, seed, shot_offset=off, frame_entry_cap=cap),
+                          oc.sample(seed, 700, shot_begin=off))
+
+
+def test_c2_entry_fallback_bit_exact(c2):
+    w, p, oc = c2
+    want = oc.sample(w.seed, 64 * 24, threads=0)
+    for cap in (64, 1100, 1180):  # every word, most words, some words fall back (mean about 1140)
+        assert np.array_equal(_gpu(p, 64 * 24, w.seed, frame_entry_cap=cap), want), cap
 
 
 @pytest.mark.parametrize("p32", [1, 4295, 429497, 4294967, 85899346, 1288490189, 2147483648, 4294967295, 4294967296])
