@@ -6,7 +6,8 @@ per step on the pure-frame path.  One step = one symft_sample call that
 writes all 2762 bit-packed rows for 2^24 shots, inputs (the compiled program)
 already resident in HBM.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c1|c3|c3fp64|c4|c5]
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+                    [--workload c2|c1|c3|c3fp64|c4|c4fp64|c5|c5fp64|c5k16]
 
 Prints one JSON line.  `roofline` prices the dominant kernel against HBM
 bandwidth (record bytes written per launch / average launch time, measured
@@ -29,7 +30,9 @@ HBM_PEAK_GBS = 8000.0
 # Measured HBM bytes per launch of the pure-frame kernel on a workload (FETCH_SIZE x 2.000 +
 # WRITE_SIZE x 1.000, the scales read off a 1 GiB device copy), kept only while the kernel is
 # the one the counters were taken on.
-FRAME_TRAFFIC_BYTES = {}
+FRAME_TRAFFIC_BYTES = {"surface_d11_r11_p1e-3": 4.383e9 + 8.405e9}
+# The same for the active kernel with HBM-resident vectors.
+ACTIVE_TRAFFIC_BYTES = {"near_clifford_n48_k16": 1.595e12 + 1.384e12}
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
@@ -57,6 +60,23 @@ def _time_launches(fn, steps, warmup, stream):
     return t0.elapsed_time(t1) / steps, sum(per) / len(per), wall
 
 
+LDS_BYTES = 160 * 1024
+
+
+def _p0_error(prog, seed, n_shots):
+    """Largest |Pr(m=0)| difference between the FP32 and FP64 kernels over the active
+    measurements of n_shots shots, and how many exceed 1e-5 (the FP64 kernel matches the
+    oracle within 1e-12 in the parity tests; a larger difference can only follow a draw that
+    fell between the two precisions' thresholds, after which both branches are valid)."""
+    import numpy as np
+    a = prog.probe(0, n_shots, seed, precision="fp32")
+    b = prog.probe(0, n_shots, seed, precision="fp64")
+    ok = ~np.isnan(b)
+    d = np.abs(a[ok] - b[ok])
+    return {"max_abs": float(d.max(initial=0.0)), "over_1e-5": int((d > 1e-5).sum()),
+            "measurements": int(d.size), "probed_shots": n_shots}
+
+
 def _cpu_baseline(circ, seed, words, threads):
     from oracle import OracleCircuit
     oc = OracleCircuit(circ)
@@ -76,10 +96,10 @@ def run(args):
     cores = os.cpu_count() or 1
     extra = {}
     wl = args.workload
-    if wl in ("c1", "c2", "c3", "c3fp64", "c5"):
+    if wl in ("c1", "c2", "c3", "c3fp64", "c5", "c5fp64", "c5k16"):
         w = {"c1": configs.c1, "c2": configs.c2, "c3": configs.c3, "c3fp64": configs.c3,
-             "c5": lambda: configs.c5(14)}[wl]()
-        prec = "fp64" if wl in ("c1", "c3fp64") else ("fp32" if wl in ("c3", "c5") else "fp64")
+             "c5": lambda: configs.c5(14), "c5fp64": lambda: configs.c5(14), "c5k16": lambda: configs.c5(16)}[wl]()
+        prec = "fp32" if wl in ("c3", "c5", "c5k16") else "fp64"
         prog = S.Program(w.circuit)
         info = prog.info()
         words = (w.shots + 63) // 64
@@ -99,6 +119,16 @@ def run(args):
                     "traffic": round(traffic / 1e9, 3) if traffic else None, "traffic_unit": "GB/launch",
                     "kernel": "frame_kernel", "bytes_per_launch": rec_bytes}
             dtype = "u64"
+        elif (1 << info["k_max"]) * (8 if prec == "fp32" else 16) > LDS_BYTES:
+            # vectors streamed from HBM scratch: one read and one write of the live vector per instruction
+            nbytes = info["dense_bytes_per_shot"] * (1 if prec == "fp32" else 2) * w.shots
+            achieved = nbytes / (ms_kernel / 1e3) / 1e9
+            traffic = ACTIVE_TRAFFIC_BYTES.get(w.name) if prec == "fp32" and w.shots == 1 << 16 else None
+            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": round(traffic / 1e9, 1) if traffic else None, "traffic_unit": "GB/launch",
+                    "kernel": "active_kernel", "bytes_per_launch": nbytes}
+            dtype = "f32" if prec == "fp32" else "f64"
         else:
             flops = info["dense_flops_per_shot"] * w.shots
             achieved = flops / (ms_kernel / 1e3) / 1e12
@@ -107,19 +137,21 @@ def run(args):
                     "frac": round(achieved / peak, 4), "traffic": None, "kernel": "active_kernel",
                     "flops_per_launch": flops}
             dtype = "f32" if prec == "fp32" else "f64"
+        if info["k_max"] and prec == "fp32":
+            extra["p0_fp32_vs_fp64"] = _p0_error(prog, w.seed, 64)
         config = {"workload": w.name, "shots": w.shots, "rows": prog.n_rows, "k_max": info["k_max"],
                   "precision": prec if info["k_max"] else "n/a (integer path)"}
-        n_cpu_words = {"c1": 256, "c2": 24, "c3": 64, "c3fp64": 64, "c5": 8}[wl]
+        n_cpu_words = {"c1": 256, "c2": 24, "c3": 64, "c3fp64": 64, "c5": 8, "c5fp64": 8, "c5k16": 2}[wl]
         sample_words = [int(i * words / n_cpu_words) for i in range(n_cpu_words)]
         circ, seed = w.circuit, w.seed
-    elif wl == "c4":
+    elif wl in ("c4", "c4fp64"):
         ws = configs.c4()
         progs = [S.Program(x.circuit) for x in ws]
         outs = [torch.empty((p.n_rows, (x.shots + 63) // 64), dtype=torch.int64, device="cuda")
                 for p, x in zip(progs, ws)]
         shots = [x.shots for x in ws]
         seeds = [x.seed for x in ws]
-        prec = args.precision
+        prec = "fp64" if wl == "c4fp64" else "fp32"
 
         def step():
             S.sample_batch(progs, shots, seeds, outs, precision=prec, graph=True, stream=stream.cuda_stream)
@@ -142,6 +174,13 @@ def run(args):
                 "frac": round(achieved / peak, 4), "traffic": None, "kernel": "active_kernel"}
         dtype = "f32" if prec == "fp32" else "f64"
         config = {"workload": "batch_128_near_clifford", "shots": total, "programs": len(ws), "precision": prec}
+        if prec == "fp32":
+            errs = [_p0_error(p, x.seed, 16) for p, x in list(zip(progs, ws))[::16]]
+            extra["p0_fp32_vs_fp64"] = {"max_abs": max(e["max_abs"] for e in errs),
+                                        "over_1e-5": sum(e["over_1e-5"] for e in errs),
+                                        "measurements": sum(e["measurements"] for e in errs),
+                                        "probed_shots": sum(e["probed_shots"] for e in errs),
+                                        "programs": len(errs)}
         circ, seed = ws[0].circuit, ws[0].seed
         sample_words = list(range(16))
     else:

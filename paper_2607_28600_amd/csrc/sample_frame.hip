@@ -62,12 +62,12 @@ __device__ __forceinline__ uint32_t pick4(uint4 r, uint32_t i) {
 }
 
 // Channel record: flip-table offset | J << 26 | uniform << 32 | step << 33 | thr_off << 41.
-__device__ __forceinline__ uint32_t branch_of(const DevProg &P, uint64_t info, uint32_t bv) {
+__device__ __forceinline__ uint32_t branch_of(const uint64_t *thr, uint64_t info, uint32_t bv) {
     const uint32_t J = (uint32_t)(info >> 26) & 0x3Fu;
     if ((info >> 32) & 1u) return (uint32_t)(((uint64_t)bv * J) >> 32);
     const uint64_t t0 = info >> 41;
     for (uint32_t t = 0; t < J; ++t)
-        if ((uint64_t)bv < P.thr[t0 + t]) return t;
+        if ((uint64_t)bv < thr[t0 + t]) return t;
     return J - 1;
 }
 
@@ -85,6 +85,14 @@ struct Walk {
     uint32_t pos, j, e;
 };
 
+// The program tables a walk reads (passed by value, so an out-of-line walk
+// needs no copy of the whole program descriptor).
+struct WalkTabs {
+    const uint64_t *chinfo, *fltab, *fl3, *thr;
+};
+
+__device__ __forceinline__ WalkTabs walk_tabs(const DevProg &P) { return WalkTabs{P.fr_chinfo, P.fr_fltab, P.fr_fl3, P.thr}; }
+
 // One walk of the stream (class c, word w): the 256 gap draws from st.j
 // (aligned down to a Philox block), cut before the first event at a position
 // >= R or with an index past the 64 branch blocks that start at st.e & ~3.
@@ -94,7 +102,7 @@ struct Walk {
 // otherwise they are applied to the word's slot column.  Returns whether the
 // walk stopped at R.
 template <bool GEN>
-__device__ bool walk(const DevProg &P, const GapFast &F, const uint64_t *Q, uint32_t c, uint32_t coff, uint32_t wlo,
+__device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const uint64_t *Q, uint32_t c, uint32_t coff, uint32_t wlo,
                      uint32_t whi, Walk &st, uint32_t R, uint32_t *tmp, uint64_t *out, uint32_t cap,
                      uint32_t *n_out, unsigned long long *col, uint32_t k0, uint32_t k1) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -214,9 +222,9 @@ __device__ bool walk(const DevProg &P, const GapFast &F, const uint64_t *Q, uint
         tag[i] = 0;
         if (ev >= st.e && ev < n_e) {
             const uint32_t at = tmp[4 * lane + i];
-            const uint64_t info = P.fr_chinfo[coff + (at >> 6)];
-            const uint32_t fi = (uint32_t)(info & 0x3FFFFFFu) + branch_of(P, info, pick4(bb, i));
-            fw[i] = P.fr_fltab[fi];
+            const uint64_t info = T.chinfo[coff + (at >> 6)];
+            const uint32_t fi = (uint32_t)(info & 0x3FFFFFFu) + branch_of(T.thr, info, pick4(bb, i));
+            fw[i] = T.fltab[fi];
             tag[i] = (uint64_t)(at & 63u) | (((info >> 33) & 0xFFu) << 8);
             k_lane += (uint32_t)(fw[i] & 0xFFu);
         }
@@ -236,7 +244,7 @@ __device__ bool walk(const DevProg &P, const GapFast &F, const uint64_t *Q, uint
             const uint32_t k = (uint32_t)(fw[i] & 0xFFu);
             const uint64_t f0 = fw[i] >> 8;
             for (uint32_t q = 0; q < k; ++q, ++o)
-                if (o < cap) out[o] = P.fr_fl3[f0 + q] | tag[i];
+                if (o < cap) out[o] = T.fl3[f0 + q] | tag[i];
         }
         *n_out += ktot;
     } else {
@@ -244,7 +252,7 @@ __device__ bool walk(const DevProg &P, const GapFast &F, const uint64_t *Q, uint
         for (uint32_t i = 0; i < 4; ++i) {
             const uint32_t k = (uint32_t)(fw[i] & 0xFFu);
             const uint64_t f0 = fw[i] >> 8;
-            for (uint32_t q = 0; q < k; ++q) apply_entry(P.fr_fl3[f0 + q] | tag[i], col);
+            for (uint32_t q = 0; q < k; ++q) apply_entry(T.fl3[f0 + q] | tag[i], col);
         }
     }
     st.pos = n_pos;
@@ -256,12 +264,12 @@ __device__ bool walk(const DevProg &P, const GapFast &F, const uint64_t *Q, uint
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Walk the word's class stream up to the end R of this step, applying events at once.
-__device__ void noise_direct(const DevProg &P, const GapFast &F, const uint64_t *Q, uint32_t c, uint32_t coff,
-                             uint32_t R, uint64_t w, FrWord *S, uint32_t *tmp, unsigned long long *col, uint32_t k0,
-                             uint32_t k1) {
+__device__ __forceinline__ void noise_direct(WalkTabs T, GapFast F, const uint64_t *Q, uint32_t c, uint32_t coff,
+                                          uint32_t R, uint64_t w, FrWord *S, uint32_t *tmp, unsigned long long *col,
+                                          uint32_t k0, uint32_t k1) {
     Walk st = {rfl(S->pos), rfl(S->j), rfl(S->e)};
     if (st.pos >= R) return;
-    while (!walk<false>(P, F, Q, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st, R, tmp, nullptr, 0, nullptr, col,
+    while (!walk<false>(T, F, Q, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st, R, tmp, nullptr, 0, nullptr, col,
                         k0, k1) &&
            st.pos < R) {
     }
@@ -403,7 +411,7 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
                     scr + (size_t)wl * A.word_entries + (A.cap_override ? c * A.cap_override : uniform(A.cap_off)[c]);
                 Walk st = {0, 0, 0};
                 uint32_t n = 0;
-                while (!walk<true>(P, F, P.cls_Q + (size_t)c * 4097, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st,
+                while (!walk<true>(walk_tabs(P), F, P.cls_Q + (size_t)c * 4097, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st,
                                    cend, tmp, out, cap, &n, nullptr, k0, k1) &&
                        st.pos < cend && n <= cap) {
                 }
@@ -448,46 +456,46 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
         };
         fetch_records(P.fr_first_emit, P.fr_first_emit_n);
         fetch_entries(P.fr_first_noise_cls);
+        auto noise_step = [&](cptr<uint32_t> r) {
+            const uint32_t c = r[1], r1 = r[2], sl = r[3];
+            const uint32_t coff = A.cap_override ? c * A.cap_override : uniform(A.cap_off)[c];
+#pragma unroll
+            for (uint32_t i = 0; i < WPW; ++i) {
+                const uint32_t wl = wave + i * NWC;
+                if (wt + wl >= A.n_words) continue;
+                unsigned long long *col = slots + wl;
+                if (rfl(ovf[wl])) {
+                    noise_direct(walk_tabs(P), load_fast(P.cls_fast, c), P.cls_Q + (size_t)c * 4097, c,
+                                 uniform(P.cls_off)[c], r1 * 64u, A.word_begin + wt + wl, &wst[wl * NC + c], gtmp,
+                                 col, k0, k1);
+                    continue;
+                }
+                const uint64_t *src = scr + (size_t)wl * A.word_entries + coff;
+                uint32_t k = rfl(cur[wl * NC + c]);
+                const uint32_t kend = rfl(cnt[wl * NC + c]);
+                bool first = pk[i] == k;
+                while (k < kend) {
+                    const uint32_t idx = k + lane;
+                    const uint64_t e = first ? pe[i] : (idx < kend ? src[idx] : 0ull);
+                    first = false;
+                    const bool take = idx < kend && ((uint32_t)(e >> 8) & 0xFFu) == sl;
+                    if (take) apply_entry(e, col);
+                    const uint32_t nd = (uint32_t)__popcll(__ballot(take));
+                    k += nd;
+                    if (nd < 64) break;
+                }
+                if (lane == 0) cur[wl * NC + c] = k;
+            }
+            fetch_entries(r[7]);
+        };
         for (uint32_t step = 0; step < n_steps; ++step) {
             const cptr<uint32_t> r = stp + (size_t)step * FR_STEP_WORDS;
-            const bool is_emit = r[0] == FR_EMIT;
             // rows staged by the previous step (if it was an EMIT step)
             if (tid < pend_n * (TW / 2))
                 store_chunk(A, stg + (size_t)((e_idx - 1) & 1u) * STG_WORDS, rows + ((e_idx - 1) & 1u) * FR_LEVEL_MAX,
                             tid, wt);
-            if (!is_emit) {
-                const uint32_t c = r[1], r1 = r[2], sl = r[3];
-                const uint32_t coff = A.cap_override ? c * A.cap_override : uniform(A.cap_off)[c];
-#pragma unroll
-                for (uint32_t i = 0; i < WPW; ++i) {
-                    const uint32_t wl = wave + i * NWC;
-                    if (wt + wl >= A.n_words) continue;
-                    unsigned long long *col = slots + wl;
-                    if (rfl(ovf[wl])) {
-                        noise_direct(P, load_fast(P.cls_fast, c), P.cls_Q + (size_t)c * 4097, c,
-                                     uniform(P.cls_off)[c], r1 * 64u, A.word_begin + wt + wl, &wst[wl * NC + c],
-                                     gtmp, col, k0, k1);
-                        continue;
-                    }
-                    const uint64_t *src = scr + (size_t)wl * A.word_entries + coff;
-                    uint32_t k = rfl(cur[wl * NC + c]);
-                    const uint32_t kend = rfl(cnt[wl * NC + c]);
-                    bool first = pk[i] == k;
-                    while (k < kend) {
-                        const uint32_t idx = k + lane;
-                        const uint64_t e = first ? pe[i] : (idx < kend ? src[idx] : 0ull);
-                        first = false;
-                        const bool take = idx < kend && ((uint32_t)(e >> 8) & 0xFFu) == sl;
-                        if (take) apply_entry(e, col);
-                        const uint32_t nd = (uint32_t)__popcll(__ballot(take));
-                        k += nd;
-                        if (nd < 64) break;
-                    }
-                    if (lane == 0) cur[wl * NC + c] = k;
-                }
-                fetch_entries(r[7]);
-                pend_n = 0;
-            } else {
+            pend_n = 0;
+            if (r[0] == FR_EMIT) {
                 const uint4 ra = pa, rb = pb;
                 const uint32_t n = r[2];
                 fetch_records(r[5], r[6]);
@@ -496,6 +504,8 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
                               rows + (e_idx & 1u) * FR_LEVEL_MAX, k0, k1);
                 pend_n = n;
                 ++e_idx;
+            } else {
+                noise_step(r);
             }
             __syncthreads();
         }
