@@ -102,6 +102,7 @@ def run(args):
         prec = "fp32" if wl in ("c3", "c5", "c5k16") else "fp64"
         prog = S.Program(w.circuit)
         info = prog.info()
+        tps = prog.autotune(prec) if info["k_max"] else 0  # launch configuration, outside the timed region
         words = (w.shots + 63) // 64
         out = torch.empty((prog.n_rows, words), dtype=torch.int64, device="cuda")
 
@@ -141,6 +142,8 @@ def run(args):
             extra["p0_fp32_vs_fp64"] = _p0_error(prog, w.seed, 64)
         config = {"workload": w.name, "shots": w.shots, "rows": prog.n_rows, "k_max": info["k_max"],
                   "precision": prec if info["k_max"] else "n/a (integer path)"}
+        if tps:
+            config["threads_per_shot"] = tps
         n_cpu_words = {"c1": 256, "c2": 24, "c3": 64, "c3fp64": 64, "c5": 8, "c5fp64": 8, "c5k16": 2}[wl]
         sample_words = [int(i * words / n_cpu_words) for i in range(n_cpu_words)]
         circ, seed = w.circuit, w.seed

@@ -171,7 +171,10 @@ symft_status symft_sample_ex(const symft_program *p, const symft_sample_opts *op
  * items ordered by decreasing cost.  records_out[i] (device, n_rows(i) x
  * ceil(shots[i]/64) words) receives program i's rows for shots[i] shots with
  * seeds[i]; precision as in symft_sample_opts.  Threads per shot come from
- * the autotuner (run on first use of each (k_max, precision)).  `graph` = 1
+ * the autotuner, run on first use of each (k_max, precision) on a 256-word
+ * sample (a batch member shares the GPU, so its own occupancy matters less
+ * than for a single launch; these choices are kept apart from
+ * symft_autotune's).  `graph` = 1
  * captures the launch (a counter-reset kernel and the persistent kernel) in
  * a HIP graph on first use and replays it on later calls with identical
  * arguments.  Programs that need their own kernel (pure frame, or vectors
@@ -182,8 +185,8 @@ symft_status symft_sample_batch(const symft_program *const *progs, const uint64_
                                 uint64_t *const *records_out, size_t n, uint32_t precision, uint32_t graph,
                                 void *stream);
 
-/* Autotuner: times each threads-per-shot configuration of the active-state
- * kernel that fits LDS on 256 words of this program and keeps the fastest
+/* Autotuner: times each threads-per-shot configuration (4 .. 256) of the
+ * active-state kernel that fits LDS on 4096 words of this program and keeps the fastest
  * for the program's (peak active width, precision); later launches with that
  * key use it (sample calls and batches alike).  Records do not depend on the
  * choice.  Synchronous; allocates a scratch output.  *tps_out (nullable)

@@ -160,7 +160,7 @@ class Program:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:  # the library may be gone at interpreter exit
             _lib.symft_program_free(h)
             self._h = None
 

@@ -7,6 +7,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/symft.h"
@@ -338,26 +339,29 @@ struct ActiveConfig {
     size_t lds;
 };
 
-// Threads per shot chosen by the autotuner, per (peak active width, precision).
+// Threads per shot chosen by the autotuner, per (peak active width, precision,
+// context).  Context 0: a launch that has the GPU to itself (tuned on 4096
+// words, so occupancy weighs in); context 1: a member of a batch, sharing the
+// GPU with the other programs (tuned on 256 words).
 static std::mutex g_tune_mu;
-static std::map<std::pair<uint32_t, bool>, uint32_t> g_tune;
+static std::map<std::tuple<uint32_t, bool, int>, uint32_t> g_tune;
 
-static uint32_t default_tps(uint32_t k) {
-    if (k <= 4) return 16;
-    if (k == 5) return 32;
-    if (k <= 8) return 64;
-    if (k == 9) return 128;
-    return 256;
+// Threads per shot before the autotuner has run: about 2^(k-4) amplitudes'
+// worth of threads in FP32 and twice that in FP64, at least 4 (the choices
+// the autotuner makes on near-Clifford programs of width 1..12).
+static uint32_t default_tps(uint32_t k, bool fp64) {
+    const int e = (int)k - (fp64 ? 3 : 4);
+    return e <= 2 ? 4u : e >= 8 ? 256u : (1u << e);
 }
 
-ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0) {
+ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, int context = 0) {
     ActiveConfig c;
     uint32_t k = P.k_max;
     c.bs = 256;
-    c.tps = default_tps(k);
+    c.tps = default_tps(k, fp64);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune.find({k, fp64});
+        auto it = g_tune.find({k, fp64, context});
         if (it != g_tune.end()) c.tps = it->second;
     }
     if (force_tps) c.tps = force_tps;
@@ -652,15 +656,16 @@ symft_status symft_gap_check(uint64_t p32, const uint32_t *v, int32_t *g_out, ui
 }
 
 // ------------------------------------------------------------ autotune ----
-// Times every threads-per-shot candidate that fits LDS on `words` words of
-// the program and keeps the fastest for (k_max, precision).  Records do not
-// depend on the choice; only branch-probability rounding does.
-static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, uint32_t *tps_out) {
+// Times every threads-per-shot candidate that fits LDS on 4096 words (context
+// 0) or 256 words (context 1) of the program and keeps the fastest for
+// (k_max, precision, context).  Records do not depend on the choice; only
+// branch-probability rounding does.
+static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, uint32_t *tps_out, int context = 0) {
     if (D.k_max >= 13 || D.fr_ok) {
         if (tps_out) *tps_out = D.k_max >= 13 ? 1024 : 0;
         return SYMFT_OK;
     }
-    const uint64_t words = 256;
+    const uint64_t words = context == 0 ? 4096 : 256;
     uint64_t *out = nullptr;
     const uint64_t rows = std::max<uint64_t>(1, p->P.n_rows());
     if (hipMalloc(&out, 8 * rows * words) != hipSuccess) return set_err(SYMFT_ENOMEM, "autotune buffer allocation failed");
@@ -673,10 +678,10 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     float best = 1e30f;
-    uint32_t best_tps = default_tps(D.k_max);
+    uint32_t best_tps = default_tps(D.k_max, fp64);
     symft_status rc = SYMFT_OK;
-    for (uint32_t tps : {16u, 32u, 64u, 128u, 256u}) {
-        if (((uint32_t)1 << D.k_max) < tps / 4 && tps > 16) continue;  // most lanes would idle
+    for (uint32_t tps : {4u, 8u, 16u, 32u, 64u, 128u, 256u}) {
+        if (((uint32_t)1 << D.k_max) < tps / 4 && tps > 4) continue;  // most lanes would idle
         if (active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
         float ms = 0;
         for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
@@ -699,7 +704,7 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[{D.k_max, fp64}] = best_tps;
+        g_tune[{D.k_max, fp64, context}] = best_tps;
     }
     if (tps_out) *tps_out = best_tps;
     return SYMFT_OK;
@@ -779,13 +784,13 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
             bool tuned;
             {
                 std::lock_guard<std::mutex> lk(g_tune_mu);
-                tuned = g_tune.count({D.k_max, fp64}) > 0;
+                tuned = g_tune.count({D.k_max, fp64, 1}) > 0;
             }
             if (!tuned && D.k_max < 13) {
-                rc = tune_program(p, D, fp64, nullptr);
+                rc = tune_program(p, D, fp64, nullptr, 1);
                 if (rc) return rc;
             }
-            c = choose_active(D, fp64);
+            c = choose_active(D, fp64, 0, 1);
             mine = c.bs == 256 && c.lds_vec;
         }
         if (!mine) {

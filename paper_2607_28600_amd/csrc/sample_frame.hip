@@ -71,14 +71,35 @@ __device__ __forceinline__ uint32_t branch_of(const uint64_t *thr, uint64_t info
     return J - 1;
 }
 
-// Flip entry: lane | cnt << 6 | step << 8 | s0 << 16 | s1 << 32 | s2 << 48.
-// `col` is the word's column of the slot array (slot s at col[s * TW]).
-__device__ __forceinline__ void apply_entry(uint64_t e, unsigned long long *col) {
+// Slot array: slot s holds the tile's 16 words at s * TW + (w ^ (s & 15)).  The
+// swizzle spreads one word column over the LDS banks (an unswizzled column sits
+// in one bank pair, so 64 lanes XOR-ing random slots of one word would
+// serialise); the two words of an even-aligned pair stay one 16-byte chunk,
+// in swapped order when s is odd.
+__device__ __forceinline__ unsigned long long *slot_word(unsigned long long *slots, uint32_t s, uint32_t w) {
+    return &slots[(size_t)s * TW + (w ^ (s & 15u))];
+}
+__device__ __forceinline__ unsigned long long *slot_pair(unsigned long long *slots, uint32_t s, uint32_t wl) {
+    return &slots[(size_t)s * TW + (wl ^ (s & 14u))];
+}
+
+// Flip entry: lane | cnt << 6 | step << 8 | s0 << 16 | s1 << 32 | s2 << 48,
+// applied to word wl of the tile.
+__device__ __forceinline__ void apply_entry(uint64_t e, unsigned long long *slots, uint32_t wl) {
     const unsigned long long bit = 1ull << (e & 63u);
     const uint32_t cnt = (uint32_t)(e >> 6) & 3u;
-    atomicXor(&col[(size_t)((e >> 16) & 0xFFFFu) * TW], bit);
-    if (cnt > 1) atomicXor(&col[(size_t)((e >> 32) & 0xFFFFu) * TW], bit);
-    if (cnt > 2) atomicXor(&col[(size_t)(e >> 48) * TW], bit);
+    atomicXor(slot_word(slots, (uint32_t)(e >> 16) & 0xFFFFu, wl), bit);
+    if (cnt > 1) atomicXor(slot_word(slots, (uint32_t)(e >> 32) & 0xFFFFu, wl), bit);
+    if (cnt > 2) atomicXor(slot_word(slots, (uint32_t)(e >> 48), wl), bit);
+}
+
+// XOR (v0, v1) into words (wl, wl + 1) of slot s.
+__device__ __forceinline__ void push_pair(unsigned long long *slots, uint32_t s, uint32_t wl, unsigned long long v0,
+                                          unsigned long long v1) {
+    unsigned long long *d = slot_pair(slots, s, wl);
+    const bool sw = s & 1u;
+    atomicXor(d, sw ? v1 : v0);
+    atomicXor(d + 1, sw ? v0 : v1);
 }
 
 struct Walk {
@@ -104,7 +125,7 @@ __device__ __forceinline__ WalkTabs walk_tabs(const DevProg &P) { return WalkTab
 template <bool GEN>
 __device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const uint64_t *Q, uint32_t c, uint32_t coff, uint32_t wlo,
                      uint32_t whi, Walk &st, uint32_t R, uint32_t *tmp, uint64_t *out, uint32_t cap,
-                     uint32_t *n_out, unsigned long long *col, uint32_t k0, uint32_t k1) {
+                     uint32_t *n_out, unsigned long long *slots, uint32_t wl, uint32_t k0, uint32_t k1) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t jal = st.j & ~3u;
     const uint4 rr = philox4x32_10(make_uint4((jal >> 2) + lane, wlo, c, (1u << 24) | whi), k0, k1);
@@ -252,7 +273,7 @@ __device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const 
         for (uint32_t i = 0; i < 4; ++i) {
             const uint32_t k = (uint32_t)(fw[i] & 0xFFu);
             const uint64_t f0 = fw[i] >> 8;
-            for (uint32_t q = 0; q < k; ++q) apply_entry(T.fl3[f0 + q] | tag[i], col);
+            for (uint32_t q = 0; q < k; ++q) apply_entry(T.fl3[f0 + q] | tag[i], slots, wl);
         }
     }
     st.pos = n_pos;
@@ -265,11 +286,12 @@ __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_re
 
 // Walk the word's class stream up to the end R of this step, applying events at once.
 __device__ __forceinline__ void noise_direct(WalkTabs T, GapFast F, const uint64_t *Q, uint32_t c, uint32_t coff,
-                                          uint32_t R, uint64_t w, FrWord *S, uint32_t *tmp, unsigned long long *col,
+                                          uint32_t R, uint64_t w, FrWord *S, uint32_t *tmp, unsigned long long *slots,
+                                          uint32_t wl,
                                           uint32_t k0, uint32_t k1) {
     Walk st = {rfl(S->pos), rfl(S->j), rfl(S->e)};
     if (st.pos >= R) return;
-    while (!walk<false>(T, F, Q, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st, R, tmp, nullptr, 0, nullptr, col,
+    while (!walk<false>(T, F, Q, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st, R, tmp, nullptr, 0, nullptr, slots, wl,
                         k0, k1) &&
            st.pos < R) {
     }
@@ -303,10 +325,11 @@ __device__ __forceinline__ void emit_pair(const DevProg &P, const FrameArgs &A, 
     const uint32_t flags = ra.x >> 24;
     unsigned long long v0 = (flags & 1u) ? ~0ull : 0ull, v1 = v0;
     if (flags & 2u) {
-        ulonglong2 *sp = (ulonglong2 *)&slots[(size_t)(ra.x & 0xFFFFFFu) * TW + wl];
+        const uint32_t sl = ra.x & 0xFFFFFFu;
+        ulonglong2 *sp = (ulonglong2 *)slot_pair(slots, sl, wl);
         const ulonglong2 sv = *sp;
-        v0 ^= sv.x;
-        v1 ^= sv.y;
+        v0 ^= (sl & 1u) ? sv.y : sv.x;
+        v1 ^= (sl & 1u) ? sv.x : sv.y;
         *sp = make_ulonglong2(0ull, 0ull);
     }
     if (flags & 4u) {
@@ -320,21 +343,9 @@ __device__ __forceinline__ void emit_pair(const DevProg &P, const FrameArgs &A, 
         rows[vi] = (ra.y != FR_NO_ROW && sec && ((A.sections >> (sec - 1)) & 1u)) ? ra.y : FR_NO_ROW;
     }
     const uint32_t np = ra.w;
-    if (np > 0) {
-        unsigned long long *d = &slots[(size_t)rb.x * TW + wl];
-        atomicXor(d, v0);
-        atomicXor(d + 1, v1);
-    }
-    if (np > 1) {
-        unsigned long long *d = &slots[(size_t)rb.y * TW + wl];
-        atomicXor(d, v0);
-        atomicXor(d + 1, v1);
-    }
-    for (uint32_t k = 2; k < np; ++k) {
-        unsigned long long *d = &slots[(size_t)P.fr_push[rb.z + k - 2] * TW + wl];
-        atomicXor(d, v0);
-        atomicXor(d + 1, v1);
-    }
+    if (np > 0) push_pair(slots, rb.x, wl, v0, v1);
+    if (np > 1) push_pair(slots, rb.y, wl, v0, v1);
+    for (uint32_t k = 2; k < np; ++k) push_pair(slots, P.fr_push[rb.z + k - 2], wl, v0, v1);
 }
 
 // One 16-byte chunk (node q / 8, words 2 (q % 8), +1) of the rows staged by
@@ -412,7 +423,7 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
                 Walk st = {0, 0, 0};
                 uint32_t n = 0;
                 while (!walk<true>(walk_tabs(P), F, P.cls_Q + (size_t)c * 4097, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st,
-                                   cend, tmp, out, cap, &n, nullptr, k0, k1) &&
+                                   cend, tmp, out, cap, &n, nullptr, 0, k0, k1) &&
                        st.pos < cend && n <= cap) {
                 }
                 over = n > cap;
@@ -463,11 +474,10 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
             for (uint32_t i = 0; i < WPW; ++i) {
                 const uint32_t wl = wave + i * NWC;
                 if (wt + wl >= A.n_words) continue;
-                unsigned long long *col = slots + wl;
                 if (rfl(ovf[wl])) {
                     noise_direct(walk_tabs(P), load_fast(P.cls_fast, c), P.cls_Q + (size_t)c * 4097, c,
                                  uniform(P.cls_off)[c], r1 * 64u, A.word_begin + wt + wl, &wst[wl * NC + c], gtmp,
-                                 col, k0, k1);
+                                 slots, wl, k0, k1);
                     continue;
                 }
                 const uint64_t *src = scr + (size_t)wl * A.word_entries + coff;
@@ -479,7 +489,7 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
                     const uint64_t e = first ? pe[i] : (idx < kend ? src[idx] : 0ull);
                     first = false;
                     const bool take = idx < kend && ((uint32_t)(e >> 8) & 0xFFu) == sl;
-                    if (take) apply_entry(e, col);
+                    if (take) apply_entry(e, slots, wl);
                     const uint32_t nd = (uint32_t)__popcll(__ballot(take));
                     k += nd;
                     if (nd < 64) break;
