@@ -62,7 +62,7 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *tmp, u
 
 // Draw the word's noise events and XOR them into exo[] (draw contract, domains 1 and 2).
 template <int BS>
-__device__ void word_noise(const DevProg &P, uint64_t seed, uint64_t w, unsigned long long *exo, uint64_t *tmp) {
+__device__ __forceinline__ void word_noise(const DevProg &P, uint64_t seed, uint64_t w, unsigned long long *exo, uint64_t *tmp) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t wlo = (uint32_t)w, whi = (uint32_t)(w >> 32);
     for (uint32_t c = 0; c < P.n_cls; ++c) {
@@ -172,7 +172,7 @@ __device__ __forceinline__ void kahan_add(T &s, T &c, T v) {
 // by A, run by this workgroup.  `slice` picks the HBM vector slice when the
 // vectors do not fit LDS.
 template <typename T, int BS, bool LDSV>
-__device__ void run_active_words(const ActiveArgs &A, uint64_t wi_begin, uint64_t wi_end, uint64_t wi_step,
+__device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t wi_begin, uint64_t wi_end, uint64_t wi_step,
                                  uint32_t slice, unsigned char *smem) {
     using V = typename C2<T>::type;
     const DevProg &P = A.P;
@@ -186,7 +186,8 @@ __device__ void run_active_words(const ActiveArgs &A, uint64_t wi_begin, uint64_
     uint64_t *tmp = (uint64_t *)(recw + P.n_rec);                                // 16
     T *red = (T *)(tmp + 16);                                                    // 2 * BS/64
     uint32_t *mbits = (uint32_t *)(red + 2 * (BS / 64) + 2);                     // G * mw
-    V *vec_lds = (V *)(((uintptr_t)(mbits + G * mw) + 15) & ~(uintptr_t)15);     // G * 2^kmax (LDS mode)
+    // G * 2^kmax (LDS mode); offset from smem so the pointer stays in the LDS address space
+    V *vec_lds = (V *)(smem + ((((unsigned char *)(mbits + G * mw) - smem) + 15) & ~(ptrdiff_t)15));
     const size_t vlen = (size_t)1 << P.k_max;
     V *vec;
     if (LDSV) vec = vec_lds + (size_t)g * vlen;

@@ -393,7 +393,10 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
     uint32_t *cur = (uint32_t *)(wst + (size_t)TW * NC);
     uint32_t *cnt = cur + (size_t)TW * NC;
     uint32_t *ovf = cnt + (size_t)TW * NC;
-    unsigned char *region = (unsigned char *)(((uintptr_t)(ovf + TW) + 15) & ~(uintptr_t)15);
+    // offsets from smem itself keep the pointers in the LDS address space (an
+    // integer round trip would turn every access into a flat one, which also
+    // waits on vector-memory counters)
+    unsigned char *region = smem + ((((unsigned char *)(ovf + TW) - smem) + 15) & ~(ptrdiff_t)15);
     uint32_t *tmp = (uint32_t *)region + (size_t)wave * 256;
     unsigned long long *stg = (unsigned long long *)region;         // [2][STG_WORDS]
     uint32_t *rows = (uint32_t *)(stg + 2 * STG_WORDS);              // [2][FR_LEVEL_MAX]
@@ -500,13 +503,23 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
         };
         for (uint32_t step = 0; step < n_steps; ++step) {
             const cptr<uint32_t> r = stp + (size_t)step * FR_STEP_WORDS;
+            const bool is_emit = r[0] == FR_EMIT;
+            // Take the data fetched for this step before issuing any store: a wait
+            // on vector memory covers every operation issued before it, so a load
+            // consumed behind fresh stores would wait for the stores as well.
+            const uint4 ra = pa, rb = pb;
+            if (is_emit) {
+                asm volatile("" : : "v"(ra.x), "v"(ra.y), "v"(ra.z), "v"(ra.w), "v"(rb.x), "v"(rb.y), "v"(rb.z));
+            } else {
+#pragma unroll
+                for (uint32_t i = 0; i < WPW; ++i) asm volatile("" : : "v"(pe[i]));
+            }
             // rows staged by the previous step (if it was an EMIT step)
             if (tid < pend_n * (TW / 2))
                 store_chunk(A, stg + (size_t)((e_idx - 1) & 1u) * STG_WORDS, rows + ((e_idx - 1) & 1u) * FR_LEVEL_MAX,
                             tid, wt);
             pend_n = 0;
-            if (r[0] == FR_EMIT) {
-                const uint4 ra = pa, rb = pb;
+            if (is_emit) {
                 const uint32_t n = r[2];
                 fetch_records(r[5], r[6]);
                 if (tid < n * (TW / 2))
