@@ -40,9 +40,10 @@ static const size_t kLdsLimit = 160 * 1024;  // LDS of one gfx950 CU
 // Margins of the table-free gap decision for one probability class (the
 // derivation is with GapFast).  The FP32 error of t = log2(v / 2^32) / log2 q
 // is bounded from: rounding v to float (2^-24 relative), the hardware log2
-// (taken as 2^-21 |log2 x| + 2^-22 absolute, several ulp), and rounding of
-// 1 / log2 q and of the product (2^-24 relative each, t < 4097); eps doubles
-// that sum.
+// (taken as 2^-21 |log2 x| + 2^-22 absolute, several ulp, with |log2 x| at
+// most log2(2^32 / Q[4096]) since smaller draws never reach it), and rounding
+// of 1 / log2 q and of the product (2^-24 relative each, t < 4097); eps
+// doubles that sum.
 static GapFast gap_fast_constants(uint64_t p32, const uint64_t *Q) {
     GapFast f;
     std::memset(&f, 0, sizeof(f));
@@ -55,7 +56,8 @@ static GapFast gap_fast_constants(uint64_t p32, const uint64_t *Q) {
     const double q = 1.0 - std::ldexp((double)p32, -32);
     const double l = -std::log2(q);  // |log2 q|
     const double D = std::ldexp(1.0, 32) / (double)p32;
-    const double Lmax = 33.0;       // |log2 x| for x = v / 2^32 >= 2^-32
+    // |log2 x| over the fast path's draws: x = v / 2^32 with v >= max(Q[4096], 1)
+    const double Lmax = 32.0 - std::log2((double)std::max<uint64_t>(Q[4096], 1)) + 1e-6;
     const double err_log = std::ldexp(1.0, -24) / std::log(2.0) + std::ldexp(1.0, -21) * Lmax + std::ldexp(1.0, -22);
     const double err_t = err_log / l * (1.0 + std::ldexp(1.0, -20)) + 4097.0 * std::ldexp(1.0, -23);
     f.invlog2q = (float)(-1.0 / l);
