@@ -7,7 +7,7 @@ writes all 2762 bit-packed rows for 2^24 shots, inputs (the compiled program)
 already resident in HBM.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
-                    [--workload c2|c1|c3|c3fp64|c4|c4fp64|c5|c5fp64|c5k16]
+                    [--workload c2|c1|c3|c3fp64|c4|c4fp64|c5|c5fp64|c5k16|post]
 
 Prints one JSON line.  `roofline` prices the dominant kernel against HBM
 bandwidth (record bytes written per launch / average launch time, measured
@@ -186,6 +186,54 @@ def run(args):
                                         "programs": len(errs)}
         circ, seed = ws[0].circuit, ws[0].seed
         sample_words = list(range(16))
+    elif wl == "post":
+        # detector postselection with the aggregate-count output: a step is one call that returns the
+        # discarded / logical-error flags and their counts for every shot; rejected shots stop their
+        # dense work at the rejecting detector
+        w = configs.postselect()
+        prec = "fp32"
+        prog = S.Program(w.circuit)
+        info = prog.info()
+        tps = prog.autotune(prec)
+        words = (w.shots + 63) // 64
+        post = list(range(prog.n_det))
+        tps_counts = prog.autotune_counts(post, precision=prec)  # launch configuration, outside the timing
+        flags = torch.empty((2, words), dtype=torch.int64, device="cuda")
+        counts = torch.zeros(2, dtype=torch.int64, device="cuda")
+
+        def step():
+            prog.sample_counts_into(flags, counts, w.shots, w.seed, post=post, precision=prec,
+                                    stream=stream.cuda_stream)
+
+        ms_step, ms_kernel, wall = _time_launches(step, args.steps, args.warmup, stream)
+        value = w.shots / (ms_step / 1e3)
+        counts.zero_()
+        step()
+        n_disc, n_log = (int(x) for x in counts.cpu())
+        out = torch.empty((prog.n_rows, words), dtype=torch.int64, device="cuda")
+
+        def records():
+            prog.sample_into(out, w.shots, w.seed, precision=prec, stream=stream.cuda_stream)
+
+        ms_rec, ms_rec_kernel, _ = _time_launches(records, max(2, args.steps // 2), 1, stream)
+        del out
+        extra["discarded_fraction"] = round(n_disc / w.shots, 5)
+        extra["logical_errors_per_kept_shot"] = round(n_log / max(1, w.shots - n_disc), 6)
+        extra["full_records"] = {"shots_per_s": round(w.shots / (ms_rec / 1e3), 1), "ms_per_step": round(ms_rec, 4)}
+        extra["counts_over_full_records"] = round(ms_rec / ms_step, 3)
+        # the full dense work of every shot, priced on the records launch, which does all of it
+        flops = info["dense_flops_per_shot"] * w.shots
+        achieved = flops / (ms_rec_kernel / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "active_kernel (full-records launch)", "flops_per_launch": flops}
+        dtype = "f32"
+        config = {"workload": w.name, "shots": w.shots, "rows": prog.n_rows, "k_max": info["k_max"],
+                  "precision": prec, "threads_per_shot": tps_counts, "threads_per_shot_full_records": tps,
+                  "postselected_detectors": len(post),
+                  "output": "per-shot discarded / logical-error flags + counts"}
+        circ, seed = w.circuit, w.seed
+        sample_words = [int(i * words / 16) for i in range(16)]
     else:
         raise SystemExit(f"unknown workload {wl}")
 

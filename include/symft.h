@@ -185,6 +185,55 @@ symft_status symft_sample_batch(const symft_program *const *progs, const uint64_
                                 uint64_t *const *records_out, size_t n, uint32_t precision, uint32_t graph,
                                 void *stream);
 
+/* Aggregate-count options (paper Sec. 6: detector postselection and the
+ * aggregate-count interface). */
+typedef struct {
+    uint64_t shot_offset;          /* global index of the first shot; must be a multiple of 64 */
+    uint32_t precision;            /* as in symft_sample_opts */
+    uint32_t n_post;               /* entries in post */
+    const uint32_t *post;          /* host, [n_post]: detector indices (0-based, circuit order); a shot in which
+                                      any of them is 1 is discarded.  Repeats are allowed.  NULL if n_post = 0 */
+    const uint8_t *obs_expected;   /* host, [n_observables] values 0/1, or NULL for all 0: a kept shot has a
+                                      logical error when some observable differs from its expected value */
+    uint32_t threads_per_shot;     /* programs with a dense active vector: 0 = automatic (the choice of
+                                      symft_autotune_counts for this program, postselection set and precision
+                                      if it has run; else one shot group per workgroup from peak width 8 on,
+                                      so a workgroup leaves a rejected shot at once, and the record path's
+                                      choice below); otherwise 4 .. 256, a power of two (peak width >= 13
+                                      always uses 1024).  Flags do not depend on it */
+    uint32_t reserved;             /* 0 */
+} symft_count_opts;
+
+/* Sample `shots` shots and report, per shot, only a discarded flag and a
+ * logical-error flag (paper Sec. 6): no record, detector or observable rows
+ * are written.
+ *   flags_out   device, 2 x ceil(shots/64) uint64 words, or NULL: row 0 bit s
+ *               = shot s discarded, row 1 bit s = shot s kept with a logical
+ *               error; padding bits are 0.
+ *   counts_out  device, 2 uint64, or NULL: the number of discarded shots and
+ *               the number of kept shots with a logical error are ADDED to
+ *               counts_out[0] and counts_out[1] (so calls over consecutive
+ *               shot ranges accumulate; zero it before the first).
+ * On programs with a dense active vector a postselected detector is checked
+ * right after the instruction that makes its last record, and a rejected
+ * shot does no further dense work.  Flags equal those computed from the full
+ * records of symft_sample_ex with the same seed and shot range.
+ * Errors: EINVAL (null program, detector index out of range, expected value
+ * not 0/1, bad offset), ECAPACITY, ENOMEM, EHIP.  shots == 0 is a no-op. */
+symft_status symft_sample_counts(const symft_program *p, const symft_count_opts *opts, uint64_t shots,
+                                 uint64_t seed, uint64_t *flags_out, uint64_t *counts_out, void *stream);
+
+/* Autotuner of the aggregate-count mode: times each threads-per-shot
+ * configuration (4 .. 256) that fits LDS on min(4096, ...) words of this
+ * program with opts' postselection set and precision (opts->threads_per_shot
+ * and shot_offset are ignored) and keeps the fastest for later
+ * symft_sample_counts calls with the same program, set and precision.
+ * Fewer shot groups per workgroup let rejected shots end sooner; more keep
+ * the lanes of small vectors busy.  Synchronous; allocates a scratch
+ * counter.  *tps_out (nullable) receives the choice (0 for pure-frame
+ * programs).  Errors as symft_sample_counts. */
+symft_status symft_autotune_counts(const symft_program *p, const symft_count_opts *opts, uint32_t *tps_out);
+
 /* Autotuner: times each threads-per-shot configuration (4 .. 256) of the
  * active-state kernel that fits LDS on 4096 words of this program and keeps the fastest
  * for the program's (peak active width, precision); later launches with that

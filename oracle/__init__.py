@@ -6,3 +6,4 @@ benchmark's CPU-baseline leg; never by the GPU library.  See
 ``dense.py`` (plain state-vector brute force for small circuits).
 """
 from .oracle import OracleCircuit, build, philox, rmeas_bit, active_u, gap_table, conjugate  # noqa: F401
+from .counts import count_flags  # noqa: F401

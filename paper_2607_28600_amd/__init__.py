@@ -61,6 +61,12 @@ class symft_sample_opts(C.Structure):
                 ("row_stride_words", C.c_uint64), ("frame_entry_cap", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+class symft_count_opts(C.Structure):
+    _fields_ = [("shot_offset", C.c_uint64), ("precision", C.c_uint32), ("n_post", C.c_uint32),
+                ("post", C.c_void_p), ("obs_expected", C.c_void_p), ("threads_per_shot", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
 _lib.symft_compile.restype = C.c_int32
 _lib.symft_compile.argtypes = [C.c_uint32, C.POINTER(symft_op), C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]
 _lib.symft_program_info.restype = C.c_int32
@@ -72,6 +78,11 @@ _lib.symft_sample.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p, C.
 _lib.symft_sample_ex.restype = C.c_int32
 _lib.symft_sample_ex.argtypes = [C.c_void_p, C.POINTER(symft_sample_opts), C.c_uint64, C.c_uint64, C.c_void_p,
                                  C.c_void_p]
+_lib.symft_sample_counts.restype = C.c_int32
+_lib.symft_sample_counts.argtypes = [C.c_void_p, C.POINTER(symft_count_opts), C.c_uint64, C.c_uint64, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]
+_lib.symft_autotune_counts.restype = C.c_int32
+_lib.symft_autotune_counts.argtypes = [C.c_void_p, C.POINTER(symft_count_opts), C.POINTER(C.c_uint32)]
 _lib.symft_sample_batch.restype = C.c_int32
 _lib.symft_sample_batch.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                     C.POINTER(C.c_void_p), C.c_size_t, C.c_uint32, C.c_uint32, C.c_void_p]
@@ -88,7 +99,7 @@ _lib.symft_program_free.argtypes = [C.c_void_p]
 _lib.symft_last_error.restype = C.c_char_p
 
 EXPORTED = ["symft_compile", "symft_program_info", "symft_program_plan", "symft_program_export",
-            "symft_sample", "symft_sample_ex",
+            "symft_sample", "symft_sample_ex", "symft_sample_counts", "symft_autotune_counts",
             "symft_sample_batch", "symft_autotune", "symft_probe", "symft_gap_check", "symft_program_free",
             "symft_last_error"]
 
@@ -156,6 +167,9 @@ class Program:
         info = self.info()
         self.n_rows = int(info["n_rows"])
         self.n_meas = int(info["n_measurements"])
+        self.n_rec = int(info["n_records"])
+        self.n_det = int(info["n_detectors"])
+        self.n_obs = int(info["n_observables"])
         self.k_max = int(info["k_max"])
 
     def __del__(self):
@@ -225,6 +239,50 @@ class Program:
             self.sample_into(out, shots, seed, shot_offset=shot_offset, precision=precision,
                              frame_entry_cap=frame_entry_cap)
         return out[: self.n_rows, :words]
+
+    def _count_opts(self, post, obs_expected, shot_offset, precision, threads_per_shot):
+        post = np.ascontiguousarray(np.asarray(post, dtype=np.uint32).reshape(-1))
+        exp = None
+        if obs_expected is not None:
+            exp = np.ascontiguousarray(np.asarray(obs_expected, dtype=np.uint8).reshape(-1))
+            if exp.size != self.n_obs:
+                raise ValueError("obs_expected needs one value per observable")
+        o = symft_count_opts(shot_offset, 0 if precision == "fp64" else 1, post.size,
+                             post.ctypes.data if post.size else None, exp.ctypes.data if exp is not None else None,
+                             threads_per_shot, 0)
+        return o, (post, exp)  # the arrays must outlive the call
+
+    def sample_counts_into(self, flags, counts, shots: int, seed: int, post=(), obs_expected=None,
+                           shot_offset: int = 0, precision: str = "fp64", stream=None,
+                           threads_per_shot: int = 0) -> None:
+        """Aggregate counts: flags (device [2, ceil(shots/64)] words, or None) receives the discarded and
+        logical-error flags; counts (device [2] uint64, or None) has the two totals added to it."""
+        import torch
+        o, keep = self._count_opts(post, obs_expected, shot_offset, precision, threads_per_shot)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        fp = None if flags is None else (flags.data_ptr() if hasattr(flags, "data_ptr") else int(flags))
+        cp = None if counts is None else (counts.data_ptr() if hasattr(counts, "data_ptr") else int(counts))
+        _check(_lib.symft_sample_counts(self._h, C.byref(o), shots, seed, C.c_void_p(fp), C.c_void_p(cp),
+                                        C.c_void_p(stream)), "symft_sample_counts")
+
+    def sample_counts(self, shots: int, seed: int, post=(), obs_expected=None, shot_offset: int = 0,
+                      precision: str = "fp64", device="cuda", threads_per_shot: int = 0):
+        """Returns (flags [2, ceil(shots/64)] int64 tensor, counts [2] int64 tensor) on the GPU."""
+        import torch
+        words = (shots + 63) // 64
+        flags = torch.zeros((2, max(words, 1)), dtype=torch.int64, device=device)
+        counts = torch.zeros(2, dtype=torch.int64, device=device)
+        self.sample_counts_into(flags, counts, shots, seed, post=post, obs_expected=obs_expected,
+                                shot_offset=shot_offset, precision=precision, threads_per_shot=threads_per_shot)
+        return flags[:, :words], counts
+
+    def autotune_counts(self, post=(), obs_expected=None, precision: str = "fp32") -> int:
+        """Run the aggregate-count autotuner for this program, postselection set and precision."""
+        o, keep = self._count_opts(post, obs_expected, 0, precision, 0)
+        v = C.c_uint32(0)
+        _check(_lib.symft_autotune_counts(self._h, C.byref(o), C.byref(v)), "symft_autotune_counts")
+        return int(v.value)
 
     def autotune(self, precision: str = "fp32") -> int:
         """Run the autotuner for this program's (k_max, precision); returns threads per shot."""

@@ -18,7 +18,7 @@ namespace symft {
 struct ActiveArgs;
 hipError_t launch_active(const ActiveArgs &A, bool fp64, uint32_t bs, uint32_t grid, hipStream_t st);
 size_t active_lds_bytes(const DevProg &P, uint32_t bs, uint32_t tps, bool lds_vec, bool fp64);
-int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds);
+int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds, bool cm);
 struct FrameArgs;
 hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st);
 struct BatchArgs;
@@ -90,14 +90,20 @@ struct symft_program {
     FrameSchedule F;
     std::mutex mu;
     std::map<int, void *> dev;  // device id -> uploaded blob
+    // aggregate-count tables (postselection bits, expected observables, check lists) by (device, content)
+    std::map<std::pair<int, std::vector<uint32_t>>, void *> count_dev;
+    // count-mode threads per shot chosen by symft_autotune_counts, by (tables, FP64)
+    std::map<std::pair<std::vector<uint32_t>, bool>, uint32_t> count_tune;
     ~symft_program() {
-        for (auto &kv : dev) {
+        auto drop = [](int d, void *ptr) {
             int cur = 0;
             hipGetDevice(&cur);
-            hipSetDevice(kv.first);
-            hipFree(kv.second);
+            hipSetDevice(d);
+            hipFree(ptr);
             hipSetDevice(cur);
-        }
+        };
+        for (auto &kv : dev) drop(kv.first, kv.second);
+        for (auto &kv : count_dev) drop(kv.first.first, kv.second);
     }
 };
 
@@ -380,10 +386,10 @@ ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, 
 static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, uint64_t word_begin, uint64_t n_words,
                                uint64_t shots, uint64_t *out, uint64_t stride, uint32_t sections, double *p0,
                                uint64_t probe_shot0, uint64_t probe_n, uint64_t seed, hipStream_t st,
-                               uint32_t force_tps = 0) {
+                               uint32_t force_tps = 0, const CountArgs *cnt = nullptr) {
     ActiveConfig c = choose_active(D, fp64, force_tps);
     if (c.lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "program tables exceed the LDS budget of the active kernel");
-    int per_cu = active_max_blocks_per_cu(fp64, c.bs, c.lds_vec, c.lds);
+    int per_cu = active_max_blocks_per_cu(fp64, c.bs, c.lds_vec, c.lds, cnt != nullptr);
     if (per_cu <= 0) per_cu = 1;
     uint64_t cap = (uint64_t)per_cu * (uint64_t)num_cus();
     if (!c.lds_vec) cap = std::min<uint64_t>(cap, (uint64_t)num_cus() * 2);
@@ -404,6 +410,7 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
     A.probe_n = probe_n;
     A.lds_vec = c.lds_vec ? 1 : 0;
     A.lds_bytes = (uint32_t)c.lds;
+    if (cnt) A.cnt = *cnt;
     void *scratch = nullptr;
     if (!c.lds_vec) {
         const uint32_t G = c.bs / c.tps;
@@ -420,7 +427,7 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
 
 static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_begin, uint64_t n_words, uint64_t shots,
                               uint64_t *out, uint64_t stride, uint32_t sections, uint64_t seed, uint32_t cap_override,
-                              hipStream_t st) {
+                              hipStream_t st, const CountArgs *cnt = nullptr) {
     size_t lds = frame_lds_bytes(D);
     if (lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "frame schedule exceeds the LDS budget");
     int per_cu = frame_max_blocks_per_cu(lds);
@@ -449,6 +456,7 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
     A.sections = sections;
     A.store16 = (((uintptr_t)out & 15u) == 0 && (stride & 1u) == 0) ? 1u : 0u;
     A.lds_bytes = (uint32_t)lds;
+    if (cnt) A.cnt = *cnt;
     hipError_t e = launch_frame(A, grid, st);
     hipFreeAsync(scratch, st);
     if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("frame kernel launch failed: ") + hipGetErrorString(e));
@@ -605,6 +613,184 @@ symft_status symft_sample_ex(const symft_program *pc, const symft_sample_opts *o
 
 symft_status symft_sample(const symft_program *p, uint64_t shots, uint64_t seed, uint64_t *records_out, void *stream) {
     return symft_sample_ex(p, nullptr, shots, seed, records_out, stream);
+}
+
+}  // extern "C"
+
+// Device tables of an aggregate-count call: postselection bits per detector,
+// expected-value bits per observable, and for each instruction the
+// postselected detectors whose last record it makes (checked right after it).
+// Uploaded once per (device, content) and kept with the program.
+static symft_status count_tables(symft_program *h, const symft_count_opts &o, CountArgs &C,
+                                 std::vector<uint32_t> *key_out = nullptr) {
+    const Program &P = h->P;
+    const size_t nd32 = std::max<size_t>(1, (P.n_det + 31) / 32), no32 = std::max<size_t>(1, (P.n_obs + 31) / 32);
+    std::vector<uint32_t> tab(nd32 + no32, 0u);
+    for (uint32_t i = 0; i < o.n_post; ++i) {
+        const uint32_t d = o.post[i];
+        if (d >= P.n_det) return set_err(SYMFT_EINVAL, "postselected detector index out of range");
+        tab[d >> 5] |= 1u << (d & 31);
+    }
+    for (uint64_t b = 0; b < P.n_obs && o.obs_expected; ++b) {
+        if (o.obs_expected[b] > 1) return set_err(SYMFT_EINVAL, "expected observable values must be 0 or 1");
+        if (o.obs_expected[b]) tab[nd32 + (b >> 5)] |= 1u << (b & 31);
+    }
+    const size_t ni = P.instrs.size();
+    std::vector<std::vector<uint32_t>> at(ni);
+    for (uint64_t d = 0; d < P.n_det; ++d) {
+        if (!((tab[d >> 5] >> (d & 31)) & 1u) || P.det_meas[d].empty()) continue;
+        int64_t last = -1;
+        for (uint32_t t : P.det_meas[d]) last = std::max<int64_t>(last, P.meas_instr[t]);
+        if (last < 0 || (size_t)last >= ni) return set_err(SYMFT_EINVAL, "detector record without an instruction");
+        at[(size_t)last].push_back((uint32_t)d);
+    }
+    const size_t o_off = tab.size();
+    tab.resize(o_off + ni + 1);
+    std::vector<uint32_t> dets;
+    for (size_t i = 0; i < ni; ++i) {
+        tab[o_off + i] = (uint32_t)dets.size();
+        dets.insert(dets.end(), at[i].begin(), at[i].end());
+    }
+    tab[o_off + ni] = (uint32_t)dets.size();
+    const size_t o_det = tab.size();
+    tab.insert(tab.end(), dets.begin(), dets.end());
+    tab.push_back(0u);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return set_err(SYMFT_EHIP, "hipGetDevice failed");
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        auto key = std::make_pair(dev, tab);
+        auto it = h->count_dev.find(key);
+        if (it != h->count_dev.end()) {
+            base = it->second;
+        } else {
+            if (hipMalloc(&base, tab.size() * 4) != hipSuccess) return set_err(SYMFT_ENOMEM, "count table allocation failed");
+            if (hipMemcpy(base, tab.data(), tab.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+                hipFree(base);
+                return set_err(SYMFT_EHIP, "count table upload failed");
+            }
+            h->count_dev[key] = base;
+        }
+    }
+    if (key_out) *key_out = tab;
+    const uint32_t *b = (const uint32_t *)base;
+    C.post = b;
+    C.obs_exp = b + nd32;
+    C.chk_off = b + o_off;
+    C.chk_det = b + o_det;
+    C.on = 1;
+    return SYMFT_OK;
+}
+
+extern "C" {
+
+symft_status symft_sample_counts(const symft_program *pc, const symft_count_opts *opts, uint64_t shots, uint64_t seed,
+                                 uint64_t *flags_out, uint64_t *counts_out, void *stream) {
+    symft_program *p = const_cast<symft_program *>(pc);
+    if (!p) return set_err(SYMFT_EINVAL, "NULL program");
+    symft_count_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (o.shot_offset % 64) return set_err(SYMFT_EINVAL, "shot_offset must be a multiple of 64");
+    if (o.precision > 1) return set_err(SYMFT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+    if (o.n_post && !o.post) return set_err(SYMFT_EINVAL, "post is NULL");
+    if (o.threads_per_shot && (o.threads_per_shot & (o.threads_per_shot - 1)))
+        return set_err(SYMFT_EINVAL, "threads_per_shot must be a power of two");
+    if (o.threads_per_shot && (o.threads_per_shot < 4 || (o.threads_per_shot > 256 && o.threads_per_shot != 1024)))
+        return set_err(SYMFT_EINVAL, "threads_per_shot must be 4 .. 256 (or 1024 at peak width >= 13)");
+    CountArgs C;
+    std::memset(&C, 0, sizeof(C));
+    std::vector<uint32_t> key;
+    symft_status rc = count_tables(p, o, C, &key);
+    if (rc) return rc;
+    if (shots == 0) return SYMFT_OK;
+    C.flags = flags_out;
+    C.counts = (unsigned long long *)counts_out;
+    DevProg D;
+    rc = device_prog(p, D);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t w0 = o.shot_offset / 64, n_words = (shots + 63) / 64;
+    if (D.fr_ok) return run_frame(p, D, w0, n_words, shots, nullptr, n_words, 0u, seed, 0, st, &C);
+    const bool fp64 = o.precision == 0;
+    if (D.k_max < 13 && o.threads_per_shot > 256)
+        return set_err(SYMFT_EINVAL, "threads_per_shot above 256 needs peak width >= 13");
+    uint32_t tps = o.threads_per_shot;
+    if (!tps) {
+        std::lock_guard<std::mutex> lk(p->mu);
+        auto it = p->count_tune.find({key, fp64});
+        if (it != p->count_tune.end()) tps = it->second;
+    }
+    // untuned: one shot group per workgroup once vectors are wide enough to keep 256 lanes busy
+    if (!tps && D.k_max >= 8 && D.k_max < 13 && active_lds_bytes(D, 256, 256, true, fp64) <= kLdsLimit) tps = 256;
+    if (D.k_max >= 13) tps = 0;
+    return run_active(p, D, fp64, w0, n_words, shots, nullptr, n_words, 0u, nullptr, 0, 0, seed, st, tps, &C);
+}
+
+symft_status symft_autotune_counts(const symft_program *pc, const symft_count_opts *opts, uint32_t *tps_out) {
+    symft_program *p = const_cast<symft_program *>(pc);
+    if (!p) return set_err(SYMFT_EINVAL, "NULL program");
+    symft_count_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (o.precision > 1) return set_err(SYMFT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+    if (o.n_post && !o.post) return set_err(SYMFT_EINVAL, "post is NULL");
+    CountArgs C;
+    std::memset(&C, 0, sizeof(C));
+    std::vector<uint32_t> key;
+    symft_status rc = count_tables(p, o, C, &key);
+    if (rc) return rc;
+    DevProg D;
+    rc = device_prog(p, D);
+    if (rc) return rc;
+    const bool fp64 = o.precision == 0;
+    if (D.fr_ok || D.k_max >= 13) {
+        if (tps_out) *tps_out = D.fr_ok ? 0 : 1024;
+        return SYMFT_OK;
+    }
+    const uint64_t words = 4096;
+    unsigned long long *cnt = nullptr;
+    if (hipMalloc(&cnt, 16) != hipSuccess) return set_err(SYMFT_ENOMEM, "autotune buffer allocation failed");
+    C.counts = cnt;
+    hipStream_t st;
+    if (hipStreamCreate(&st) != hipSuccess) {
+        hipFree(cnt);
+        return set_err(SYMFT_EHIP, "stream creation failed");
+    }
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best = 1e30f;
+    uint32_t best_tps = 0;
+    for (uint32_t tps : {4u, 8u, 16u, 32u, 64u, 128u, 256u}) {
+        if (((uint32_t)1 << D.k_max) < tps / 4 && tps > 4) continue;  // most lanes would idle
+        if (active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
+        float ms = 0;
+        for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
+            hipEventRecord(e0, st);
+            rc = run_active(p, D, fp64, 0, words, words * 64, nullptr, words, 0u, nullptr, 0, 0, 0x7E57ull, st, tps, &C);
+            hipEventRecord(e1, st);
+            hipEventSynchronize(e1);
+            hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (rc) break;
+        if (ms < best) {
+            best = ms;
+            best_tps = tps;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamDestroy(st);
+    hipFree(cnt);
+    if (rc) return rc;
+    if (best_tps) {
+        std::lock_guard<std::mutex> lk(p->mu);
+        p->count_tune[{key, fp64}] = best_tps;
+    }
+    if (tps_out) *tps_out = best_tps;
+    return SYMFT_OK;
 }
 
 symft_status symft_probe(const symft_program *pc, uint64_t shot_begin, uint32_t n_shots, uint64_t seed,

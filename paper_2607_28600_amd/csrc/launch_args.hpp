@@ -10,6 +10,20 @@ namespace symft {
 
 struct Program;
 
+// Aggregate-count mode (detector postselection and the per-shot discarded /
+// logical-error flags of the paper's Sec. 6): no record rows are written; a
+// shot is discarded when any postselected detector fires, and a kept shot has
+// a logical error when any observable differs from its expected value.
+struct CountArgs {
+    const uint32_t *post;         // bit d: detector d is postselected
+    const uint32_t *obs_exp;      // bit o: expected value of observable o
+    const uint32_t *chk_off;      // active kernel: n_instr + 1 offsets into chk_det
+    const uint32_t *chk_det;      // postselected detectors whose last record instruction i makes
+    uint64_t *flags;              // [2][n_words] (row 0 discarded, row 1 logical error) or nullptr
+    unsigned long long *counts;   // [2] discarded shots, kept shots with a logical error (added to), or nullptr
+    uint32_t on, pad;
+};
+
 struct ActiveArgs {
     DevProg P;
     uint64_t seed;
@@ -26,6 +40,7 @@ struct ActiveArgs {
     uint64_t probe_shot0, probe_n;
     uint32_t lds_vec;         // 1: vectors in LDS
     uint32_t lds_bytes;
+    CountArgs cnt;
 };
 
 // One item of the batched work queue: words [w0, w1) of call `call`.
@@ -58,6 +73,7 @@ struct FrameArgs {
     uint32_t store16;         // output rows may be stored 16 bytes at a time
     uint32_t lds_bytes;
     uint32_t pad;
+    CountArgs cnt;
 };
 
 // Pure-frame schedule (programs with peak active width 0); steps run in

@@ -13,6 +13,12 @@
 //      the shot.  The vector of each group lives in LDS or, when 2^k_max does
 //      not fit, in an HBM scratch slice of the workgroup;
 //   4. the word's records, detectors and observables are written.
+// Aggregate-count mode (detector postselection, paper Sec. 6) writes per shot
+// only a discarded flag and a logical-error flag.  A postselected detector is
+// evaluated right after the instruction that makes its last record; a shot
+// it rejects stops its dense work there (its group keeps to the workgroup's
+// barriers), and the stream is left early once every shot group in flight is
+// discarded.
 // Branch probabilities are reduced in the amplitude precision (FP32 with
 // compensated per-thread sums and pairwise wave trees, or FP64), and the
 // threshold Pr(m = 0) and the renormalisation scale are formed in FP64.
@@ -170,8 +176,9 @@ __device__ __forceinline__ void kahan_add(T &s, T &c, T v) {
 
 // Words [wi_begin, wi_end) (step wi_step, call-relative) of the call described
 // by A, run by this workgroup.  `slice` picks the HBM vector slice when the
-// vectors do not fit LDS.
-template <typename T, int BS, bool LDSV>
+// vectors do not fit LDS.  CM: aggregate-count mode (A.cnt), compiled apart
+// so that the record path carries none of its state.
+template <typename T, int BS, bool LDSV, bool CM>
 __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t wi_begin, uint64_t wi_end, uint64_t wi_step,
                                  uint32_t slice, unsigned char *smem) {
     using V = typename C2<T>::type;
@@ -183,8 +190,8 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
     // LDS carve-up
     unsigned long long *exo = (unsigned long long *)smem;                       // n_instr
     unsigned long long *recw = exo + P.n_instr;                                  // n_rec
-    uint64_t *tmp = (uint64_t *)(recw + P.n_rec);                                // 16
-    T *red = (T *)(tmp + 16);                                                    // 2 * BS/64
+    uint64_t *tmp = (uint64_t *)(recw + P.n_rec);                                // 16 + 4 count words
+    T *red = (T *)(tmp + 20);                                                    // 2 * BS/64
     uint32_t *mbits = (uint32_t *)(red + 2 * (BS / 64) + 2);                     // G * mw
     // G * 2^kmax (LDS mode); offset from smem so the pointer stays in the LDS address space
     V *vec_lds = (V *)(smem + ((((unsigned char *)(mbits + G * mw) - smem) + 15) & ~(ptrdiff_t)15));
@@ -194,11 +201,27 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
     else vec = (V *)A.scratch + ((size_t)slice * G + g) * A.scratch_stride;
     uint32_t *mb = mbits + g * mw;
     const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
+    constexpr bool cm = CM;
+    // count mode: the word's discarded / logical-error flags, and the workgroup's totals
+    unsigned long long *fdisc = (unsigned long long *)&tmp[16], *flogic = (unsigned long long *)&tmp[17];
+    unsigned long long *tot = (unsigned long long *)&tmp[18];
+    // during the instruction stream (tmp[0..15] serve only the noise scan): three
+    // vote words and one discarded byte per shot group (G <= 64)
+    uint32_t *vote = (uint32_t *)tmp;
+    uint8_t *gdead = (uint8_t *)tmp + 16;
+    if (cm && threadIdx.x == 0) {
+        tot[0] = 0ull;
+        tot[1] = 0ull;
+    }
 
     for (uint64_t wi = wi_begin; wi < wi_end; wi += wi_step) {
         const uint64_t w = A.word_begin + wi;
         for (uint32_t i = threadIdx.x; i < P.n_instr; i += BS) exo[i] = 0;
         for (uint32_t i = threadIdx.x; i < P.n_rec; i += BS) recw[i] = 0;
+        if (cm && threadIdx.x == 0) {
+            *fdisc = 0ull;
+            *flogic = 0ull;
+        }
         __syncthreads();
         word_noise<BS>(P, A.seed, w, exo, tmp);
         for (uint32_t i = threadIdx.x; i < P.n_rm; i += BS) {
@@ -214,17 +237,24 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
             const uint64_t shot = w * 64 + (uint64_t)lane;
             for (uint32_t i = (uint32_t)r; i < mw; i += (uint32_t)tps) mb[i] = 0;
             if (r == 0) { vec[0].x = (T)1; vec[0].y = (T)0; }
+            bool dead = false;  // the shot was discarded by a postselected detector
+            uint32_t nchk = 0;  // checks done in this batch of shots
+            if (cm) {
+                if (r == 0) gdead[g] = 0;
+                if (threadIdx.x == 0) vote[0] = vote[1] = vote[2] = 0u;
+            }
             __syncthreads();
             for (uint32_t ii = 0; ii < P.n_instr; ++ii) {
                 const DevInstr I = P.instr[ii];
                 const uint32_t N = 1u << I.k_in;
+                const uint32_t Nw = dead ? 0u : N;  // amplitudes this group still works on
                 const int lam = (int)I.lam_c ^ (int)((exo[ii] >> lane) & 1ull) ^ causal_parity(P, I, mb, tps);
                 const T c = sizeof(T) == 8 ? (T)I.c : (T)I.cf;
                 const T s = sizeof(T) == 8 ? (T)I.s : (T)I.sf;
                 switch (I.kind) {
                 case 1: {  // PromoteRot: x0 <- c a_x, x1 <- -i (-1)^lam s a_x
                     const T ss = lam ? -s : s;
-                    for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
+                    for (uint32_t x = (uint32_t)r; x < Nw; x += (uint32_t)tps) {
                         V v = vec[x];
                         V hi;
                         hi.x = ss * v.y;
@@ -237,7 +267,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 }
                 case 2: {  // ActiveDiagRot: a_x *= c - i sigma s, sigma = (-1)^lam mu (-1)^(b.x)
                     const int neg = lam ^ (I.mu == 2 ? 1 : 0);
-                    for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
+                    for (uint32_t x = (uint32_t)r; x < Nw; x += (uint32_t)tps) {
                         const T sg = (neg ^ parity(I.b & x)) ? -s : s;
                         V v = vec[x];
                         V o;
@@ -250,7 +280,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 case 3: {  // ActivePairRot on pairs (x0, x0 ^ a), bit h of x0 = 0
                     // a'_x = c a_x - i (-1)^lam s mu (-1)^(b.(x^a)) a_(x^a); with mu = i^m:
                     // -i mu = i^(m+3)
-                    const uint32_t half = N >> 1;
+                    const uint32_t half = Nw >> 1;
                     const int e0 = (int)I.mu + 3 + 2 * lam;
                     for (uint32_t z = (uint32_t)r; z < half; z += (uint32_t)tps) {
                         const uint32_t x0 = insert_bit(z, I.h, 0), x1 = x0 ^ I.a;
@@ -297,14 +327,14 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                     T s0 = 0, s1 = 0, c0 = 0, c1 = 0;
                     const T rs2 = (T)0.70710678118654752440;
                     if (!pair) {
-                        for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
+                        for (uint32_t x = (uint32_t)r; x < Nw; x += (uint32_t)tps) {
                             V v = vec[x];
                             T m2 = v.x * v.x + v.y * v.y;
                             if (parity(I.b & x)) kahan_add(s1, c1, m2); else kahan_add(s0, c0, m2);
                         }
                     } else {
                         const int mc = (4 - (int)I.mu) & 3;  // conj(mu) = i^mc
-                        for (uint32_t z = (uint32_t)r; z < half; z += (uint32_t)tps) {
+                        for (uint32_t z = (uint32_t)r; z < (Nw >> 1); z += (uint32_t)tps) {
                             const uint32_t u0 = insert_bit(z, I.h, 0);
                             V a0 = vec[u0], a1 = vec[u0 ^ I.a];
                             const int q = (mc + 2 * parity(I.b & u0)) & 3;
@@ -342,7 +372,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const uint32_t z = z0 + (uint32_t)e * (uint32_t)tps + (uint32_t)r;
-                            if (z < half) {
+                            if (z < half && !dead) {
                                 if (!pair) {
                                     const uint32_t uu = insert_bit(z, I.h, (uint32_t)y);
                                     const uint32_t x = uu ^ ((uint32_t)parity(bl & uu) << I.h);
@@ -363,7 +393,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const uint32_t z = z0 + (uint32_t)e * (uint32_t)tps + (uint32_t)r;
-                            if (z < half) vec[z] = vals[e];
+                            if (z < half && !dead) vec[z] = vals[e];
                         }
                         __syncthreads();
                     }
@@ -371,10 +401,55 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 }
                 default: break;
                 }
+                // Postselected detectors whose last record this instruction made:
+                // the thread that wrote the group's outcome bits checks them and
+                // publishes the verdict through the barrier that ends the
+                // instruction.  Check c votes in word c % 3, and word (c + 2) % 3
+                // is cleared after it: that word was last read before this
+                // barrier and is next written after the following one.
+                const bool chk = cm && A.cnt.chk_off[ii] < A.cnt.chk_off[ii + 1];
+                if (chk && r == 0 && !dead) {
+                    uint32_t x = 0;  // some detector fired
+                    for (uint32_t q = A.cnt.chk_off[ii]; q < A.cnt.chk_off[ii + 1] && !x; ++q) {
+                        const uint32_t d = A.cnt.chk_det[q];
+                        for (uint32_t e = P.det_off[d]; e < P.det_off[d + 1]; ++e) {
+                            const uint32_t t = P.rec_meas[P.det_rows[e]];
+                            x ^= (mb[t >> 5] >> (t & 31)) & 1u;  // the parity of detector d
+                        }
+                    }
+                    if (x) gdead[g] = 1;
+                    else vote[nchk % 3] = 1u;
+                }
                 __syncthreads();
+                if (chk) {
+                    dead = gdead[g] != 0;
+                    // leave the stream once no group in flight has a live shot
+                    if (vote[nchk % 3] == 0u) break;
+                    if (threadIdx.x == 0) vote[(nchk + 2) % 3] = 0u;
+                    ++nchk;
+                }
             }
-            // visible records of this shot into the word's rows
-            if (shot - A.word_begin * 64 < A.shots) {
+            if (cm) {
+                // the shot's flags: discarded, or a logical error when an
+                // observable differs from its expected value
+                if (r == 0) {
+                    if (dead) {
+                        atomicOr(fdisc, 1ull << lane);
+                    } else {
+                        uint32_t le = 0;
+                        for (uint32_t b = 0; b < P.n_obs; ++b) {
+                            uint32_t x = (A.cnt.obs_exp[b >> 5] >> (b & 31)) & 1u;
+                            for (uint32_t q = P.obs_off[b]; q < P.obs_off[b + 1]; ++q) {
+                                const uint32_t t = P.rec_meas[P.obs_rows[q]];
+                                x ^= (mb[t >> 5] >> (t & 31)) & 1u;
+                            }
+                            le |= x;
+                        }
+                        if (le) atomicOr(flogic, 1ull << lane);
+                    }
+                }
+            } else if (shot - A.word_begin * 64 < A.shots) {
+                // visible records of this shot into the word's rows
                 for (uint32_t row = (uint32_t)r; row < P.n_rec; row += (uint32_t)tps) {
                     const uint32_t t = P.rec_meas[row];
                     if ((mb[t >> 5] >> (t & 31)) & 1u) atomicOr(&recw[row], 1ull << lane);
@@ -382,8 +457,23 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
             }
             __syncthreads();
         }
-        // write rows: records, detectors, observables
         const uint64_t col = wi;
+        if (cm) {
+            if (threadIdx.x == 0) {
+                const uint64_t s0 = wi * 64;
+                const unsigned long long m = s0 + 64 <= A.shots ? ~0ull : (1ull << (A.shots - s0)) - 1ull;
+                const unsigned long long d = *fdisc & m, l = *flogic & ~d & m;
+                if (A.cnt.flags) {
+                    A.cnt.flags[col] = d;
+                    A.cnt.flags[A.n_words + col] = l;
+                }
+                tot[0] += (unsigned long long)__popcll(d);
+                tot[1] += (unsigned long long)__popcll(l);
+            }
+            __syncthreads();
+            continue;
+        }
+        // write rows: records, detectors, observables
         if (A.sections & 1u)
             for (uint32_t row = threadIdx.x; row < P.n_rec; row += BS) A.out[(uint64_t)row * A.row_stride + col] = recw[row];
         if (A.sections & 2u)
@@ -400,12 +490,16 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
             }
         __syncthreads();
     }
+    if (cm && A.cnt.counts && threadIdx.x == 0) {
+        if (tot[0]) atomicAdd(&A.cnt.counts[0], tot[0]);
+        if (tot[1]) atomicAdd(&A.cnt.counts[1], tot[1]);
+    }
 }
 
-template <typename T, int BS, bool LDSV>
+template <typename T, int BS, bool LDSV, bool CM>
 __global__ void __launch_bounds__(BS) active_kernel(ActiveArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
-    run_active_words<T, BS, LDSV>(A, blockIdx.x, A.n_words, gridDim.x, blockIdx.x, smem);
+    run_active_words<T, BS, LDSV, CM>(A, blockIdx.x, A.n_words, gridDim.x, blockIdx.x, smem);
 }
 
 // Persistent work queue over (program, word range) items: every workgroup
@@ -422,16 +516,16 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs B) {
         __syncthreads();
         if (idx >= B.n_items) break;
         const BatchItem it = B.items[idx];
-        run_active_words<T, BS, true>(B.calls[it.call], it.w0, it.w1, 1, blockIdx.x, smem);
+        run_active_words<T, BS, true, false>(B.calls[it.call], it.w0, it.w1, 1, blockIdx.x, smem);
     }
 }
 
 __global__ void reset_counter_kernel(uint32_t *counter) { counter[threadIdx.x] = 0u; }
 
 // ---------------------------------------------------------------- host ----
-template <typename T, int BS, bool LDSV>
+template <typename T, int BS, bool LDSV, bool CM>
 static hipError_t launch_one(const ActiveArgs &A, uint32_t grid, hipStream_t st) {
-    auto kfn = active_kernel<T, BS, LDSV>;
+    auto kfn = active_kernel<T, BS, LDSV, CM>;
     hipError_t e = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kfn, dim3(grid), dim3(BS), A.lds_bytes, st, A);
@@ -441,26 +535,45 @@ static hipError_t launch_one(const ActiveArgs &A, uint32_t grid, hipStream_t st)
 size_t active_lds_bytes(const DevProg &P, uint32_t bs, uint32_t tps, bool lds_vec, bool fp64) {
     const uint32_t G = bs / tps;
     const uint32_t mw = (P.n_meas + 31) / 32;
-    size_t b = 8ull * P.n_instr + 8ull * P.n_rec + 8 * 16 + (fp64 ? 8 : 4) * (2 * (bs / 64) + 2) + 4ull * G * mw;
+    size_t b = 8ull * P.n_instr + 8ull * P.n_rec + 8 * 20 + (fp64 ? 8 : 4) * (2 * (bs / 64) + 2) + 4ull * G * mw;
     b = (b + 15) & ~(size_t)15;
     if (lds_vec) b += (size_t)G * ((size_t)1 << P.k_max) * (fp64 ? 16 : 8);
     return b;
 }
 
-template <typename T, int BS, bool LDSV>
+template <typename T, int BS, bool LDSV, bool CM>
 static int blocks_per_cu(size_t lds) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, active_kernel<T, BS, LDSV>, BS, lds) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, active_kernel<T, BS, LDSV, CM>, BS, lds) != hipSuccess) return 1;
     return nb;
 }
 
-int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds) {
+// The instantiation for (precision, block size, vector residency, count mode).
+template <template <typename, int, bool, bool> class F, typename... Args>
+static auto dispatch(bool fp64, uint32_t bs, bool lds_vec, bool cm, Args... args) {
+#define SYMFT_PICK(T, B)                                                                             \
+    return lds_vec ? (cm ? F<T, B, true, true>::run(args...) : F<T, B, true, false>::run(args...))  \
+                   : (cm ? F<T, B, false, true>::run(args...) : F<T, B, false, false>::run(args...))
     if (fp64) {
-        if (bs == 1024) return lds_vec ? blocks_per_cu<double, 1024, true>(lds) : blocks_per_cu<double, 1024, false>(lds);
-        return lds_vec ? blocks_per_cu<double, 256, true>(lds) : blocks_per_cu<double, 256, false>(lds);
+        if (bs == 1024) SYMFT_PICK(double, 1024);
+        SYMFT_PICK(double, 256);
     }
-    if (bs == 1024) return lds_vec ? blocks_per_cu<float, 1024, true>(lds) : blocks_per_cu<float, 1024, false>(lds);
-    return lds_vec ? blocks_per_cu<float, 256, true>(lds) : blocks_per_cu<float, 256, false>(lds);
+    if (bs == 1024) SYMFT_PICK(float, 1024);
+    SYMFT_PICK(float, 256);
+#undef SYMFT_PICK
+}
+
+template <typename T, int BS, bool LDSV, bool CM>
+struct LaunchOne {
+    static hipError_t run(const ActiveArgs &A, uint32_t grid, hipStream_t st) { return launch_one<T, BS, LDSV, CM>(A, grid, st); }
+};
+template <typename T, int BS, bool LDSV, bool CM>
+struct BlocksPerCu {
+    static int run(size_t lds) { return blocks_per_cu<T, BS, LDSV, CM>(lds); }
+};
+
+int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds, bool cm) {
+    return dispatch<BlocksPerCu>(fp64, bs, lds_vec, cm, lds);
 }
 
 template <typename T>
@@ -485,12 +598,7 @@ int batch_max_blocks_per_cu(bool fp64, size_t lds) {
 }
 
 hipError_t launch_active(const ActiveArgs &A, bool fp64, uint32_t bs, uint32_t grid, hipStream_t st) {
-    if (fp64) {
-        if (bs == 1024) return A.lds_vec ? launch_one<double, 1024, true>(A, grid, st) : launch_one<double, 1024, false>(A, grid, st);
-        return A.lds_vec ? launch_one<double, 256, true>(A, grid, st) : launch_one<double, 256, false>(A, grid, st);
-    }
-    if (bs == 1024) return A.lds_vec ? launch_one<float, 1024, true>(A, grid, st) : launch_one<float, 1024, false>(A, grid, st);
-    return A.lds_vec ? launch_one<float, 256, true>(A, grid, st) : launch_one<float, 256, false>(A, grid, st);
+    return dispatch<LaunchOne>(fp64, bs, A.lds_vec != 0, A.cnt.on != 0, A, grid, st);
 }
 
 }  // namespace symft

@@ -20,6 +20,10 @@
 // A (word, class) stream with more entries than its capacity (8 standard
 // deviations above the mean) is instead walked afresh at every NOISE step
 // and applied at once, so records never depend on the capacity.
+// Aggregate-count mode (paper Sec. 6) writes no rows: EMIT ORs postselected
+// detectors and (expected-value-corrected) observables into per-word flag
+// words, and each tile ends by writing its discarded / logical-error flags.
+// A word's 64 shots run bit-parallel, so a discarded shot cannot stop early.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -320,7 +324,7 @@ __device__ __forceinline__ unsigned long long rm_word(uint32_t t, uint64_t w, ui
 // is not written) and XOR-ed into the successors' slots.
 __device__ __forceinline__ void emit_pair(const DevProg &P, const FrameArgs &A, uint4 ra, uint4 rb, uint32_t q,
                                           uint64_t wt, unsigned long long *slots, unsigned long long *stg,
-                                          uint32_t *rows, uint32_t k0, uint32_t k1) {
+                                          uint32_t *rows, unsigned long long *fl, uint32_t k0, uint32_t k1) {
     const uint32_t vi = q >> 3, wl = 2 * (q & 7u);
     const uint32_t flags = ra.x >> 24;
     unsigned long long v0 = (flags & 1u) ? ~0ull : 0ull, v1 = v0;
@@ -336,6 +340,23 @@ __device__ __forceinline__ void emit_pair(const DevProg &P, const FrameArgs &A, 
         const uint64_t w = A.word_begin + wt + wl;
         v0 ^= rm_word(ra.z, w, k0, k1);
         v1 ^= rm_word(ra.z, w + 1, k0, k1);
+    }
+    if (A.cnt.on) {
+        // aggregate counts: a postselected detector ORs into the discarded
+        // flags, an observable (XOR its expected value) into the logical ones
+        const uint32_t sec = (flags >> 4) & 3u;
+        if (sec == 2u) {
+            const uint32_t d = ra.y - P.n_rec;
+            if ((A.cnt.post[d >> 5] >> (d & 31u)) & 1u) {
+                atomicOr(&fl[wl], v0);
+                atomicOr(&fl[wl + 1], v1);
+            }
+        } else if (sec == 3u) {
+            const uint32_t o = ra.y - P.n_rec - P.n_det;
+            const unsigned long long x = ((A.cnt.obs_exp[o >> 5] >> (o & 31u)) & 1u) ? ~0ull : 0ull;
+            atomicOr(&fl[TW + wl], v0 ^ x);
+            atomicOr(&fl[TW + wl + 1], v1 ^ x);
+        }
     }
     *(ulonglong2 *)&stg[vi * TW + wl] = make_ulonglong2(v0, v1);
     if (wl == 0) {
@@ -372,7 +393,8 @@ constexpr uint32_t STG_WORDS = FR_LEVEL_MAX * TW;  // staged u64 per buffer
 constexpr uint32_t WPW = TW / NWC;                 // words per wave in NOISE steps
 
 // Workgroup: 8 waves.  LDS: slots [NS][TW] u64 | stream states [TW][NC] |
-// entry cursors and counts [TW][NC] | overflow flags [TW] | one region used by
+// entry cursors and counts [TW][NC] | overflow flags [TW] | aggregate-count
+// flags [2][TW] u64 (discarded, logical error) | one region used by
 // phase G as walk positions [NWC][256] and by phase S as two staging buffers
 // ([FR_LEVEL_MAX][TW] u64 + [FR_LEVEL_MAX] rows).
 // Phase S orders each step so that nothing it waits for was issued in the
@@ -396,7 +418,8 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
     // offsets from smem itself keep the pointers in the LDS address space (an
     // integer round trip would turn every access into a flat one, which also
     // waits on vector-memory counters)
-    unsigned char *region = smem + ((((unsigned char *)(ovf + TW) - smem) + 15) & ~(ptrdiff_t)15);
+    unsigned long long *fl = (unsigned long long *)(smem + ((((unsigned char *)(ovf + TW) - smem) + 15) & ~(ptrdiff_t)15));
+    unsigned char *region = (unsigned char *)(fl + 2 * TW);
     uint32_t *tmp = (uint32_t *)region + (size_t)wave * 256;
     unsigned long long *stg = (unsigned long long *)region;         // [2][STG_WORDS]
     uint32_t *rows = (uint32_t *)(stg + 2 * STG_WORDS);              // [2][FR_LEVEL_MAX]
@@ -405,6 +428,8 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
     uint64_t *scr = A.scratch + (size_t)blockIdx.x * (TW * A.word_entries + NWC * 128);
     uint32_t *gtmp = (uint32_t *)(scr + (size_t)TW * A.word_entries) + (size_t)wave * 256;  // fallback walks
     for (uint32_t i = tid; i < NS * TW; i += NWC * 64) slots[i] = 0ull;
+    if (tid < 2 * TW) fl[tid] = 0ull;
+    unsigned long long n_disc = 0, n_logic = 0;  // aggregate counts of this workgroup (threads < TW)
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t wt = tile * TW;
         for (uint32_t i = tid; i < TW * NC; i += NWC * 64) {
@@ -524,7 +549,7 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
                 fetch_records(r[5], r[6]);
                 if (tid < n * (TW / 2))
                     emit_pair(P, A, ra, rb, tid, wt, slots, stg + (size_t)(e_idx & 1u) * STG_WORDS,
-                              rows + (e_idx & 1u) * FR_LEVEL_MAX, k0, k1);
+                              rows + (e_idx & 1u) * FR_LEVEL_MAX, fl, k0, k1);
                 pend_n = n;
                 ++e_idx;
             } else {
@@ -536,6 +561,33 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
             store_chunk(A, stg + (size_t)((e_idx - 1) & 1u) * STG_WORDS, rows + ((e_idx - 1) & 1u) * FR_LEVEL_MAX,
                         tid, wt);
         __syncthreads();
+        if (A.cnt.on && tid < TW) {
+            // the tile's flags: kept shots only can have a logical error; bits past the shot count are 0
+            const uint64_t wi = wt + tid;
+            if (wi < A.n_words) {
+                const unsigned long long m = word_mask(wi, A.shots);
+                const unsigned long long d = fl[tid] & m, l = fl[TW + tid] & ~d & m;
+                if (A.cnt.flags) {
+                    A.cnt.flags[wi] = d;
+                    A.cnt.flags[A.n_words + wi] = l;
+                }
+                n_disc += (unsigned long long)__popcll(d);
+                n_logic += (unsigned long long)__popcll(l);
+            }
+            fl[tid] = 0ull;
+            fl[TW + tid] = 0ull;
+        }
+    }
+    if (A.cnt.on && A.cnt.counts && wave == 0) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            n_disc += __shfl_xor(n_disc, off, 64);
+            n_logic += __shfl_xor(n_logic, off, 64);
+        }
+        if (lane == 0) {
+            if (n_disc) atomicAdd(&A.cnt.counts[0], n_disc);
+            if (n_logic) atomicAdd(&A.cnt.counts[1], n_logic);
+        }
     }
 }
 
@@ -549,10 +601,11 @@ __global__ void gap_check_kernel(GapFast F, const uint64_t *Q, const uint32_t *v
 }
 
 size_t frame_lds_bytes(const DevProg &P) {
-    // slots | stream states | cursors and counts | overflow flags | (walk positions or staging)
+    // slots | stream states | cursors and counts | overflow flags | count flags | (walk positions or staging)
     const size_t head = (size_t)P.fr_n_slots * TW * 8 + (size_t)TW * P.n_cls * (sizeof(FrWord) + 8) + TW * 4;
+    const size_t flags = 2 * TW * 8;
     const size_t region = std::max<size_t>((size_t)NWC * 256 * 4, 2 * (STG_WORDS * 8 + FR_LEVEL_MAX * 4));
-    return ((head + 15) & ~(size_t)15) + region;
+    return ((head + 15) & ~(size_t)15) + flags + region;
 }
 
 // Scratch per workgroup, in u64: flip entries of 16 words plus the fallback walks' positions.

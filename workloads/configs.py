@@ -6,6 +6,8 @@ C3  near-Clifford n=20, 400 layers, 24 pi/8 rotations, 60 measurements, p=5e-4, 
 C4  128 near-Clifford programs, n = 12..40, peak widths 1..12, shots log-uniform 2^10..2^18
 C5  near-Clifford n=48, 400 layers, 80 rotations, 200 measurements, p=5e-4, peak width 14 (and a
     variant peaking at 16), 2^16 shots
+POST  coherent-noise surface code d=5, 5 rounds, exp(-i 0.1 Z / 2) on every data qubit each round,
+    p=1e-3, peak width 12, every detector postselected (aggregate counts), 2^18 shots
 
 Sampling seeds are 0x5EED0000 + config number.
 """
@@ -61,6 +63,11 @@ def c4() -> List[Workload]:
 def c5(k: int = 14, shots: int = 1 << 16) -> Workload:
     key = "c5_k14" if k == 14 else "c5_k16"
     return Workload(f"near_clifford_n48_k{k}", nc.c5(_seeds()[key], k), shots, 0x5EED0005)
+
+
+def postselect() -> Workload:
+    return Workload("coherent_surface_d5_r5_theta0.1_postselect", rotated_memory_z(5, 5, 1e-3, coherent=0.1),
+                    1 << 18, 0x5EED0006)
 
 
 def small_surface() -> Tuple[Circuit, int]:

@@ -46,7 +46,9 @@ def _corners(kind: str, r: int, c: int):
     return (nw, ne, sw, se) if kind == "X" else (nw, sw, ne, se)
 
 
-def rotated_memory_z(d: int, rounds: int, p: float) -> Circuit:
+def rotated_memory_z(d: int, rounds: int, p: float, coherent: float = 0.0) -> Circuit:
+    """`coherent` != 0 adds a coherent error exp(-i coherent Z / 2) on every data qubit at the start of every
+    round (the coherent-noise surface-code family), which makes the circuit near-Clifford."""
     data, checks, anc = layout(d)
     n = 2 * d * d - 1
     circ = Circuit(n)
@@ -77,6 +79,9 @@ def rotated_memory_z(d: int, rounds: int, p: float) -> Circuit:
     circ.append("X_ERROR", all_q, arg=p)
     rec_of: Dict[int, List[int]] = {a: [] for a in aq}
     for rnd in range(rounds):
+        if coherent:
+            for q in dq:
+                circ.rot([(q, "Z")], coherent)
         circ.append("H", xa)
         circ.append("DEPOLARIZE1", xa, arg=p)
         circ.append("DEPOLARIZE1", idle(xa), arg=p)
