@@ -644,16 +644,23 @@ static symft_status count_tables(symft_program *h, const symft_count_opts &o, Co
         if (last < 0 || (size_t)last >= ni) return set_err(SYMFT_EINVAL, "detector record without an instruction");
         at[(size_t)last].push_back((uint32_t)d);
     }
+    // chk_off [ni + 1] -> entries; chk_mo [entries + 1] -> measurement ids
     const size_t o_off = tab.size();
     tab.resize(o_off + ni + 1);
-    std::vector<uint32_t> dets;
+    std::vector<uint32_t> mo, ms;
     for (size_t i = 0; i < ni; ++i) {
-        tab[o_off + i] = (uint32_t)dets.size();
-        dets.insert(dets.end(), at[i].begin(), at[i].end());
+        tab[o_off + i] = (uint32_t)mo.size();
+        for (uint32_t d : at[i]) {
+            mo.push_back((uint32_t)ms.size());
+            ms.insert(ms.end(), P.det_meas[d].begin(), P.det_meas[d].end());
+        }
     }
-    tab[o_off + ni] = (uint32_t)dets.size();
-    const size_t o_det = tab.size();
-    tab.insert(tab.end(), dets.begin(), dets.end());
+    tab[o_off + ni] = (uint32_t)mo.size();
+    mo.push_back((uint32_t)ms.size());
+    const size_t o_mo = tab.size();
+    tab.insert(tab.end(), mo.begin(), mo.end());
+    const size_t o_ms = tab.size();
+    tab.insert(tab.end(), ms.begin(), ms.end());
     tab.push_back(0u);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return set_err(SYMFT_EHIP, "hipGetDevice failed");
@@ -678,7 +685,8 @@ static symft_status count_tables(symft_program *h, const symft_count_opts &o, Co
     C.post = b;
     C.obs_exp = b + nd32;
     C.chk_off = b + o_off;
-    C.chk_det = b + o_det;
+    C.chk_mo = b + o_mo;
+    C.chk_meas = b + o_ms;
     C.on = 1;
     return SYMFT_OK;
 }

@@ -6,7 +6,7 @@
 
 namespace symft {
 
-// One sampling instruction (48 bytes).  cos/sin(theta/2) are computed once on
+// One sampling instruction (56 bytes).  cos/sin(theta/2) are computed once on
 // the host in FP64; the FP32 copies are rounded from them, so the kernels
 // evaluate no transcendental function.
 struct DevInstr {

@@ -17,8 +17,10 @@ struct Program;
 struct CountArgs {
     const uint32_t *post;         // bit d: detector d is postselected
     const uint32_t *obs_exp;      // bit o: expected value of observable o
-    const uint32_t *chk_off;      // active kernel: n_instr + 1 offsets into chk_det
-    const uint32_t *chk_det;      // postselected detectors whose last record instruction i makes
+    const uint32_t *chk_off;      // active kernel: n_instr + 1 offsets into chk_mo
+    const uint32_t *chk_mo;       // per postselected detector whose last record instruction i makes: the
+                                  // offset of its measurement ids in chk_meas (one more entry at the end)
+    const uint32_t *chk_meas;
     uint64_t *flags;              // [2][n_words] (row 0 discarded, row 1 logical error) or nullptr
     unsigned long long *counts;   // [2] discarded shots, kept shots with a logical error (added to), or nullptr
     uint32_t on, pad;

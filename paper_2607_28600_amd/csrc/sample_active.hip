@@ -42,6 +42,33 @@ __device__ __forceinline__ uint32_t insert_bit(uint32_t z, uint32_t h, uint32_t 
 
 __device__ __forceinline__ int parity(uint32_t v) { return __popc(v) & 1; }
 
+// Instruction descriptors are read with a wave-uniform index; through the
+// constant address space they come by scalar loads (no vector-memory wait, no
+// lane-to-scalar moves).
+__device__ __forceinline__ DevInstr load_instr(const DevInstr *p, uint32_t i) {
+    const __attribute__((address_space(4))) uint32_t *q = (const __attribute__((address_space(4))) uint32_t *)(p + i);
+    DevInstr d;
+    const uint32_t w0 = q[0], w1 = q[1];
+    d.kind = (uint8_t)w0;
+    d.k_in = (uint8_t)(w0 >> 8);
+    d.h = (uint8_t)(w0 >> 16);
+    d.mu = (uint8_t)(w0 >> 24);
+    d.eta = (uint8_t)w1;
+    d.lam_c = (uint8_t)(w1 >> 8);
+    d.pad0 = d.pad1 = 0;
+    d.a = q[2];
+    d.b = q[3];
+    d.meas = (int32_t)q[4];
+    d.cm_off = q[5];
+    d.cm_len = q[6];
+    d.pad2 = 0;
+    d.c = __hiloint2double((int)q[9], (int)q[8]);
+    d.s = __hiloint2double((int)q[11], (int)q[10]);
+    d.cf = __uint_as_float(q[12]);
+    d.sf = __uint_as_float(q[13]);
+    return d;
+}
+
 // Block-wide exclusive scan of (a, b) pairs packed as 64-bit (a in low 32).
 template <int BS>
 __device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *tmp, uint64_t &total) {
@@ -148,13 +175,24 @@ __device__ __forceinline__ void group_sum2(T &s0, T &s1, int tps, T *red) {
     }
 }
 
-// Parity of the causal part of lambda for the shot of this group.
-__device__ __forceinline__ int causal_parity(const DevProg &P, const DevInstr &I, const uint32_t *mb, int tps) {
+// The causal measurement ref a lane of a shot group reads first (ref
+// threadIdx % min(tps, 64)).  (Fetching it, and the descriptor, an
+// instruction ahead costs more in register pressure than it hides.)
+__device__ __forceinline__ uint32_t first_cref(const DevProg &P, const DevInstr &I, int tps) {
+    const uint32_t unit = tps < 64 ? (uint32_t)tps : 64u;
+    const uint32_t r = threadIdx.x % unit;
+    return r < I.cm_len ? P.cmeas[I.cm_off + r] : 0u;
+}
+
+// Parity of the causal part of lambda for the shot of this group; t0 is the
+// lane's first ref (first_cref).
+__device__ __forceinline__ int causal_parity(const DevProg &P, const DevInstr &I, const uint32_t *mb, int tps,
+                                             uint32_t t0) {
     if (I.cm_len == 0) return 0;
     const int unit = tps < 64 ? tps : 64;
     const int r = (int)(threadIdx.x % unit);
-    int x = 0;
-    for (uint32_t j = (uint32_t)r; j < I.cm_len; j += (uint32_t)unit) {
+    int x = (uint32_t)r < I.cm_len ? (int)((mb[t0 >> 5] >> (t0 & 31)) & 1u) : 0;
+    for (uint32_t j = (uint32_t)(r + unit); j < I.cm_len; j += (uint32_t)unit) {
         uint32_t t = P.cmeas[I.cm_off + j];
         x ^= (int)((mb[t >> 5] >> (t & 31)) & 1u);
     }
@@ -190,8 +228,8 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
     // LDS carve-up
     unsigned long long *exo = (unsigned long long *)smem;                       // n_instr
     unsigned long long *recw = exo + P.n_instr;                                  // n_rec
-    uint64_t *tmp = (uint64_t *)(recw + P.n_rec);                                // 16 + 4 count words
-    T *red = (T *)(tmp + 20);                                                    // 2 * BS/64
+    uint64_t *tmp = (uint64_t *)(recw + P.n_rec);                                // 16 + 4 + 24 count words
+    T *red = (T *)(tmp + 44);                                                    // 2 * BS/64
     uint32_t *mbits = (uint32_t *)(red + 2 * (BS / 64) + 2);                     // G * mw
     // G * 2^kmax (LDS mode); offset from smem so the pointer stays in the LDS address space
     V *vec_lds = (V *)(smem + ((((unsigned char *)(mbits + G * mw) - smem) + 15) & ~(ptrdiff_t)15));
@@ -205,10 +243,8 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
     // count mode: the word's discarded / logical-error flags, and the workgroup's totals
     unsigned long long *fdisc = (unsigned long long *)&tmp[16], *flogic = (unsigned long long *)&tmp[17];
     unsigned long long *tot = (unsigned long long *)&tmp[18];
-    // during the instruction stream (tmp[0..15] serve only the noise scan): three
-    // vote words and one discarded byte per shot group (G <= 64)
-    uint32_t *vote = (uint32_t *)tmp;
-    uint8_t *gdead = (uint8_t *)tmp + 16;
+    // three rows of 64 verdict bytes, one byte per shot group (G <= 64)
+    uint8_t *gv = (uint8_t *)&tmp[20];
     if (cm && threadIdx.x == 0) {
         tot[0] = 0ull;
         tot[1] = 0ull;
@@ -232,6 +268,21 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
         }
         __syncthreads();
 
+        // Shot groups of at most 64 threads lie inside one wave and touch only
+        // their own vector and outcome bits, so with LDS vectors the batch loop
+        // needs no workgroup barrier: a wave's LDS accesses are performed in
+        // issue order, and a wave-scope fence keeps the compiler's order.  The
+        // waves then run their shots independently until the word's end.
+        const bool wsync = LDSV && tps <= 64;
+        auto gsync = [&]() {
+            if (wsync) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else {
+                __syncthreads();
+            }
+        };
         for (int base = 0; base < 64; base += G) {
             const int lane = base + g;
             const uint64_t shot = w * 64 + (uint64_t)lane;
@@ -239,18 +290,22 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
             if (r == 0) { vec[0].x = (T)1; vec[0].y = (T)0; }
             bool dead = false;  // the shot was discarded by a postselected detector
             uint32_t nchk = 0;  // checks done in this batch of shots
-            if (cm) {
-                if (r == 0) gdead[g] = 0;
-                if (threadIdx.x == 0) vote[0] = vote[1] = vote[2] = 0u;
+            if (cm && !wsync) {
+                // verdict rows start "live" for the G groups and "discarded" past them
+                for (uint32_t i = threadIdx.x; i < 3 * 64; i += BS) gv[i] = (i & 63u) < (uint32_t)G ? 0 : 1;
             }
-            __syncthreads();
+            gsync();
+            // the next instruction's descriptor and first causal ref are fetched
+            // while this one runs
             for (uint32_t ii = 0; ii < P.n_instr; ++ii) {
-                const DevInstr I = P.instr[ii];
+                const DevInstr I = load_instr(P.instr, ii);
+                const uint32_t cref = first_cref(P, I, tps);
                 const uint32_t N = 1u << I.k_in;
                 const uint32_t Nw = dead ? 0u : N;  // amplitudes this group still works on
-                const int lam = (int)I.lam_c ^ (int)((exo[ii] >> lane) & 1ull) ^ causal_parity(P, I, mb, tps);
+                const int lam = (int)I.lam_c ^ (int)((exo[ii] >> lane) & 1ull) ^ causal_parity(P, I, mb, tps, cref);
                 const T c = sizeof(T) == 8 ? (T)I.c : (T)I.cf;
                 const T s = sizeof(T) == 8 ? (T)I.s : (T)I.sf;
+                uint32_t mbit = 0;  // this instruction's outcome, known to every thread of the group
                 switch (I.kind) {
                 case 1: {  // PromoteRot: x0 <- c a_x, x1 <- -i (-1)^lam s a_x
                     const T ss = lam ? -s : s;
@@ -303,6 +358,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                     break;
                 }
                 case 4: {  // RandomMeas
+                    mbit = (uint32_t)(exo[ii] >> lane) & 1u;
                     if (r == 0) {
                         const uint32_t t = (uint32_t)I.meas;
                         if ((exo[ii] >> lane) & 1ull) mb[t >> 5] |= 1u << (t & 31);
@@ -311,6 +367,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                     break;
                 }
                 case 5: {  // DetMeas: m = lambda ^ eta (exo holds the noise part of lambda)
+                    mbit = (uint32_t)(lam ^ I.eta);
                     if (r == 0) {
                         const uint32_t t = (uint32_t)I.meas;
                         if (lam ^ I.eta) mb[t >> 5] |= 1u << (t & 31);
@@ -323,6 +380,9 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 case 7: {  // ActivePairMeas
                     const uint32_t half = N >> 1;
                     const bool pair = I.kind == 7;
+                    // the uniform draw first: it overlaps the branch sums
+                    const uint32_t t = (uint32_t)I.meas;
+                    const uint4 o = philox4x32_10(make_uint4(t, (uint32_t)shot, (uint32_t)(shot >> 32), 4u << 24), k0, k1);
                     // conj(mu) (-1)^(b.u0) for the pair case; diag: parity classes of b.x
                     T s0 = 0, s1 = 0, c0 = 0, c1 = 0;
                     const T rs2 = (T)0.70710678118654752440;
@@ -351,10 +411,9 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                     const int flip = pair ? lam : (lam ^ (int)I.eta);
                     const double S0 = (double)s0, S1 = (double)s1;
                     const double p0 = (flip ? S1 : S0) / (S0 + S1);
-                    const uint32_t t = (uint32_t)I.meas;
-                    uint4 o = philox4x32_10(make_uint4(t, (uint32_t)shot, (uint32_t)(shot >> 32), 4u << 24), k0, k1);
                     const double u = (double)(((uint64_t)o.x << 21) + (uint64_t)(o.y >> 11)) * 0x1p-53;
                     const int m = (u < p0) ? 0 : 1;
+                    mbit = (uint32_t)m;
                     const int y = m ^ flip;  // kept class
                     const double Sy = y ? S1 : S0;
                     const T scale = (T)(1.0 / sqrt(Sy > 0x1p-1000 ? Sy : 0x1p-1000));
@@ -389,43 +448,62 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                                 }
                             }
                         }
-                        __syncthreads();
+                        gsync();
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const uint32_t z = z0 + (uint32_t)e * (uint32_t)tps + (uint32_t)r;
                             if (z < half && !dead) vec[z] = vals[e];
                         }
-                        __syncthreads();
+                        gsync();
                     }
                     break;
                 }
                 default: break;
                 }
                 // Postselected detectors whose last record this instruction made:
-                // the thread that wrote the group's outcome bits checks them and
-                // publishes the verdict through the barrier that ends the
-                // instruction.  Check c votes in word c % 3, and word (c + 2) % 3
-                // is cleared after it: that word was last read before this
-                // barrier and is next written after the following one.
+                // the group's threads take one detector each; its parity comes
+                // from the group's earlier outcome bits and, for this
+                // instruction's own outcome, from the register every thread of
+                // the group holds.
                 const bool chk = cm && A.cnt.chk_off[ii] < A.cnt.chk_off[ii + 1];
-                if (chk && r == 0 && !dead) {
-                    uint32_t x = 0;  // some detector fired
-                    for (uint32_t q = A.cnt.chk_off[ii]; q < A.cnt.chk_off[ii + 1] && !x; ++q) {
-                        const uint32_t d = A.cnt.chk_det[q];
-                        for (uint32_t e = P.det_off[d]; e < P.det_off[d + 1]; ++e) {
-                            const uint32_t t = P.rec_meas[P.det_rows[e]];
-                            x ^= (mb[t >> 5] >> (t & 31)) & 1u;  // the parity of detector d
+                uint32_t fired = 0;
+                if (chk && !dead) {
+                    for (uint32_t q = A.cnt.chk_off[ii] + (uint32_t)r; q < A.cnt.chk_off[ii + 1]; q += (uint32_t)tps) {
+                        uint32_t x = 0;
+                        for (uint32_t e = A.cnt.chk_mo[q]; e < A.cnt.chk_mo[q + 1]; ++e) {
+                            const uint32_t t = A.cnt.chk_meas[e];
+                            x ^= t == (uint32_t)I.meas ? mbit : (mb[t >> 5] >> (t & 31)) & 1u;
                         }
+                        fired |= x;
                     }
-                    if (x) gdead[g] = 1;
-                    else vote[nchk % 3] = 1u;
                 }
+                if (wsync) {
+                    gsync();
+                    if (chk) {
+                        // the group's lanes are contiguous in the wave
+                        const uint64_t bal = __ballot(fired);
+                        const uint32_t sub = (threadIdx.x & 63u) & ~((uint32_t)tps - 1u);
+                        const uint64_t gm = (tps == 64 ? ~0ull : ((1ull << tps) - 1ull)) << sub;
+                        dead = dead || (bal & gm) != 0;
+                        // this wave leaves the stream once all its groups are discarded
+                        if (__ballot(!dead) == 0) break;
+                    }
+                    continue;
+                }
+                // Groups spanning waves: a verdict byte per group in row c % 3
+                // (check c of this batch), read back after the barrier that ends
+                // the instruction.  Row (c + 2) % 3 is cleared after it: its last
+                // reads precede this barrier, its next writes follow the next one.
+                uint8_t *row = gv + 64u * (nchk % 3u);
+                if (chk && (dead ? r == 0 : fired != 0)) row[g] = 1;
                 __syncthreads();
                 if (chk) {
-                    dead = gdead[g] != 0;
+                    dead = row[g] != 0;
                     // leave the stream once no group in flight has a live shot
-                    if (vote[nchk % 3] == 0u) break;
-                    if (threadIdx.x == 0) vote[(nchk + 2) % 3] = 0u;
+                    bool all = true;  // bytes past G read as discarded
+                    for (uint32_t i = 0; i < (uint32_t)G; i += 4u) all = all && *(const uint32_t *)(row + i) == 0x01010101u;
+                    if (all) break;
+                    if (threadIdx.x < 64u) gv[64u * ((nchk + 2u) % 3u) + threadIdx.x] = threadIdx.x < (uint32_t)G ? 0 : 1;
                     ++nchk;
                 }
             }
@@ -455,8 +533,9 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                     if ((mb[t >> 5] >> (t & 31)) & 1u) atomicOr(&recw[row], 1ull << lane);
                 }
             }
-            __syncthreads();
+            gsync();
         }
+        __syncthreads();
         const uint64_t col = wi;
         if (cm) {
             if (threadIdx.x == 0) {
@@ -535,7 +614,7 @@ static hipError_t launch_one(const ActiveArgs &A, uint32_t grid, hipStream_t st)
 size_t active_lds_bytes(const DevProg &P, uint32_t bs, uint32_t tps, bool lds_vec, bool fp64) {
     const uint32_t G = bs / tps;
     const uint32_t mw = (P.n_meas + 31) / 32;
-    size_t b = 8ull * P.n_instr + 8ull * P.n_rec + 8 * 20 + (fp64 ? 8 : 4) * (2 * (bs / 64) + 2) + 4ull * G * mw;
+    size_t b = 8ull * P.n_instr + 8ull * P.n_rec + 8 * 44 + (fp64 ? 8 : 4) * (2 * (bs / 64) + 2) + 4ull * G * mw;
     b = (b + 15) & ~(size_t)15;
     if (lds_vec) b += (size_t)G * ((size_t)1 << P.k_max) * (fp64 ? 16 : 8);
     return b;
