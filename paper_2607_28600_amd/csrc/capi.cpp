@@ -142,9 +142,17 @@ static void lower(symft_program *h) {
             continue;  // its sign is never evaluated while sampling
         }
         D.lam_c = I.lam.c;
-        D.cm_off = (uint32_t)cmeas.size();
-        D.cm_len = (uint32_t)I.lam.meas.size();
-        cmeas.insert(cmeas.end(), I.lam.meas.begin(), I.lam.meas.end());
+        // causal refs as (outcome word, bit mask) pairs; a ref listed twice cancels
+        std::map<uint32_t, uint32_t> words;
+        for (uint32_t t : I.lam.meas) words[t >> 5] ^= 1u << (t & 31);
+        D.cm_off = (uint32_t)(cmeas.size() / 2);
+        D.cm_len = 0;
+        for (auto &kv : words) {
+            if (!kv.second) continue;
+            cmeas.push_back(kv.first);
+            cmeas.push_back(kv.second);
+            ++D.cm_len;
+        }
         for (uint32_t s : I.lam.noise) cons[s].push_back((uint32_t)i);
     }
     std::vector<uint32_t> symoff(P.n_noise_sym + 1, 0), symcons;

@@ -14,7 +14,7 @@ struct DevInstr {
     uint8_t eta, lam_c, pad0, pad1;
     uint32_t a, b;
     int32_t meas;                  // measurement index (measurements)
-    uint32_t cm_off, cm_len;       // causal measurement refs of lambda
+    uint32_t cm_off, cm_len;       // causal refs of lambda: cm_len (word, mask) pairs from pair cm_off
     uint32_t pad2;
     double c, s;
     float cf, sf;
@@ -51,7 +51,7 @@ static_assert(sizeof(GapFast) == 32, "GapFast layout");
 // Pointers into one device allocation (all read-only in the kernels).
 struct DevProg {
     const DevInstr *instr;
-    const uint32_t *cmeas;       // causal refs (measurement ids)
+    const uint32_t *cmeas;       // causal refs of each lambda: (outcome word, bit mask) pairs
     const uint32_t *rm_list;     // instructions that are RandomMeas
     const uint32_t *rec_meas;    // record row -> measurement id
     const uint32_t *det_off;     // n_det + 1

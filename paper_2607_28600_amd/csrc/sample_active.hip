@@ -175,33 +175,15 @@ __device__ __forceinline__ void group_sum2(T &s0, T &s1, int tps, T *red) {
     }
 }
 
-// The causal measurement ref a lane of a shot group reads first (ref
-// threadIdx % min(tps, 64)).  (Fetching it, and the descriptor, an
-// instruction ahead costs more in register pressure than it hides.)
-__device__ __forceinline__ uint32_t first_cref(const DevProg &P, const DevInstr &I, int tps) {
-    const uint32_t unit = tps < 64 ? (uint32_t)tps : 64u;
-    const uint32_t r = threadIdx.x % unit;
-    return r < I.cm_len ? P.cmeas[I.cm_off + r] : 0u;
-}
-
-// Parity of the causal part of lambda for the shot of this group; t0 is the
-// lane's first ref (first_cref).
-__device__ __forceinline__ int causal_parity(const DevProg &P, const DevInstr &I, const uint32_t *mb, int tps,
-                                             uint32_t t0) {
-    if (I.cm_len == 0) return 0;
-    const int unit = tps < 64 ? tps : 64;
-    const int r = (int)(threadIdx.x % unit);
-    int x = (uint32_t)r < I.cm_len ? (int)((mb[t0 >> 5] >> (t0 & 31)) & 1u) : 0;
-    for (uint32_t j = (uint32_t)(r + unit); j < I.cm_len; j += (uint32_t)unit) {
-        uint32_t t = P.cmeas[I.cm_off + j];
-        x ^= (int)((mb[t >> 5] >> (t & 31)) & 1u);
-    }
-    uint64_t bal = __ballot(x);
-    if (unit < 64) {
-        const int sub = (int)((threadIdx.x & 63) / unit);
-        bal = (bal >> (sub * unit)) & ((1ull << unit) - 1ull);
-    }
-    return __popcll(bal) & 1;
+// Parity of the causal part of lambda for the shot of this group: the refs
+// come as (outcome word, bit mask) pairs, read by scalar loads, and the
+// group's outcome words from LDS.
+__device__ __forceinline__ int causal_parity(const DevProg &P, const DevInstr &I, const uint32_t *mb) {
+    const __attribute__((address_space(4))) uint32_t *q =
+        (const __attribute__((address_space(4))) uint32_t *)(P.cmeas + 2 * (size_t)I.cm_off);
+    uint32_t x = 0;
+    for (uint32_t j = 0; j < I.cm_len; ++j) x ^= mb[q[2 * j]] & q[2 * j + 1];
+    return __popc(x) & 1;
 }
 
 template <typename T>
@@ -299,10 +281,9 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
             // while this one runs
             for (uint32_t ii = 0; ii < P.n_instr; ++ii) {
                 const DevInstr I = load_instr(P.instr, ii);
-                const uint32_t cref = first_cref(P, I, tps);
                 const uint32_t N = 1u << I.k_in;
                 const uint32_t Nw = dead ? 0u : N;  // amplitudes this group still works on
-                const int lam = (int)I.lam_c ^ (int)((exo[ii] >> lane) & 1ull) ^ causal_parity(P, I, mb, tps, cref);
+                const int lam = (int)I.lam_c ^ (int)((exo[ii] >> lane) & 1ull) ^ causal_parity(P, I, mb);
                 const T c = sizeof(T) == 8 ? (T)I.c : (T)I.cf;
                 const T s = sizeof(T) == 8 ? (T)I.s : (T)I.sf;
                 uint32_t mbit = 0;  // this instruction's outcome, known to every thread of the group
