@@ -169,7 +169,7 @@ def run(args):
 
         ms64, _, _ = _time_launches(plain_fp64, max(2, args.steps // 4), 1, stream)
         extra["fp64_per_circuit_launches"] = {"shots_per_s": round(total / (ms64 / 1e3), 1), "ms_per_step": round(ms64, 4)}
-        extra["batched_fp32_over_fp64_plain"] = round(ms64 / ms_step, 3)
+        extra[f"batched_{prec}_over_fp64_plain"] = round(ms64 / ms_step, 3)
         flops = sum(p.info()["dense_flops_per_shot"] * s for p, s in zip(progs, shots))
         achieved = flops / (ms_kernel / 1e3) / 1e12
         peak = FP32_PEAK_TFLOPS if prec == "fp32" else FP64_PEAK_TFLOPS
