@@ -370,7 +370,10 @@ static uint32_t default_tps(uint32_t k, bool fp64) {
     return e <= 2 ? 4u : e >= 8 ? 256u : (1u << e);
 }
 
-ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, int context = 0) {
+// count_mode: a workgroup holds one shot group when groups are a wave or
+// more (64 .. 256 threads), so it drops a discarded shot at once.
+ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, int context = 0,
+                           bool count_mode = false) {
     ActiveConfig c;
     uint32_t k = P.k_max;
     c.bs = 256;
@@ -381,6 +384,7 @@ ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, 
         if (it != g_tune.end()) c.tps = it->second;
     }
     if (force_tps) c.tps = force_tps;
+    if (count_mode && c.tps >= 64 && c.tps <= 256) c.bs = c.tps;
     if (k >= 13) {
         c.bs = 1024;
         c.tps = 1024;
@@ -395,7 +399,7 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
                                uint64_t shots, uint64_t *out, uint64_t stride, uint32_t sections, double *p0,
                                uint64_t probe_shot0, uint64_t probe_n, uint64_t seed, hipStream_t st,
                                uint32_t force_tps = 0, const CountArgs *cnt = nullptr) {
-    ActiveConfig c = choose_active(D, fp64, force_tps);
+    ActiveConfig c = choose_active(D, fp64, force_tps, 0, cnt != nullptr);
     if (c.lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "program tables exceed the LDS budget of the active kernel");
     int per_cu = active_max_blocks_per_cu(fp64, c.bs, c.lds_vec, c.lds, cnt != nullptr);
     if (per_cu <= 0) per_cu = 1;

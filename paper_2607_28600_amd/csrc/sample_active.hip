@@ -282,7 +282,9 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
             for (uint32_t ii = 0; ii < P.n_instr; ++ii) {
                 const DevInstr I = load_instr(P.instr, ii);
                 const uint32_t N = 1u << I.k_in;
-                const uint32_t Nw = dead ? 0u : N;  // amplitudes this group still works on
+                // A discarded group skips the barrier-free loops below; guarding them
+                // (rather than shortening their bounds) keeps the loop control scalar.
+                const bool live = !dead;
                 const int lam = (int)I.lam_c ^ (int)((exo[ii] >> lane) & 1ull) ^ causal_parity(P, I, mb);
                 const T c = sizeof(T) == 8 ? (T)I.c : (T)I.cf;
                 const T s = sizeof(T) == 8 ? (T)I.s : (T)I.sf;
@@ -290,7 +292,8 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 switch (I.kind) {
                 case 1: {  // PromoteRot: x0 <- c a_x, x1 <- -i (-1)^lam s a_x
                     const T ss = lam ? -s : s;
-                    for (uint32_t x = (uint32_t)r; x < Nw; x += (uint32_t)tps) {
+                    if (live)
+                    for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
                         V v = vec[x];
                         V hi;
                         hi.x = ss * v.y;
@@ -303,7 +306,8 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 }
                 case 2: {  // ActiveDiagRot: a_x *= c - i sigma s, sigma = (-1)^lam mu (-1)^(b.x)
                     const int neg = lam ^ (I.mu == 2 ? 1 : 0);
-                    for (uint32_t x = (uint32_t)r; x < Nw; x += (uint32_t)tps) {
+                    if (live)
+                    for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
                         const T sg = (neg ^ parity(I.b & x)) ? -s : s;
                         V v = vec[x];
                         V o;
@@ -316,8 +320,9 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 case 3: {  // ActivePairRot on pairs (x0, x0 ^ a), bit h of x0 = 0
                     // a'_x = c a_x - i (-1)^lam s mu (-1)^(b.(x^a)) a_(x^a); with mu = i^m:
                     // -i mu = i^(m+3)
-                    const uint32_t half = Nw >> 1;
+                    const uint32_t half = N >> 1;
                     const int e0 = (int)I.mu + 3 + 2 * lam;
+                    if (live)
                     for (uint32_t z = (uint32_t)r; z < half; z += (uint32_t)tps) {
                         const uint32_t x0 = insert_bit(z, I.h, 0), x1 = x0 ^ I.a;
                         V a0 = vec[x0], a1 = vec[x1];
@@ -367,15 +372,16 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                     // conj(mu) (-1)^(b.u0) for the pair case; diag: parity classes of b.x
                     T s0 = 0, s1 = 0, c0 = 0, c1 = 0;
                     const T rs2 = (T)0.70710678118654752440;
-                    if (!pair) {
-                        for (uint32_t x = (uint32_t)r; x < Nw; x += (uint32_t)tps) {
+                    if (!live) {
+                    } else if (!pair) {
+                        for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
                             V v = vec[x];
                             T m2 = v.x * v.x + v.y * v.y;
                             if (parity(I.b & x)) kahan_add(s1, c1, m2); else kahan_add(s0, c0, m2);
                         }
                     } else {
                         const int mc = (4 - (int)I.mu) & 3;  // conj(mu) = i^mc
-                        for (uint32_t z = (uint32_t)r; z < (Nw >> 1); z += (uint32_t)tps) {
+                        for (uint32_t z = (uint32_t)r; z < half; z += (uint32_t)tps) {
                             const uint32_t u0 = insert_bit(z, I.h, 0);
                             V a0 = vec[u0], a1 = vec[u0 ^ I.a];
                             const int q = (mc + 2 * parity(I.b & u0)) & 3;
@@ -446,10 +452,17 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 // from the group's earlier outcome bits and, for this
                 // instruction's own outcome, from the register every thread of
                 // the group holds.
-                const bool chk = cm && A.cnt.chk_off[ii] < A.cnt.chk_off[ii + 1];
+                uint32_t c0 = 0, c1 = 0;  // this instruction's checks (scalar loads)
+                if (cm) {
+                    const __attribute__((address_space(4))) uint32_t *co =
+                        (const __attribute__((address_space(4))) uint32_t *)A.cnt.chk_off;
+                    c0 = co[ii];
+                    c1 = co[ii + 1];
+                }
+                const bool chk = c0 < c1;
                 uint32_t fired = 0;
                 if (chk && !dead) {
-                    for (uint32_t q = A.cnt.chk_off[ii] + (uint32_t)r; q < A.cnt.chk_off[ii + 1]; q += (uint32_t)tps) {
+                    for (uint32_t q = c0 + (uint32_t)r; q < c1; q += (uint32_t)tps) {
                         uint32_t x = 0;
                         for (uint32_t e = A.cnt.chk_mo[q]; e < A.cnt.chk_mo[q + 1]; ++e) {
                             const uint32_t t = A.cnt.chk_meas[e];
@@ -614,13 +627,21 @@ static auto dispatch(bool fp64, uint32_t bs, bool lds_vec, bool cm, Args... args
 #define SYMFT_PICK(T, B)                                                                             \
     return lds_vec ? (cm ? F<T, B, true, true>::run(args...) : F<T, B, true, false>::run(args...))  \
                    : (cm ? F<T, B, false, true>::run(args...) : F<T, B, false, false>::run(args...))
+    // one-group workgroups of 64 or 128 threads exist in count mode only
+#define SYMFT_PICK_CM(T, B) \
+    return lds_vec ? F<T, B, true, true>::run(args...) : F<T, B, false, true>::run(args...)
     if (fp64) {
         if (bs == 1024) SYMFT_PICK(double, 1024);
+        if (cm && bs == 128) SYMFT_PICK_CM(double, 128);
+        if (cm && bs == 64) SYMFT_PICK_CM(double, 64);
         SYMFT_PICK(double, 256);
     }
     if (bs == 1024) SYMFT_PICK(float, 1024);
+    if (cm && bs == 128) SYMFT_PICK_CM(float, 128);
+    if (cm && bs == 64) SYMFT_PICK_CM(float, 64);
     SYMFT_PICK(float, 256);
 #undef SYMFT_PICK
+#undef SYMFT_PICK_CM
 }
 
 template <typename T, int BS, bool LDSV, bool CM>

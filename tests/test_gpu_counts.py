@@ -160,7 +160,7 @@ def test_counts_do_not_depend_on_threads_per_shot_and_autotune():
     p = S.Program(c)
     post = list(range(c.num_detectors))
     ref_f, ref_c = p.sample_counts(64 * 5 + 9, 0x5EED0C06, post=post, precision="fp32")
-    for tps in (4, 16, 64, 256):
+    for tps in (4, 16, 64, 128, 256):
         f, n = p.sample_counts(64 * 5 + 9, 0x5EED0C06, post=post, precision="fp32", threads_per_shot=tps)
         assert torch.equal(f, ref_f), tps
         assert torch.equal(n, ref_c), tps
