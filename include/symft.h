@@ -200,7 +200,8 @@ typedef struct {
                                       if it has run; else one shot group per workgroup from peak width 8 on,
                                       so a workgroup leaves a rejected shot at once, and the record path's
                                       choice below); otherwise 4 .. 256, a power of two (peak width >= 13
-                                      always uses 1024).  Flags do not depend on it */
+                                      always uses 1024).  From 64 on a workgroup holds one shot group.
+                                      Flags do not depend on it */
     uint32_t reserved;             /* 0 */
 } symft_count_opts;
 
