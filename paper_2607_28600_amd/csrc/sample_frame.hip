@@ -372,10 +372,17 @@ __device__ __forceinline__ void emit_pair(const DevProg &P, const FrameArgs &A, 
 // One 16-byte chunk (node q / 8, words 2 (q % 8), +1) of the rows staged by
 // an EMIT step of n nodes.
 __device__ __forceinline__ void store_chunk(const FrameArgs &A, const unsigned long long *stg, const uint32_t *rows,
-                                            uint32_t q, uint64_t wt) {
+                                            uint32_t q, uint64_t wt, bool full) {
     const uint32_t v = q >> 3, pw = 2 * (q & 7u);
     const uint32_t row = rows[v];
     const uint64_t wi = wt + pw;
+    if (full) {
+        // every word of the tile is whole and 16-byte stores are allowed
+        if (row == FR_NO_ROW) return;
+        *(ulonglong2 *)((unsigned long long *)A.out + (uint64_t)row * A.row_stride + wi) =
+            *(const ulonglong2 *)&stg[v * TW + pw];
+        return;
+    }
     if (row == FR_NO_ROW || wi >= A.n_words) return;
     const ulonglong2 val = *(const ulonglong2 *)&stg[v * TW + pw];
     const unsigned long long m0 = word_mask(wi, A.shots), m1 = word_mask(wi + 1, A.shots);
@@ -432,6 +439,7 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
     unsigned long long n_disc = 0, n_logic = 0;  // aggregate counts of this workgroup (threads < TW)
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t wt = tile * TW;
+        const bool full = A.store16 && (wt + TW) * 64 <= A.shots;
         for (uint32_t i = tid; i < TW * NC; i += NWC * 64) {
             wst[i] = FrWord{0, 0, 0, 0};
             cur[i] = 0;
@@ -542,7 +550,7 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
             // rows staged by the previous step (if it was an EMIT step)
             if (tid < pend_n * (TW / 2))
                 store_chunk(A, stg + (size_t)((e_idx - 1) & 1u) * STG_WORDS, rows + ((e_idx - 1) & 1u) * FR_LEVEL_MAX,
-                            tid, wt);
+                            tid, wt, full);
             pend_n = 0;
             if (is_emit) {
                 const uint32_t n = r[2];
@@ -559,7 +567,7 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
         }
         if (tid < pend_n * (TW / 2))
             store_chunk(A, stg + (size_t)((e_idx - 1) & 1u) * STG_WORDS, rows + ((e_idx - 1) & 1u) * FR_LEVEL_MAX,
-                        tid, wt);
+                        tid, wt, full);
         __syncthreads();
         if (A.cnt.on && tid < TW) {
             // the tile's flags: kept shots only can have a logical error; bits past the shot count are 0
