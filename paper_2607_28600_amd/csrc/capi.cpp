@@ -77,7 +77,7 @@ static symft_status set_err(symft_status code, const std::string &msg) {
 struct HostLayout {
     std::vector<uint8_t> blob;
     // offsets of each array inside blob
-    size_t o_instr, o_cmeas, o_rm, o_recmeas, o_detoff, o_detrows, o_obsoff, o_obsrows, o_clsQ, o_clsoff, o_clschan,
+    size_t o_instr, o_cmeas, o_am, o_rm, o_recmeas, o_detoff, o_detrows, o_obsoff, o_obsrows, o_clsQ, o_clsoff, o_clschan,
         o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_invlog, o_clsfast, o_frstep, o_frnodes, o_frpush, o_frchinfo,
         o_frfltab, o_frfl3, o_frcap, o_frcapoff;
     uint32_t word_entries = 0;  // flip entries per word over all classes (frame kernel scratch)
@@ -119,7 +119,7 @@ static void lower(symft_program *h) {
     const Program &P = h->P;
     HostLayout &L = h->L;
     std::vector<DevInstr> ins(P.instrs.size());
-    std::vector<uint32_t> cmeas, rm;
+    std::vector<uint32_t> cmeas, rm, am;
     std::vector<std::vector<uint32_t>> cons(P.n_noise_sym);
     for (size_t i = 0; i < P.instrs.size(); ++i) {
         const Instr &I = P.instrs[i];
@@ -137,6 +137,10 @@ static void lower(symft_program *h) {
         D.s = std::sin(I.theta / 2);
         D.cf = (float)D.c;
         D.sf = (float)D.s;
+        if (I.kind == ACTIVE_DIAG_MEAS || I.kind == ACTIVE_PAIR_MEAS) {
+            D.am_idx = (uint32_t)am.size();
+            am.push_back((uint32_t)I.meas);
+        }
         if (I.kind == RANDOM_MEAS) {
             rm.push_back((uint32_t)i);
             continue;  // its sign is never evaluated while sampling
@@ -208,6 +212,7 @@ static void lower(symft_program *h) {
     L.blob.clear();
     L.o_instr = put(L.blob, ins);
     L.o_cmeas = put(L.blob, cmeas);
+    L.o_am = put(L.blob, am);
     L.o_rm = put(L.blob, rm);
     L.o_recmeas = put(L.blob, recmeas);
     L.o_detoff = put(L.blob, detoff);
@@ -242,6 +247,7 @@ static void lower(symft_program *h) {
     m.n_instr = (uint32_t)ins.size();
     m.n_meas = (uint32_t)P.n_meas;
     m.n_rm = (uint32_t)rm.size();
+    m.n_am = (uint32_t)am.size();
     m.n_rec = (uint32_t)P.n_rec;
     m.n_det = (uint32_t)P.n_det;
     m.n_obs = (uint32_t)P.n_obs;
@@ -277,6 +283,7 @@ static symft_status device_prog(symft_program *h, DevProg &out) {
     out = L.meta;
     out.instr = (const DevInstr *)(b + L.o_instr);
     out.cmeas = (const uint32_t *)(b + L.o_cmeas);
+    out.am_meas = (const uint32_t *)(b + L.o_am);
     out.rm_list = (const uint32_t *)(b + L.o_rm);
     out.rec_meas = (const uint32_t *)(b + L.o_recmeas);
     out.det_off = (const uint32_t *)(b + L.o_detoff);

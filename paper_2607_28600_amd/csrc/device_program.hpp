@@ -15,7 +15,7 @@ struct DevInstr {
     uint32_t a, b;
     int32_t meas;                  // measurement index (measurements)
     uint32_t cm_off, cm_len;       // causal refs of lambda: cm_len (word, mask) pairs from pair cm_off
-    uint32_t pad2;
+    uint32_t am_idx;               // active measurements: ordinal among them in stream order
     double c, s;
     float cf, sf;
 };
@@ -52,6 +52,7 @@ static_assert(sizeof(GapFast) == 32, "GapFast layout");
 struct DevProg {
     const DevInstr *instr;
     const uint32_t *cmeas;       // causal refs of each lambda: (outcome word, bit mask) pairs
+    const uint32_t *am_meas;     // measurement id of every active measurement, in stream order
     const uint32_t *rm_list;     // instructions that are RandomMeas
     const uint32_t *rec_meas;    // record row -> measurement id
     const uint32_t *det_off;     // n_det + 1
@@ -79,7 +80,7 @@ struct DevProg {
     const uint32_t *fr_capoff;   // per class + 1: prefix of fr_cap
     uint32_t n_instr, n_meas, n_rm, n_rec, n_det, n_obs, n_cls, k_max;
     uint32_t fr_n_steps, fr_n_slots, n_sym, fr_ok;   // fr_ok: the pure-frame kernel can run the program
-    uint32_t fr_first_emit, fr_first_emit_n, fr_first_noise_cls, pad;
+    uint32_t fr_first_emit, fr_first_emit_n, fr_first_noise_cls, n_am;
 };
 
 }  // namespace symft

@@ -61,7 +61,7 @@ __device__ __forceinline__ DevInstr load_instr(const DevInstr *p, uint32_t i) {
     d.meas = (int32_t)q[4];
     d.cm_off = q[5];
     d.cm_len = q[6];
-    d.pad2 = 0;
+    d.am_idx = q[7];
     d.c = __hiloint2double((int)q[9], (int)q[8]);
     d.s = __hiloint2double((int)q[11], (int)q[10]);
     d.cf = __uint_as_float(q[12]);
@@ -271,6 +271,12 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
             for (uint32_t i = (uint32_t)r; i < mw; i += (uint32_t)tps) mb[i] = 0;
             if (r == 0) { vec[0].x = (T)1; vec[0].y = (T)0; }
             bool dead = false;  // the shot was discarded by a postselected detector
+            // Uniform draws of active measurements: each lane of a group draws the one
+            // for a different upcoming active measurement of the group's shot, a batch
+            // of min(tps, 64) at a time, and the group reads the one it needs by a
+            // shuffle (one Philox block per lane per batch instead of per measurement).
+            const uint32_t unit = tps < 64 ? (uint32_t)tps : 64u;
+            uint32_t ux = 0, uy = 0, ubase = 0, uend = 0;
             uint32_t nchk = 0;  // checks done in this batch of shots
             if (cm && !wsync) {
                 // verdict rows start "live" for the G groups and "discarded" past them
@@ -366,9 +372,21 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 case 7: {  // ActivePairMeas
                     const uint32_t half = N >> 1;
                     const bool pair = I.kind == 7;
-                    // the uniform draw first: it overlaps the branch sums
                     const uint32_t t = (uint32_t)I.meas;
-                    const uint4 o = philox4x32_10(make_uint4(t, (uint32_t)shot, (uint32_t)(shot >> 32), 4u << 24), k0, k1);
+                    if (I.am_idx >= uend) {
+                        ubase = I.am_idx;
+                        uend = ubase + unit;
+                        const uint32_t j = ubase + threadIdx.x % unit;
+                        if (j < P.n_am) {
+                            const uint32_t tj = P.am_meas[j];
+                            const uint4 oj =
+                                philox4x32_10(make_uint4(tj, (uint32_t)shot, (uint32_t)(shot >> 32), 4u << 24), k0, k1);
+                            ux = oj.x;
+                            uy = oj.y;
+                        }
+                    }
+                    const int usrc = (int)(((threadIdx.x & 63u) & ~(unit - 1u)) + (I.am_idx - ubase));
+                    const uint32_t ox = (uint32_t)__shfl((int)ux, usrc, 64), oy = (uint32_t)__shfl((int)uy, usrc, 64);
                     // conj(mu) (-1)^(b.u0) for the pair case; diag: parity classes of b.x
                     T s0 = 0, s1 = 0, c0 = 0, c1 = 0;
                     const T rs2 = (T)0.70710678118654752440;
@@ -398,7 +416,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                     const int flip = pair ? lam : (lam ^ (int)I.eta);
                     const double S0 = (double)s0, S1 = (double)s1;
                     const double p0 = (flip ? S1 : S0) / (S0 + S1);
-                    const double u = (double)(((uint64_t)o.x << 21) + (uint64_t)(o.y >> 11)) * 0x1p-53;
+                    const double u = (double)(((uint64_t)ox << 21) + (uint64_t)(oy >> 11)) * 0x1p-53;
                     const int m = (u < p0) ? 0 : 1;
                     mbit = (uint32_t)m;
                     const int y = m ^ flip;  // kept class
