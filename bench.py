@@ -77,6 +77,24 @@ def _p0_error(prog, seed, n_shots):
             "measurements": int(d.size), "probed_shots": n_shots}
 
 
+def _amp_error(prog, seed, n_shots):
+    """Largest |amplitude| difference between the FP32 and FP64 kernels over the final active vectors of
+    n_shots shots whose records agree in both precisions (a shot whose draw fell between the two
+    precisions' thresholds took another branch and is left out; the count is reported)."""
+    import numpy as np
+    import paper_2607_28600_amd as S
+    a32 = prog.probe_amplitudes(0, n_shots, seed, precision="fp32")
+    a64 = prog.probe_amplitudes(0, n_shots, seed, precision="fp64")
+    r32 = S.bits_to_numpy(prog.sample(n_shots, seed, precision="fp32"))
+    r64 = S.bits_to_numpy(prog.sample(n_shots, seed, precision="fp64"))
+    same = [s for s in range(n_shots)
+            if np.array_equal((r32[:, s // 64] >> np.uint64(s % 64)) & np.uint64(1),
+                              (r64[:, s // 64] >> np.uint64(s % 64)) & np.uint64(1))]
+    d = np.abs(a32[same] - a64[same]) if same else np.zeros(1)
+    return {"max_abs": float(d.max(initial=0.0)), "shots_compared": len(same), "probed_shots": n_shots,
+            "amplitudes_per_shot": int(a64.shape[1])}
+
+
 def _cpu_baseline(circ, seed, words, threads):
     from oracle import OracleCircuit
     oc = OracleCircuit(circ)
@@ -140,6 +158,7 @@ def run(args):
             dtype = "f32" if prec == "fp32" else "f64"
         if info["k_max"] and prec == "fp32":
             extra["p0_fp32_vs_fp64"] = _p0_error(prog, w.seed, 64)
+            extra["amplitude_fp32_vs_fp64"] = _amp_error(prog, w.seed, 64)
         config = {"workload": w.name, "shots": w.shots, "rows": prog.n_rows, "k_max": info["k_max"],
                   "precision": prec if info["k_max"] else "n/a (integer path)"}
         if tps:

@@ -250,6 +250,18 @@ symft_status symft_autotune(const symft_program *p, uint32_t precision, uint32_t
 symft_status symft_probe(const symft_program *p, uint64_t shot_begin, uint32_t n_shots, uint64_t seed,
                          uint32_t precision, double *p0_host);
 
+/* Probe of the final active state: for shots [shot_begin, shot_begin + n_shots)
+ * the dense active vector after the last instruction (paper Sec. 4-5: the
+ * active amplitudes alpha_x over the 2^k_end active coordinates, k_end the
+ * width after the last op as symft_program_plan reports it), computed by the
+ * same GPU kernels in FP64 (precision 0) or FP32 (1) and written to host
+ * amp_host[n_shots][2^k_end][2] as (re, im) FP64 pairs (nullable: then only
+ * *k_end is set).  Pure-frame programs report k_end = 0 and the amplitude
+ * 1.  Synchronous.  For tests and FP32 error reports.  Errors: EINVAL,
+ * ENOMEM, EHIP. */
+symft_status symft_probe_amplitudes(const symft_program *p, uint64_t shot_begin, uint32_t n_shots, uint64_t seed,
+                                    uint32_t precision, double *amp_host, uint32_t *k_end);
+
 /* Gap check: the geometric gap G = max { g <= 4096 : v < Q[g] } of the
  * noise draw contract (Q the exact table of a class with per-draw firing
  * probability p32 / 2^32, 0 < p32 <= 2^32) for n draws v (device array),

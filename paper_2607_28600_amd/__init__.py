@@ -92,6 +92,9 @@ _lib.symft_gap_check.restype = C.c_int32
 _lib.symft_gap_check.argtypes = [C.c_uint64, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p]
 _lib.symft_probe.restype = C.c_int32
 _lib.symft_probe.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.POINTER(C.c_double)]
+_lib.symft_probe_amplitudes.restype = C.c_int32
+_lib.symft_probe_amplitudes.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_void_p,
+                                        C.POINTER(C.c_uint32)]
 _lib.symft_program_export.restype = C.c_int32
 _lib.symft_program_export.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p]
@@ -100,7 +103,7 @@ _lib.symft_last_error.restype = C.c_char_p
 
 EXPORTED = ["symft_compile", "symft_program_info", "symft_program_plan", "symft_program_export",
             "symft_sample", "symft_sample_ex", "symft_sample_counts", "symft_autotune_counts",
-            "symft_sample_batch", "symft_autotune", "symft_probe", "symft_gap_check", "symft_program_free",
+            "symft_sample_batch", "symft_autotune", "symft_probe", "symft_probe_amplitudes", "symft_gap_check", "symft_program_free",
             "symft_last_error"]
 
 
@@ -296,6 +299,19 @@ class Program:
         _check(_lib.symft_probe(self._h, shot_begin, n_shots, seed, 0 if precision == "fp64" else 1,
                                 p0.ctypes.data_as(C.POINTER(C.c_double))), "symft_probe")
         return p0[:, : self.n_meas]
+
+
+def _probe_amplitudes(prog, shot_begin: int, n_shots: int, seed: int, precision: str = "fp64") -> np.ndarray:
+    """Final active vector of shots [shot_begin, +n_shots) from the GPU kernels: [n_shots, 2^k_end] complex128."""
+    k = C.c_uint32(0)
+    _check(_lib.symft_probe_amplitudes(prog._h, shot_begin, 0, seed, 0, None, C.byref(k)), "symft_probe_amplitudes")
+    amp = np.zeros((n_shots, (1 << k.value) * 2), dtype=np.float64)
+    _check(_lib.symft_probe_amplitudes(prog._h, shot_begin, n_shots, seed, 0 if precision == "fp64" else 1,
+                                       amp.ctypes.data, C.byref(k)), "symft_probe_amplitudes")
+    return amp[:, 0::2] + 1j * amp[:, 1::2]
+
+
+Program.probe_amplitudes = _probe_amplitudes
 
 
 def compile(circ) -> Program:  # noqa: A001 - mirrors symft_compile

@@ -405,7 +405,8 @@ ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, 
 static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, uint64_t word_begin, uint64_t n_words,
                                uint64_t shots, uint64_t *out, uint64_t stride, uint32_t sections, double *p0,
                                uint64_t probe_shot0, uint64_t probe_n, uint64_t seed, hipStream_t st,
-                               uint32_t force_tps = 0, const CountArgs *cnt = nullptr) {
+                               uint32_t force_tps = 0, const CountArgs *cnt = nullptr, double *amp = nullptr,
+                               uint32_t amp_k = 0) {
     ActiveConfig c = choose_active(D, fp64, force_tps, 0, cnt != nullptr);
     if (c.lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "program tables exceed the LDS budget of the active kernel");
     int per_cu = active_max_blocks_per_cu(fp64, c.bs, c.lds_vec, c.lds, cnt != nullptr);
@@ -425,6 +426,8 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
     A.sections = sections;
     A.tps = c.tps;
     A.p0_out = p0;
+    A.amp_out = amp;
+    A.amp_k = amp_k;
     A.probe_shot0 = probe_shot0;
     A.probe_n = probe_n;
     A.lds_vec = c.lds_vec ? 1 : 0;
@@ -848,6 +851,47 @@ symft_status symft_probe(const symft_program *pc, uint64_t shot_begin, uint32_t 
             rc = set_err(SYMFT_EHIP, "probe copy failed");
     }
     hipFree(dp0);
+    hipFree(drec);
+    return rc;
+}
+
+symft_status symft_probe_amplitudes(const symft_program *pc, uint64_t shot_begin, uint32_t n_shots, uint64_t seed,
+                                    uint32_t precision, double *amp_host, uint32_t *k_end) {
+    symft_program *p = const_cast<symft_program *>(pc);
+    if (!p) return set_err(SYMFT_EINVAL, "NULL program");
+    if (precision > 1) return set_err(SYMFT_EINVAL, "precision must be 0 or 1");
+    const uint32_t k = p->P.k_after_op.empty() ? 0u : (uint32_t)std::max<int16_t>(0, p->P.k_after_op.back());
+    if (k_end) *k_end = k;
+    if (n_shots == 0 || !amp_host) return SYMFT_OK;
+    if (p->P.k_max == 0) {
+        for (uint64_t i = 0; i < n_shots; ++i) {
+            amp_host[2 * i] = 1.0;
+            amp_host[2 * i + 1] = 0.0;
+        }
+        return SYMFT_OK;
+    }
+    DevProg D;
+    symft_status rc = device_prog(p, D);
+    if (rc) return rc;
+    const uint64_t w0 = shot_begin / 64, w1 = (shot_begin + n_shots + 63) / 64;
+    const uint64_t nw = w1 - w0;
+    const size_t namp = (size_t)n_shots * (2ull << k);
+    double *damp = nullptr;
+    uint64_t *drec = nullptr;
+    const uint64_t rows = std::max<uint64_t>(1, p->P.n_rows());
+    if (hipMalloc(&damp, sizeof(double) * namp) != hipSuccess) return set_err(SYMFT_ENOMEM, "probe allocation failed");
+    if (hipMalloc(&drec, 8 * rows * nw) != hipSuccess) {
+        hipFree(damp);
+        return set_err(SYMFT_ENOMEM, "probe allocation failed");
+    }
+    rc = run_active(p, D, precision == 0, w0, nw, nw * 64, drec, nw, 7u, nullptr, shot_begin, n_shots, seed, nullptr, 0,
+                    nullptr, damp, k);
+    if (rc == SYMFT_OK) {
+        if (hipDeviceSynchronize() != hipSuccess ||
+            hipMemcpy(amp_host, damp, sizeof(double) * namp, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = set_err(SYMFT_EHIP, "probe copy failed");
+    }
+    hipFree(damp);
     hipFree(drec);
     return rc;
 }

@@ -39,7 +39,9 @@ struct ActiveArgs {
     void *scratch;            // HBM vectors (nullptr when LDS-resident)
     uint64_t scratch_stride;  // elements per group slice
     double *p0_out;           // probe: [shot][n_meas] or nullptr
+    double *amp_out;          // probe: final active vector [shot][2^amp_k] as (re, im) FP64 pairs, or nullptr
     uint64_t probe_shot0, probe_n;
+    uint32_t amp_k, pad_a;
     uint32_t lds_vec;         // 1: vectors in LDS
     uint32_t lds_bytes;
     CountArgs cnt;

@@ -519,6 +519,16 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                     ++nchk;
                 }
             }
+            if (A.amp_out && shot - A.probe_shot0 < A.probe_n) {
+                // probe: the shot's final active vector (complete: every instruction
+                // ends with the group's synchronisation)
+                double *dst = A.amp_out + (shot - A.probe_shot0) * (2ull << A.amp_k);
+                for (uint32_t x = (uint32_t)r; x < (1u << A.amp_k); x += (uint32_t)tps) {
+                    const V v = vec[x];
+                    dst[2 * x] = (double)v.x;
+                    dst[2 * x + 1] = (double)v.y;
+                }
+            }
             if (cm) {
                 // the shot's flags: discarded, or a logical error when an
                 // observable differs from its expected value

@@ -302,3 +302,25 @@ def test_gap_decision_at_table_boundaries(p32):
     got = S.gap_check(p32, v).cpu().numpy()
     bad = np.flatnonzero(got != want)
     assert bad.size == 0, (p32, cand[bad[:5]], got[bad[:5]], want[bad[:5]])
+
+
+@pytest.mark.parametrize("name", ["c3", "c4_11"])
+def test_final_amplitudes_fp32_vs_fp64(name):
+    """The amplitude probe: unit-norm final active vectors, FP32 within 1e-5 of FP64 on shots whose
+    records agree in both precisions, and a width equal to the plan's last width."""
+    w = configs.c3() if name == "c3" else configs.c4()[11]
+    p = S.Program(w.circuit)
+    n = 64
+    a64 = p.probe_amplitudes(0, n, w.seed, precision="fp64")
+    a32 = p.probe_amplitudes(0, n, w.seed, precision="fp32")
+    k_end = int(p.plan()["k"][-1])
+    assert a64.shape == (n, 1 << k_end) and k_end > 0
+    assert np.allclose(np.sum(np.abs(a64) ** 2, axis=1), 1.0, atol=1e-12)
+    assert np.allclose(np.sum(np.abs(a32) ** 2, axis=1), 1.0, atol=1e-5)
+    r64 = _gpu(p, n, w.seed, precision="fp64")
+    r32 = _gpu(p, n, w.seed, precision="fp32")
+    same = [s for s in range(n)
+            if np.array_equal((r32[:, s // 64] >> np.uint64(s % 64)) & np.uint64(1),
+                              (r64[:, s // 64] >> np.uint64(s % 64)) & np.uint64(1))]
+    assert len(same) >= n - 2
+    assert np.max(np.abs(a32[same] - a64[same])) < 1e-5
