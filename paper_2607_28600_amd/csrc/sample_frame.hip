@@ -110,6 +110,22 @@ struct Walk {
     uint32_t pos, j, e;
 };
 
+// Inclusive prefix sum over the 64 lanes of a wave by DPP: a 4-lane window
+// inside each row of 16 (row shifts 1..3), then banks (row shifts 4 and 8
+// into the upper banks), then rows (broadcasts of lanes 15 and 31).
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+    const int xi = (int)x;
+    uint32_t s = x;
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x111, 0xf, 0xf, true);  // row_shr:1
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x112, 0xf, 0xf, true);  // row_shr:2
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x113, 0xf, 0xf, true);  // row_shr:3
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x114, 0xf, 0xe, false);  // row_shr:4, banks 1-3
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x118, 0xf, 0xc, false);  // row_shr:8, banks 2-3
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x142, 0xa, 0xf, false);  // row_bcast:15, rows 1, 3
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x143, 0xc, 0xf, false);  // row_bcast:31, rows 2, 3
+    return s;
+}
+
 // The program tables a walk reads (passed by value, so an out-of-line walk
 // needs no copy of the whole program descriptor).
 struct WalkTabs {
@@ -177,13 +193,8 @@ __device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const 
     }
     // (events << 23 | advance): a walk advances at most 2^20 positions and finds at most 256 events
     const uint32_t mine = (nev << 23) | inc;
-    uint32_t x = mine;
-#pragma unroll
-    for (uint32_t off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    const uint32_t total = __shfl(x, 63, 64);
+    const uint32_t x = wave_incl_sum(mine);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
     const uint32_t ex = x - mine;
     const uint32_t p = st.pos + (ex & 0x7FFFFFu), e = st.e + (ex >> 23);
     const uint32_t eb = st.e & ~3u, elim = eb + 256u;
@@ -210,10 +221,10 @@ __device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const 
     uint32_t n_pos, n_e, n_j;
     bool cutR;
     if (cut_lane < 64) {
-        n_pos = __shfl(cut_p, (int)cut_lane, 64);
-        n_e = __shfl(cut_e, (int)cut_lane, 64);
-        n_j = jal + 4 * cut_lane + (uint32_t)__shfl(cut_i, (int)cut_lane, 64);
-        cutR = __shfl(cut_r, (int)cut_lane, 64) != 0;
+        n_pos = (uint32_t)__builtin_amdgcn_readlane((int)cut_p, (int)cut_lane);
+        n_e = (uint32_t)__builtin_amdgcn_readlane((int)cut_e, (int)cut_lane);
+        n_j = jal + 4 * cut_lane + (uint32_t)__builtin_amdgcn_readlane(cut_i, (int)cut_lane);
+        cutR = __builtin_amdgcn_readlane((int)cut_r, (int)cut_lane) != 0;
     } else {
         n_pos = st.pos + (total & 0x7FFFFFu);
         n_e = st.e + (total >> 23);
@@ -256,13 +267,8 @@ __device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const 
     }
     if (GEN) {
         // entries of this lane's events go after those of the lanes below it
-        uint32_t xs = k_lane;
-#pragma unroll
-        for (uint32_t off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(xs, off, 64);
-            if (lane >= off) xs += y;
-        }
-        const uint32_t ktot = __shfl(xs, 63, 64);
+        const uint32_t xs = wave_incl_sum(k_lane);
+        const uint32_t ktot = (uint32_t)__builtin_amdgcn_readlane((int)xs, 63);
         uint32_t o = *n_out + xs - k_lane;
 #pragma unroll
         for (uint32_t i = 0; i < 4; ++i) {
