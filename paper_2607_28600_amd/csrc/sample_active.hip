@@ -155,11 +155,43 @@ __device__ __forceinline__ void word_noise(const DevProg &P, uint64_t seed, uint
     }
 }
 
-// Sum over the TPS lanes of a shot group; every lane gets the same value.
+// v from another lane of the same row by the DPP pattern CTRL (a lane
+// permutation: quad permutes and row mirrors).
+template <int CTRL>
+__device__ __forceinline__ float dpp_perm(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the TPS lanes of a shot group; every lane gets the same value
+// (each step adds a lane's partner, and a + b == b + a exactly).  Inside a
+// row of 16 lanes the partners come by DPP: quad permutes [1,0,3,2] and
+// [2,3,0,1], then the half-row and row mirrors; wider groups add the other
+// row halves of the wave by shuffles.
 template <typename T, int BS>
 __device__ __forceinline__ void group_sum2(T &s0, T &s1, int tps, T *red) {
-    const int lim = tps < 64 ? tps : 64;
-    for (int off = lim >> 1; off > 0; off >>= 1) {
+    if (tps >= 2) {
+        s0 += dpp_perm<0xB1>(s0);
+        s1 += dpp_perm<0xB1>(s1);
+    }
+    if (tps >= 4) {
+        s0 += dpp_perm<0x4E>(s0);
+        s1 += dpp_perm<0x4E>(s1);
+    }
+    if (tps >= 8) {
+        s0 += dpp_perm<0x141>(s0);
+        s1 += dpp_perm<0x141>(s1);
+    }
+    if (tps >= 16) {
+        s0 += dpp_perm<0x140>(s0);
+        s1 += dpp_perm<0x140>(s1);
+    }
+    for (int off = 16; off < 64 && off < tps; off <<= 1) {
         s0 += __shfl_xor(s0, off, 64);
         s1 += __shfl_xor(s1, off, 64);
     }
