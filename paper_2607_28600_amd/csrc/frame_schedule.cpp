@@ -314,7 +314,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             const Node &v = nd[id];
             uint32_t flags = (v.cst ? 1u : 0u) | (v.slot >= 0 ? 2u : 0u) | (v.rm ? 4u : 0u) | ((uint32_t)v.sec << 4);
             const uint32_t np = (uint32_t)v.succs.size();
-            F.nodes.push_back((v.slot >= 0 ? (uint32_t)v.slot : 0u) | (flags << 24));
+            F.nodes.push_back((v.slot >= 0 ? (uint32_t)v.slot : F.n_slots) | (flags << 24));
             F.nodes.push_back(v.row);
             F.nodes.push_back(v.meas);
             F.nodes.push_back(np);

@@ -334,7 +334,8 @@ __device__ __forceinline__ void emit_pair(const DevProg &P, const FrameArgs &A, 
     const uint32_t vi = q >> 3, wl = 2 * (q & 7u);
     const uint32_t flags = ra.x >> 24;
     unsigned long long v0 = (flags & 1u) ? ~0ull : 0ull, v1 = v0;
-    if (flags & 2u) {
+    {
+        // a node with no contributions reads the extra slot past the schedule's, which stays zero
         const uint32_t sl = ra.x & 0xFFFFFFu;
         ulonglong2 *sp = (ulonglong2 *)slot_pair(slots, sl, wl);
         const ulonglong2 sv = *sp;
@@ -365,7 +366,8 @@ __device__ __forceinline__ void emit_pair(const DevProg &P, const FrameArgs &A, 
         }
     }
     *(ulonglong2 *)&stg[vi * TW + wl] = make_ulonglong2(v0, v1);
-    if (wl == 0) {
+    {
+        // every lane of the node writes the same row index
         const uint32_t sec = (flags >> 4) & 3u;
         rows[vi] = (ra.y != FR_NO_ROW && sec && ((A.sections >> (sec - 1)) & 1u)) ? ra.y : FR_NO_ROW;
     }
@@ -424,7 +426,7 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
     const uint32_t NC = P.n_cls, NS = P.fr_n_slots, n_steps = P.fr_n_steps;
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     unsigned long long *slots = (unsigned long long *)smem;
-    FrWord *wst = (FrWord *)(slots + (size_t)NS * TW);
+    FrWord *wst = (FrWord *)(slots + (size_t)(NS + 1) * TW);
     uint32_t *cur = (uint32_t *)(wst + (size_t)TW * NC);
     uint32_t *cnt = cur + (size_t)TW * NC;
     uint32_t *ovf = cnt + (size_t)TW * NC;
@@ -440,7 +442,7 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
     const uint64_t n_tiles = (A.n_words + TW - 1) / TW;
     uint64_t *scr = A.scratch + (size_t)blockIdx.x * (TW * A.word_entries + NWC * 128);
     uint32_t *gtmp = (uint32_t *)(scr + (size_t)TW * A.word_entries) + (size_t)wave * 256;  // fallback walks
-    for (uint32_t i = tid; i < NS * TW; i += NWC * 64) slots[i] = 0ull;
+    for (uint32_t i = tid; i < (NS + 1) * TW; i += NWC * 64) slots[i] = 0ull;
     if (tid < 2 * TW) fl[tid] = 0ull;
     unsigned long long n_disc = 0, n_logic = 0;  // aggregate counts of this workgroup (threads < TW)
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
@@ -616,7 +618,7 @@ __global__ void gap_check_kernel(GapFast F, const uint64_t *Q, const uint32_t *v
 
 size_t frame_lds_bytes(const DevProg &P) {
     // slots | stream states | cursors and counts | overflow flags | count flags | (walk positions or staging)
-    const size_t head = (size_t)P.fr_n_slots * TW * 8 + (size_t)TW * P.n_cls * (sizeof(FrWord) + 8) + TW * 4;
+    const size_t head = (size_t)(P.fr_n_slots + 1) * TW * 8 + (size_t)TW * P.n_cls * (sizeof(FrWord) + 8) + TW * 4;
     const size_t flags = 2 * TW * 8;
     const size_t region = std::max<size_t>((size_t)NWC * 256 * 4, 2 * (STG_WORDS * 8 + FR_LEVEL_MAX * 4));
     return ((head + 15) & ~(size_t)15) + flags + region;
