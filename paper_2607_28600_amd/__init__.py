@@ -19,6 +19,11 @@ LIB = os.path.join(HERE, "libsymft.so")
 if not os.path.exists(LIB):
     raise ImportError(f"{LIB} is not built; run `python paper_2607_28600_amd/build.py` (or __graft_entry__.build())")
 
+# PyTorch ships its own HIP runtime under the same soname.  Loading it first
+# makes the library bind to that one runtime; loaded the other way round, the
+# process would hold two HIP runtimes, and the library's would find no device.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB)
 
 OK = 0

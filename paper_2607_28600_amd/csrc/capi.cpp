@@ -74,6 +74,10 @@ static symft_status set_err(symft_status code, const std::string &msg) {
     return code;
 }
 
+static symft_status hip_err(const char *what, hipError_t e) {
+    return set_err(SYMFT_EHIP, std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+
 struct HostLayout {
     std::vector<uint8_t> blob;
     // offsets of each array inside blob
@@ -264,7 +268,7 @@ static void lower(symft_program *h) {
 
 static symft_status device_prog(symft_program *h, DevProg &out) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return set_err(SYMFT_EHIP, "hipGetDevice failed");
+    if (const hipError_t e = hipGetDevice(&dev)) return hip_err("hipGetDevice failed", e);
     std::lock_guard<std::mutex> lk(h->mu);
     void *base = nullptr;
     auto it = h->dev.find(dev);
@@ -685,7 +689,7 @@ static symft_status count_tables(symft_program *h, const symft_count_opts &o, Co
     tab.insert(tab.end(), ms.begin(), ms.end());
     tab.push_back(0u);
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return set_err(SYMFT_EHIP, "hipGetDevice failed");
+    if (const hipError_t e = hipGetDevice(&dev)) return hip_err("hipGetDevice failed", e);
     void *base = nullptr;
     {
         std::lock_guard<std::mutex> lk(h->mu);
