@@ -5,8 +5,12 @@
 // earlier records (paper Sec. 5: DetMeas assigns lambda ^ eta; RandomMeas is
 // uniform).  Walking the circuit in order, consecutive noise channels become
 // NOISE steps (one per probability class, a contiguous rank range) and
-// consecutive measurement / detector nodes become EMIT levels, split where a
-// node depends on another node of the same level.  A node with any incoming
+// consecutive measurement / detector nodes become EMIT levels.  A node that
+// depends on a node of the open level takes that node's expression in place of
+// the dependency (values add over GF(2)), so chains of records determined by
+// records just made, such as the final data measurements of a memory
+// experiment, share one level; a level is split only where that would need
+// two RandomMeas words in one node or exceed the size caps.  A node with any incoming
 // contribution (a noise symbol of its sign, or an earlier record it XORs in)
 // owns an accumulator slot from the step of its first contribution to the
 // step that emits it; slots are interval-coloured, and a slot is reused only
@@ -40,6 +44,25 @@ static uint64_t pack_flips(const std::vector<uint32_t> &fl, std::vector<uint64_t
     return k | (off << 8);
 }
 
+// Elements of odd total multiplicity in a and b: the sum over GF(2) of two
+// sets of symbols or records.
+static std::vector<uint32_t> xor_sets(std::vector<uint32_t> a, const std::vector<uint32_t> &b) {
+    a.insert(a.end(), b.begin(), b.end());
+    std::sort(a.begin(), a.end());
+    std::vector<uint32_t> r;
+    for (size_t i = 0; i < a.size();) {
+        size_t j = i;
+        while (j < a.size() && a[j] == a[i]) ++j;
+        if ((j - i) & 1) r.push_back(a[i]);
+        i = j;
+    }
+    return r;
+}
+
+// Caps on a folded node's expression (they bound the pushes and flip entries
+// that folding adds).
+static const size_t FOLD_MAX_PREDS = 64, FOLD_MAX_NOISE = 1024;
+
 void build_frame_schedule(const Program &P, FrameSchedule &F) {
     F = FrameSchedule();
     if (P.k_max != 0) return;
@@ -55,7 +78,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
     const uint32_t NN = M + D + B;
     struct Node {
         uint8_t cst = 0, rm = 0, sec = 0;
-        uint32_t row = FR_NO_ROW, meas = 0;
+        uint32_t row = FR_NO_ROW, rm_t = 0;  // rm_t: the measurement whose RandomMeas word is added
         std::vector<uint32_t> preds, succs, noise;
         int emit = -1, first = 1 << 30, slot = -1;
     };
@@ -63,9 +86,9 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
     for (uint32_t t = 0; t < M; ++t) {
         const Instr &I = P.instrs[(size_t)P.meas_instr[t]];
         Node &v = nd[t];
-        v.meas = t;
         if (I.kind == RANDOM_MEAS) {
             v.rm = 1;
+            v.rm_t = t;
         } else {
             v.cst = (uint8_t)(I.lam.c ^ I.eta);
             v.preds = I.lam.meas;
@@ -91,9 +114,6 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
         v.row = (uint32_t)(P.n_rec + P.n_det + b);
         v.sec = 3;
     }
-    for (uint32_t i = 0; i < NN; ++i)
-        for (uint32_t u : nd[i].preds) nd[u].succs.push_back(i);
-
     // items in circuit order: (op, kind, id); kind 0 channel, 1 measurement, 2 detector
     struct Item {
         int64_t op;
@@ -123,6 +143,38 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
     std::vector<uint32_t> seg_chans;
     std::vector<uint32_t> level;
     std::vector<uint8_t> in_level(NN, 0);
+    // v's expression with every dependency on the open level replaced by that
+    // node's expression; false (v unchanged) past the caps or where two
+    // different RandomMeas words would meet.  A node of the level depends on no
+    // other node of it, and the nodes it depends on precede it, so each
+    // replacement removes one dependency on the level.
+    auto fold = [&](Node &v) -> bool {
+        std::vector<uint32_t> preds = xor_sets(v.preds, {}), noise = xor_sets(v.noise, {});
+        uint8_t cst = v.cst, rm = v.rm;
+        uint32_t rm_t = v.rm_t;
+        for (;;) {
+            int64_t u = -1;
+            for (uint32_t x : preds)
+                if (in_level[x]) u = x;
+            if (u < 0) break;
+            const Node &a = nd[(size_t)u];
+            if (a.rm) {
+                if (rm && rm_t != a.rm_t) return false;
+                rm_t = a.rm_t;
+                rm ^= 1;
+            }
+            cst ^= a.cst;
+            preds = xor_sets(xor_sets(preds, {(uint32_t)u}), a.preds);
+            noise = xor_sets(noise, a.noise);
+            if (preds.size() > FOLD_MAX_PREDS || noise.size() > FOLD_MAX_NOISE) return false;
+        }
+        v.preds = preds;
+        v.noise = noise;
+        v.cst = cst;
+        v.rm = rm;
+        v.rm_t = rm ? rm_t : 0;
+        return true;
+    };
     auto flush_noise = [&]() {
         for (auto &kv : seg) {
             Step s;
@@ -166,13 +218,15 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             flush_noise();
             bool dep = false;
             for (uint32_t u : nd[it.id].preds) dep |= in_level[u] != 0;
-            if (dep) flush_level();
+            if (dep && !fold(nd[it.id])) flush_level();
             level.push_back(it.id);
             in_level[it.id] = 1;
         }
     }
     flush_noise();
     flush_level();
+    for (uint32_t i = 0; i < NN; ++i)
+        for (uint32_t u : nd[i].preds) nd[u].succs.push_back(i);
 
     // noise symbol -> channel
     std::vector<int32_t> sym_chan(P.n_noise_sym, -1);
@@ -316,7 +370,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             const uint32_t np = (uint32_t)v.succs.size();
             F.nodes.push_back((v.slot >= 0 ? (uint32_t)v.slot : F.n_slots) | (flags << 24));
             F.nodes.push_back(v.row);
-            F.nodes.push_back(v.meas);
+            F.nodes.push_back(v.rm_t);
             F.nodes.push_back(np);
             F.nodes.push_back(np > 0 ? (uint32_t)nd[v.succs[0]].slot : 0u);
             F.nodes.push_back(np > 1 ? (uint32_t)nd[v.succs[1]].slot : 0u);
