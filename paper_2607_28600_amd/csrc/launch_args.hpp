@@ -94,11 +94,12 @@ struct FrameArgs {
 // kernel fetch a step's data ahead of the step.
 // Node record (8 x uint32): slot | flags << 24 (flags bit0 const, bit1 has
 // slot, bit2 RandomMeas, bits 4..5 section: 1 record, 2 detector,
-// 3 observable, 0 hidden), output row, measurement index, push count, first
-// two successor slots, offset of further successors in the push list, 0.
+// 3 observable, 0 hidden), output row, the measurement whose RandomMeas word
+// is added, push count, first two successor slots, offset of further
+// successors in the push list, 0.
 enum FrameStepKind : uint32_t { FR_NOISE = 1, FR_EMIT = 2 };
 static const uint32_t FR_NO_ROW = 0xFFFFFFFFu;
-static const uint32_t FR_LEVEL_MAX = 64;  // nodes per EMIT step: one (node, word pair) per thread of 8 waves
+static const uint32_t FR_LEVEL_MAX = 128;  // nodes per EMIT step: one (node, 4 words) per thread of 8 waves
 static const uint32_t FR_STEP_WORDS = 8;
 static const uint32_t FR_NONE = 0xFFFFFFFFu;
 

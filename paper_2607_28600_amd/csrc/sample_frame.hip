@@ -13,9 +13,9 @@
 //    in L2 / the Infinity Cache;
 //  * phase S: the push-based schedule (launch_args.hpp), a barrier after
 //    every step.  NOISE: each wave streams its words' entries of the step and
-//    XORs the lane bits into the slots.  EMIT: lanes take (node, pair of
-//    words), read and clear the node's two slot words, add its constant or
-//    RandomMeas words, store 16 bytes of its row and XOR the values into its
+//    XORs the lane bits into the slots.  EMIT: lanes take (node, 4 words),
+//    read and clear the node's four slot words, add its constant or
+//    RandomMeas words, store 32 bytes of its row and XOR the values into its
 //    successors' slots.
 // A (word, class) stream with more entries than its capacity (8 standard
 // deviations above the mean) is instead walked afresh at every NOISE step
@@ -78,13 +78,13 @@ __device__ __forceinline__ uint32_t branch_of(const uint64_t *thr, uint64_t info
 // Slot array: slot s holds the tile's 16 words at s * TW + (w ^ (s & 15)).  The
 // swizzle spreads one word column over the LDS banks (an unswizzled column sits
 // in one bank pair, so 64 lanes XOR-ing random slots of one word would
-// serialise); the two words of an even-aligned pair stay one 16-byte chunk,
-// in swapped order when s is odd.
+// serialise); the four words wl .. wl + 3 of an aligned quad stay one 32-byte
+// block, word wl + i at element i ^ (s & 3).
 __device__ __forceinline__ unsigned long long *slot_word(unsigned long long *slots, uint32_t s, uint32_t w) {
     return &slots[(size_t)s * TW + (w ^ (s & 15u))];
 }
-__device__ __forceinline__ unsigned long long *slot_pair(unsigned long long *slots, uint32_t s, uint32_t wl) {
-    return &slots[(size_t)s * TW + (wl ^ (s & 14u))];
+__device__ __forceinline__ unsigned long long *slot_quad(unsigned long long *slots, uint32_t s, uint32_t wl) {
+    return &slots[(size_t)s * TW + (wl ^ (s & 12u))];
 }
 
 // Flip entry: lane | cnt << 6 | step << 8 | s0 << 16 | s1 << 32 | s2 << 48,
@@ -97,13 +97,12 @@ __device__ __forceinline__ void apply_entry(uint64_t e, unsigned long long *slot
     if (cnt > 2) atomicXor(slot_word(slots, (uint32_t)(e >> 48), wl), bit);
 }
 
-// XOR (v0, v1) into words (wl, wl + 1) of slot s.
-__device__ __forceinline__ void push_pair(unsigned long long *slots, uint32_t s, uint32_t wl, unsigned long long v0,
-                                          unsigned long long v1) {
-    unsigned long long *d = slot_pair(slots, s, wl);
-    const bool sw = s & 1u;
-    atomicXor(d, sw ? v1 : v0);
-    atomicXor(d + 1, sw ? v0 : v1);
+// XOR v[0 .. 3] into words wl .. wl + 3 of slot s.
+__device__ __forceinline__ void push_quad(unsigned long long *slots, uint32_t s, uint32_t wl, const unsigned long long *v) {
+    unsigned long long *d = slot_quad(slots, s, wl);
+    const uint32_t x = s & 3u;
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) atomicXor(d + (i ^ x), v[i]);
 }
 
 struct Walk {
@@ -324,29 +323,41 @@ __device__ __forceinline__ unsigned long long rm_word(uint32_t t, uint64_t w, ui
     return (t & 1) ? ((uint64_t)o.z | ((uint64_t)o.w << 32)) : ((uint64_t)o.x | ((uint64_t)o.y << 32));
 }
 
-// One (node, word pair) of an EMIT step: the pair's two slot words are read
-// and cleared, the node's constant and RandomMeas words added, the values
-// staged for the store wave (with the node's row, or FR_NO_ROW when the row
-// is not written) and XOR-ed into the successors' slots.
-__device__ __forceinline__ void emit_pair(const DevProg &P, const FrameArgs &A, uint4 ra, uint4 rb, uint32_t q,
+// One (node, 4 words) of an EMIT step: the four slot words are read and
+// cleared, the node's constant and RandomMeas words added, the values staged
+// for the next step's stores (with the node's row, or FR_NO_ROW when the row
+// is not written) and XOR-ed into the successors' slots.  Thread q always
+// stages at the same place, so it stores the previous step's chunk and
+// stages the next one in program order without a second buffer.
+__device__ __forceinline__ void emit_quad(const DevProg &P, const FrameArgs &A, uint4 ra, uint4 rb, uint32_t q,
                                           uint64_t wt, unsigned long long *slots, unsigned long long *stg,
                                           uint32_t *rows, unsigned long long *fl, uint32_t k0, uint32_t k1) {
-    const uint32_t vi = q >> 3, wl = 2 * (q & 7u);
+    const uint32_t vi = q >> 2, wl = 4 * (q & 3u);
     const uint32_t flags = ra.x >> 24;
-    unsigned long long v0 = (flags & 1u) ? ~0ull : 0ull, v1 = v0;
+    const unsigned long long c = (flags & 1u) ? ~0ull : 0ull;
+    unsigned long long v[4] = {c, c, c, c};
     {
         // a node with no contributions reads the extra slot past the schedule's, which stays zero
-        const uint32_t sl = ra.x & 0xFFFFFFu;
-        ulonglong2 *sp = (ulonglong2 *)slot_pair(slots, sl, wl);
-        const ulonglong2 sv = *sp;
-        v0 ^= (sl & 1u) ? sv.y : sv.x;
-        v1 ^= (sl & 1u) ? sv.x : sv.y;
-        *sp = make_ulonglong2(0ull, 0ull);
+        const uint32_t sl = ra.x & 0xFFFFFFu, x = sl & 3u;
+        unsigned long long *sp = slot_quad(slots, sl, wl);
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) v[i] ^= sp[i ^ x];
+        ((ulonglong2 *)sp)[0] = make_ulonglong2(0ull, 0ull);
+        ((ulonglong2 *)sp)[1] = make_ulonglong2(0ull, 0ull);
     }
     if (flags & 4u) {
+        // one word at a time (four Philox blocks in flight would spill registers):
+        // each pass adds the word to v[0] and rotates, which after four passes
+        // leaves every word back in place
         const uint64_t w = A.word_begin + wt + wl;
-        v0 ^= rm_word(ra.z, w, k0, k1);
-        v1 ^= rm_word(ra.z, w + 1, k0, k1);
+#pragma unroll 1
+        for (uint32_t i = 0; i < 4; ++i) {
+            const unsigned long long t = v[0] ^ rm_word(ra.z, w + i, k0, k1);
+            v[0] = v[1];
+            v[1] = v[2];
+            v[2] = v[3];
+            v[3] = t;
+        }
     }
     if (A.cnt.on) {
         // aggregate counts: a postselected detector ORs into the discarded
@@ -355,66 +366,75 @@ __device__ __forceinline__ void emit_pair(const DevProg &P, const FrameArgs &A, 
         if (sec == 2u) {
             const uint32_t d = ra.y - P.n_rec;
             if ((A.cnt.post[d >> 5] >> (d & 31u)) & 1u) {
-                atomicOr(&fl[wl], v0);
-                atomicOr(&fl[wl + 1], v1);
+#pragma unroll
+                for (uint32_t i = 0; i < 4; ++i) atomicOr(&fl[wl + i], v[i]);
             }
         } else if (sec == 3u) {
             const uint32_t o = ra.y - P.n_rec - P.n_det;
             const unsigned long long x = ((A.cnt.obs_exp[o >> 5] >> (o & 31u)) & 1u) ? ~0ull : 0ull;
-            atomicOr(&fl[TW + wl], v0 ^ x);
-            atomicOr(&fl[TW + wl + 1], v1 ^ x);
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) atomicOr(&fl[TW + wl + i], v[i] ^ x);
         }
     }
-    *(ulonglong2 *)&stg[vi * TW + wl] = make_ulonglong2(v0, v1);
+    ((ulonglong2 *)&stg[vi * TW + wl])[0] = make_ulonglong2(v[0], v[1]);
+    ((ulonglong2 *)&stg[vi * TW + wl])[1] = make_ulonglong2(v[2], v[3]);
     {
         // every lane of the node writes the same row index
         const uint32_t sec = (flags >> 4) & 3u;
         rows[vi] = (ra.y != FR_NO_ROW && sec && ((A.sections >> (sec - 1)) & 1u)) ? ra.y : FR_NO_ROW;
     }
     const uint32_t np = ra.w;
-    if (np > 0) push_pair(slots, rb.x, wl, v0, v1);
-    if (np > 1) push_pair(slots, rb.y, wl, v0, v1);
-    for (uint32_t k = 2; k < np; ++k) push_pair(slots, P.fr_push[rb.z + k - 2], wl, v0, v1);
+    if (np > 0) push_quad(slots, rb.x, wl, v);
+    if (np > 1) push_quad(slots, rb.y, wl, v);
+    for (uint32_t k = 2; k < np; ++k) push_quad(slots, P.fr_push[rb.z + k - 2], wl, v);
 }
 
-// One 16-byte chunk (node q / 8, words 2 (q % 8), +1) of the rows staged by
-// an EMIT step of n nodes.
+// One 32-byte chunk (node q / 4, words 4 (q % 4) .. + 3) of the rows staged
+// by an EMIT step.
 __device__ __forceinline__ void store_chunk(const FrameArgs &A, const unsigned long long *stg, const uint32_t *rows,
                                             uint32_t q, uint64_t wt, bool full) {
-    const uint32_t v = q >> 3, pw = 2 * (q & 7u);
+    const uint32_t v = q >> 2, pw = 4 * (q & 3u);
     const uint32_t row = rows[v];
     const uint64_t wi = wt + pw;
+    const ulonglong2 *src = (const ulonglong2 *)&stg[v * TW + pw];
     if (full) {
         // every word of the tile is whole and 16-byte stores are allowed
         if (row == FR_NO_ROW) return;
-        *(ulonglong2 *)((unsigned long long *)A.out + (uint64_t)row * A.row_stride + wi) =
-            *(const ulonglong2 *)&stg[v * TW + pw];
+        ulonglong2 *dst = (ulonglong2 *)((unsigned long long *)A.out + (uint64_t)row * A.row_stride + wi);
+        const ulonglong2 a = src[0], b = src[1];
+        dst[0] = a;
+        dst[1] = b;
         return;
     }
-    if (row == FR_NO_ROW || wi >= A.n_words) return;
-    const ulonglong2 val = *(const ulonglong2 *)&stg[v * TW + pw];
-    const unsigned long long m0 = word_mask(wi, A.shots), m1 = word_mask(wi + 1, A.shots);
-    unsigned long long *dst = (unsigned long long *)A.out + (uint64_t)row * A.row_stride + wi;
-    if (A.store16 && wi + 1 < A.n_words) {
-        *(ulonglong2 *)dst = make_ulonglong2(val.x & m0, val.y & m1);
-    } else {
-        dst[0] = val.x & m0;
-        if (wi + 1 < A.n_words) dst[1] = val.y & m1;
+    if (row == FR_NO_ROW) return;
+#pragma unroll
+    for (uint32_t h = 0; h < 2; ++h) {
+        const uint64_t wh = wi + 2 * h;
+        if (wh >= A.n_words) return;
+        const ulonglong2 val = src[h];
+        const unsigned long long m0 = word_mask(wh, A.shots), m1 = word_mask(wh + 1, A.shots);
+        unsigned long long *dst = (unsigned long long *)A.out + (uint64_t)row * A.row_stride + wh;
+        if (A.store16 && wh + 1 < A.n_words) {
+            *(ulonglong2 *)dst = make_ulonglong2(val.x & m0, val.y & m1);
+        } else {
+            dst[0] = val.x & m0;
+            if (wh + 1 < A.n_words) dst[1] = val.y & m1;
+        }
     }
 }
 
-constexpr uint32_t NWC = 8;                        // waves; FR_LEVEL_MAX * TW / 2 = NWC * 64
-constexpr uint32_t STG_WORDS = FR_LEVEL_MAX * TW;  // staged u64 per buffer
+constexpr uint32_t NWC = 8;                        // waves; FR_LEVEL_MAX * TW / 4 = NWC * 64
+constexpr uint32_t STG_WORDS = FR_LEVEL_MAX * TW;  // staged u64
 constexpr uint32_t WPW = TW / NWC;                 // words per wave in NOISE steps
 
 // Workgroup: 8 waves.  LDS: slots [NS][TW] u64 | stream states [TW][NC] |
 // entry cursors and counts [TW][NC] | overflow flags [TW] | aggregate-count
 // flags [2][TW] u64 (discarded, logical error) | one region used by
-// phase G as walk positions [NWC][256] and by phase S as two staging buffers
+// phase G as walk positions [NWC][256] and by phase S as the staging buffer
 // ([FR_LEVEL_MAX][TW] u64 + [FR_LEVEL_MAX] rows).
 // Phase S orders each step so that nothing it waits for was issued in the
 // same step: the rows staged by the previous EMIT step are stored first (one
-// 16-byte chunk per thread), node records were fetched one EMIT step ahead
+// 32-byte chunk per thread), node records were fetched one EMIT step ahead
 // and the first flip entries of a NOISE step right after the previous NOISE
 // step; a step record (one scalar load) names what the next steps need.  (Vector loads and stores share one completion counter, so a load
 // issued behind fresh stores would wait for them.)  Every slot is zero
@@ -436,8 +456,8 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
     unsigned long long *fl = (unsigned long long *)(smem + ((((unsigned char *)(ovf + TW) - smem) + 15) & ~(ptrdiff_t)15));
     unsigned char *region = (unsigned char *)(fl + 2 * TW);
     uint32_t *tmp = (uint32_t *)region + (size_t)wave * 256;
-    unsigned long long *stg = (unsigned long long *)region;         // [2][STG_WORDS]
-    uint32_t *rows = (uint32_t *)(stg + 2 * STG_WORDS);              // [2][FR_LEVEL_MAX]
+    unsigned long long *stg = (unsigned long long *)region;         // [STG_WORDS]
+    uint32_t *rows = (uint32_t *)(stg + STG_WORDS);                  // [FR_LEVEL_MAX]
     const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
     const uint64_t n_tiles = (A.n_words + TW - 1) / TW;
     uint64_t *scr = A.scratch + (size_t)blockIdx.x * (TW * A.word_entries + NWC * 128);
@@ -481,13 +501,13 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
         __syncthreads();
         // phase S
         const cptr<uint32_t> stp = uniform(P.fr_step);
-        uint32_t e_idx = 0, pend_n = 0;
+        uint32_t pend_n = 0;
         uint4 pa = make_uint4(0, 0, 0, 0), pb = pa;
         uint64_t pe[WPW];
         uint32_t pk[WPW];
         auto fetch_records = [&](uint32_t first, uint32_t n) {
-            if (tid < n * (TW / 2)) {
-                const uint4 *rec = (const uint4 *)(P.fr_nodes + 8 * (size_t)(first + (tid >> 3)));
+            if (tid < n * (TW / 4)) {
+                const uint4 *rec = (const uint4 *)(P.fr_nodes + 8 * (size_t)(first + (tid >> 2)));
                 pa = rec[0];
                 pb = rec[1];
             }
@@ -556,26 +576,19 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
                 for (uint32_t i = 0; i < WPW; ++i) asm volatile("" : : "v"(pe[i]));
             }
             // rows staged by the previous step (if it was an EMIT step)
-            if (tid < pend_n * (TW / 2))
-                store_chunk(A, stg + (size_t)((e_idx - 1) & 1u) * STG_WORDS, rows + ((e_idx - 1) & 1u) * FR_LEVEL_MAX,
-                            tid, wt, full);
+            if (tid < pend_n * (TW / 4)) store_chunk(A, stg, rows, tid, wt, full);
             pend_n = 0;
             if (is_emit) {
                 const uint32_t n = r[2];
                 fetch_records(r[5], r[6]);
-                if (tid < n * (TW / 2))
-                    emit_pair(P, A, ra, rb, tid, wt, slots, stg + (size_t)(e_idx & 1u) * STG_WORDS,
-                              rows + (e_idx & 1u) * FR_LEVEL_MAX, fl, k0, k1);
+                if (tid < n * (TW / 4)) emit_quad(P, A, ra, rb, tid, wt, slots, stg, rows, fl, k0, k1);
                 pend_n = n;
-                ++e_idx;
             } else {
                 noise_step(r);
             }
             __syncthreads();
         }
-        if (tid < pend_n * (TW / 2))
-            store_chunk(A, stg + (size_t)((e_idx - 1) & 1u) * STG_WORDS, rows + ((e_idx - 1) & 1u) * FR_LEVEL_MAX,
-                        tid, wt, full);
+        if (tid < pend_n * (TW / 4)) store_chunk(A, stg, rows, tid, wt, full);
         __syncthreads();
         if (A.cnt.on && tid < TW) {
             // the tile's flags: kept shots only can have a logical error; bits past the shot count are 0
@@ -620,7 +633,7 @@ size_t frame_lds_bytes(const DevProg &P) {
     // slots | stream states | cursors and counts | overflow flags | count flags | (walk positions or staging)
     const size_t head = (size_t)(P.fr_n_slots + 1) * TW * 8 + (size_t)TW * P.n_cls * (sizeof(FrWord) + 8) + TW * 4;
     const size_t flags = 2 * TW * 8;
-    const size_t region = std::max<size_t>((size_t)NWC * 256 * 4, 2 * (STG_WORDS * 8 + FR_LEVEL_MAX * 4));
+    const size_t region = std::max<size_t>((size_t)NWC * 256 * 4, STG_WORDS * 8 + FR_LEVEL_MAX * 4);
     return ((head + 15) & ~(size_t)15) + flags + region;
 }
 
