@@ -74,7 +74,7 @@ struct DevProg {
     const uint32_t *fr_nodes;    // 8 words per node: slot | flags << 24, row, meas, push count, two successor slots, push offset, 0
     const uint32_t *fr_push;     // successor slots
     const uint64_t *fr_chinfo;   // per (class, rank): flip-table offset | J << 26 | uniform << 32 | step << 33 | thr_off << 41
-    const uint64_t *fr_fltab;    // per (channel, branch): flip-entry count | first entry << 8
+    const uint64_t *fr_fltab;    // per (channel, branch): its one flip entry, or entry count | first entry << 8
     const uint64_t *fr_fl3;      // flip entries: cnt << 6 | up to three 16-bit slots from bit 16
     const uint32_t *fr_cap;      // per class: flip entries kept per (word, class)
     const uint32_t *fr_capoff;   // per class + 1: prefix of fr_cap

@@ -31,17 +31,22 @@
 namespace symft {
 
 // Flip entries of one (channel, branch): ceil(n / 3) entries
-// cnt << 6 | s0 << 16 | s1 << 32 | s2 << 48 (cnt = slots in the entry, 1..3);
-// returns the flip-table word: entry count | first entry << 8.
+// cnt << 6 | s0 << 16 | s1 << 32 | s2 << 48 (cnt = slots in the entry, 1..3).
+// Returns the flip-table word: the entry itself when there is exactly one
+// (bits 6..7 nonzero), else entry count | first entry << 8 (bits 6..7 zero,
+// count < 64), so the common single-entry event needs no second lookup.
 static uint64_t pack_flips(const std::vector<uint32_t> &fl, std::vector<uint64_t> &fl3) {
-    const uint64_t off = fl3.size(), k = (fl.size() + 2) / 3;
+    std::vector<uint64_t> es;
     for (size_t i = 0; i < fl.size(); i += 3) {
         const size_t cnt = std::min<size_t>(3, fl.size() - i);
         uint64_t e = (uint64_t)cnt << 6;
         for (size_t q = 0; q < cnt; ++q) e |= (uint64_t)fl[i + q] << (16 + 16 * q);
-        fl3.push_back(e);
+        es.push_back(e);
     }
-    return k | (off << 8);
+    if (es.size() == 1) return es[0];
+    const uint64_t off = fl3.size();
+    fl3.insert(fl3.end(), es.begin(), es.end());
+    return (uint64_t)es.size() | (off << 8);
 }
 
 // Elements of odd total multiplicity in a and b: the sum over GF(2) of two
@@ -287,7 +292,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             for (auto &kv : par)
                 if (kv.second) fl.push_back(kv.first);
             F.n_flips += fl.size();
-            if ((fl.size() + 2) / 3 > 255) return;  // flip-table words hold 8-bit entry counts
+            if ((fl.size() + 2) / 3 > 63) return;  // flip-table words hold 6-bit entry counts
             F.fltab.push_back(pack_flips(fl, F.fl3));
             // branch probability under the draw contract
             double pj = 1.0 / ch.J;

@@ -110,7 +110,7 @@ struct FrameSchedule {
     std::vector<uint32_t> nodes;    // 8 per node
     std::vector<uint32_t> push;
     std::vector<uint64_t> chinfo;   // indexed by class offset + rank
-    std::vector<uint64_t> fltab;    // per (channel, branch): entry count | first flip entry << 8
+    std::vector<uint64_t> fltab;    // per (channel, branch): its one flip entry, or entry count | first entry << 8
     std::vector<uint64_t> fl3;      // flip entries: cnt << 6 | three 16-bit slots from bit 16
     std::vector<uint32_t> cls_cap;  // flip entries kept per (word, class)
     uint32_t n_slots = 0;

@@ -109,6 +109,11 @@ struct Walk {
     uint32_t pos, j, e;
 };
 
+// Flip-table word of a (channel, branch): its single flip entry (slot count
+// in bits 6..7, nonzero), or entry count (bits 0..5) | first entry << 8.
+__device__ __forceinline__ bool flip_inline(uint64_t fw) { return ((fw >> 6) & 3u) != 0; }
+__device__ __forceinline__ uint32_t flip_count(uint64_t fw) { return flip_inline(fw) ? 1u : (uint32_t)(fw & 63u); }
+
 // Inclusive prefix sum over the 64 lanes of a wave by DPP: a 4-lane window
 // inside each row of 16 (row shifts 1..3), then banks (row shifts 4 and 8
 // into the upper banks), then rows (broadcasts of lanes 15 and 31).
@@ -261,7 +266,7 @@ __device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const 
             const uint32_t fi = (uint32_t)(info & 0x3FFFFFFu) + branch_of(T.thr, info, pick4(bb, i));
             fw[i] = T.fltab[fi];
             tag[i] = (uint64_t)(at & 63u) | (((info >> 33) & 0xFFu) << 8);
-            k_lane += (uint32_t)(fw[i] & 0xFFu);
+            k_lane += flip_count(fw[i]);
         }
     }
     if (GEN) {
@@ -271,7 +276,12 @@ __device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const 
         uint32_t o = *n_out + xs - k_lane;
 #pragma unroll
         for (uint32_t i = 0; i < 4; ++i) {
-            const uint32_t k = (uint32_t)(fw[i] & 0xFFu);
+            if (flip_inline(fw[i])) {
+                if (o < cap) out[o] = fw[i] | tag[i];
+                ++o;
+                continue;
+            }
+            const uint32_t k = flip_count(fw[i]);
             const uint64_t f0 = fw[i] >> 8;
             for (uint32_t q = 0; q < k; ++q, ++o)
                 if (o < cap) out[o] = T.fl3[f0 + q] | tag[i];
@@ -280,7 +290,11 @@ __device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const 
     } else {
 #pragma unroll
         for (uint32_t i = 0; i < 4; ++i) {
-            const uint32_t k = (uint32_t)(fw[i] & 0xFFu);
+            if (flip_inline(fw[i])) {
+                apply_entry(fw[i] | tag[i], slots, wl);
+                continue;
+            }
+            const uint32_t k = flip_count(fw[i]);
             const uint64_t f0 = fw[i] >> 8;
             for (uint32_t q = 0; q < k; ++q) apply_entry(T.fl3[f0 + q] | tag[i], slots, wl);
         }
