@@ -136,3 +136,27 @@ def test_sample_rejects_bad_offset_before_touching_the_gpu():
     o = S.symft_sample_opts()
     assert S._lib.symft_sample_ex(p.handle, C.byref(o), 64, 1, None, None) == -1
     assert S._lib.symft_sample_ex(p.handle, C.byref(o), 0, 1, None, None) == 0  # no-op
+
+
+def _fold_chain_circuit(n=6, p=0.1):
+    """A GHZ-style chain: Z_0 is random, every later Z_i is determined by the one just before it, and the
+    detectors compare neighbours.  No noise sits between the measurements."""
+    c = Circuit(n)
+    c.append("H", [0])
+    c.append("CX", [q for i in range(n - 1) for q in (i, i + 1)])
+    c.append("X_ERROR", list(range(n)), arg=p)
+    c.append("M", list(range(n)))
+    for i in range(n - 1):
+        c.detector([i, i + 1])
+    c.observable(0, [n - 1])
+    return c
+
+
+def test_frame_schedule_folds_same_level_dependencies():
+    """The chain's records and detectors each depend on nodes of their own level; folding those
+    dependencies (one RandomMeas word per node at most) puts all of them in one EMIT step after the
+    NOISE step, instead of a step per link."""
+    info = S.Program(_fold_chain_circuit()).info()
+    assert info["k_max"] == 0
+    assert info["frame_noise_steps"] == 1
+    assert info["frame_steps"] == 2

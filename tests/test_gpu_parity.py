@@ -290,6 +290,18 @@ def test_c2_entry_fallback_bit_exact(c2):
         assert np.array_equal(_gpu(p, 64 * 24, w.seed, frame_entry_cap=cap), want), cap
 
 
+def test_frame_folded_chain_bit_exact():
+    """Records and detectors of a chain folded into one EMIT level (each determined by the record just
+    before it, starting from a random outcome) equal the oracle's bit for bit."""
+    from tests.test_compile import _fold_chain_circuit
+    c = _fold_chain_circuit()
+    p = S.Program(c)
+    assert p.info()["frame_steps"] == 2
+    oc = OracleCircuit(c)
+    for n, off in ((64 * 9 + 5, 0), (64 * 40, 64 * 13)):
+        assert np.array_equal(_gpu(p, n, 0xF01D, shot_offset=off), oc.sample(0xF01D, n, shot_begin=off))
+
+
 @pytest.mark.parametrize("p32", [1, 4295, 429497, 4294967, 85899346, 1288490189, 2147483648, 4294967295, 4294967296])
 def test_gap_decision_at_table_boundaries(p32):
     Q = O.gap_table(p32).astype(np.int64)
