@@ -199,9 +199,10 @@ typedef struct {
                                       symft_autotune_counts for this program, postselection set and precision
                                       if it has run; else one shot group per workgroup from peak width 8 on,
                                       so a workgroup leaves a rejected shot at once, and the record path's
-                                      choice below); otherwise 4 .. 256, a power of two (peak width >= 13
-                                      always uses 1024).  From 64 on a workgroup holds one shot group.
-                                      Flags do not depend on it */
+                                      choice below); otherwise 4 .. 256, a power of two, or 1024 at peak
+                                      width >= 13 (peak widths 13 and 14 run 64 .. 256 with vectors in HBM,
+                                      values below 64 as 64; width 15 and above always uses 1024).  From 64
+                                      on a workgroup holds one shot group.  Flags do not depend on it */
     uint32_t reserved;             /* 0 */
 } symft_count_opts;
 
@@ -225,8 +226,9 @@ symft_status symft_sample_counts(const symft_program *p, const symft_count_opts 
                                  uint64_t seed, uint64_t *flags_out, uint64_t *counts_out, void *stream);
 
 /* Autotuner of the aggregate-count mode: times each threads-per-shot
- * configuration (4 .. 256) that fits LDS on min(4096, ...) words of this
- * program with opts' postselection set and precision (opts->threads_per_shot
+ * configuration (4 .. 256 that fits LDS; at peak widths 13 and 14, 64 .. 256
+ * with vectors in HBM and 1024) on 4096 words of this program (256 at widths
+ * 13 and 14) with opts' postselection set and precision (opts->threads_per_shot
  * and shot_offset are ignored) and keeps the fastest for later
  * symft_sample_counts calls with the same program, set and precision.
  * Fewer shot groups per workgroup let rejected shots end sooner; more keep
@@ -236,7 +238,10 @@ symft_status symft_sample_counts(const symft_program *p, const symft_count_opts 
 symft_status symft_autotune_counts(const symft_program *p, const symft_count_opts *opts, uint32_t *tps_out);
 
 /* Autotuner: times each threads-per-shot configuration (4 .. 256) of the
- * active-state kernel that fits LDS on 4096 words of this program and keeps the fastest
+ * active-state kernel that fits LDS on 4096 words of this program (at peak
+ * widths 13 and 14: 64 .. 256 with vectors in HBM, and 1024, on 256 words;
+ * untuned, those widths run 128 threads per shot in FP32 and 256 in FP64; from
+ * width 15 on, 1024 always) and keeps the fastest
  * for the program's (peak active width, precision); later launches with that
  * key use it (sample calls and batches alike).  Records do not depend on the
  * choice.  Synchronous; allocates a scratch output.  *tps_out (nullable)

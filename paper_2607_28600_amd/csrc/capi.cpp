@@ -381,6 +381,15 @@ static uint32_t default_tps(uint32_t k, bool fp64) {
     return e <= 2 ? 4u : e >= 8 ? 256u : (1u << e);
 }
 
+// Peak widths 13 and 14: narrow shot groups with vectors in HBM scratch
+// (which the L2 and the Infinity Cache hold at these sizes) keep many shots
+// in flight.  One shot per 1024-thread workgroup, with its vector in LDS,
+// left most threads idle at the small widths where a shot spends most of its
+// instructions (C5 at width 14: 72 ms against 15 ms at 128 threads per
+// shot).  From width 15 on, streaming the vector bounds the kernel, and 1024
+// threads per shot stream it best.
+static bool narrow_wide(uint32_t k) { return k >= 13 && k <= 14; }
+
 // count_mode: a workgroup holds one shot group when groups are a wave or
 // more (64 .. 256 threads), so it drops a discarded shot at once.
 ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, int context = 0,
@@ -388,20 +397,21 @@ ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, 
     ActiveConfig c;
     uint32_t k = P.k_max;
     c.bs = 256;
-    c.tps = default_tps(k, fp64);
+    c.tps = narrow_wide(k) ? (fp64 ? 256u : 128u) : default_tps(k, fp64);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find({k, fp64, context});
         if (it != g_tune.end()) c.tps = it->second;
     }
     if (force_tps) c.tps = force_tps;
+    if (narrow_wide(k) && c.tps < 64) c.tps = 64;
     if (count_mode && c.tps >= 64 && c.tps <= 256) c.bs = c.tps;
-    if (k >= 13) {
+    if (k >= 13 && (!narrow_wide(k) || c.tps > 256)) {
         c.bs = 1024;
         c.tps = 1024;
     }
     c.lds = active_lds_bytes(P, c.bs, c.tps, true, fp64);
-    c.lds_vec = c.lds <= kLdsLimit;
+    c.lds_vec = c.lds <= kLdsLimit && !(narrow_wide(k) && c.tps <= 256);
     if (!c.lds_vec) c.lds = active_lds_bytes(P, c.bs, c.tps, false, fp64);
     return c;
 }
@@ -416,7 +426,8 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
     int per_cu = active_max_blocks_per_cu(fp64, c.bs, c.lds_vec, c.lds, cnt != nullptr);
     if (per_cu <= 0) per_cu = 1;
     uint64_t cap = (uint64_t)per_cu * (uint64_t)num_cus();
-    if (!c.lds_vec) cap = std::min<uint64_t>(cap, (uint64_t)num_cus() * 2);
+    // HBM-resident vectors: about 1024 threads of shot groups per CU
+    if (!c.lds_vec) cap = std::min<uint64_t>(cap, (uint64_t)num_cus() * std::max<uint32_t>(2u, 1024u / c.bs));
     uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_words, cap));
     ActiveArgs A;
     std::memset(&A, 0, sizeof(A));
@@ -758,7 +769,7 @@ symft_status symft_sample_counts(const symft_program *pc, const symft_count_opts
     }
     // untuned: one shot group per workgroup once vectors are wide enough to keep 256 lanes busy
     if (!tps && D.k_max >= 8 && D.k_max < 13 && active_lds_bytes(D, 256, 256, true, fp64) <= kLdsLimit) tps = 256;
-    if (D.k_max >= 13) tps = 0;
+    if (D.k_max >= 13 && !narrow_wide(D.k_max)) tps = 0;
     return run_active(p, D, fp64, w0, n_words, shots, nullptr, n_words, 0u, nullptr, 0, 0, seed, st, tps, &C);
 }
 
@@ -779,11 +790,12 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
     rc = device_prog(p, D);
     if (rc) return rc;
     const bool fp64 = o.precision == 0;
-    if (D.fr_ok || D.k_max >= 13) {
+    if (D.fr_ok || (D.k_max >= 13 && !narrow_wide(D.k_max))) {
         if (tps_out) *tps_out = D.fr_ok ? 0 : 1024;
         return SYMFT_OK;
     }
-    const uint64_t words = 4096;
+    const bool wide = narrow_wide(D.k_max);
+    const uint64_t words = wide ? 256 : 4096;
     unsigned long long *cnt = nullptr;
     if (hipMalloc(&cnt, 16) != hipSuccess) return set_err(SYMFT_ENOMEM, "autotune buffer allocation failed");
     C.counts = cnt;
@@ -797,9 +809,10 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
     hipEventCreate(&e1);
     float best = 1e30f;
     uint32_t best_tps = 0;
-    for (uint32_t tps : {4u, 8u, 16u, 32u, 64u, 128u, 256u}) {
+    for (uint32_t tps : {4u, 8u, 16u, 32u, 64u, 128u, 256u, 1024u}) {
+        if (wide ? tps < 64 : tps > 256) continue;  // widths 13 and 14: 64 .. 256 threads, or 1024
         if (((uint32_t)1 << D.k_max) < tps / 4 && tps > 4) continue;  // most lanes would idle
-        if (active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
+        if (!wide && active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
         float ms = 0;
         for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
             hipEventRecord(e0, st);
@@ -924,11 +937,12 @@ symft_status symft_gap_check(uint64_t p32, const uint32_t *v, int32_t *g_out, ui
 // (k_max, precision, context).  Records do not depend on the choice; only
 // branch-probability rounding does.
 static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, uint32_t *tps_out, int context = 0) {
-    if (D.k_max >= 13 || D.fr_ok) {
+    if ((D.k_max >= 13 && !narrow_wide(D.k_max)) || D.fr_ok) {
         if (tps_out) *tps_out = D.k_max >= 13 ? 1024 : 0;
         return SYMFT_OK;
     }
-    const uint64_t words = context == 0 ? 4096 : 256;
+    const bool wide = narrow_wide(D.k_max);
+    const uint64_t words = wide || context != 0 ? 256 : 4096;
     uint64_t *out = nullptr;
     const uint64_t rows = std::max<uint64_t>(1, p->P.n_rows());
     if (hipMalloc(&out, 8 * rows * words) != hipSuccess) return set_err(SYMFT_ENOMEM, "autotune buffer allocation failed");
@@ -943,9 +957,10 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
     float best = 1e30f;
     uint32_t best_tps = default_tps(D.k_max, fp64);
     symft_status rc = SYMFT_OK;
-    for (uint32_t tps : {4u, 8u, 16u, 32u, 64u, 128u, 256u}) {
+    for (uint32_t tps : {4u, 8u, 16u, 32u, 64u, 128u, 256u, 1024u}) {
+        if (wide ? tps < 64 : tps > 256) continue;  // widths 13 and 14: 64 .. 256 threads, or 1024
         if (((uint32_t)1 << D.k_max) < tps / 4 && tps > 4) continue;  // most lanes would idle
-        if (active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
+        if (!wide && active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
         float ms = 0;
         for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
             hipEventRecord(e0, st);
