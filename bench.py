@@ -138,8 +138,9 @@ def run(args):
                     "traffic": round(traffic / 1e9, 3) if traffic else None, "traffic_unit": "GB/launch",
                     "kernel": "frame_kernel", "bytes_per_launch": rec_bytes}
             dtype = "u64"
-        elif (1 << info["k_max"]) * (8 if prec == "fp32" else 16) > LDS_BYTES:
-            # vectors streamed from HBM scratch: one read and one write of the live vector per instruction
+        elif (1 << info["k_max"]) * (8 if prec == "fp32" else 16) > LDS_BYTES or (13 <= info["k_max"] <= 14 and tps != 1024):
+            # vectors streamed from HBM scratch (always at peak widths 13 and 14 unless one shot runs per
+            # 1024-thread workgroup): one read and one write of the live vector per instruction
             nbytes = info["dense_bytes_per_shot"] * (1 if prec == "fp32" else 2) * w.shots
             achieved = nbytes / (ms_kernel / 1e3) / 1e9
             traffic = ACTIVE_TRAFFIC_BYTES.get(w.name) if prec == "fp32" and w.shots == 1 << 16 else None

@@ -795,7 +795,7 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
         return SYMFT_OK;
     }
     const bool wide = narrow_wide(D.k_max);
-    const uint64_t words = wide ? 256 : 4096;
+    const uint64_t words = wide ? 1024 : 4096;
     unsigned long long *cnt = nullptr;
     if (hipMalloc(&cnt, 16) != hipSuccess) return set_err(SYMFT_ENOMEM, "autotune buffer allocation failed");
     C.counts = cnt;
@@ -941,8 +941,9 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
         if (tps_out) *tps_out = D.k_max >= 13 ? 1024 : 0;
         return SYMFT_OK;
     }
+    // widths 13 and 14 run up to 1024 workgroups: time enough words to fill them
     const bool wide = narrow_wide(D.k_max);
-    const uint64_t words = wide || context != 0 ? 256 : 4096;
+    const uint64_t words = wide ? 1024 : context != 0 ? 256 : 4096;
     uint64_t *out = nullptr;
     const uint64_t rows = std::max<uint64_t>(1, p->P.n_rows());
     if (hipMalloc(&out, 8 * rows * words) != hipSuccess) return set_err(SYMFT_ENOMEM, "autotune buffer allocation failed");
