@@ -226,8 +226,9 @@ symft_status symft_sample_counts(const symft_program *p, const symft_count_opts 
                                  uint64_t seed, uint64_t *flags_out, uint64_t *counts_out, void *stream);
 
 /* Autotuner of the aggregate-count mode: times each threads-per-shot
- * configuration (4 .. 256 that fits LDS; at peak widths 13 and 14, 64 .. 256
- * with vectors in HBM and 1024) on 4096 words of this program (1024 at widths
+ * configuration (4 .. 256 that fits LDS; at widths 9 .. 12 also 64 .. 256 with
+ * vectors in HBM; at peak widths 13 and 14, 64 .. 256 with vectors in HBM and
+ * 1024) on 4096 words of this program (1024 at widths
  * 13 and 14) with opts' postselection set and precision (opts->threads_per_shot
  * and shot_offset are ignored) and keeps the fastest for later
  * symft_sample_counts calls with the same program, set and precision.
@@ -239,7 +240,8 @@ symft_status symft_autotune_counts(const symft_program *p, const symft_count_opt
 
 /* Autotuner: times each threads-per-shot configuration (4 .. 256) of the
  * active-state kernel that fits LDS on 4096 words of this program (at peak
- * widths 13 and 14: 64 .. 256 with vectors in HBM, and 1024, on 1024 words;
+ * widths 13 and 14: 64 .. 256 with vectors in HBM, and 1024, on 1024 words; at
+ * widths 9 .. 12 also 64 .. 256 with vectors in HBM instead of LDS;
  * untuned, those widths run 128 threads per shot in FP32 and 256 in FP64; from
  * width 15 on, 1024 always) and keeps the fastest
  * for the program's (peak active width, precision); later launches with that

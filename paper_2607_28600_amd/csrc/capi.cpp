@@ -390,6 +390,13 @@ static uint32_t default_tps(uint32_t k, bool fp64) {
 // threads per shot stream it best.
 static bool narrow_wide(uint32_t k) { return k >= 13 && k <= 14; }
 
+// A tuned (or forced) launch choice at peak widths 9..12 may carry this bit:
+// narrow groups with vectors in HBM scratch instead of LDS.  Only launches
+// that have the GPU to themselves are tuned that way; batch members keep LDS
+// vectors, which the batch kernel needs.
+static const uint32_t kHbmVec = 1u << 16;
+static bool hbm_candidate(uint32_t k) { return k >= 9 && k <= 12; }
+
 // count_mode: a workgroup holds one shot group when groups are a wave or
 // more (64 .. 256 threads), so it drops a discarded shot at once.
 ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, int context = 0,
@@ -404,6 +411,8 @@ ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, 
         if (it != g_tune.end()) c.tps = it->second;
     }
     if (force_tps) c.tps = force_tps;
+    const bool hbm = (c.tps & kHbmVec) && hbm_candidate(k);
+    c.tps &= ~kHbmVec;
     if (narrow_wide(k) && c.tps < 64) c.tps = 64;
     if (count_mode && c.tps >= 64 && c.tps <= 256) c.bs = c.tps;
     if (k >= 13 && (!narrow_wide(k) || c.tps > 256)) {
@@ -411,7 +420,7 @@ ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, 
         c.tps = 1024;
     }
     c.lds = active_lds_bytes(P, c.bs, c.tps, true, fp64);
-    c.lds_vec = c.lds <= kLdsLimit && !(narrow_wide(k) && c.tps <= 256);
+    c.lds_vec = c.lds <= kLdsLimit && !(narrow_wide(k) && c.tps <= 256) && !hbm;
     if (!c.lds_vec) c.lds = active_lds_bytes(P, c.bs, c.tps, false, fp64);
     return c;
 }
@@ -809,14 +818,16 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
     hipEventCreate(&e1);
     float best = 1e30f;
     uint32_t best_tps = 0;
-    for (uint32_t tps : {4u, 8u, 16u, 32u, 64u, 128u, 256u, 1024u}) {
+    for (uint32_t cand : {4u, 8u, 16u, 32u, 64u, 128u, 256u, 1024u, 64u | kHbmVec, 128u | kHbmVec, 256u | kHbmVec}) {
+        const uint32_t tps = cand & ~kHbmVec;
+        if ((cand & kHbmVec) && !hbm_candidate(D.k_max)) continue;
         if (wide ? tps < 64 : tps > 256) continue;  // widths 13 and 14: 64 .. 256 threads, or 1024
         if (((uint32_t)1 << D.k_max) < tps / 4 && tps > 4) continue;  // most lanes would idle
-        if (!wide && active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
+        if (!wide && !(cand & kHbmVec) && active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
         float ms = 0;
         for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
             hipEventRecord(e0, st);
-            rc = run_active(p, D, fp64, 0, words, words * 64, nullptr, words, 0u, nullptr, 0, 0, 0x7E57ull, st, tps, &C);
+            rc = run_active(p, D, fp64, 0, words, words * 64, nullptr, words, 0u, nullptr, 0, 0, 0x7E57ull, st, cand, &C);
             hipEventRecord(e1, st);
             hipEventSynchronize(e1);
             hipEventElapsedTime(&ms, e0, e1);
@@ -824,7 +835,7 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
         if (rc) break;
         if (ms < best) {
             best = ms;
-            best_tps = tps;
+            best_tps = cand;
         }
     }
     hipEventDestroy(e0);
@@ -836,7 +847,7 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
         std::lock_guard<std::mutex> lk(p->mu);
         p->count_tune[{key, fp64}] = best_tps;
     }
-    if (tps_out) *tps_out = best_tps;
+    if (tps_out) *tps_out = best_tps & ~kHbmVec;
     return SYMFT_OK;
 }
 
@@ -958,14 +969,17 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
     float best = 1e30f;
     uint32_t best_tps = default_tps(D.k_max, fp64);
     symft_status rc = SYMFT_OK;
-    for (uint32_t tps : {4u, 8u, 16u, 32u, 64u, 128u, 256u, 1024u}) {
+    const bool hbm_try = context == 0 && hbm_candidate(D.k_max);
+    for (uint32_t cand : {4u, 8u, 16u, 32u, 64u, 128u, 256u, 1024u, 64u | kHbmVec, 128u | kHbmVec, 256u | kHbmVec}) {
+        const uint32_t tps = cand & ~kHbmVec;
+        if ((cand & kHbmVec) && !hbm_try) continue;
         if (wide ? tps < 64 : tps > 256) continue;  // widths 13 and 14: 64 .. 256 threads, or 1024
         if (((uint32_t)1 << D.k_max) < tps / 4 && tps > 4) continue;  // most lanes would idle
-        if (!wide && active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
+        if (!wide && !(cand & kHbmVec) && active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
         float ms = 0;
         for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
             hipEventRecord(e0, st);
-            rc = run_active(p, D, fp64, 0, words, words * 64, out, words, 7u, nullptr, 0, 0, 0x7E57ull, st, tps);
+            rc = run_active(p, D, fp64, 0, words, words * 64, out, words, 7u, nullptr, 0, 0, 0x7E57ull, st, cand);
             hipEventRecord(e1, st);
             hipEventSynchronize(e1);
             hipEventElapsedTime(&ms, e0, e1);
@@ -973,7 +987,7 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
         if (rc) break;
         if (ms < best) {
             best = ms;
-            best_tps = tps;
+            best_tps = cand;
         }
     }
     hipEventDestroy(e0);
@@ -985,7 +999,7 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[{D.k_max, fp64, context}] = best_tps;
     }
-    if (tps_out) *tps_out = best_tps;
+    if (tps_out) *tps_out = best_tps & ~kHbmVec;
     return SYMFT_OK;
 }
 

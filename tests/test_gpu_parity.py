@@ -240,6 +240,22 @@ def test_autotune_choice_keeps_records():
     compare_records(got, oc.sample(w.seed, w.shots), w.circuit, oc, w.seed, 0, TOL["fp32"])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_autotuned_width_12_records(prec):
+    """A width-12 program after the autotuner, which at widths 9..12 also times narrow groups with vectors
+    in HBM scratch: records equal the oracle's outside the threshold exclusion, whichever it keeps."""
+    w = configs.postselect()
+    p = S.Program(w.circuit)
+    assert p.k_max == 12
+    tps = p.autotune(prec)
+    print(f"width-12 autotune {prec}: {tps} threads per shot", flush=True)
+    assert tps in (4, 8, 16, 32, 64, 128, 256)
+    oc = OracleCircuit(w.circuit)
+    n, off = 64 * 3 + 11, 64 * 40
+    got = _gpu(p, n, w.seed, shot_offset=off, precision=prec)
+    compare_records(got, oc.sample(w.seed, n, shot_begin=off), w.circuit, oc, w.seed, off, TOL[prec])
+
+
 def _multiclass_surface(d, rounds, k):
     """Surface-code memory whose channels carry k different probabilities (k classes, interleaved
     along the circuit), and one non-uniform general channel."""
