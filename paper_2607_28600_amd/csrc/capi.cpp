@@ -163,6 +163,12 @@ static void lower(symft_program *h) {
         }
         for (uint32_t s : I.lam.noise) cons[s].push_back((uint32_t)i);
     }
+    // A rotation followed at once by a promotion at the same width runs both in
+    // one pass over the vector: the promotion reads what the rotation writes.
+    for (size_t i = 0; i + 1 < ins.size(); ++i)
+        if ((ins[i].kind == ACTIVE_DIAG_ROT || ins[i].kind == ACTIVE_PAIR_ROT) && ins[i + 1].kind == PROMOTE_ROT &&
+            ins[i + 1].k_in == ins[i].k_in && !(i > 0 && ins[i - 1].fuse))
+            ins[i].fuse = 1;
     std::vector<uint32_t> symoff(P.n_noise_sym + 1, 0), symcons;
     for (uint32_t s = 0; s < P.n_noise_sym; ++s) {
         symoff[s] = (uint32_t)symcons.size();

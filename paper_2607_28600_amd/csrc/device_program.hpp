@@ -11,7 +11,10 @@ namespace symft {
 // evaluate no transcendental function.
 struct DevInstr {
     uint8_t kind, k_in, h, mu;     // mu: power of i
-    uint8_t eta, lam_c, pad0, pad1;
+    uint8_t eta, lam_c;
+    uint8_t fuse;                  // rotations: 1 = the next instruction, a PromoteRot at the same width,
+                                   // is applied in the same pass over the vector
+    uint8_t pad1;
     uint32_t a, b;
     int32_t meas;                  // measurement index (measurements)
     uint32_t cm_off, cm_len;       // causal refs of lambda: cm_len (word, mask) pairs from pair cm_off

@@ -55,7 +55,8 @@ __device__ __forceinline__ DevInstr load_instr(const DevInstr *p, uint32_t i) {
     d.mu = (uint8_t)(w0 >> 24);
     d.eta = (uint8_t)w1;
     d.lam_c = (uint8_t)(w1 >> 8);
-    d.pad0 = d.pad1 = 0;
+    d.fuse = (uint8_t)(w1 >> 16);
+    d.pad1 = 0;
     d.a = q[2];
     d.b = q[3];
     d.meas = (int32_t)q[4];
@@ -67,6 +68,18 @@ __device__ __forceinline__ DevInstr load_instr(const DevInstr *p, uint32_t i) {
     d.cf = __uint_as_float(q[12]);
     d.sf = __uint_as_float(q[13]);
     return d;
+}
+
+// PromoteRot of amplitude v at x < N: x keeps c v, x + N gets -i ss v (ss = (-1)^lambda s).
+template <typename V, typename T>
+__device__ __forceinline__ void put_promoted(V *vec, uint32_t x, uint32_t N, V v, T c, T ss) {
+    V hi;
+    hi.x = ss * v.y;
+    hi.y = -ss * v.x;
+    vec[x + N] = hi;
+    v.x *= c;
+    v.y *= c;
+    vec[x] = v;
 }
 
 // Block-wide exclusive scan of (a, b) pairs packed as 64-bit (a in low 32).
@@ -317,6 +330,14 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
             gsync();
             // the next instruction's descriptor and first causal ref are fetched
             // while this one runs
+            // coefficients of the PromoteRot at instruction j, for a rotation that runs it in its own pass
+            auto promote_coef = [&](uint32_t j, T &pc, T &pss) {
+                const DevInstr J = load_instr(P.instr, j);
+                const int lam2 = (int)J.lam_c ^ (int)((exo[j] >> lane) & 1ull) ^ causal_parity(P, J, mb);
+                pc = sizeof(T) == 8 ? (T)J.c : (T)J.cf;
+                const T s2 = sizeof(T) == 8 ? (T)J.s : (T)J.sf;
+                pss = lam2 ? -s2 : s2;
+            };
             for (uint32_t ii = 0; ii < P.n_instr; ++ii) {
                 const DevInstr I = load_instr(P.instr, ii);
                 const uint32_t N = 1u << I.k_in;
@@ -331,19 +352,13 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 case 1: {  // PromoteRot: x0 <- c a_x, x1 <- -i (-1)^lam s a_x
                     const T ss = lam ? -s : s;
                     if (live)
-                    for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
-                        V v = vec[x];
-                        V hi;
-                        hi.x = ss * v.y;
-                        hi.y = -ss * v.x;
-                        vec[x + N] = hi;
-                        v.x *= c; v.y *= c;
-                        vec[x] = v;
-                    }
+                    for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) put_promoted(vec, x, N, vec[x], c, ss);
                     break;
                 }
                 case 2: {  // ActiveDiagRot: a_x *= c - i sigma s, sigma = (-1)^lam mu (-1)^(b.x)
                     const int neg = lam ^ (I.mu == 2 ? 1 : 0);
+                    T pc = 0, pss = 0;
+                    if (I.fuse) promote_coef(ii + 1, pc, pss);
                     if (live)
                     for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
                         const T sg = (neg ^ parity(I.b & x)) ? -s : s;
@@ -351,8 +366,10 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                         V o;
                         o.x = c * v.x + sg * v.y;
                         o.y = c * v.y - sg * v.x;
-                        vec[x] = o;
+                        if (I.fuse) put_promoted(vec, x, N, o, pc, pss);
+                        else vec[x] = o;
                     }
+                    if (I.fuse) ++ii;  // the PromoteRot ran in this pass
                     break;
                 }
                 case 3: {  // ActivePairRot on pairs (x0, x0 ^ a), bit h of x0 = 0
@@ -360,6 +377,8 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                     // -i mu = i^(m+3)
                     const uint32_t half = N >> 1;
                     const int e0 = (int)I.mu + 3 + 2 * lam;
+                    T pc = 0, pss = 0;
+                    if (I.fuse) promote_coef(ii + 1, pc, pss);
                     if (live)
                     for (uint32_t z = (uint32_t)r; z < half; z += (uint32_t)tps) {
                         const uint32_t x0 = insert_bit(z, I.h, 0), x1 = x0 ^ I.a;
@@ -376,9 +395,15 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                         V n0, n1;
                         n0.x = c * a0.x + s * t0.x; n0.y = c * a0.y + s * t0.y;
                         n1.x = c * a1.x + s * t1.x; n1.y = c * a1.y + s * t1.y;
-                        vec[x0] = n0;
-                        vec[x1] = n1;
+                        if (I.fuse) {
+                            put_promoted(vec, x0, N, n0, pc, pss);
+                            put_promoted(vec, x1, N, n1, pc, pss);
+                        } else {
+                            vec[x0] = n0;
+                            vec[x1] = n1;
+                        }
                     }
+                    if (I.fuse) ++ii;  // the PromoteRot ran in this pass
                     break;
                 }
                 case 4: {  // RandomMeas
