@@ -163,12 +163,25 @@ static void lower(symft_program *h) {
         }
         for (uint32_t s : I.lam.noise) cons[s].push_back((uint32_t)i);
     }
-    // A rotation followed at once by a promotion at the same width runs both in
-    // one pass over the vector: the promotion reads what the rotation writes.
-    for (size_t i = 0; i + 1 < ins.size(); ++i)
-        if ((ins[i].kind == ACTIVE_DIAG_ROT || ins[i].kind == ACTIVE_PAIR_ROT) && ins[i + 1].kind == PROMOTE_ROT &&
-            ins[i + 1].k_in == ins[i].k_in && !(i > 0 && ins[i - 1].fuse))
-            ins[i].fuse = 1;
+    // Rotations followed at once by more work at the same width share one pass
+    // over the vector (each step reads what the one before it writes): a pair
+    // rotation and a pair rotation with another mask (on the cosets of both
+    // masks), optionally then a promotion; or any rotation and a promotion.
+    for (size_t i = 0; i + 1 < ins.size(); ++i) {
+        DevInstr &R = ins[i];
+        if (R.kind != ACTIVE_DIAG_ROT && R.kind != ACTIVE_PAIR_ROT) continue;
+        const DevInstr &X = ins[i + 1];
+        if (R.kind == ACTIVE_PAIR_ROT && X.kind == ACTIVE_PAIR_ROT && X.k_in == R.k_in && X.a != R.a) {
+            const bool prom = i + 2 < ins.size() && ins[i + 2].kind == PROMOTE_ROT && ins[i + 2].k_in == R.k_in;
+            R.fuse = prom ? 3 : 2;
+            // FP64 kernels run only rotation-promotion passes; they take this mark
+            if (prom) ins[i + 1].fuse = 1;
+            i += prom ? 2 : 1;
+        } else if (X.kind == PROMOTE_ROT && X.k_in == R.k_in) {
+            R.fuse = 1;
+            i += 1;
+        }
+    }
     std::vector<uint32_t> symoff(P.n_noise_sym + 1, 0), symcons;
     for (uint32_t s = 0; s < P.n_noise_sym; ++s) {
         symoff[s] = (uint32_t)symcons.size();

@@ -12,8 +12,12 @@ namespace symft {
 struct DevInstr {
     uint8_t kind, k_in, h, mu;     // mu: power of i
     uint8_t eta, lam_c;
-    uint8_t fuse;                  // rotations: 1 = the next instruction, a PromoteRot at the same width,
-                                   // is applied in the same pass over the vector
+    uint8_t fuse;                  // rotations: instructions that follow at the same width and run in the
+                                   // same pass over the vector: 1 a PromoteRot; 2 a pair rotation (after a
+                                   // pair rotation with another mask); 3 a pair rotation, then a PromoteRot
+                                   // (2 and 3 with FP32 vectors in HBM scratch and a coset per thread
+                                   // only; otherwise such a pair rotation runs alone, and the middle one
+                                   // of 3 carries mark 1)
     uint8_t pad1;
     uint32_t a, b;
     int32_t meas;                  // measurement index (measurements)

@@ -70,6 +70,25 @@ __device__ __forceinline__ DevInstr load_instr(const DevInstr *p, uint32_t i) {
     return d;
 }
 
+// One pair of an ActivePairRot: (va at ya, vb at yb = ya ^ a) become
+// c va + s i^q(ya) vb and c vb + s i^q(yb) va, q(y) = e0 + 2 b.(y ^ a) mod 4.
+template <typename V, typename T>
+__device__ __forceinline__ void pair_update(V &va, V &vb, uint32_t ya, uint32_t yb, int e0, uint32_t b, T c, T s) {
+    const int qa = (e0 + 2 * parity(b & yb)) & 3;
+    const int qb = (e0 + 2 * parity(b & ya)) & 3;
+    // multiply by i^q
+    V ta, tb;
+    ta.x = (qa == 0) ? vb.x : (qa == 1) ? -vb.y : (qa == 2) ? -vb.x : vb.y;
+    ta.y = (qa == 0) ? vb.y : (qa == 1) ? vb.x : (qa == 2) ? -vb.y : -vb.x;
+    tb.x = (qb == 0) ? va.x : (qb == 1) ? -va.y : (qb == 2) ? -va.x : va.y;
+    tb.y = (qb == 0) ? va.y : (qb == 1) ? va.x : (qb == 2) ? -va.y : -va.x;
+    V na, nb;
+    na.x = c * va.x + s * ta.x; na.y = c * va.y + s * ta.y;
+    nb.x = c * vb.x + s * tb.x; nb.y = c * vb.y + s * tb.y;
+    va = na;
+    vb = nb;
+}
+
 // PromoteRot of amplitude v at x < N: x keeps c v, x + N gets -i ss v (ss = (-1)^lambda s).
 template <typename V, typename T>
 __device__ __forceinline__ void put_promoted(V *vec, uint32_t x, uint32_t N, V v, T c, T ss) {
@@ -375,10 +394,52 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 case 3: {  // ActivePairRot on pairs (x0, x0 ^ a), bit h of x0 = 0
                     // a'_x = c a_x - i (-1)^lam s mu (-1)^(b.(x^a)) a_(x^a); with mu = i^m:
                     // -i mu = i^(m+3)
-                    const uint32_t half = N >> 1;
                     const int e0 = (int)I.mu + 3 + 2 * lam;
+                    // passes over two pair rotations: vectors in HBM scratch and FP32 only
+                    // (with LDS vectors the four scattered reads of a coset cost more than
+                    // the second pass; FP64 would lose occupancy), and only when every
+                    // thread of the group has a coset
+                    const uint32_t fz =
+                        (I.fuse >= 2 && (LDSV || sizeof(T) == 8 || (N >> 2) < (uint32_t)tps)) ? 0u : I.fuse;
                     T pc = 0, pss = 0;
-                    if (I.fuse) promote_coef(ii + 1, pc, pss);
+                    if (fz == 1 || fz == 3) promote_coef(ii + (fz == 3 ? 2u : 1u), pc, pss);
+                    if (fz >= 2) {
+                        // with the pair rotation (mask a2) that follows, on the cosets
+                        // x + {0, a, a2, a ^ a2}: x has zeros at h and at the top bit of
+                        // a2 reduced by a at h, two pivots no coset repeats
+                        const DevInstr I2 = load_instr(P.instr, ii + 1);
+                        const int lam2 = (int)I2.lam_c ^ (int)((exo[ii + 1] >> lane) & 1ull) ^ causal_parity(P, I2, mb);
+                        const T c2 = sizeof(T) == 8 ? (T)I2.c : (T)I2.cf;
+                        const T s2 = sizeof(T) == 8 ? (T)I2.s : (T)I2.sf;
+                        const int e02 = (int)I2.mu + 3 + 2 * lam2;
+                        const uint32_t a2r = I2.a ^ (((I2.a >> I.h) & 1u) ? I.a : 0u);
+                        const uint32_t h2 = 31u - (uint32_t)__builtin_clz(a2r);
+                        const uint32_t plo = h2 < I.h ? h2 : (uint32_t)I.h, phi = h2 < I.h ? (uint32_t)I.h : h2;
+                        if (live)
+                        for (uint32_t z = (uint32_t)r; z < (N >> 2); z += (uint32_t)tps) {
+                            const uint32_t y0 = insert_bit(insert_bit(z, plo, 0), phi, 0);
+                            const uint32_t y1 = y0 ^ I.a, y2 = y0 ^ I2.a, y3 = y1 ^ I2.a;
+                            V v0 = vec[y0], v1 = vec[y1], v2 = vec[y2], v3 = vec[y3];
+                            pair_update(v0, v1, y0, y1, e0, I.b, c, s);
+                            pair_update(v2, v3, y2, y3, e0, I.b, c, s);
+                            pair_update(v0, v2, y0, y2, e02, I2.b, c2, s2);
+                            pair_update(v1, v3, y1, y3, e02, I2.b, c2, s2);
+                            if (fz == 3) {
+                                put_promoted(vec, y0, N, v0, pc, pss);
+                                put_promoted(vec, y1, N, v1, pc, pss);
+                                put_promoted(vec, y2, N, v2, pc, pss);
+                                put_promoted(vec, y3, N, v3, pc, pss);
+                            } else {
+                                vec[y0] = v0;
+                                vec[y1] = v1;
+                                vec[y2] = v2;
+                                vec[y3] = v3;
+                            }
+                        }
+                        ii += fz == 3 ? 2u : 1u;  // the instructions that ran in this pass
+                        break;
+                    }
+                    const uint32_t half = N >> 1;
                     if (live)
                     for (uint32_t z = (uint32_t)r; z < half; z += (uint32_t)tps) {
                         const uint32_t x0 = insert_bit(z, I.h, 0), x1 = x0 ^ I.a;
@@ -395,7 +456,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                         V n0, n1;
                         n0.x = c * a0.x + s * t0.x; n0.y = c * a0.y + s * t0.y;
                         n1.x = c * a1.x + s * t1.x; n1.y = c * a1.y + s * t1.y;
-                        if (I.fuse) {
+                        if (fz) {
                             put_promoted(vec, x0, N, n0, pc, pss);
                             put_promoted(vec, x1, N, n1, pc, pss);
                         } else {
@@ -403,7 +464,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                             vec[x1] = n1;
                         }
                     }
-                    if (I.fuse) ++ii;  // the PromoteRot ran in this pass
+                    if (fz) ++ii;  // the PromoteRot ran in this pass
                     break;
                 }
                 case 4: {  // RandomMeas
