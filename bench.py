@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # the one the counters were taken on.
 FRAME_TRAFFIC_BYTES = {"surface_d11_r11_p1e-3": (1874670 * 2 + 8218314) * 1024}
 # The same for the active kernel with HBM-resident vectors (FP32, 2^16 shots).
-ACTIVE_TRAFFIC_BYTES = {"near_clifford_n48_k16": (770688326 * 2 + 1308289750) * 1024}
+ACTIVE_TRAFFIC_BYTES = {"near_clifford_n48_k16": (688241884 * 2 + 1133273003) * 1024}
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
