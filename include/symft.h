@@ -51,15 +51,15 @@ typedef int32_t symft_status;
 enum symft_op_kind {
     SYMFT_OP_H = 1, SYMFT_OP_S, SYMFT_OP_S_DAG, SYMFT_OP_X, SYMFT_OP_Y, SYMFT_OP_Z, /* 1q Cliffords on each qubit */
     SYMFT_OP_CX, SYMFT_OP_CZ, SYMFT_OP_SWAP,          /* on qubit pairs (q0,q1),(q2,q3),... */
-    SYMFT_OP_R,            /* reset each qubit to |0> (unrecorded Z measurement + X feedback) */
-    SYMFT_OP_M,            /* recorded Z measurement of each qubit */
-    SYMFT_OP_MR,           /* recorded Z measurement, then reset, of each qubit */
+    SYMFT_OP_R,            /* reset each qubit to |0> (unrecorded Z measurement + X feedback); arg must be 0 */
+    SYMFT_OP_M,            /* recorded Z measurement of each qubit, reported bit flipped w.p. arg */
+    SYMFT_OP_MR,           /* recorded Z measurement, then reset, of each qubit, reported bit flipped w.p. arg */
     SYMFT_OP_X_ERROR,      /* per qubit: X with probability arg */
     SYMFT_OP_DEPOLARIZE1,  /* per qubit: X, Y, Z each with probability arg/3 */
     SYMFT_OP_DEPOLARIZE2,  /* per pair: each of the 15 non-identity two-qubit Paulis with probability arg/15 */
     SYMFT_OP_PAULI_CHANNEL,/* one channel on `qubits` (<= 16): branch j (< 64) applies branch_paulis[j*n..] w.p. probs[j] */
     SYMFT_OP_ROT,          /* R_P(arg) = exp(-i arg P / 2), P = (-1)^negate * prod paulis (paper Sec. 2) */
-    SYMFT_OP_MPP,          /* recorded measurement of P = (-1)^negate * prod paulis */
+    SYMFT_OP_MPP,          /* recorded measurement of P = (-1)^negate * prod paulis, reported bit flipped w.p. arg */
     SYMFT_OP_FEEDBACK,     /* apply P if the XOR of records `recs` is 1 */
     SYMFT_OP_DETECTOR,     /* detector row = XOR of records `recs` */
     SYMFT_OP_OBSERVABLE,   /* XOR records `recs` into observable row obs_id */
@@ -72,7 +72,8 @@ typedef struct {
     const uint32_t *qubits;        /* host, [n] */
     const uint8_t *paulis;         /* host, [n] letters for ROT / MPP / FEEDBACK; else NULL */
     uint32_t negate;               /* ROT / MPP: sign of P (the Pauli stays Hermitian) */
-    double arg;                    /* ROT: theta; X_ERROR / DEPOLARIZE1 / DEPOLARIZE2: p */
+    double arg;                    /* ROT: theta; X_ERROR / DEPOLARIZE1 / DEPOLARIZE2: p;
+                                      M / MR / MPP: readout-flip probability in [0, 1] (see below) */
     uint32_t n_branches;           /* PAULI_CHANNEL */
     const double *probs;           /* host, [n_branches] */
     const uint8_t *branch_paulis;  /* host, [n_branches * n] letters 0..3 */
@@ -80,6 +81,18 @@ typedef struct {
     const int64_t *recs;           /* host, [n_recs]: absolute record ids, or < 0 = look-back (-1 = last) */
     uint32_t obs_id;               /* OBSERVABLE */
 } symft_op;
+
+/* Readout flips (paper Sec. 6, sampling independent symbols: readout flips are
+ * exogenous symbols like Pauli noise choices): an M, MR
+ * or MPP with arg = p > 0 reports the complement of its outcome with
+ * probability p and leaves the post-measurement state that of the true
+ * outcome (an MR resets on the true outcome).  Each flip is a one-branch
+ * noise channel of probability p placed at its measurement, one per target of
+ * M / MR and one for MPP, ranked in circuit order with every other channel.
+ * A measurement of P whose flip fires is a measurement of -P: the
+ * measurement's own draw (RandomMeas word or uniform) decides the reported
+ * bit.  arg = 0 adds no channel.  Errors: EPROB for arg outside [0, 1],
+ * EINVAL for a nonzero arg on R. */
 
 typedef struct symft_program symft_program; /* opaque, immutable after compile */
 

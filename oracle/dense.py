@@ -9,6 +9,12 @@ outcomes a tableau shot took, ``replay`` recomputes every Pr(m = 0) by
 projection.  ``exact_record_distribution`` enumerates the outcome tree (with
 density matrices for noise) to give exact record probabilities for small
 circuits.  Qubit q is bit q of the basis index.
+
+Readout flips (an M / MR / MPP with ``arg`` = p > 0; paper Sec. 6 counts them
+among the exogenous symbols) are taken by their plain definition: the state
+is projected on the true outcome and, with probability p, the complement of
+that outcome is recorded; a reset acts on the true outcome.  Each flip is one
+channel, in circuit order with the noise channels.
 """
 from __future__ import annotations
 
@@ -112,17 +118,28 @@ def replay(circ, fired: Sequence[int], outcomes: Sequence[int]) -> Dict[str, np.
     t = 0
     ch = 0
 
-    def measure(psi, P, negate=False):
+    def flip_fired(op):
+        # the op's next readout-flip channel, if it has them
+        nonlocal ch
+        if op.name == "R" or op.arg <= 0:
+            return 0
+        f = int(fired[ch]) >= 0
+        ch += 1
+        return int(f)
+
+    def measure(psi, P, negate=False, flip=0):
+        # `outcomes` holds reported bits; the true outcome is the reported one
+        # XOR the flip, and Pr(m = 0) is returned for the reported bit
         nonlocal t
         Ppsi = pauli_apply(psi, n, P, negate)
         plus = (psi + Ppsi) / 2
         p0 = float(np.vdot(plus, plus).real)
-        m = int(outcomes[t])
+        m = int(outcomes[t]) ^ flip
         proj = plus if m == 0 else (psi - Ppsi) / 2
         pr = float(np.vdot(proj, proj).real)
         if pr <= 1e-14:
             raise AssertionError(f"measurement {t}: outcome {m} has probability {pr}")
-        p0s.append(p0)
+        p0s.append(1.0 - p0 if flip else p0)
         t += 1
         return proj / np.sqrt(pr), m
 
@@ -136,14 +153,16 @@ def replay(circ, fired: Sequence[int], outcomes: Sequence[int]) -> Dict[str, np.
                 psi = apply_2q(psi, n, GATE_2Q[nm], op.targets[i], op.targets[i + 1])
         elif nm in ("R", "M", "MR"):
             for q in op.targets:
-                psi, m = measure(psi, ((q, "Z"),))
+                f = flip_fired(op)
+                psi, m = measure(psi, ((q, "Z"),), flip=f)
                 if nm != "R":
-                    recs.append(m)
+                    recs.append(m ^ f)
                 if nm != "M" and m:
                     psi = apply_1q(psi, n, _X, q)
         elif nm == "MPP":
-            psi, m = measure(psi, op.pauli, op.negate)
-            recs.append(m)
+            f = flip_fired(op)
+            psi, m = measure(psi, op.pauli, op.negate, flip=f)
+            recs.append(m ^ f)
         elif nm == "ROT":
             c, s = np.cos(op.arg / 2), np.sin(op.arg / 2)
             psi = c * psi - 1j * s * pauli_apply(psi, n, op.pauli, op.negate)
@@ -225,6 +244,7 @@ def exact_record_distribution(circ, cutoff: float = 1e-15) -> Dict[Tuple[int, ..
                         return
                     P, neg, q = Ps[j]
                     PM = pmat(P, neg)
+                    pf = op.arg if nm != "R" else 0.0  # readout flip of the recorded bit
                     for m in (0, 1):
                         Pi = (np.eye(dim) + (-1) ** m * PM) / 2
                         r2 = Pi @ rho @ Pi
@@ -235,7 +255,12 @@ def exact_record_distribution(circ, cutoff: float = 1e-15) -> Dict[Tuple[int, ..
                         if nm in ("R", "MR") and m:
                             Xq = pmat(((q, "X"),))
                             r2 = Xq @ r2 @ Xq
-                        branch(j + 1, r2, prob * pm, recs + ([m] if nm != "R" else []))
+                        if nm == "R":
+                            branch(j + 1, r2, prob * pm, recs)
+                            continue
+                        for f, pr in ((0, 1.0 - pf), (1, pf)):
+                            if pr > 0:
+                                branch(j + 1, r2, prob * pm * pr, recs + [m ^ f])
                 branch(0, rho, prob, recs)
                 return
             i += 1

@@ -27,6 +27,13 @@
  * instead stores the measured eigenspace directly, i.e. the new dormant
  * stabilizer is (-1)^m P.
  *
+ * Readout flips (paper Sec. 6 lists them among the exogenous symbols): an M,
+ * MR or MPP with probability p > 0 owns one one-branch channel per record; a
+ * fired flip reports the complement of the true outcome and leaves the state
+ * of the true outcome.  That instrument is exactly a measurement of -P with
+ * the outcome reported as is, which is how it runs here, so the measurement's
+ * own draw decides the reported bit; a reset acts on the true outcome.
+ *
  * Pivot rules (they only change the basis, never a probability or record):
  *   - dormant pivot: the lowest dormant coordinate whose Zbar anticommutes
  *     with P; a promoted coordinate is then swapped to position k (0-based);
@@ -259,6 +266,20 @@ typedef struct {
 
 static int is_noise(int k) { return k == OK_XERR || k == OK_DEP1 || k == OK_DEP2 || k == OK_CHAN; }
 
+/* Channels an op owns: noise ops their Pauli channels; a recorded measurement
+ * with a readout-flip probability (arg > 0) one flip per record it writes
+ * (paper Sec. 6: readout flips are exogenous symbols). */
+static int op_channels(const OOp *o) {
+    switch (o->kind) {
+    case OK_XERR: case OK_DEP1: return o->nq;
+    case OK_DEP2: return o->nq / 2;
+    case OK_CHAN: return 1;
+    case OK_M: case OK_MR: return o->arg > 0 ? o->nq : 0;
+    case OK_MPP: return o->arg > 0 ? 1 : 0;
+    default: return 0;
+    }
+}
+
 /* Tape layout (int64): n_ops, then per op:
  *   kind, nq, q[nq], negate, n_let, let[n_let], nrec, recs[nrec], obs, nbr, blet[nbr*nq]
  * doubles, consumed in order: arg for every op, then probs[nbr] for PAULI_CHANNEL. */
@@ -292,10 +313,8 @@ void *orc_circuit_new(int n_qubits, const int64_t *tape, const double *dargs) {
         o->chan0 = nch;
         o->meas0 = nm;
         o->rec0 = nr;
+        nch += op_channels(o);
         switch (o->kind) {
-        case OK_XERR: case OK_DEP1: nch += o->nq; break;
-        case OK_DEP2: nch += o->nq / 2; break;
-        case OK_CHAN: nch += 1; break;
         case OK_R: nm += o->nq; break;
         case OK_M: case OK_MR: nm += o->nq; nr += o->nq; break;
         case OK_MPP: nm += 1; nr += 1; break;
@@ -323,8 +342,7 @@ void *orc_circuit_new(int n_qubits, const int64_t *tape, const double *dargs) {
         } else if (o->kind == OK_OBS) {
             C->obs_ops[o->obs][C->obs_ops_n[o->obs]++] = i;
         }
-        if (!is_noise(o->kind)) continue;
-        int cnt = o->kind == OK_DEP2 ? o->nq / 2 : (o->kind == OK_CHAN ? 1 : o->nq);
+        int cnt = op_channels(o);
         for (int j = 0; j < cnt; ++j) {
             OChan *c = &C->ch[ci++];
             c->op = i;
@@ -332,8 +350,13 @@ void *orc_circuit_new(int n_qubits, const int64_t *tape, const double *dargs) {
             c->qa = -1; c->qb = -1;
             double ptot;
             if (o->kind == OK_DEP2) { c->qa = o->q[2 * j]; c->qb = o->q[2 * j + 1]; }
-            else if (o->kind != OK_CHAN) { c->qa = o->q[j]; }
-            if (o->kind == OK_CHAN) {
+            else if (o->kind != OK_CHAN && o->kind != OK_MPP) { c->qa = o->q[j]; }
+            if (!is_noise(o->kind)) {
+                /* readout flip: one branch of probability arg */
+                ptot = o->arg;
+                c->uniform = 1;
+                c->J = 1;
+            } else if (o->kind == OK_CHAN) {
                 /* general channel: total in branch order, integer thresholds */
                 ptot = 0.0;
                 for (int b = 0; b < o->nbr; ++b) ptot += o->probs[b];
@@ -845,14 +868,17 @@ static void run_shot(const OCirc *C, Shot *S, uint64_t seed, uint64_t sh, const 
             break;
         case OK_R: case OK_M: case OK_MR:
             for (int j = 0; j < o->nq; ++j) {
+                /* a fired readout flip: the reported bit is the outcome of -Z, the true one its complement */
+                int f = op_channels(o) && fired[(size_t)(o->chan0 + j) * 64 + lane] >= 0;
                 set_single_z(S, o->q[j]);
-                int m = do_measure(S, 0, seed, o->meas0 + j, sh);
-                if (o->kind != OK_M && m) apply_x_on(S, o->q[j]); /* reset: flip back to |0> */
+                int m = do_measure(S, 2 * f, seed, o->meas0 + j, sh);
+                if (o->kind != OK_M && (m ^ f)) apply_x_on(S, o->q[j]); /* reset: flip back to |0> */
             }
             break;
         case OK_MPP: {
+            int f = op_channels(o) && fired[(size_t)o->chan0 * 64 + lane] >= 0;
             int pe = op_pauli(S, o);
-            do_measure(S, pe, seed, o->meas0, sh);
+            do_measure(S, (pe + 2 * f) & 3, seed, o->meas0, sh);
             break;
         }
         case OK_ROT: {

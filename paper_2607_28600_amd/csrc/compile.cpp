@@ -479,8 +479,17 @@ int compile_program(uint32_t n_qubits, const void *ops_v, size_t n_ops, Program 
                 if (o.qubits[j] == o.qubits[j + 1])
                     return fail(err, SYMFT_EINVAL, "op " + std::to_string(i) + ": repeated qubit in a pair");
             break;
-        case SYMFT_OP_R: nm += o.n; break;
-        case SYMFT_OP_M: case SYMFT_OP_MR: nm += o.n; nr += o.n; break;
+        case SYMFT_OP_R:
+            if (o.arg != 0.0) return fail(err, SYMFT_EINVAL, "op " + std::to_string(i) + ": a reset has no record to flip");
+            nm += o.n;
+            break;
+        case SYMFT_OP_M: case SYMFT_OP_MR:
+            if (!(o.arg >= 0.0 && o.arg <= 1.0))
+                return fail(err, SYMFT_EPROB, "op " + std::to_string(i) + ": readout-flip probability outside [0,1]");
+            nm += o.n;
+            nr += o.n;
+            if (o.arg > 0.0) nsym += o.n;
+            break;
         case SYMFT_OP_X_ERROR: case SYMFT_OP_DEPOLARIZE1: case SYMFT_OP_DEPOLARIZE2:
             if (!(o.arg >= 0.0 && o.arg <= 1.0))
                 return fail(err, SYMFT_EPROB, "op " + std::to_string(i) + ": probability outside [0,1]");
@@ -518,7 +527,13 @@ int compile_program(uint32_t n_qubits, const void *ops_v, size_t n_ops, Program 
                 seen[o.qubits[j]] = 1;
             }
             for (uint32_t j = 0; j < o.n; ++j) seen[o.qubits[j]] = 0;
-            if (o.kind == SYMFT_OP_MPP) { nm += 1; nr += 1; }
+            if (o.kind == SYMFT_OP_MPP) {
+                if (!(o.arg >= 0.0 && o.arg <= 1.0))
+                    return fail(err, SYMFT_EPROB, "op " + std::to_string(i) + ": readout-flip probability outside [0,1]");
+                nm += 1;
+                nr += 1;
+                if (o.arg > 0.0) nsym += 1;
+            }
             if (o.kind == SYMFT_OP_ROT && !std::isfinite(o.arg)) return fail(err, SYMFT_EINVAL, "non-finite angle");
             break;
         }
@@ -612,6 +627,23 @@ int compile_program(uint32_t n_qubits, const void *ops_v, size_t n_ops, Program 
         P.chans.push_back(std::move(ch));
     };
 
+    // Readout flip of probability p (paper Sec. 6: an exogenous symbol): a
+    // one-branch channel whose symbol s enters only the sign of the measured
+    // Pauli, so a flipped measurement of P is one of -P.  Returns s.
+    auto add_readout_flip = [&](double p) -> uint32_t {
+        Channel ch;
+        ch.op = (int32_t)cur_op;
+        ch.J = 1;
+        ch.uniform = 1;
+        ch.sym0 = sym;
+        ch.nsym = 1;
+        ch.bmask.push_back(1u);
+        const double f = std::ldexp(p, 32);
+        ch.p32 = p >= 1.0 ? (uint64_t(1) << 32) : (f <= 0.0 ? 0 : (uint64_t)std::floor(f));
+        P.chans.push_back(std::move(ch));
+        return 1 + sym++;
+    };
+
     static const uint8_t D2[15][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 0}, {1, 1}, {1, 2}, {1, 3}, {2, 0},
                                       {2, 1}, {2, 2}, {2, 3}, {3, 0}, {3, 1}, {3, 2}, {3, 3}};
     for (size_t i = 0; i < n_ops; ++i) {
@@ -628,26 +660,31 @@ int compile_program(uint32_t n_qubits, const void *ops_v, size_t n_ops, Program 
             for (uint32_t j = 0; j < o.n; ++j) {
                 uint32_t q = o.qubits[j];
                 uint8_t z = 3;
+                const uint32_t flip = (o.kind != SYMFT_OP_R && o.arg > 0.0) ? add_readout_flip(o.arg) : 0u;
                 PauliV Q = K.pull_back(&q, &z, 1, false);
                 K.lambda_of(Q, lam);
+                if (flip) lam.flip(flip);
                 if (o.kind != SYMFT_OP_R) {
                     P.meas_row[t] = (int64_t)rec_meas.size();
                     rec_meas.push_back(t);
                 }
                 K.plan_measurement(Q, lam, t, (int)i);
-                if (o.kind != SYMFT_OP_M) {  // reset: X^{m_t} feedback
+                if (o.kind != SYMFT_OP_M) {  // reset: X^{m_t} feedback on the true outcome m_t + s
                     uint8_t x = 1;
                     PauliV F = K.pull_back(&q, &x, 1, false);
                     fb.clear();
                     fb.flip(K.sym_meas(t));
+                    if (flip) fb.flip(flip);
                     K.frame_add_expr(F, fb);
                 }
                 ++t;
             }
             break;
         case SYMFT_OP_MPP: {
+            const uint32_t flip = o.arg > 0.0 ? add_readout_flip(o.arg) : 0u;
             PauliV Q = K.pull_back(o.qubits, o.paulis, o.n, o.negate != 0);
             K.lambda_of(Q, lam);
+            if (flip) lam.flip(flip);
             P.meas_row[t] = (int64_t)rec_meas.size();
             rec_meas.push_back(t);
             K.plan_measurement(Q, lam, t, (int)i);

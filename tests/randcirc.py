@@ -4,7 +4,9 @@ import numpy as np
 from workloads.circuit import Circuit
 
 
-def random_circuit(rng, n, length, p_noise=0.3, allow_reset=True):
+def random_circuit(rng, n, length, p_noise=0.3, allow_reset=True, p_flip=0.0):
+    # p_flip > 0: every M / MR / MPP gets a readout flip of probability p_flip
+    # (no extra draws otherwise, so the circuits of a seed stay as they were)
     c = Circuit(n)
     for _ in range(length):
         r = rng.random()
@@ -21,7 +23,8 @@ def random_circuit(rng, n, length, p_noise=0.3, allow_reset=True):
         elif r < 0.72:
             w = int(rng.integers(1, min(n, 4) + 1))
             qs = rng.choice(n, w, replace=False)
-            c.mpp([(int(q), str(rng.choice(list("XYZ")))) for q in qs], negate=bool(rng.random() < 0.3))
+            c.mpp([(int(q), str(rng.choice(list("XYZ")))) for q in qs], negate=bool(rng.random() < 0.3),
+                  p_flip=p_flip)
             if rng.random() < 0.5:
                 qs2 = rng.choice(n, int(rng.integers(1, min(n, 2) + 1)), replace=False)
                 nr = c.num_records
@@ -29,7 +32,8 @@ def random_circuit(rng, n, length, p_noise=0.3, allow_reset=True):
                 c.feedback([(int(q), str(rng.choice(list("XYZ")))) for q in qs2], recs)
         elif r < 0.8:
             names = ["M", "MR", "R"] if allow_reset else ["M"]
-            c.append(str(rng.choice(names)), [int(rng.integers(n))])
+            nm = str(rng.choice(names))
+            c.append(nm, [int(rng.integers(n))], arg=p_flip if nm != "R" else 0.0)
         elif r < 0.9:
             c.append("DEPOLARIZE1", [int(rng.integers(n))], arg=p_noise)
         elif r < 0.95 and n >= 2:

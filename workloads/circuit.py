@@ -34,7 +34,8 @@ class Op:
     # ROT / MPP / FEEDBACK: the Pauli as ((qubit, letter), ...) with letter in "XYZ"
     pauli: Tuple[Tuple[int, str], ...] = ()
     negate: bool = False
-    # ROT: angle theta; X_ERROR / DEPOLARIZE1 / DEPOLARIZE2: probability p
+    # ROT: angle theta; X_ERROR / DEPOLARIZE1 / DEPOLARIZE2: probability p;
+    # M / MR / MPP: readout-flip probability (the recorded bit is complemented)
     arg: float = 0.0
     # FEEDBACK / DETECTOR / OBSERVABLE_INCLUDE: absolute record ids
     recs: Tuple[int, ...] = ()
@@ -59,8 +60,8 @@ class Circuit:
         self.ops.append(Op("ROT", pauli=tuple((int(q), s) for q, s in pauli), arg=float(theta), negate=negate))
         return self
 
-    def mpp(self, pauli: Sequence[Tuple[int, str]], negate: bool = False) -> int:
-        self.ops.append(Op("MPP", pauli=tuple((int(q), s) for q, s in pauli), negate=negate))
+    def mpp(self, pauli: Sequence[Tuple[int, str]], negate: bool = False, p_flip: float = 0.0) -> int:
+        self.ops.append(Op("MPP", pauli=tuple((int(q), s) for q, s in pauli), negate=negate, arg=float(p_flip)))
         return self.num_records - 1
 
     def feedback(self, pauli: Sequence[Tuple[int, str]], recs: Sequence[int]) -> "Circuit":

@@ -12,7 +12,8 @@ correctly and hook errors lie across the logical operator.
 Noise (parameter p, all channels): X_ERROR after every reset and before every
 measurement, DEPOLARIZE1 after single-qubit gates and on idle qubits of every
 layer, DEPOLARIZE2 after every CNOT, DEPOLARIZE1 on the data during ancilla
-measurement.  Detectors: Z checks in round 1, every check against its
+measurement.  `p_meas` > 0 adds a readout flip of that probability to every
+recorded measurement (the ancilla MR and the final data M).  Detectors: Z checks in round 1, every check against its
 previous round from round 2 on, and each Z check's final data parity
 against its last round.  Observable 0: the final Z measurements of data row 0.
 Counts: M = r(d^2-1) + d^2 records, D = r(d^2-1) detectors, 1 observable.
@@ -46,7 +47,7 @@ def _corners(kind: str, r: int, c: int):
     return (nw, ne, sw, se) if kind == "X" else (nw, sw, ne, se)
 
 
-def rotated_memory_z(d: int, rounds: int, p: float, coherent: float = 0.0) -> Circuit:
+def rotated_memory_z(d: int, rounds: int, p: float, coherent: float = 0.0, p_meas: float = 0.0) -> Circuit:
     """`coherent` != 0 adds a coherent error exp(-i coherent Z / 2) on every data qubit at the start of every
     round (the coherent-noise surface-code family), which makes the circuit near-Clifford."""
     data, checks, anc = layout(d)
@@ -95,7 +96,7 @@ def rotated_memory_z(d: int, rounds: int, p: float, coherent: float = 0.0) -> Ci
         circ.append("DEPOLARIZE1", idle(xa), arg=p)
         circ.append("X_ERROR", aq, arg=p)
         base = circ.num_records
-        circ.append("MR", aq)
+        circ.append("MR", aq, arg=p_meas)
         for i, a in enumerate(aq):
             rec_of[a].append(base + i)
         circ.append("X_ERROR", aq, arg=p)
@@ -109,7 +110,7 @@ def rotated_memory_z(d: int, rounds: int, p: float, coherent: float = 0.0) -> Ci
                 circ.detector([rec_of[a][-1], rec_of[a][-2]])
     circ.append("X_ERROR", dq, arg=p)
     base = circ.num_records
-    circ.append("M", dq)
+    circ.append("M", dq, arg=p_meas)
     drec = {q: base + i for i, q in enumerate(dq)}
     for kind, (r, c) in checks:
         if kind != "Z":
