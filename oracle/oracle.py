@@ -57,6 +57,9 @@ def _load():
                                   C.POINTER(C.c_int16)]
         lib.orc_noise_counts.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64, C.POINTER(C.c_uint64),
                                          C.POINTER(C.c_uint64)]
+        lib.orc_final_state.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(C.c_int),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                        C.POINTER(C.c_int)]
         lib.orc_philox.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         lib.orc_rmeas_bit.restype = C.c_int
         lib.orc_rmeas_bit.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64]
@@ -181,6 +184,27 @@ class OracleCircuit:
             "meas_kind": kind[: self.n_meas], "m": m[: self.n_meas], "p0": p0[: self.n_meas],
             "rot_kind": rot[:n_ops], "k": kk[:n_ops], "fired": fired[: self.n_chan],
         }
+
+    def final_state(self, seed: int, shot: int) -> Dict[str, np.ndarray]:
+        """Active vector alpha (complex, 2^k) after the last op, and the signed
+        tableau: rows 0..n-1 Zbar_j, n..2n-1 Xbar_j as integer bit masks x, z
+        and phase exponents e (row = i^e X^x Z^z)."""
+        lib = _load()
+        n = self.circuit.n_qubits
+        W = (n + 63) // 64
+        k = C.c_int(0)
+        lib.orc_final_state(self._h, seed, shot, C.byref(k), None, None, None, None)
+        amp = np.zeros(2 << k.value, dtype=np.float64)
+        tx = np.zeros(2 * n * W, dtype=np.uint64)
+        tz = np.zeros(2 * n * W, dtype=np.uint64)
+        te = np.zeros(2 * n, dtype=np.int32)
+        lib.orc_final_state(self._h, seed, shot, C.byref(k), _ptr(amp, C.c_double), _ptr(tx, C.c_uint64),
+                            _ptr(tz, C.c_uint64), _ptr(te, C.c_int))
+
+        def rows(t):
+            return [sum(int(t[r * W + i]) << (64 * i) for i in range(W)) for r in range(2 * n)]
+
+        return {"k": k.value, "alpha": amp[0::2] + 1j * amp[1::2], "x": rows(tx), "z": rows(tz), "e": te}
 
     def channel_info(self):
         lib = _load()

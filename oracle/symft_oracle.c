@@ -1011,6 +1011,39 @@ int orc_trace(void *h, uint64_t seed, uint64_t sh, int8_t *kind, uint8_t *m, dou
     return 0;
 }
 
+/*
+ * Final state of one shot: *k_out = active width after the last op; amp
+ * (nullable, 2 * 2^k doubles as (re, im)) = the active vector alpha; tab_x /
+ * tab_z (nullable, 2n rows of W = ceil(n / 64) words: Zbar_1..Zbar_n then
+ * Xbar_1..Xbar_n) and tab_e (2n phase exponents, row = i^e X^x Z^z) = the
+ * signed tableau, so that psi = sum_x alpha_x Xbar_1^x1 ... Xbar_k^xk |0bar>.
+ */
+int orc_final_state(void *h, uint64_t seed, uint64_t sh, int *k_out, double *amp, uint64_t *tab_x, uint64_t *tab_z,
+                    int *tab_e) {
+    OCirc *C = (OCirc *)h;
+    int64_t **rmap = build_rank_maps(C);
+    int16_t *fired = (int16_t *)malloc(sizeof(int16_t) * ((size_t)C->n_chan * 64 + 1));
+    word_events(C, seed, sh / 64, fired, rmap);
+    Shot S;
+    shot_init(&S, C);
+    run_shot(C, &S, seed, sh, fired);
+    *k_out = S.k;
+    if (amp)
+        for (size_t x = 0; x < ((size_t)1 << S.k); ++x) {
+            amp[2 * x] = creal(S.a[x]);
+            amp[2 * x + 1] = cimag(S.a[x]);
+        }
+    size_t nw = (size_t)2 * S.n * S.W;
+    if (tab_x) memcpy(tab_x, S.T.x, 8 * nw);
+    if (tab_z) memcpy(tab_z, S.T.z, 8 * nw);
+    if (tab_e)
+        for (int r = 0; r < 2 * S.n; ++r) tab_e[r] = S.T.e[r] & 3;
+    shot_free(&S);
+    free(fired);
+    free_rank_maps(C, rmap);
+    return 0;
+}
+
 /* Per-word noise-event count of each channel over shots [shot_begin, +n_words*64):
  * counts[c] += events, branch_counts[c*16+j] += events in branch j. */
 int orc_noise_counts(void *h, uint64_t seed, uint64_t word_begin, uint64_t n_words, uint64_t *counts,

@@ -57,3 +57,58 @@ def compare_records(got, want, circ, oc, seed, shot_base, tol):
             assert np.array_equal(g[early], w[early]), f"shot {shot}: records before the tied draw differ"
             excluded += 1
     return excluded
+
+
+def frame_relation(a, b, tol):
+    """Whether a_x = e^{i phi} (-1)^{s.x} b_{x XOR y} for some phase phi and bit
+    vectors s, y (returned as (y, s), else None).  Two representations of one
+    state on the same active coordinates differ by exactly such a map: a Pauli
+    frame F = i^e Xbar^y Zbar^s' (times dormant factors) sends
+    sum_x alpha_x Xbar^x |0bar> to i^e sum_x (-1)^{s'.x} alpha_x Xbar^(x XOR y) |0bar>,
+    and sign conventions of the generators add further characters."""
+    a = np.asarray(a, dtype=complex)
+    b = np.asarray(b, dtype=complex)
+    if a.shape != b.shape:
+        return None
+    N = a.size
+    k = N.bit_length() - 1
+    idx = np.arange(N)
+    mag_a = np.abs(a)
+    r = int(np.argmax(mag_a))
+    # entries large enough for their sign to be read at this tolerance
+    sig = mag_a > 100 * tol
+    for y in range(N):
+        bb = b[idx ^ y]
+        if np.max(np.abs(mag_a - np.abs(bb))) > tol:
+            continue
+        ph = a[r] / bb[r]
+        ph /= abs(ph)
+        # the signs must be a character of x XOR r: solve s over GF(2), then check every entry
+        xs = (idx[sig] ^ r).tolist()
+        bits = ((a[sig] * np.conj(ph * bb[sig])).real < 0).astype(int).tolist()
+        basis = {}  # pivot bit -> (row, rhs)
+        ok = True
+        for x, v in zip(xs, bits):
+            for p in sorted(basis, reverse=True):
+                if (x >> p) & 1:
+                    x ^= basis[p][0]
+                    v ^= basis[p][1]
+            if x == 0:
+                if v:
+                    ok = False
+                    break
+                continue
+            basis[x.bit_length() - 1] = (x, v)
+        if not ok:
+            continue
+        s = 0
+        for p in sorted(basis):
+            row, v = basis[p]
+            lower = row & ~(1 << p)
+            par = bin(lower & s).count("1") & 1
+            if v ^ par:
+                s |= 1 << p
+        chi = np.array([(-1) ** (bin(s & (x ^ r)).count("1") & 1) for x in range(N)])
+        if np.max(np.abs(a - ph * chi * bb)) <= tol:
+            return y, s
+    return None

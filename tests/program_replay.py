@@ -23,7 +23,7 @@ def _par(v):
     return bin(v).count("1") & 1
 
 
-def replay_shot(exp, circ, seed, shot, fired):
+def replay_shot(exp, circ, seed, shot, fired, return_state=False):
     instr, theta = exp["instr"], exp["theta"]
     noise_refs, meas_refs = exp["noise"], exp["meas"]
     chan, bmask = exp["chan"], exp["bmask"]
@@ -102,6 +102,8 @@ def replay_shot(exp, circ, seed, shot, fired):
             a = beta[y] / np.sqrt(S[y])
             mvals[t] = m
             p0s[t] = p0
+    if return_state:
+        return mvals, p0s, a
     return mvals, p0s
 
 

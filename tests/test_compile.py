@@ -160,3 +160,44 @@ def test_frame_schedule_folds_same_level_dependencies():
     assert info["k_max"] == 0
     assert info["frame_noise_steps"] == 1
     assert info["frame_steps"] == 2
+
+
+def test_frame_relation_accepts_frame_maps_and_rejects_other_states():
+    from tests.parity_util import frame_relation
+    rng = np.random.default_rng(3)
+    b = rng.normal(size=16) + 1j * rng.normal(size=16)
+    b /= np.linalg.norm(b)
+    y, s, ph = 0b0110, 0b1010, np.exp(0.7j)
+    chi = np.array([(-1) ** (bin(s & x).count("1") & 1) for x in range(16)])
+    a = ph * chi * b[np.arange(16) ^ y]
+    assert frame_relation(a, b, 1e-12) is not None
+    bad = a.copy()
+    bad[3] *= -1                                   # one sign off the character
+    assert frame_relation(bad, b, 1e-9) is None
+    bad = a.copy()
+    bad[[1, 2]] = bad[[2, 1]]                      # two amplitudes exchanged
+    assert frame_relation(bad, b, 1e-9) is None
+    assert frame_relation(a * np.exp(1j * 0.3 * (np.arange(16) == 5)), b, 1e-9) is None  # a relative phase
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_replay_final_vector_matches_oracle_up_to_frame(seed):
+    """The planner-basis active vector at the end of a shot (the vector the
+    kernels hold) against the oracle's, which carries concrete signs instead of
+    a symbolic frame: equal up to the frame's index shift, sign character and
+    global phase."""
+    from tests.parity_util import frame_relation
+    rng = np.random.default_rng(7700 + seed)
+    nonzero = 0
+    for trial in range(40):
+        c = random_circuit(rng, int(rng.integers(2, 7)), int(rng.integers(5, 45)))
+        exp = S.Program(c).export()
+        oc = OracleCircuit(c)
+        s = 800 + trial
+        for shot in (5, 70):
+            tr = oc.trace(s, shot)
+            _, _, a = replay_shot(exp, c, s, shot, tr["fired"], return_state=True)
+            fs = oc.final_state(s, shot)
+            assert frame_relation(a, fs["alpha"], 1e-9) is not None
+            nonzero += fs["k"] > 0
+    assert nonzero > 20

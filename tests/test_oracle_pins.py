@@ -7,6 +7,7 @@
 * Closed forms for each instruction kind (paper Sec. 4.1 / 4.2).
 * Exact record distributions (density matrices + outcome tree) vs oracle histograms.
 * Noiseless detector determinism; surface-code counts vs the paper's d=7/9 figures.
+* The whole final state (signed tableau + active vector) against the dense replay.
 """
 import os
 
@@ -269,3 +270,39 @@ def test_k_trajectory_is_shot_independent():
     assert np.array_equal(a["k"], b["k"])
     assert np.array_equal(a["meas_kind"], b["meas_kind"])
     assert int(a["k"].max()) == 8
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_final_state_matches_dense_replay(seed):
+    """The oracle's whole final state, psi = sum_x alpha_x Xbar^x |0bar> rebuilt
+    from its signed tableau and active vector, against the dense replay of the
+    same shot (noise branches and outcomes from the oracle's trace), up to a
+    global phase."""
+    rng = np.random.default_rng(7300 + seed)
+    checked = 0
+    for trial in range(25):
+        n = int(rng.integers(2, 6))
+        c = random_circuit(rng, n, int(rng.integers(5, 40)), p_flip=0.2 if trial % 2 else 0.0)
+        oc = OracleCircuit(c)
+        s = 500 + trial
+        for shot in (3, 64 + 17):
+            tr = oc.trace(s, shot)
+            psi_d = dense.replay(c, tr["fired"], tr["m"])["state"]
+            fs = oc.final_state(s, shot)
+            zbar = [_pauli_mat(n, fs["x"][j], fs["z"][j], int(fs["e"][j])) for j in range(n)]
+            xbar = [_pauli_mat(n, fs["x"][n + j], fs["z"][n + j], int(fs["e"][n + j])) for j in range(n)]
+            v = rng.normal(size=2 ** n) + 1j * rng.normal(size=2 ** n)
+            for Z in zbar:
+                v = (v + Z @ v) / 2
+            v /= np.linalg.norm(v)
+            psi_o = np.zeros(2 ** n, dtype=complex)
+            for x, a in enumerate(fs["alpha"]):
+                w = v
+                for j in range(fs["k"]):
+                    if (x >> j) & 1:
+                        w = xbar[j] @ w
+                psi_o += a * w
+            assert abs(np.linalg.norm(psi_o) - 1) < 1e-12
+            assert abs(abs(np.vdot(psi_o, psi_d)) - 1) < 1e-10
+            checked += fs["k"] > 0
+    assert checked > 0
