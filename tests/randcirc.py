@@ -46,3 +46,28 @@ def random_circuit(rng, n, length, p_noise=0.3, allow_reset=True, p_flip=0.0):
     if c.num_records >= 1:
         c.observable(0, [c.num_records - 1])
     return c
+
+
+def wide_circuit(k, seed, p_noise=2e-2, p_flip=1e-2):
+    """A state of peak active width k + 2 on k + 4 qubits: |+>^n, a Z rotation
+    on each of the first k qubits (one promotion each), then twelve rounds of a
+    CNOT, depolarizing noise and a weight-3 rotation anywhere (two more
+    promotions, pair and diagonal rotations), then an X measurement of every
+    qubit with readout flips (active-diagonal measurements down to width 0)."""
+    rng = np.random.default_rng(seed)
+    n = k + 4
+    c = Circuit(n)
+    c.append("H", list(range(n)))
+    for q in range(k):
+        c.rot([(q, "Z")], float(rng.uniform(0.2, 1.2)))
+    for _ in range(12):
+        a, b = (int(v) for v in rng.choice(k, 2, replace=False))
+        c.append("CX", [a, b])
+        c.append("DEPOLARIZE1", [a, b], arg=p_noise)
+        qs = rng.choice(n, 3, replace=False)
+        c.rot([(int(q), "XYZ"[int(rng.integers(3))]) for q in qs], float(rng.uniform(-1, 1)))
+    for q in range(n):
+        c.mpp([(q, "X")], p_flip=p_flip)
+    c.detector([0, 1])
+    c.observable(0, [n - 1])
+    return c

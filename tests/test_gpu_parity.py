@@ -18,7 +18,7 @@ import oracle as O  # noqa: E402
 import paper_2607_28600_amd as S  # noqa: E402
 from oracle import OracleCircuit  # noqa: E402
 from tests.parity_util import compare_records, frame_relation  # noqa: E402
-from tests.randcirc import random_circuit  # noqa: E402
+from tests.randcirc import random_circuit, wide_circuit  # noqa: E402
 from workloads import configs  # noqa: E402
 
 TOL = {"fp64": 1e-9, "fp32": 1e-5}
@@ -155,6 +155,20 @@ def test_c5_large_active_state(k, prec):
     got = _gpu(p, n, w.seed, precision=prec)
     want = oc.sample(w.seed, n)
     compare_records(got, want, w.circuit, oc, w.seed, 0, TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_widest_state_records(prec):
+    """Maximum size: a peak active width of 20 (2^20 amplitudes per shot, HBM-resident, 1024 threads per
+    shot), 64 shots against the oracle."""
+    c = wide_circuit(18, 7)
+    p = S.Program(c)
+    assert p.k_max == 20
+    oc = OracleCircuit(c)
+    seed = 4242
+    print(f"widest state k_max={p.k_max} {prec}", flush=True)
+    got = _gpu(p, 64, seed, precision=prec)
+    compare_records(got, oc.sample(seed, 64), c, oc, seed, 0, TOL[prec])
 
 
 def test_random_small_circuits():
