@@ -169,8 +169,9 @@ typedef struct {
 
 /* Sample `shots` shots (paper Sec. 5) into device buffer records_out
  * (n_rows x ceil(shots/64) uint64 words, record-major as above), with
- * complex FP64 amplitudes.  shots == 0 is a no-op.  Errors: EINVAL (null
- * program or output), ECAPACITY, ENOMEM, EHIP. */
+ * complex FP64 amplitudes.  shots == 0 is a no-op, and so is a program with
+ * no rows (no records, detectors or observables; records_out may then be
+ * NULL).  Errors: EINVAL (null program or output), ECAPACITY, ENOMEM, EHIP. */
 symft_status symft_sample(const symft_program *p, uint64_t shots, uint64_t seed, uint64_t *records_out,
                           void *stream);
 

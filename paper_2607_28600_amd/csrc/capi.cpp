@@ -660,7 +660,7 @@ symft_status symft_sample_ex(const symft_program *pc, const symft_sample_opts *o
     if (opts) o = *opts;
     if (o.shot_offset % 64) return set_err(SYMFT_EINVAL, "shot_offset must be a multiple of 64");
     if (o.precision > 1) return set_err(SYMFT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
-    if (shots == 0) return SYMFT_OK;
+    if (shots == 0 || p->P.n_rows() == 0) return SYMFT_OK;  // nothing observable to write
     if (!records_out) return set_err(SYMFT_EINVAL, "records_out is NULL");
     const uint64_t n_words = (shots + 63) / 64;
     const uint64_t stride = o.row_stride_words ? o.row_stride_words : n_words;
