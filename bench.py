@@ -7,7 +7,7 @@ writes all 2762 bit-packed rows for 2^24 shots, inputs (the compiled program)
 already resident in HBM.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
-                    [--workload c2|c1|c3|c3fp64|c4|c4fp64|c5|c5fp64|c5k16|post]
+                    [--workload c2|c1|c3|c3fp64|c4|c4fp64|c5|c5fp64|c5k16|post|distill]
 
 Prints one JSON line.  `roofline` prices the dominant kernel against HBM
 bandwidth (record bytes written per launch / average launch time, measured
@@ -206,11 +206,11 @@ def run(args):
                                         "programs": len(errs)}
         circ, seed = ws[0].circuit, ws[0].seed
         sample_words = list(range(16))
-    elif wl == "post":
+    elif wl in ("post", "distill"):
         # detector postselection with the aggregate-count output: a step is one call that returns the
         # discarded / logical-error flags and their counts for every shot; rejected shots stop their
         # dense work at the rejecting detector
-        w = configs.postselect()
+        w = configs.postselect() if wl == "post" else configs.distill()
         prec = "fp32"
         prog = S.Program(w.circuit)
         info = prog.info()
@@ -253,7 +253,8 @@ def run(args):
                   "postselected_detectors": len(post),
                   "output": "per-shot discarded / logical-error flags + counts"}
         circ, seed = w.circuit, w.seed
-        sample_words = [int(i * words / 16) for i in range(16)]
+        n_cpu_words = 16 if wl == "post" else 8192  # the width-5 distillation oracle runs ~1e5 shots/s
+        sample_words = [int(i * words / n_cpu_words) for i in range(n_cpu_words)]
     else:
         raise SystemExit(f"unknown workload {wl}")
 

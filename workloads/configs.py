@@ -21,6 +21,7 @@ from typing import List, Tuple
 
 from . import near_clifford as nc
 from .circuit import Circuit
+from .distill import distill_15to1
 from .surface import rotated_memory_z
 
 _SEEDS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "seeds.json")
@@ -68,6 +69,10 @@ def c5(k: int = 14, shots: int = 1 << 16) -> Workload:
 def postselect() -> Workload:
     return Workload("coherent_surface_d5_r5_theta0.1_postselect", rotated_memory_z(5, 5, 1e-3, coherent=0.1),
                     1 << 18, 0x5EED0006)
+
+
+def distill() -> Workload:
+    return Workload("distill_15to1_p1e-3_postselect", distill_15to1(1e-3), 1 << 22, 0x5EED0007)
 
 
 def small_surface() -> Tuple[Circuit, int]:
