@@ -287,7 +287,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build samples on one GPU; shots shard by 64-shot word ranges, "
+        print(json.dumps({"error": "the sampler runs on one GPU only; shots shard by 64-shot word ranges, "
                                    "so N GPUs would each run this same kernel on 1/N of the words"}))
         raise SystemExit(2)
     run(args)

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libsymft.so")
 
 if not os.path.exists(LIB):
-    raise ImportError(f"{LIB} is not built; run `python paper_2607_28600_amd/build.py` (or __graft_entry__.build())")
+    raise ImportError(f"{LIB} is not built; run `python paper_2607_28600_amd/build.py`")
 
 # PyTorch ships its own HIP runtime under the same soname.  Loading it first
 # makes the library bind to that one runtime; loaded the other way round, the
