@@ -120,11 +120,28 @@ typedef struct {
     uint64_t frame_max_level;      /* largest emit level */
     uint64_t frame_pushes;         /* record-to-consumer XORs over the schedule */
     uint64_t frame_noise_consumers;/* noise-symbol-to-consumer XORs, summed over symbols */
+    uint64_t rotations_removed;    /* rotations fused into an earlier one or cancelled (symft_compile_opts) */
 } symft_info;
+
+/* Compile options.  simplify = 1 runs a conservative commutation-aware
+ * rewrite before planning (paper Sec. 6, simplification before planning):
+ * a rotation R_P(b) later in the circuit is fused into an earlier R_P(a) with
+ * the same Pauli body (the same qubits and letters; R_-P(t) = R_P(-t)) when
+ * every op between them acts on qubits disjoint from P's support and no
+ * detector lies between them; the fused rotation is R_P(a + b), and it is
+ * removed when a + b is a multiple of 2 pi (global phase dropped).  The
+ * fused rotation keeps the earlier rotation's place; the later op becomes a
+ * no-op, so per-op arrays keep the circuit's length.  Records, detectors and
+ * measurement order are unchanged.  Measurements are not moved. */
+typedef struct {
+    uint32_t simplify;
+    uint32_t reserved[3];          /* 0 */
+} symft_compile_opts;
 
 /* Compile `ops` (paper Sec. 2 circuit) into a sampling program (Sec. 3-4).
  * Host only; no GPU work.  Errors: EINVAL (bad op / qubit / arity), EACAUSAL,
- * EPROB, ECAPACITY (k_max > 30), ENOMEM.  `opts` is reserved (pass NULL).
+ * EPROB, ECAPACITY (k_max > 30), ENOMEM.  `opts` points to a
+ * symft_compile_opts, or is NULL for the defaults (no simplification).
  * On success *out owns the program; free it with symft_program_free. */
 symft_status symft_compile(uint32_t n_qubits, const symft_op *ops, size_t n_ops, const void *opts,
                            symft_program **out);

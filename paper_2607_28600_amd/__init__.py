@@ -58,7 +58,12 @@ class symft_info(C.Structure):
         ("expr_meas_nnz", C.c_uint64), ("dense_flops_per_shot", C.c_double), ("dense_bytes_per_shot", C.c_double),
         ("frame_steps", C.c_uint64), ("frame_noise_steps", C.c_uint64), ("frame_slots", C.c_uint64),
         ("frame_max_level", C.c_uint64), ("frame_pushes", C.c_uint64), ("frame_noise_consumers", C.c_uint64),
+        ("rotations_removed", C.c_uint64),
     ]
+
+
+class symft_compile_opts(C.Structure):
+    _fields_ = [("simplify", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
 class symft_sample_opts(C.Structure):
@@ -166,10 +171,14 @@ def _marshal(circ):
 class Program:
     """A compiled SymFT sampling program (owned by the C library)."""
 
-    def __init__(self, circ):
+    def __init__(self, circ, simplify: bool = False):
+        """simplify: fuse and cancel rotations with the same Pauli body across ops on other qubits
+        (symft_compile_opts.simplify)."""
         arr, keep = _marshal(circ)
         h = C.c_void_p()
-        _check(_lib.symft_compile(circ.n_qubits, arr, len(circ.ops), None, C.byref(h)), "symft_compile")
+        opts = symft_compile_opts(simplify=1 if simplify else 0)
+        _check(_lib.symft_compile(circ.n_qubits, arr, len(circ.ops), C.cast(C.pointer(opts), C.c_void_p), C.byref(h)),
+               "symft_compile")
         self._h = h
         self.n_ops = len(circ.ops)
         info = self.info()

@@ -533,14 +533,29 @@ extern "C" {
 const char *symft_last_error(void) { return g_err.c_str(); }
 
 symft_status symft_compile(uint32_t n_qubits, const symft_op *ops, size_t n_ops, const void *opts, symft_program **out) {
-    (void)opts;
     if (!out) return set_err(SYMFT_EINVAL, "out is NULL");
     *out = nullptr;
+    symft_compile_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *(const symft_compile_opts *)opts;
+    if (o.simplify > 1) return set_err(SYMFT_EINVAL, "simplify must be 0 or 1");
     symft_program *h = nullptr;
     try {
         h = new symft_program();
         std::string err;
-        int rc = compile_program(n_qubits, ops, n_ops, h->P, err);
+        std::vector<symft_op> rewritten;
+        uint64_t removed = 0;
+        if (o.simplify && n_ops) {
+            // the rewrite reads qubit and Pauli arrays, so check their presence first
+            for (size_t i = 0; i < n_ops; ++i)
+                if (ops[i].n && (!ops[i].qubits || (ops[i].kind == SYMFT_OP_ROT && !ops[i].paulis))) {
+                    delete h;
+                    return set_err(SYMFT_EINVAL, "op " + std::to_string(i) + ": qubits or paulis is NULL");
+                }
+            rewritten = simplify_rotations(ops, n_ops, removed);
+        }
+        int rc = compile_program(n_qubits, o.simplify && n_ops ? rewritten.data() : ops, n_ops, h->P, err);
+        h->P.rot_removed = removed;
         if (rc) {
             delete h;
             return set_err(rc, err);
@@ -594,6 +609,7 @@ symft_status symft_program_info(const symft_program *p, symft_info *info) {
     info->frame_slots = p->F.n_slots;
     info->frame_max_level = p->F.max_level;
     info->frame_noise_consumers = p->F.n_flips;
+    info->rotations_removed = p->P.rot_removed;
     info->frame_pushes = p->F.n_pushes;
     for (size_t i = 0; i < p->F.steps.size(); i += FR_STEP_WORDS)
         if (p->F.steps[i] == FR_NOISE) info->frame_noise_steps += 1;

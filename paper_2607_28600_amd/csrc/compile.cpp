@@ -793,6 +793,67 @@ int compile_program(uint32_t n_qubits, const void *ops_v, size_t n_ops, Program 
     return 0;
 }
 
+// Commutation-aware simplification before planning (paper Sec. 6), in its
+// conservative circuit-level form: R_P(a) ... R_P(b) with nothing between
+// them touching P's qubits and no detector between them is R_P(a + b) at the
+// first place (every op between commutes with P, acting on other qubits), and
+// nothing at all when a + b is a multiple of 2 pi.
+std::vector<symft_op> simplify_rotations(const symft_op *ops, size_t n_ops, uint64_t &removed) {
+    std::vector<symft_op> out(ops, ops + n_ops);
+    removed = 0;
+    // sorted (qubit, letter) pairs; empty for a body the compiler would reject
+    // (bad letter, repeated qubit), so that such an op is never fused away
+    auto body = [](const symft_op &o) {
+        std::vector<std::pair<uint32_t, uint8_t>> b;
+        for (uint32_t j = 0; j < o.n; ++j) {
+            if (o.paulis[j] < 1 || o.paulis[j] > 3) return std::vector<std::pair<uint32_t, uint8_t>>{};
+            b.push_back({o.qubits[j], o.paulis[j]});
+        }
+        std::sort(b.begin(), b.end());
+        for (size_t j = 1; j < b.size(); ++j)
+            if (b[j].first == b[j - 1].first) return std::vector<std::pair<uint32_t, uint8_t>>{};
+        return b;
+    };
+    const double two_pi = 6.283185307179586;
+    for (size_t i = 0; i < n_ops; ++i) {
+        if (out[i].kind != SYMFT_OP_ROT || out[i].n == 0) continue;
+        const auto bi = body(out[i]);
+        if (bi.empty()) continue;
+        double theta = out[i].negate ? -out[i].arg : out[i].arg;
+        bool fused = false;
+        for (size_t j = i + 1; j < n_ops; ++j) {
+            const symft_op &o = out[j];
+            if (o.kind == SYMFT_OP_DETECTOR) break;
+            if (o.kind == SYMFT_OP_ROT && o.n == bi.size() && body(o) == bi) {
+                theta += o.negate ? -o.arg : o.arg;
+                out[j] = symft_op{};
+                out[j].kind = SYMFT_OP_TICK;
+                ++removed;
+                fused = true;
+                continue;
+            }
+            bool touch = false;
+            for (uint32_t t = 0; t < o.n && !touch; ++t)
+                for (const auto &q : bi)
+                    if (o.qubits[t] == q.first) {
+                        touch = true;
+                        break;
+                    }
+            if (touch) break;
+        }
+        if (!fused) continue;
+        if (std::fabs(std::remainder(theta, two_pi)) < 1e-12) {
+            out[i] = symft_op{};
+            out[i].kind = SYMFT_OP_TICK;
+            ++removed;
+        } else {
+            out[i].negate = 0;
+            out[i].arg = theta;
+        }
+    }
+    return out;
+}
+
 void gap_table(uint64_t p32, uint64_t *Q) {
     Q[0] = uint64_t(1) << 32;
     for (int g = 0; g < 4096; ++g) {

@@ -5,6 +5,8 @@
 #include <string>
 #include <vector>
 
+#include "../../include/symft.h"
+
 namespace symft {
 
 enum InstrKind : uint8_t {
@@ -66,6 +68,7 @@ struct Program {
     uint32_t k_max = 0;
     uint64_t n_ops = 0, n_meas = 0, n_rec = 0, n_det = 0, n_obs = 0;
     uint32_t n_noise_sym = 0;
+    uint64_t rot_removed = 0;  // rotations fused or cancelled by the simplification pass
     std::vector<Instr> instrs;
     std::vector<int32_t> meas_instr;            // measurement -> instruction
     std::vector<int64_t> meas_row;              // measurement -> record row, -1 hidden
@@ -83,5 +86,11 @@ struct Program {
 
 // Returns 0 or a negative symft status; err receives the message.
 int compile_program(uint32_t n_qubits, const void *ops, size_t n_ops, Program &out, std::string &err);
+
+// The conservative commutation-aware rewrite of symft_compile_opts.simplify
+// on a validated-shape op list: returns the rewritten list (same length; ops
+// it removes become TICK) and the number of rotations removed.  The returned
+// ops borrow the input's arrays.
+std::vector<symft_op> simplify_rotations(const symft_op *ops, size_t n_ops, uint64_t &removed);
 
 }  // namespace symft
