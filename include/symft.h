@@ -131,8 +131,12 @@ typedef struct {
  * detector lies between them; the fused rotation is R_P(a + b), and it is
  * removed when a + b is a multiple of 2 pi (global phase dropped).  The
  * fused rotation keeps the earlier rotation's place; the later op becomes a
- * no-op, so per-op arrays keep the circuit's length.  Records, detectors and
- * measurement order are unchanged.  Measurements are not moved. */
+ * no-op, so per-op arrays keep the circuit's length.  A rotation that reaches
+ * a measurement of +-P in the same way (an MPP of the same body; M, MR or R of
+ * the qubit when P = Z_q) is removed: before such a measurement R_P is a phase
+ * per outcome (the paper's move of a measurement toward a rotation of the same
+ * body, which then reduces to a branch phase).  Records, detectors and
+ * measurement order are unchanged. */
 typedef struct {
     uint32_t simplify;
     uint32_t reserved[3];          /* 0 */

@@ -14,7 +14,10 @@ rotation can move next to the earlier one, and R_P(a) R_P(b) = R_P(a + b).
 The merged rotation stays at the earlier place; the later operation becomes a
 TICK (nothing), so operation indices are kept.  A merged angle that is a
 multiple of 2 pi leaves -I or I, a global phase, and the earlier rotation
-goes too.
+goes too.  A rotation that reaches, under the same condition, a measurement of
++-P (an MPP of the same body, or M / MR / R of qubit q when P = Z_q) only
+multiplies each outcome's branch by a phase, since the measurement's
+projectors are eigenspaces of P, so it is removed.
 """
 from __future__ import annotations
 
@@ -44,7 +47,7 @@ def simplify(circ: Circuit) -> Tuple[Circuit, int]:
         body = frozenset(o.pauli)
         support = {q for q, _ in o.pauli}
         theta = _signed(o)
-        merged = False
+        merged = absorbed = False
         for j in range(i + 1, len(ops)):
             x = ops[j]
             if x.name == "DETECTOR":
@@ -56,7 +59,15 @@ def simplify(circ: Circuit) -> Tuple[Circuit, int]:
                 merged = True
                 continue
             if support & (set(x.targets) | {q for q, _ in x.pauli}):
+                if x.name == "MPP":
+                    absorbed = len(x.pauli) == len(o.pauli) and frozenset(x.pauli) == body
+                elif x.name in ("M", "MR", "R"):
+                    absorbed = len(o.pauli) == 1 and o.pauli[0][1] == "Z"
                 break
+        if absorbed:
+            ops[i] = Op("TICK")
+            removed += 1
+            continue
         if not merged:
             continue
         if abs(math.remainder(theta, 2 * math.pi)) < 1e-12:

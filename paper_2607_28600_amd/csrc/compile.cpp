@@ -797,7 +797,8 @@ int compile_program(uint32_t n_qubits, const void *ops_v, size_t n_ops, Program 
 // conservative circuit-level form: R_P(a) ... R_P(b) with nothing between
 // them touching P's qubits and no detector between them is R_P(a + b) at the
 // first place (every op between commutes with P, acting on other qubits), and
-// nothing at all when a + b is a multiple of 2 pi.
+// nothing at all when a + b is a multiple of 2 pi.  A rotation that reaches,
+// the same way, a measurement of +-P is a phase per outcome and goes too.
 std::vector<symft_op> simplify_rotations(const symft_op *ops, size_t n_ops, uint64_t &removed) {
     std::vector<symft_op> out(ops, ops + n_ops);
     removed = 0;
@@ -820,7 +821,7 @@ std::vector<symft_op> simplify_rotations(const symft_op *ops, size_t n_ops, uint
         const auto bi = body(out[i]);
         if (bi.empty()) continue;
         double theta = out[i].negate ? -out[i].arg : out[i].arg;
-        bool fused = false;
+        bool fused = false, absorbed = false;
         for (size_t j = i + 1; j < n_ops; ++j) {
             const symft_op &o = out[j];
             if (o.kind == SYMFT_OP_DETECTOR) break;
@@ -839,7 +840,23 @@ std::vector<symft_op> simplify_rotations(const symft_op *ops, size_t n_ops, uint
                         touch = true;
                         break;
                     }
-            if (touch) break;
+            if (!touch) continue;
+            // The rotation commutes up to this op.  A measurement of +-P next
+            // (MPP of the same body; M, MR or R of the qubit when P = Z_q)
+            // sees R_P only as a phase per outcome, so the rotation goes.
+            if (o.kind == SYMFT_OP_MPP) {
+                absorbed = o.n == bi.size() && body(o) == bi;
+            } else if ((o.kind == SYMFT_OP_M || o.kind == SYMFT_OP_MR || o.kind == SYMFT_OP_R) && bi.size() == 1 &&
+                       bi[0].second == 3) {
+                absorbed = true;  // touch means one of its qubits is P's
+            }
+            break;
+        }
+        if (absorbed) {
+            out[i] = symft_op{};
+            out[i].kind = SYMFT_OP_TICK;
+            ++removed;
+            continue;
         }
         if (!fused) continue;
         if (std::fabs(std::remainder(theta, two_pi)) < 1e-12) {

@@ -11,7 +11,9 @@ symft_compile_opts.simplify, on the CPU.
   circuit gives the oracle's records bit for bit.
 * Closed cases: a cancelled pair across a gate on another qubit leaves a
   pure-frame program; a gate on a shared qubit or a detector between the two
-  stops the fusion; a negated Pauli turns the angle.
+  stops the fusion; a negated Pauli turns the angle; a rotation followed by a
+  measurement of the same body (or of its qubit, for Z) is removed, one of
+  another body is not.
 """
 import numpy as np
 import pytest
@@ -42,6 +44,8 @@ def fusable_circuit(rng, n, length, p_noise=0.2):
         want = -(-o.arg if o.negate else o.arg) if rng.random() < 0.5 else float(rng.uniform(-3, 3))
         pauli = tuple(o.pauli[::-1])
         ops.append(Op("ROT", pauli=pauli, negate=neg, arg=-want if neg else want))
+        if rng.random() < 0.25:  # a measurement of the same body, which absorbs the rotation
+            ops.append(Op("MPP", pauli=pauli, negate=bool(rng.random() < 0.5)))
     c.ops = ops
     return c
 
@@ -71,7 +75,7 @@ def test_fusion_stops_at_shared_qubits_and_detectors():
     c.rot([(0, "Z")], 0.3)
     c.append("H", [0])           # touches the rotation's qubit
     c.rot([(0, "Z")], -0.3)
-    c.append("M", [0])
+    c.mpp([(0, "X")])            # another body: absorbs nothing
     assert _plan(c)[2] == 0
     c = Circuit(2)
     c.append("H", [0])
@@ -86,6 +90,22 @@ def test_fusion_stops_at_shared_qubits_and_detectors():
     c.rot([(0, "Z")], 0.3, negate=True)  # R_-Z(0.3) = R_Z(-0.3): cancels
     c.append("M", [0])
     assert _plan(c)[2] == 2
+
+
+def test_rotation_before_a_measurement_of_its_body_is_removed():
+    c = Circuit(3)
+    c.append("H", [0, 1, 2])
+    c.rot([(0, "X"), (1, "Y")], 0.7)
+    c.append("H", [2])
+    c.mpp([(1, "Y"), (0, "X")], negate=True)   # -P: still the same body
+    c.rot([(2, "Z")], 0.4)
+    c.append("MR", [2])
+    c.rot([(0, "X")], 0.4)
+    c.append("M", [0])                           # a Z measurement: another body, kept
+    p, _, removed = _plan(c)
+    assert removed == 2
+    assert simplify(c)[1] == 2
+    assert [o.name for o in simplify(c)[0].ops].count("ROT") == 1
 
 
 @pytest.mark.parametrize("seed", range(3))
