@@ -185,7 +185,10 @@ typedef struct {
                                       kept per (64-shot word, probability class) before that word falls back to
                                       drawing its events again at every step (records are unchanged; for tests
                                       of that fallback) */
-    uint32_t reserved;             /* 0 */
+    uint32_t frame_tile_words;     /* pure-frame programs: 0 = automatic (32-word tiles, one 16-wave workgroup
+                                      per CU, when the schedule fits LDS at that width and there are at least
+                                      two such tiles per CU; else 16-word tiles); 16 or 32 forces the width
+                                      (ECAPACITY if it does not fit; records are unchanged) */
 } symft_sample_opts;
 
 /* Sample `shots` shots (paper Sec. 5) into device buffer records_out

@@ -20,13 +20,13 @@ hipError_t launch_active(const ActiveArgs &A, bool fp64, uint32_t bs, uint32_t g
 size_t active_lds_bytes(const DevProg &P, uint32_t bs, uint32_t tps, bool lds_vec, bool fp64);
 int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds, bool cm);
 struct FrameArgs;
-hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st);
+hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st, uint32_t tw);
 struct BatchArgs;
 hipError_t launch_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t lds, hipStream_t st);
 int batch_max_blocks_per_cu(bool fp64, size_t lds);
-size_t frame_lds_bytes(const DevProg &P);
-size_t frame_scratch_words(uint32_t word_entries);
-int frame_max_blocks_per_cu(size_t lds);
+size_t frame_lds_bytes(const DevProg &P, uint32_t tw);
+size_t frame_scratch_words(uint32_t word_entries, uint32_t tw);
+int frame_max_blocks_per_cu(size_t lds, uint32_t tw);
 hipError_t launch_gap_check(const GapFast &F, const uint64_t *Q, const uint32_t *v, int32_t *g, uint64_t n,
                             hipStream_t st);
 }  // namespace symft
@@ -281,7 +281,7 @@ static void lower(symft_program *h) {
     m.fr_first_emit = h->F.first_emit[0];
     m.fr_first_emit_n = h->F.first_emit[1];
     m.fr_first_noise_cls = h->F.first_noise_cls;
-    m.fr_ok = h->F.ok && frame_lds_bytes(m) <= kLdsLimit ? 1u : 0u;
+    m.fr_ok = h->F.ok && frame_lds_bytes(m, 16) <= kLdsLimit ? 1u : 0u;
     m.n_sym = P.n_noise_sym;
 }
 
@@ -492,12 +492,19 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
 
 static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_begin, uint64_t n_words, uint64_t shots,
                               uint64_t *out, uint64_t stride, uint32_t sections, uint64_t seed, uint32_t cap_override,
-                              hipStream_t st, const CountArgs *cnt = nullptr) {
-    size_t lds = frame_lds_bytes(D);
+                              hipStream_t st, const CountArgs *cnt = nullptr, uint32_t tile_words = 0) {
+    if (tile_words != 0 && tile_words != 16 && tile_words != 32)
+        return set_err(SYMFT_EINVAL, "frame_tile_words must be 0, 16 or 32");
+    // 32-word tiles halve the barrier steps per word; they need the slots of
+    // 32 words in LDS and leave one workgroup per CU, so they are taken only
+    // with at least two tiles per CU
+    uint32_t tw = tile_words;
+    if (!tw) tw = frame_lds_bytes(D, 32) <= kLdsLimit && (n_words + 31) / 32 >= 2 * (uint64_t)num_cus() ? 32 : 16;
+    size_t lds = frame_lds_bytes(D, tw);
     if (lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "frame schedule exceeds the LDS budget");
-    int per_cu = frame_max_blocks_per_cu(lds);
+    int per_cu = frame_max_blocks_per_cu(lds, tw);
     if (per_cu <= 0) per_cu = 1;
-    uint64_t tiles = (n_words + 15) / 16;  // 16-word tiles
+    uint64_t tiles = (n_words + tw - 1) / tw;
     uint64_t cap = (uint64_t)per_cu * (uint64_t)num_cus();
     uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
     FrameArgs A;
@@ -506,7 +513,7 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
     A.cap_override = cap_override;
     A.cap = D.fr_cap;
     A.cap_off = D.fr_capoff;
-    const size_t scratch_bytes = (size_t)grid * frame_scratch_words(A.word_entries) * 8;
+    const size_t scratch_bytes = (size_t)grid * frame_scratch_words(A.word_entries, tw) * 8;
     void *scratch = nullptr;
     if (pool_alloc(&scratch, scratch_bytes, st) != hipSuccess)
         return set_err(SYMFT_ENOMEM, "frame scratch allocation failed");
@@ -522,7 +529,7 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
     A.store16 = (((uintptr_t)out & 15u) == 0 && (stride & 1u) == 0) ? 1u : 0u;
     A.lds_bytes = (uint32_t)lds;
     if (cnt) A.cnt = *cnt;
-    hipError_t e = launch_frame(A, grid, st);
+    hipError_t e = launch_frame(A, grid, st, tw);
     hipFreeAsync(scratch, st);
     if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("frame kernel launch failed: ") + hipGetErrorString(e));
     return SYMFT_OK;
@@ -688,7 +695,8 @@ symft_status symft_sample_ex(const symft_program *pc, const symft_sample_opts *o
     hipStream_t st = (hipStream_t)stream;
     const uint64_t w0 = o.shot_offset / 64;
     if (D.fr_ok)
-        return run_frame(p, D, w0, n_words, shots, records_out, stride, sections, seed, o.frame_entry_cap, st);
+        return run_frame(p, D, w0, n_words, shots, records_out, stride, sections, seed, o.frame_entry_cap, st,
+                         nullptr, o.frame_tile_words);
     return run_active(p, D, o.precision == 0, w0, n_words, shots, records_out, stride, sections, nullptr, 0, 0, seed, st);
 }
 

@@ -1,8 +1,10 @@
 // sample_frame.hip -- pure-frame sampling (peak active width 0) for gfx950.
 //
-// A workgroup owns a tile of 16 consecutive 64-shot words.  One uint64 holds
-// one row of one word's 64 shots, so a row of a tile is one aligned 128-byte
-// line of the record-major output.  Per tile:
+// A workgroup owns a tile of TW = 16 or 32 consecutive 64-shot words.  One
+// uint64 holds one row of one word's 64 shots, so a row of a tile is one or two
+// aligned 128-byte lines of the record-major output.  32-word tiles (16 waves,
+// one workgroup per CU) spend each barrier step on twice the words; they are
+// taken when the schedule's slots fit LDS at that width.  Per tile:
 //  * phase G (no barriers): the waves share out the tile's words and draw
 //    every noise event of each (word, probability class) stream under the
 //    draw contract -- walks of 64 lanes x 4 gap draws decided without the
@@ -33,7 +35,18 @@
 
 namespace symft {
 
-constexpr uint32_t TW = 16;  // words per tile
+// Tile shape, by tile width TW (16 or 32 words): TW / 2 waves, each walking
+// two words in phase G and streaming two words' entries in NOISE steps; an
+// EMIT step gives each thread one (node, 4 words) of up to FR_LEVEL_MAX nodes.
+template <uint32_t TW>
+struct Tile {
+    static_assert(TW == 16 || TW == 32, "tile of 16 or 32 words");
+    static constexpr uint32_t NWC = TW / 2;                    // waves
+    static constexpr uint32_t WPW = TW / NWC;                  // words per wave in NOISE steps
+    static constexpr uint32_t QPN = TW / 4;                    // word quads per node
+    static constexpr uint32_t STG_WORDS = FR_LEVEL_MAX * TW;   // staged u64
+    static_assert(FR_LEVEL_MAX * QPN == NWC * 64, "one (node, 4 words) per thread");
+};
 
 // Program data read with wave-uniform indices goes through the constant
 // address space, so it is fetched by scalar loads: those are counted apart
@@ -75,31 +88,35 @@ __device__ __forceinline__ uint32_t branch_of(const uint64_t *thr, uint64_t info
     return J - 1;
 }
 
-// Slot array: slot s holds the tile's 16 words at s * TW + (w ^ (s & 15)).  The
-// swizzle spreads one word column over the LDS banks (an unswizzled column sits
-// in one bank pair, so 64 lanes XOR-ing random slots of one word would
+// Slot array: slot s holds the tile's TW words at s * TW + (w ^ (s & (TW - 1))).
+// The swizzle spreads one word column over the LDS banks (an unswizzled column
+// sits in one bank pair, so 64 lanes XOR-ing random slots of one word would
 // serialise); the four words wl .. wl + 3 of an aligned quad stay one 32-byte
 // block, word wl + i at element i ^ (s & 3).
+template <uint32_t TW>
 __device__ __forceinline__ unsigned long long *slot_word(unsigned long long *slots, uint32_t s, uint32_t w) {
-    return &slots[(size_t)s * TW + (w ^ (s & 15u))];
+    return &slots[(size_t)s * TW + (w ^ (s & (TW - 1)))];
 }
+template <uint32_t TW>
 __device__ __forceinline__ unsigned long long *slot_quad(unsigned long long *slots, uint32_t s, uint32_t wl) {
-    return &slots[(size_t)s * TW + (wl ^ (s & 12u))];
+    return &slots[(size_t)s * TW + (wl ^ (s & (TW - 4)))];
 }
 
 // Flip entry: lane | cnt << 6 | step << 8 | s0 << 16 | s1 << 32 | s2 << 48,
 // applied to word wl of the tile.
+template <uint32_t TW>
 __device__ __forceinline__ void apply_entry(uint64_t e, unsigned long long *slots, uint32_t wl) {
     const unsigned long long bit = 1ull << (e & 63u);
     const uint32_t cnt = (uint32_t)(e >> 6) & 3u;
-    atomicXor(slot_word(slots, (uint32_t)(e >> 16) & 0xFFFFu, wl), bit);
-    if (cnt > 1) atomicXor(slot_word(slots, (uint32_t)(e >> 32) & 0xFFFFu, wl), bit);
-    if (cnt > 2) atomicXor(slot_word(slots, (uint32_t)(e >> 48), wl), bit);
+    atomicXor(slot_word<TW>(slots, (uint32_t)(e >> 16) & 0xFFFFu, wl), bit);
+    if (cnt > 1) atomicXor(slot_word<TW>(slots, (uint32_t)(e >> 32) & 0xFFFFu, wl), bit);
+    if (cnt > 2) atomicXor(slot_word<TW>(slots, (uint32_t)(e >> 48), wl), bit);
 }
 
 // XOR v[0 .. 3] into words wl .. wl + 3 of slot s.
+template <uint32_t TW>
 __device__ __forceinline__ void push_quad(unsigned long long *slots, uint32_t s, uint32_t wl, const unsigned long long *v) {
-    unsigned long long *d = slot_quad(slots, s, wl);
+    unsigned long long *d = slot_quad<TW>(slots, s, wl);
     const uint32_t x = s & 3u;
 #pragma unroll
     for (uint32_t i = 0; i < 4; ++i) atomicXor(d + (i ^ x), v[i]);
@@ -146,7 +163,7 @@ __device__ __forceinline__ WalkTabs walk_tabs(const DevProg &P) { return WalkTab
 // out[*n_out ...] (those past `cap` are dropped, *n_out still counts them);
 // otherwise they are applied to the word's slot column.  Returns whether the
 // walk stopped at R.
-template <bool GEN>
+template <uint32_t TW, bool GEN>
 __device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const uint64_t *Q, uint32_t c, uint32_t coff, uint32_t wlo,
                      uint32_t whi, Walk &st, uint32_t R, uint32_t *tmp, uint64_t *out, uint32_t cap,
                      uint32_t *n_out, unsigned long long *slots, uint32_t wl, uint32_t k0, uint32_t k1) {
@@ -291,12 +308,12 @@ __device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const 
 #pragma unroll
         for (uint32_t i = 0; i < 4; ++i) {
             if (flip_inline(fw[i])) {
-                apply_entry(fw[i] | tag[i], slots, wl);
+                apply_entry<TW>(fw[i] | tag[i], slots, wl);
                 continue;
             }
             const uint32_t k = flip_count(fw[i]);
             const uint64_t f0 = fw[i] >> 8;
-            for (uint32_t q = 0; q < k; ++q) apply_entry(T.fl3[f0 + q] | tag[i], slots, wl);
+            for (uint32_t q = 0; q < k; ++q) apply_entry<TW>(T.fl3[f0 + q] | tag[i], slots, wl);
         }
     }
     st.pos = n_pos;
@@ -308,13 +325,14 @@ __device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const 
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Walk the word's class stream up to the end R of this step, applying events at once.
+template <uint32_t TW>
 __device__ __forceinline__ void noise_direct(WalkTabs T, GapFast F, const uint64_t *Q, uint32_t c, uint32_t coff,
                                           uint32_t R, uint64_t w, FrWord *S, uint32_t *tmp, unsigned long long *slots,
                                           uint32_t wl,
                                           uint32_t k0, uint32_t k1) {
     Walk st = {rfl(S->pos), rfl(S->j), rfl(S->e)};
     if (st.pos >= R) return;
-    while (!walk<false>(T, F, Q, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st, R, tmp, nullptr, 0, nullptr, slots, wl,
+    while (!walk<TW, false>(T, F, Q, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st, R, tmp, nullptr, 0, nullptr, slots, wl,
                         k0, k1) &&
            st.pos < R) {
     }
@@ -343,17 +361,18 @@ __device__ __forceinline__ unsigned long long rm_word(uint32_t t, uint64_t w, ui
 // is not written) and XOR-ed into the successors' slots.  Thread q always
 // stages at the same place, so it stores the previous step's chunk and
 // stages the next one in program order without a second buffer.
+template <uint32_t TW>
 __device__ __forceinline__ void emit_quad(const DevProg &P, const FrameArgs &A, uint4 ra, uint4 rb, uint32_t q,
                                           uint64_t wt, unsigned long long *slots, unsigned long long *stg,
                                           uint32_t *rows, unsigned long long *fl, uint32_t k0, uint32_t k1) {
-    const uint32_t vi = q >> 2, wl = 4 * (q & 3u);
+    const uint32_t vi = q / Tile<TW>::QPN, wl = 4 * (q % Tile<TW>::QPN);
     const uint32_t flags = ra.x >> 24;
     const unsigned long long c = (flags & 1u) ? ~0ull : 0ull;
     unsigned long long v[4] = {c, c, c, c};
     {
         // a node with no contributions reads the extra slot past the schedule's, which stays zero
         const uint32_t sl = ra.x & 0xFFFFFFu, x = sl & 3u;
-        unsigned long long *sp = slot_quad(slots, sl, wl);
+        unsigned long long *sp = slot_quad<TW>(slots, sl, wl);
 #pragma unroll
         for (uint32_t i = 0; i < 4; ++i) v[i] ^= sp[i ^ x];
         ((ulonglong2 *)sp)[0] = make_ulonglong2(0ull, 0ull);
@@ -398,16 +417,17 @@ __device__ __forceinline__ void emit_quad(const DevProg &P, const FrameArgs &A, 
         rows[vi] = (ra.y != FR_NO_ROW && sec && ((A.sections >> (sec - 1)) & 1u)) ? ra.y : FR_NO_ROW;
     }
     const uint32_t np = ra.w;
-    if (np > 0) push_quad(slots, rb.x, wl, v);
-    if (np > 1) push_quad(slots, rb.y, wl, v);
-    for (uint32_t k = 2; k < np; ++k) push_quad(slots, P.fr_push[rb.z + k - 2], wl, v);
+    if (np > 0) push_quad<TW>(slots, rb.x, wl, v);
+    if (np > 1) push_quad<TW>(slots, rb.y, wl, v);
+    for (uint32_t k = 2; k < np; ++k) push_quad<TW>(slots, P.fr_push[rb.z + k - 2], wl, v);
 }
 
 // One 32-byte chunk (node q / 4, words 4 (q % 4) .. + 3) of the rows staged
 // by an EMIT step.
+template <uint32_t TW>
 __device__ __forceinline__ void store_chunk(const FrameArgs &A, const unsigned long long *stg, const uint32_t *rows,
                                             uint32_t q, uint64_t wt, bool full) {
-    const uint32_t v = q >> 2, pw = 4 * (q & 3u);
+    const uint32_t v = q / Tile<TW>::QPN, pw = 4 * (q % Tile<TW>::QPN);
     const uint32_t row = rows[v];
     const uint64_t wi = wt + pw;
     const ulonglong2 *src = (const ulonglong2 *)&stg[v * TW + pw];
@@ -437,11 +457,7 @@ __device__ __forceinline__ void store_chunk(const FrameArgs &A, const unsigned l
     }
 }
 
-constexpr uint32_t NWC = 8;                        // waves; FR_LEVEL_MAX * TW / 4 = NWC * 64
-constexpr uint32_t STG_WORDS = FR_LEVEL_MAX * TW;  // staged u64
-constexpr uint32_t WPW = TW / NWC;                 // words per wave in NOISE steps
-
-// Workgroup: 8 waves.  LDS: slots [NS][TW] u64 | stream states [TW][NC] |
+// Workgroup: TW / 2 waves.  LDS: slots [NS][TW] u64 | stream states [TW][NC] |
 // entry cursors and counts [TW][NC] | overflow flags [TW] | aggregate-count
 // flags [2][TW] u64 (discarded, logical error) | one region used by
 // phase G as walk positions [NWC][256] and by phase S as the staging buffer
@@ -454,7 +470,9 @@ constexpr uint32_t WPW = TW / NWC;                 // words per wave in NOISE st
 // issued behind fresh stores would wait for them.)  Every slot is zero
 // between tiles: each one that receives a contribution is read and cleared by
 // the node that owns it, and every node is emitted.
-__global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4))) frame_kernel(FrameArgs A) {
+template <uint32_t TW>
+__global__ void __launch_bounds__(TW * 32) __attribute__((amdgpu_waves_per_eu(4))) frame_kernel(FrameArgs A) {
+    constexpr uint32_t NWC = Tile<TW>::NWC, WPW = Tile<TW>::WPW, QPN = Tile<TW>::QPN, STG_WORDS = Tile<TW>::STG_WORDS;
     extern __shared__ __align__(16) unsigned char smem[];
     const DevProg &P = A.P;
     const uint32_t NC = P.n_cls, NS = P.fr_n_slots, n_steps = P.fr_n_steps;
@@ -500,7 +518,7 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
                     scr + (size_t)wl * A.word_entries + (A.cap_override ? c * A.cap_override : uniform(A.cap_off)[c]);
                 Walk st = {0, 0, 0};
                 uint32_t n = 0;
-                while (!walk<true>(walk_tabs(P), F, P.cls_Q + (size_t)c * 4097, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st,
+                while (!walk<TW, true>(walk_tabs(P), F, P.cls_Q + (size_t)c * 4097, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st,
                                    cend, tmp, out, cap, &n, nullptr, 0, k0, k1) &&
                        st.pos < cend && n <= cap) {
                 }
@@ -520,8 +538,8 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
         uint64_t pe[WPW];
         uint32_t pk[WPW];
         auto fetch_records = [&](uint32_t first, uint32_t n) {
-            if (tid < n * (TW / 4)) {
-                const uint4 *rec = (const uint4 *)(P.fr_nodes + 8 * (size_t)(first + (tid >> 2)));
+            if (tid < n * QPN) {
+                const uint4 *rec = (const uint4 *)(P.fr_nodes + 8 * (size_t)(first + tid / QPN));
                 pa = rec[0];
                 pb = rec[1];
             }
@@ -553,7 +571,7 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
                 const uint32_t wl = wave + i * NWC;
                 if (wt + wl >= A.n_words) continue;
                 if (rfl(ovf[wl])) {
-                    noise_direct(walk_tabs(P), load_fast(P.cls_fast, c), P.cls_Q + (size_t)c * 4097, c,
+                    noise_direct<TW>(walk_tabs(P), load_fast(P.cls_fast, c), P.cls_Q + (size_t)c * 4097, c,
                                  uniform(P.cls_off)[c], r1 * 64u, A.word_begin + wt + wl, &wst[wl * NC + c], gtmp,
                                  slots, wl, k0, k1);
                     continue;
@@ -567,7 +585,7 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
                     const uint64_t e = first ? pe[i] : (idx < kend ? src[idx] : 0ull);
                     first = false;
                     const bool take = idx < kend && ((uint32_t)(e >> 8) & 0xFFu) == sl;
-                    if (take) apply_entry(e, slots, wl);
+                    if (take) apply_entry<TW>(e, slots, wl);
                     const uint32_t nd = (uint32_t)__popcll(__ballot(take));
                     k += nd;
                     if (nd < 64) break;
@@ -590,19 +608,19 @@ __global__ void __launch_bounds__(NWC * 64) __attribute__((amdgpu_waves_per_eu(4
                 for (uint32_t i = 0; i < WPW; ++i) asm volatile("" : : "v"(pe[i]));
             }
             // rows staged by the previous step (if it was an EMIT step)
-            if (tid < pend_n * (TW / 4)) store_chunk(A, stg, rows, tid, wt, full);
+            if (tid < pend_n * QPN) store_chunk<TW>(A, stg, rows, tid, wt, full);
             pend_n = 0;
             if (is_emit) {
                 const uint32_t n = r[2];
                 fetch_records(r[5], r[6]);
-                if (tid < n * (TW / 4)) emit_quad(P, A, ra, rb, tid, wt, slots, stg, rows, fl, k0, k1);
+                if (tid < n * QPN) emit_quad<TW>(P, A, ra, rb, tid, wt, slots, stg, rows, fl, k0, k1);
                 pend_n = n;
             } else {
                 noise_step(r);
             }
             __syncthreads();
         }
-        if (tid < pend_n * (TW / 4)) store_chunk(A, stg, rows, tid, wt, full);
+        if (tid < pend_n * QPN) store_chunk<TW>(A, stg, rows, tid, wt, full);
         __syncthreads();
         if (A.cnt.on && tid < TW) {
             // the tile's flags: kept shots only can have a logical error; bits past the shot count are 0
@@ -643,29 +661,39 @@ __global__ void gap_check_kernel(GapFast F, const uint64_t *Q, const uint32_t *v
     g[i] = G;
 }
 
-size_t frame_lds_bytes(const DevProg &P) {
+template <uint32_t TW>
+static size_t lds_bytes_of(const DevProg &P) {
     // slots | stream states | cursors and counts | overflow flags | count flags | (walk positions or staging)
     const size_t head = (size_t)(P.fr_n_slots + 1) * TW * 8 + (size_t)TW * P.n_cls * (sizeof(FrWord) + 8) + TW * 4;
     const size_t flags = 2 * TW * 8;
-    const size_t region = std::max<size_t>((size_t)NWC * 256 * 4, STG_WORDS * 8 + FR_LEVEL_MAX * 4);
+    const size_t region =
+        std::max<size_t>((size_t)Tile<TW>::NWC * 256 * 4, Tile<TW>::STG_WORDS * 8 + FR_LEVEL_MAX * 4);
     return ((head + 15) & ~(size_t)15) + flags + region;
 }
 
-// Scratch per workgroup, in u64: flip entries of 16 words plus the fallback walks' positions.
-size_t frame_scratch_words(uint32_t word_entries) { return (size_t)TW * word_entries + NWC * 128; }
+// Tile width tw is 16 or 32 in all of these.
+size_t frame_lds_bytes(const DevProg &P, uint32_t tw) { return tw == 32 ? lds_bytes_of<32>(P) : lds_bytes_of<16>(P); }
 
-uint32_t frame_threads() { return NWC * 64; }
+// Scratch per workgroup, in u64: flip entries of the tile's words plus the fallback walks' positions.
+size_t frame_scratch_words(uint32_t word_entries, uint32_t tw) { return (size_t)tw * word_entries + (tw / 2) * 128; }
 
-int frame_max_blocks_per_cu(size_t lds) {
+uint32_t frame_threads(uint32_t tw) { return tw * 32; }
+
+int frame_max_blocks_per_cu(size_t lds, uint32_t tw) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, frame_kernel, (int)frame_threads(), lds) != hipSuccess) return 1;
+    const void *k = tw == 32 ? (const void *)frame_kernel<32> : (const void *)frame_kernel<16>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)frame_threads(tw), lds) != hipSuccess) return 1;
     return nb;
 }
 
-hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st) {
-    hipError_t e = hipFuncSetAttribute((const void *)frame_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds_bytes);
+hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st, uint32_t tw) {
+    const void *k = tw == 32 ? (const void *)frame_kernel<32> : (const void *)frame_kernel<16>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(frame_kernel, dim3(grid), dim3(frame_threads()), A.lds_bytes, st, A);
+    if (tw == 32)
+        hipLaunchKernelGGL(frame_kernel<32>, dim3(grid), dim3(frame_threads(32)), A.lds_bytes, st, A);
+    else
+        hipLaunchKernelGGL(frame_kernel<16>, dim3(grid), dim3(frame_threads(16)), A.lds_bytes, st, A);
     return hipGetLastError();
 }
 

@@ -168,3 +168,19 @@ def test_counts_do_not_depend_on_threads_per_shot_and_autotune():
     assert tps in (4, 8, 16, 32, 64, 128, 256)
     f, n = p.sample_counts(64 * 5 + 9, 0x5EED0C06, post=post, precision="fp32")
     assert torch.equal(f, ref_f) and torch.equal(n, ref_c)
+
+
+def test_counts_with_32_word_tiles_match_forced_16_word_records(c1):
+    """2^20 shots of C1: the count launch takes 32-word tiles (at least two per CU), and its flags must
+    equal those derived from records written with 16-word tiles (which the record tests pin to the
+    oracle)."""
+    w, p, oc = c1
+    shots = 1 << 20
+    post = list(range(0, w.circuit.num_detectors, 3))
+    print("counts C1 2^20 shots, 32-word tiles", flush=True)
+    flags_t, counts_t = p.sample_counts(shots, w.seed, post=post)
+    rec = S.bits_to_numpy(p.sample(shots, w.seed, frame_tile_words=16))
+    c = w.circuit
+    want_f, want_c = count_flags(rec, c.num_records, c.num_detectors, c.num_observables, shots, post, None)
+    assert np.array_equal(S.bits_to_numpy(flags_t), want_f)
+    assert list(counts_t.cpu().numpy()) == list(want_c)

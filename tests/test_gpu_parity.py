@@ -295,9 +295,10 @@ def _multiclass_surface(d, rounds, k):
     return c
 
 
+@pytest.mark.parametrize("tw", [0, 32])
 @pytest.mark.parametrize("k", [3, 12])
 @pytest.mark.parametrize("cap", [0, 8])
-def test_frame_multiclass_bit_exact(k, cap):
+def test_frame_multiclass_bit_exact(k, cap, tw):
     """cap = 8 flip entries per (word, class) sends nearly every word down the fallback that
     draws its events again at every NOISE step."""
     c = _multiclass_surface(5, 4, k)
@@ -307,10 +308,41 @@ def test_frame_multiclass_bit_exact(k, cap):
     oc = OracleCircuit(c)
     seed = 0xC1A55 + k
     n = 64 * 40 + 17
-    assert np.array_equal(_gpu(p, n, seed, frame_entry_cap=cap), oc.sample(seed, n))
+    assert np.array_equal(_gpu(p, n, seed, frame_entry_cap=cap, frame_tile_words=tw), oc.sample(seed, n))
     off = 64 * 21
-    assert np.array_equal(_gpu(p, 700, seed, shot_offset=off, frame_entry_cap=cap),
+    assert np.array_equal(_gpu(p, 700, seed, shot_offset=off, frame_entry_cap=cap, frame_tile_words=tw),
                           oc.sample(seed, 700, shot_begin=off))
+
+
+@pytest.mark.parametrize("tw", [16, 32])
+def test_frame_tile_widths_bit_exact(c1, c2, tw):
+    """Both tile widths forced: C1 in full (256 words) and ragged at an offset, C2 over 40 words (a
+    32-word tile and a partial one)."""
+    w, p, oc = c1
+    print(f"C1 tile width {tw}", flush=True)
+    assert np.array_equal(_gpu(p, w.shots, w.seed, frame_tile_words=tw), oc.sample(w.seed, w.shots))
+    assert np.array_equal(_gpu(p, 1000, w.seed, shot_offset=64 * 37, frame_tile_words=tw),
+                          oc.sample(w.seed, 1000, shot_begin=64 * 37))
+    w, p, oc = c2
+    print(f"C2 tile width {tw}", flush=True)
+    assert np.array_equal(_gpu(p, 64 * 40, w.seed, frame_tile_words=tw), oc.sample(w.seed, 64 * 40))
+
+
+def test_frame_tile_width_falls_back_to_16_words():
+    """A schedule whose slots fit LDS at 16 words per tile but not at 32: the automatic choice takes 16,
+    and forcing 32 is a capacity error, raised before any launch."""
+    from workloads.surface import rotated_memory_z
+    c = rotated_memory_z(13, 3, 1e-3)
+    p = S.Program(c)
+    oc = OracleCircuit(c)
+    print("d13 r3: automatic tile width", flush=True)
+    assert np.array_equal(_gpu(p, 64 * 600, 5), _gpu(p, 64 * 600, 5, frame_tile_words=16))
+    assert np.array_equal(_gpu(p, 64 * 4, 5), oc.sample(5, 64 * 4))
+    with pytest.raises(S.SymftError) as ei:
+        _gpu(p, 64 * 600, 5, frame_tile_words=32)
+    assert ei.value.code == -5
+    with pytest.raises(S.SymftError):
+        _gpu(p, 64, 5, frame_tile_words=24)
 
 
 def test_c2_entry_fallback_bit_exact(c2):
