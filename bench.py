@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # Measured HBM bytes per launch of the pure-frame kernel on a workload (FETCH_SIZE x 2.000 +
 # WRITE_SIZE x 1.000, the scales read off a 1 GiB device copy), kept only while the kernel is
 # the one the counters were taken on.
-FRAME_TRAFFIC_BYTES = {"surface_d11_r11_p1e-3": (1874670 * 2 + 8218314) * 1024}
+FRAME_TRAFFIC_BYTES = {"surface_d11_r11_p1e-3": (1563095 * 2 + 8400322) * 1024}
 # The same for the active kernel with HBM-resident vectors (FP32, 2^16 shots).
 ACTIVE_TRAFFIC_BYTES = {"near_clifford_n48_k16": (688241884 * 2 + 1133273003) * 1024}
 FP32_PEAK_TFLOPS = 157.3
