@@ -241,7 +241,12 @@ typedef struct {
                                       width >= 13 (peak widths 13 and 14 run 64 .. 256 with vectors in HBM,
                                       values below 64 as 64; width 15 and above always uses 1024).  From 64
                                       on a workgroup holds one shot group.  Flags do not depend on it */
-    uint32_t reserved;             /* 0 */
+    uint32_t mode;                 /* programs with a dense active vector: 0 = automatic (the path
+                                      symft_autotune_counts timed faster, else 1); 1 = the count kernel, which
+                                      stops a rejected shot's dense work; 2 = detector and observable rows
+                                      written to scratch by the record kernel, then reduced to the flags (for
+                                      programs that reject few shots).  Flags do not depend on it.  Pure-frame
+                                      programs always use the frame kernel's flags */
 } symft_count_opts;
 
 /* Sample `shots` shots and report, per shot, only a discarded flag and a

@@ -74,7 +74,7 @@ class symft_sample_opts(C.Structure):
 class symft_count_opts(C.Structure):
     _fields_ = [("shot_offset", C.c_uint64), ("precision", C.c_uint32), ("n_post", C.c_uint32),
                 ("post", C.c_void_p), ("obs_expected", C.c_void_p), ("threads_per_shot", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("mode", C.c_uint32)]
 
 
 _lib.symft_compile.restype = C.c_int32
@@ -258,7 +258,7 @@ class Program:
                              frame_entry_cap=frame_entry_cap, frame_tile_words=frame_tile_words)
         return out[: self.n_rows, :words]
 
-    def _count_opts(self, post, obs_expected, shot_offset, precision, threads_per_shot):
+    def _count_opts(self, post, obs_expected, shot_offset, precision, threads_per_shot, mode=0):
         post = np.ascontiguousarray(np.asarray(post, dtype=np.uint32).reshape(-1))
         exp = None
         if obs_expected is not None:
@@ -267,16 +267,16 @@ class Program:
                 raise ValueError("obs_expected needs one value per observable")
         o = symft_count_opts(shot_offset, 0 if precision == "fp64" else 1, post.size,
                              post.ctypes.data if post.size else None, exp.ctypes.data if exp is not None else None,
-                             threads_per_shot, 0)
+                             threads_per_shot, mode)
         return o, (post, exp)  # the arrays must outlive the call
 
     def sample_counts_into(self, flags, counts, shots: int, seed: int, post=(), obs_expected=None,
                            shot_offset: int = 0, precision: str = "fp64", stream=None,
-                           threads_per_shot: int = 0) -> None:
+                           threads_per_shot: int = 0, mode: int = 0) -> None:
         """Aggregate counts: flags (device [2, ceil(shots/64)] words, or None) receives the discarded and
         logical-error flags; counts (device [2] uint64, or None) has the two totals added to it."""
         import torch
-        o, keep = self._count_opts(post, obs_expected, shot_offset, precision, threads_per_shot)
+        o, keep = self._count_opts(post, obs_expected, shot_offset, precision, threads_per_shot, mode)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         fp = None if flags is None else (flags.data_ptr() if hasattr(flags, "data_ptr") else int(flags))
@@ -285,14 +285,15 @@ class Program:
                                         C.c_void_p(stream)), "symft_sample_counts")
 
     def sample_counts(self, shots: int, seed: int, post=(), obs_expected=None, shot_offset: int = 0,
-                      precision: str = "fp64", device="cuda", threads_per_shot: int = 0):
+                      precision: str = "fp64", device="cuda", threads_per_shot: int = 0, mode: int = 0):
         """Returns (flags [2, ceil(shots/64)] int64 tensor, counts [2] int64 tensor) on the GPU."""
         import torch
         words = (shots + 63) // 64
         flags = torch.zeros((2, max(words, 1)), dtype=torch.int64, device=device)
         counts = torch.zeros(2, dtype=torch.int64, device=device)
         self.sample_counts_into(flags, counts, shots, seed, post=post, obs_expected=obs_expected,
-                                shot_offset=shot_offset, precision=precision, threads_per_shot=threads_per_shot)
+                                shot_offset=shot_offset, precision=precision, threads_per_shot=threads_per_shot,
+                                mode=mode)
         return flags[:, :words], counts
 
     def autotune_counts(self, post=(), obs_expected=None, precision: str = "fp32") -> int:

@@ -20,11 +20,14 @@ hipError_t launch_active(const ActiveArgs &A, bool fp64, uint32_t bs, uint32_t g
 size_t active_lds_bytes(const DevProg &P, uint32_t bs, uint32_t tps, bool lds_vec, bool fp64);
 int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds, bool cm);
 struct FrameArgs;
+struct CountArgs;
 hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st, uint32_t tw);
 struct BatchArgs;
 hipError_t launch_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t lds, hipStream_t st);
 int batch_max_blocks_per_cu(bool fp64, size_t lds);
 size_t frame_lds_bytes(const DevProg &P, uint32_t tw);
+hipError_t launch_flags_from_rows(const uint64_t *rows, uint64_t n_words, uint64_t shots, uint64_t n_rec,
+                                  uint32_t n_det, uint32_t n_obs, const CountArgs &C, hipStream_t st);
 size_t frame_scratch_words(uint32_t word_entries, uint32_t tw);
 int frame_max_blocks_per_cu(size_t lds, uint32_t tw);
 hipError_t launch_gap_check(const GapFast &F, const uint64_t *Q, const uint32_t *v, int32_t *g, uint64_t n,
@@ -782,6 +785,26 @@ static symft_status count_tables(symft_program *h, const symft_count_opts &o, Co
 
 extern "C" {
 
+// Count path 2: the record kernel writes the detector and observable rows of
+// every shot to scratch, and a reduction turns them into the flags.
+static constexpr uint32_t kViaRecords = 1u << 20;  // count-tuner choice: path 2
+
+static symft_status counts_via_records(symft_program *p, const DevProg &D, bool fp64, uint64_t w0, uint64_t n_words,
+                                       uint64_t shots, uint64_t seed, hipStream_t st, const CountArgs &C) {
+    const Program &P = p->P;
+    void *buf = nullptr;
+    if (pool_alloc(&buf, (size_t)std::max<uint64_t>(1, P.n_rows()) * n_words * 8, st) != hipSuccess)
+        return set_err(SYMFT_ENOMEM, "count row scratch allocation failed");
+    symft_status rc = run_active(p, D, fp64, w0, n_words, shots, (uint64_t *)buf, n_words, 6u, nullptr, 0, 0, seed, st);
+    if (rc == SYMFT_OK) {
+        hipError_t e = launch_flags_from_rows((const uint64_t *)buf, n_words, shots, P.n_rec, (uint32_t)P.n_det,
+                                              (uint32_t)P.n_obs, C, st);
+        if (e != hipSuccess) rc = set_err(SYMFT_EHIP, std::string("flag reduction launch failed: ") + hipGetErrorString(e));
+    }
+    hipFreeAsync(buf, st);
+    return rc;
+}
+
 symft_status symft_sample_counts(const symft_program *pc, const symft_count_opts *opts, uint64_t shots, uint64_t seed,
                                  uint64_t *flags_out, uint64_t *counts_out, void *stream) {
     symft_program *p = const_cast<symft_program *>(pc);
@@ -796,6 +819,7 @@ symft_status symft_sample_counts(const symft_program *pc, const symft_count_opts
         return set_err(SYMFT_EINVAL, "threads_per_shot must be a power of two");
     if (o.threads_per_shot && (o.threads_per_shot < 4 || (o.threads_per_shot > 256 && o.threads_per_shot != 1024)))
         return set_err(SYMFT_EINVAL, "threads_per_shot must be 4 .. 256 (or 1024 at peak width >= 13)");
+    if (o.mode > 2) return set_err(SYMFT_EINVAL, "mode must be 0, 1 or 2");
     CountArgs C;
     std::memset(&C, 0, sizeof(C));
     std::vector<uint32_t> key;
@@ -814,11 +838,15 @@ symft_status symft_sample_counts(const symft_program *pc, const symft_count_opts
     if (D.k_max < 13 && o.threads_per_shot > 256)
         return set_err(SYMFT_EINVAL, "threads_per_shot above 256 needs peak width >= 13");
     uint32_t tps = o.threads_per_shot;
-    if (!tps) {
+    uint32_t tuned = 0;
+    {
         std::lock_guard<std::mutex> lk(p->mu);
         auto it = p->count_tune.find({key, fp64});
-        if (it != p->count_tune.end()) tps = it->second;
+        if (it != p->count_tune.end()) tuned = it->second;
     }
+    if (o.mode == 2 || (o.mode == 0 && (tuned & kViaRecords)))
+        return counts_via_records(p, D, fp64, w0, n_words, shots, seed, st, C);
+    if (!tps && !(tuned & kViaRecords)) tps = tuned;
     // untuned: one shot group per workgroup once vectors are wide enough to keep 256 lanes busy
     if (!tps && D.k_max >= 8 && D.k_max < 13 && active_lds_bytes(D, 256, 256, true, fp64) <= kLdsLimit) tps = 256;
     if (D.k_max >= 13 && !narrow_wide(D.k_max)) tps = 0;
@@ -881,6 +909,21 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
             best_tps = cand;
         }
     }
+    // path 2: rows written by the record kernel, then reduced
+    if (rc == SYMFT_OK && best_tps) {
+        float ms = 0;
+        for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
+            hipEventRecord(e0, st);
+            rc = counts_via_records(p, D, fp64, 0, words, words * 64, 0x7E57ull, st, C);
+            hipEventRecord(e1, st);
+            hipEventSynchronize(e1);
+            hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (rc == SYMFT_OK && ms < best) {
+            best = ms;
+            best_tps = choose_active(D, fp64, 0, 0, false).tps | kViaRecords;
+        }
+    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     hipStreamDestroy(st);
@@ -890,7 +933,7 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
         std::lock_guard<std::mutex> lk(p->mu);
         p->count_tune[{key, fp64}] = best_tps;
     }
-    if (tps_out) *tps_out = best_tps & ~kHbmVec;
+    if (tps_out) *tps_out = best_tps & ~(kHbmVec | kViaRecords);
     return SYMFT_OK;
 }
 

@@ -741,6 +741,49 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs B) {
 
 __global__ void reset_counter_kernel(uint32_t *counter) { counter[threadIdx.x] = 0u; }
 
+// Aggregate counts from full rows (the count path that writes detector and
+// observable rows first): per 64-shot word, discarded = OR of the postselected
+// detectors, logical error = OR of (observable XOR expected) on kept shots.
+// One thread per word; one atomic add per wave and counter.
+__global__ void flags_from_rows_kernel(const uint64_t *rows, uint64_t n_words, uint64_t shots, uint64_t n_rec,
+                                       uint32_t n_det, uint32_t n_obs, CountArgs C) {
+    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long d = 0, l = 0;
+    if (w < n_words) {
+        for (uint32_t k = 0; k < n_det; ++k)
+            if ((C.post[k >> 5] >> (k & 31u)) & 1u) d |= rows[(n_rec + k) * n_words + w];
+        for (uint32_t o = 0; o < n_obs; ++o) {
+            const unsigned long long x = ((C.obs_exp[o >> 5] >> (o & 31u)) & 1u) ? ~0ull : 0ull;
+            l |= rows[(n_rec + n_det + o) * n_words + w] ^ x;
+        }
+        const uint64_t s0 = w * 64;
+        const unsigned long long m = s0 + 64 <= shots ? ~0ull : ((1ull << (shots - s0)) - 1ull);
+        d &= m;
+        l &= ~d & m;
+        if (C.flags) {
+            C.flags[w] = d;
+            C.flags[n_words + w] = l;
+        }
+    }
+    unsigned long long nd = (unsigned long long)__popcll(d), nl = (unsigned long long)__popcll(l);
+    for (int off = 32; off > 0; off >>= 1) {
+        nd += __shfl_xor(nd, off, 64);
+        nl += __shfl_xor(nl, off, 64);
+    }
+    if ((threadIdx.x & 63u) == 0 && C.counts) {
+        if (nd) atomicAdd(&C.counts[0], nd);
+        if (nl) atomicAdd(&C.counts[1], nl);
+    }
+}
+
+hipError_t launch_flags_from_rows(const uint64_t *rows, uint64_t n_words, uint64_t shots, uint64_t n_rec,
+                                  uint32_t n_det, uint32_t n_obs, const CountArgs &C, hipStream_t st) {
+    if (n_words == 0) return hipSuccess;
+    hipLaunchKernelGGL(flags_from_rows_kernel, dim3((uint32_t)((n_words + 255) / 256)), dim3(256), 0, st, rows,
+                       n_words, shots, n_rec, n_det, n_obs, C);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- host ----
 template <typename T, int BS, bool LDSV, bool CM>
 static hipError_t launch_one(const ActiveArgs &A, uint32_t grid, hipStream_t st) {

@@ -33,10 +33,11 @@ def _popcount(a):
     return int(sum(bin(int(x)).count("1") for x in np.asarray(a, dtype=np.uint64).reshape(-1)))
 
 
-def _check(circ, prog, oc, shots, seed, post, exp=None, prec="fp64", shot_offset=0):
-    print(f"counts: k_max={prog.k_max} shots={shots} offset={shot_offset} prec={prec} post={len(post)}", flush=True)
+def _check(circ, prog, oc, shots, seed, post, exp=None, prec="fp64", shot_offset=0, mode=0):
+    print(f"counts: k_max={prog.k_max} shots={shots} offset={shot_offset} prec={prec} post={len(post)} mode={mode}",
+          flush=True)
     flags_t, counts_t = prog.sample_counts(shots, seed, post=post, obs_expected=exp, shot_offset=shot_offset,
-                                           precision=prec)
+                                           precision=prec, mode=mode)
     flags = S.bits_to_numpy(flags_t)
     counts = counts_t.cpu().numpy()
     nr, nd, no = circ.num_records, circ.num_detectors, circ.num_observables
@@ -184,3 +185,29 @@ def test_counts_with_32_word_tiles_match_forced_16_word_records(c1):
     want_f, want_c = count_flags(rec, c.num_records, c.num_detectors, c.num_observables, shots, post, None)
     assert np.array_equal(S.bits_to_numpy(flags_t), want_f)
     assert list(counts_t.cpu().numpy()) == list(want_c)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_counts_via_records_path(prec):
+    """Count path 2 (rows written by the record kernel, then reduced) against the oracle, on a coherent-noise
+    surface code and random circuits, with a ragged range at an offset; and the autotuner's choice keeps the
+    flags."""
+    from tests.randcirc import random_circuit
+    c = rotated_memory_z(3, 3, 2e-3, coherent=0.15)
+    p = S.Program(c)
+    oc = OracleCircuit(c)
+    post = list(range(c.num_detectors))
+    _check(c, p, oc, 64 * 9 + 5, 31, post, prec=prec, shot_offset=64 * 3, mode=2)
+    exp = [1] * c.num_observables
+    _check(c, p, oc, 64 * 5, 32, post[::2], exp=exp, prec=prec, mode=2)
+    rng = np.random.default_rng(77)
+    for trial in range(6):
+        rc = random_circuit(rng, int(rng.integers(2, 7)), int(rng.integers(15, 50)))
+        if rc.num_detectors == 0:
+            continue
+        rp = S.Program(rc)
+        _check(rc, rp, OracleCircuit(rc), 64 * 3, 40 + trial, list(range(rc.num_detectors)), prec=prec, mode=2)
+    p.autotune_counts(post, precision=prec)
+    a, _ = p.sample_counts(64 * 7, 33, post=post, precision=prec)
+    b, _ = p.sample_counts(64 * 7, 33, post=post, precision=prec, mode=1)
+    assert np.array_equal(S.bits_to_numpy(a), S.bits_to_numpy(b))
