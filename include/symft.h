@@ -41,6 +41,12 @@ extern "C" {
 typedef int32_t symft_status;
 #define SYMFT_OK 0
 #define SYMFT_EINVAL (-1)     /* malformed op, null pointer, bad size or offset */
+/* Code -2 is reserved for a non-Hermitian Pauli (paper Sec. 2 admits only
+ * Hermitian ones) and is never returned: an op names its Pauli by the letters
+ * X, Y, Z per qubit and a sign bit `negate`, which can express only the
+ * Hermitian operators +-P; a phase of +-i has no encoding.  Letters outside
+ * 0..3 are EINVAL. */
+#define SYMFT_ENONHERMITIAN (-2)
 #define SYMFT_EACAUSAL (-3)   /* a record referenced before it is measured (paper Sec. 5, causality) */
 #define SYMFT_EPROB (-4)      /* probability < 0, > 1, or a channel total > 1 (paper Sec. 2) */
 #define SYMFT_ECAPACITY (-5)  /* peak active width or scratch need exceeds what the library supports */
@@ -112,7 +118,9 @@ typedef struct {
     uint64_t n_channels, n_classes, n_noise_symbols;
     uint64_t expr_noise_nnz;       /* noise-symbol references over all sign expressions */
     uint64_t expr_meas_nnz;        /* measurement-symbol references over all sign expressions */
-    double dense_flops_per_shot;   /* algorithmic flops of the dense instructions, see DESIGN */
+    double dense_flops_per_shot;   /* algorithmic flops of the dense instructions: per amplitude of the width
+                                      before the instruction, PromoteRot 4, ActiveDiagRot 6, ActivePairRot 6,
+                                      ActiveDiagMeas 5, ActivePairMeas 11 */
     double dense_bytes_per_shot;   /* one read + one write of the live vector per dense instruction (complex FP32) */
     uint64_t frame_steps;          /* pure-frame schedule: steps (0 when the program needs the active kernel) */
     uint64_t frame_noise_steps;    /* of which noise steps */
@@ -121,6 +129,10 @@ typedef struct {
     uint64_t frame_pushes;         /* record-to-consumer XORs over the schedule */
     uint64_t frame_noise_consumers;/* noise-symbol-to-consumer XORs, summed over symbols */
     uint64_t rotations_removed;    /* rotations fused into an earlier one or cancelled (symft_compile_opts) */
+    uint64_t frame_kernel;         /* pure-frame kernel of the automatic choice: 1 wave-owned, 2 step-synchronous;
+                                      0 when the program runs on the active kernel */
+    uint64_t frame_wave_batches;   /* wave-owned schedule: node batches (one node per lane) */
+    uint64_t frame_wave_flushes;   /* wave-owned schedule: staged-row flushes (workgroup barriers) */
 } symft_info;
 
 /* Compile options.  simplify = 1 runs a conservative commutation-aware
@@ -189,6 +201,12 @@ typedef struct {
                                       per CU, when the schedule fits LDS at that width and there are at least
                                       two such tiles per CU; else 16-word tiles); 16 or 32 forces the width
                                       (ECAPACITY if it does not fit; records are unchanged) */
+    uint32_t frame_kernel;         /* pure-frame programs: 0 = automatic (the wave-owned kernel, in which each
+                                      wave of a 16-wave workgroup owns one 64-shot word for the whole schedule,
+                                      when its LDS fits; else the step-synchronous kernel); 1 = wave-owned
+                                      (ECAPACITY if it does not fit); 2 = step-synchronous.  A nonzero
+                                      frame_tile_words selects the step-synchronous kernel.  Records are
+                                      unchanged */
 } symft_sample_opts;
 
 /* Sample `shots` shots (paper Sec. 5) into device buffer records_out
@@ -247,6 +265,8 @@ typedef struct {
                                       written to scratch by the record kernel, then reduced to the flags (for
                                       programs that reject few shots).  Flags do not depend on it.  Pure-frame
                                       programs always use the frame kernel's flags */
+    uint32_t frame_kernel;         /* pure-frame programs: as in symft_sample_opts (0 automatic, 1 wave-owned,
+                                      2 step-synchronous); flags do not depend on it */
 } symft_count_opts;
 
 /* Sample `shots` shots and report, per shot, only a discarded flag and a

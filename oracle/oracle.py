@@ -140,6 +140,8 @@ class OracleCircuit:
         lib = _load()
         self._tape, self._dargs = _marshal(circ)
         self._h = lib.orc_circuit_new(circ.n_qubits, _ptr(self._tape, C.c_int64), _ptr(self._dargs, C.c_double))
+        if not self._h:
+            raise ValueError(f"oracle rejects the circuit: {circ.n_qubits} qubits (1 .. 4096) or a qubit out of range")
         info = np.zeros(8, dtype=np.int64)
         lib.orc_circuit_info(self._h, _ptr(info, C.c_int64))
         self.n_meas, self.n_rec, self.n_det, self.n_obs, self.n_chan, self.n_cls = (int(v) for v in info[:6])

@@ -283,7 +283,39 @@ static int op_channels(const OOp *o) {
 /* Tape layout (int64): n_ops, then per op:
  *   kind, nq, q[nq], negate, n_let, let[n_let], nrec, recs[nrec], obs, nbr, blet[nbr*nq]
  * doubles, consumed in order: arg for every op, then probs[nbr] for PAULI_CHANNEL. */
+/* Largest register: the per-shot Pauli scratch rows (nx, nz, tmp) are fixed
+ * arrays of 64 words. */
+#define ORC_MAX_QUBITS 4096
+
+/* NULL when n_qubits is outside [1, ORC_MAX_QUBITS] or an op names a qubit
+ * outside [0, n_qubits). */
 void *orc_circuit_new(int n_qubits, const int64_t *tape, const double *dargs) {
+    if (n_qubits < 1 || n_qubits > ORC_MAX_QUBITS || !tape || !dargs) return NULL;
+    {
+        /* bounds pass over the tape before anything is allocated */
+        size_t ti = 0;
+        const int64_t n_ops = tape[ti++];
+        if (n_ops < 0) return NULL;
+        for (int64_t i = 0; i < n_ops; ++i) {
+            ti++; /* kind */
+            const int64_t nq = tape[ti++];
+            if (nq < 0) return NULL;
+            for (int64_t j = 0; j < nq; ++j)
+                if (tape[ti + (size_t)j] < 0 || tape[ti + (size_t)j] >= n_qubits) return NULL;
+            ti += (size_t)nq;
+            ti++; /* negate */
+            const int64_t nl = tape[ti++];
+            if (nl < 0) return NULL;
+            ti += (size_t)nl;
+            const int64_t nrec = tape[ti++];
+            if (nrec < 0) return NULL;
+            ti += (size_t)nrec;
+            ti++; /* obs */
+            const int64_t nbr = tape[ti++];
+            if (nbr < 0) return NULL;
+            ti += (size_t)(nbr * nq);
+        }
+    }
     OCirc *C = (OCirc *)calloc(1, sizeof(OCirc));
     C->n = n_qubits;
     size_t ti = 0, di = 0;

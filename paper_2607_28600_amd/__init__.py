@@ -27,7 +27,7 @@ import torch  # noqa: E402,F401
 _lib = C.CDLL(LIB)
 
 OK = 0
-ERRORS = {-1: "EINVAL", -3: "EACAUSAL", -4: "EPROB", -5: "ECAPACITY", -6: "ENOMEM", -7: "EHIP"}
+ERRORS = {-1: "EINVAL", -2: "ENONHERMITIAN", -3: "EACAUSAL", -4: "EPROB", -5: "ECAPACITY", -6: "ENOMEM", -7: "EHIP"}
 
 OP = {
     "H": 1, "S": 2, "S_DAG": 3, "X": 4, "Y": 5, "Z": 6, "CX": 7, "CZ": 8, "SWAP": 9,
@@ -58,7 +58,8 @@ class symft_info(C.Structure):
         ("expr_meas_nnz", C.c_uint64), ("dense_flops_per_shot", C.c_double), ("dense_bytes_per_shot", C.c_double),
         ("frame_steps", C.c_uint64), ("frame_noise_steps", C.c_uint64), ("frame_slots", C.c_uint64),
         ("frame_max_level", C.c_uint64), ("frame_pushes", C.c_uint64), ("frame_noise_consumers", C.c_uint64),
-        ("rotations_removed", C.c_uint64),
+        ("rotations_removed", C.c_uint64), ("frame_kernel", C.c_uint64), ("frame_wave_batches", C.c_uint64),
+        ("frame_wave_flushes", C.c_uint64),
     ]
 
 
@@ -68,13 +69,14 @@ class symft_compile_opts(C.Structure):
 
 class symft_sample_opts(C.Structure):
     _fields_ = [("shot_offset", C.c_uint64), ("precision", C.c_uint32), ("sections", C.c_uint32),
-                ("row_stride_words", C.c_uint64), ("frame_entry_cap", C.c_uint32), ("frame_tile_words", C.c_uint32)]
+                ("row_stride_words", C.c_uint64), ("frame_entry_cap", C.c_uint32), ("frame_tile_words", C.c_uint32),
+                ("frame_kernel", C.c_uint32)]
 
 
 class symft_count_opts(C.Structure):
     _fields_ = [("shot_offset", C.c_uint64), ("precision", C.c_uint32), ("n_post", C.c_uint32),
                 ("post", C.c_void_p), ("obs_expected", C.c_void_p), ("threads_per_shot", C.c_uint32),
-                ("mode", C.c_uint32)]
+                ("mode", C.c_uint32), ("frame_kernel", C.c_uint32)]
 
 
 _lib.symft_compile.restype = C.c_int32
@@ -236,29 +238,30 @@ class Program:
     # -- sampling (device) ------------------------------------------------
     def sample_into(self, out, shots: int, seed: int, shot_offset: int = 0, precision: str = "fp64",
                     sections: int = 0, row_stride_words: int = 0, stream=None, frame_entry_cap: int = 0,
-                    frame_tile_words: int = 0) -> None:
+                    frame_tile_words: int = 0, frame_kernel: int = 0) -> None:
         """out: a device tensor / pointer holding n_rows x stride uint64 words."""
         import torch
         ptr = out.data_ptr() if hasattr(out, "data_ptr") else int(out)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         o = symft_sample_opts(shot_offset, 0 if precision == "fp64" else 1, sections, row_stride_words,
-                              frame_entry_cap, frame_tile_words)
+                              frame_entry_cap, frame_tile_words, frame_kernel)
         _check(_lib.symft_sample_ex(self._h, C.byref(o), shots, seed, C.c_void_p(ptr), C.c_void_p(stream)),
                "symft_sample_ex")
 
     def sample(self, shots: int, seed: int, shot_offset: int = 0, precision: str = "fp64", device="cuda",
-               frame_entry_cap: int = 0, frame_tile_words: int = 0):
+               frame_entry_cap: int = 0, frame_tile_words: int = 0, frame_kernel: int = 0):
         """Returns a [n_rows, ceil(shots/64)] int64 tensor on the GPU (uint64 bit patterns)."""
         import torch
         words = (shots + 63) // 64
         out = torch.zeros((max(self.n_rows, 1), max(words, 1)), dtype=torch.int64, device=device)
         if shots:
             self.sample_into(out, shots, seed, shot_offset=shot_offset, precision=precision,
-                             frame_entry_cap=frame_entry_cap, frame_tile_words=frame_tile_words)
+                             frame_entry_cap=frame_entry_cap, frame_tile_words=frame_tile_words,
+                             frame_kernel=frame_kernel)
         return out[: self.n_rows, :words]
 
-    def _count_opts(self, post, obs_expected, shot_offset, precision, threads_per_shot, mode=0):
+    def _count_opts(self, post, obs_expected, shot_offset, precision, threads_per_shot, mode=0, frame_kernel=0):
         post = np.ascontiguousarray(np.asarray(post, dtype=np.uint32).reshape(-1))
         exp = None
         if obs_expected is not None:
@@ -267,16 +270,16 @@ class Program:
                 raise ValueError("obs_expected needs one value per observable")
         o = symft_count_opts(shot_offset, 0 if precision == "fp64" else 1, post.size,
                              post.ctypes.data if post.size else None, exp.ctypes.data if exp is not None else None,
-                             threads_per_shot, mode)
+                             threads_per_shot, mode, frame_kernel)
         return o, (post, exp)  # the arrays must outlive the call
 
     def sample_counts_into(self, flags, counts, shots: int, seed: int, post=(), obs_expected=None,
                            shot_offset: int = 0, precision: str = "fp64", stream=None,
-                           threads_per_shot: int = 0, mode: int = 0) -> None:
+                           threads_per_shot: int = 0, mode: int = 0, frame_kernel: int = 0) -> None:
         """Aggregate counts: flags (device [2, ceil(shots/64)] words, or None) receives the discarded and
         logical-error flags; counts (device [2] uint64, or None) has the two totals added to it."""
         import torch
-        o, keep = self._count_opts(post, obs_expected, shot_offset, precision, threads_per_shot, mode)
+        o, keep = self._count_opts(post, obs_expected, shot_offset, precision, threads_per_shot, mode, frame_kernel)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         fp = None if flags is None else (flags.data_ptr() if hasattr(flags, "data_ptr") else int(flags))
@@ -285,7 +288,8 @@ class Program:
                                         C.c_void_p(stream)), "symft_sample_counts")
 
     def sample_counts(self, shots: int, seed: int, post=(), obs_expected=None, shot_offset: int = 0,
-                      precision: str = "fp64", device="cuda", threads_per_shot: int = 0, mode: int = 0):
+                      precision: str = "fp64", device="cuda", threads_per_shot: int = 0, mode: int = 0,
+                      frame_kernel: int = 0):
         """Returns (flags [2, ceil(shots/64)] int64 tensor, counts [2] int64 tensor) on the GPU."""
         import torch
         words = (shots + 63) // 64
@@ -293,7 +297,7 @@ class Program:
         counts = torch.zeros(2, dtype=torch.int64, device=device)
         self.sample_counts_into(flags, counts, shots, seed, post=post, obs_expected=obs_expected,
                                 shot_offset=shot_offset, precision=precision, threads_per_shot=threads_per_shot,
-                                mode=mode)
+                                mode=mode, frame_kernel=frame_kernel)
         return flags[:, :words], counts
 
     def autotune_counts(self, post=(), obs_expected=None, precision: str = "fp32") -> int:

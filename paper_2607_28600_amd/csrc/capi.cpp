@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -27,8 +28,13 @@ hipError_t launch_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t l
 int batch_max_blocks_per_cu(bool fp64, size_t lds);
 size_t frame_lds_bytes(const DevProg &P, uint32_t tw);
 hipError_t launch_flags_from_rows(const uint64_t *rows, uint64_t n_words, uint64_t shots, uint64_t n_rec,
-                                  uint32_t n_det, uint32_t n_obs, const CountArgs &C, hipStream_t st);
+                                  uint32_t n_det, uint32_t n_obs, const CountArgs &C, uint64_t flag_off,
+                                  uint64_t flag_stride, hipStream_t st);
 size_t frame_scratch_words(uint32_t word_entries, uint32_t tw);
+struct WaveArgs;
+hipError_t launch_frame_wave(const WaveArgs &A, uint32_t grid, hipStream_t st);
+size_t frame_wave_lds_bytes(const DevProg &P);
+int frame_wave_max_blocks_per_cu(size_t lds, bool cm);
 int frame_max_blocks_per_cu(size_t lds, uint32_t tw);
 hipError_t launch_gap_check(const GapFast &F, const uint64_t *Q, const uint32_t *v, int32_t *g, uint64_t n,
                             hipStream_t st);
@@ -86,12 +92,22 @@ struct HostLayout {
     // offsets of each array inside blob
     size_t o_instr, o_cmeas, o_am, o_rm, o_recmeas, o_detoff, o_detrows, o_obsoff, o_obsrows, o_clsQ, o_clsoff, o_clschan,
         o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_invlog, o_clsfast, o_frstep, o_frnodes, o_frpush, o_frchinfo,
-        o_frfltab, o_frfl3, o_frcap, o_frcapoff;
+        o_frfltab, o_frfl3, o_frcap, o_frcapoff, o_wvops, o_wvrows, o_wvfl, o_wvsl, o_wvrm, o_wvcap, o_wvcapoff;
     uint32_t word_entries = 0;  // flip entries per word over all classes (frame kernel scratch)
+    uint32_t wv_word_entries = 0;  // slot flips per word over all classes (wave kernel scratch)
     DevProg meta;  // counts only; pointers filled at upload
 };
 
+struct symft_program;
+// Batch plans cache device argument blocks that point into a program's device
+// blob; freeing the program must release every plan that holds it.
+static void drop_batch_plans(const symft_program *p);
+// Programs are told apart by a serial number, never by their address, which
+// the allocator may hand to a later program.
+static std::atomic<uint64_t> g_prog_serial{1};
+
 struct symft_program {
+    const uint64_t serial = g_prog_serial.fetch_add(1);
     Program P;
     HostLayout L;
     FrameSchedule F;
@@ -102,6 +118,7 @@ struct symft_program {
     // count-mode threads per shot chosen by symft_autotune_counts, by (tables, FP64)
     std::map<std::pair<std::vector<uint32_t>, bool>, uint32_t> count_tune;
     ~symft_program() {
+        drop_batch_plans(this);
         auto drop = [](int d, void *ptr) {
             int cur = 0;
             hipGetDevice(&cur);
@@ -268,6 +285,18 @@ static void lower(symft_program *h) {
         L.o_frcapoff = put(L.blob, capoff);
         L.word_entries = capoff.back();
     }
+    L.o_wvops = put(L.blob, h->F.wops);
+    L.o_wvrows = put(L.blob, h->F.wrows);
+    L.o_wvfl = put(L.blob, h->F.wfl);
+    L.o_wvsl = put(L.blob, h->F.wsl);
+    L.o_wvrm = put(L.blob, h->F.rm_meas);
+    {
+        std::vector<uint32_t> capoff(1, 0);
+        for (uint32_t c : h->F.wcap) capoff.push_back(capoff.back() + c);
+        L.o_wvcap = put(L.blob, h->F.wcap);
+        L.o_wvcapoff = put(L.blob, capoff);
+        L.wv_word_entries = capoff.back();
+    }
     DevProg &m = L.meta;
     std::memset(&m, 0, sizeof(m));
     m.n_instr = (uint32_t)ins.size();
@@ -284,8 +313,14 @@ static void lower(symft_program *h) {
     m.fr_first_emit = h->F.first_emit[0];
     m.fr_first_emit_n = h->F.first_emit[1];
     m.fr_first_noise_cls = h->F.first_noise_cls;
-    m.fr_ok = h->F.ok && frame_lds_bytes(m, 16) <= kLdsLimit ? 1u : 0u;
     m.n_sym = P.n_noise_sym;
+    m.wv_n_ops = (uint32_t)(h->F.wops.size() / WV_OP_WORDS);
+    m.wv_n_rm = (uint32_t)h->F.rm_meas.size();
+    m.wv_first_noise_cls = h->F.w_first_noise_cls;
+    m.wv_first_batch = h->F.w_first_batch[0];
+    m.wv_first_batch_n = h->F.w_first_batch[1];
+    m.wv_ok = h->F.ok && h->F.wave_ok && frame_wave_lds_bytes(m) <= kLdsLimit ? 1u : 0u;
+    m.fr_ok = h->F.ok && (m.wv_ok || frame_lds_bytes(m, 16) <= kLdsLimit) ? 1u : 0u;
 }
 
 static symft_status device_prog(symft_program *h, DevProg &out) {
@@ -334,6 +369,13 @@ static symft_status device_prog(symft_program *h, DevProg &out) {
     out.fr_fl3 = (const uint64_t *)(b + L.o_frfl3);
     out.fr_cap = (const uint32_t *)(b + L.o_frcap);
     out.fr_capoff = (const uint32_t *)(b + L.o_frcapoff);
+    out.wv_ops = (const uint32_t *)(b + L.o_wvops);
+    out.wv_rows = (const uint32_t *)(b + L.o_wvrows);
+    out.wv_fl = (const uint64_t *)(b + L.o_wvfl);
+    out.wv_sl = (const uint16_t *)(b + L.o_wvsl);
+    out.wv_rm = (const uint32_t *)(b + L.o_wvrm);
+    out.wv_cap = (const uint32_t *)(b + L.o_wvcap);
+    out.wv_capoff = (const uint32_t *)(b + L.o_wvcapoff);
     return SYMFT_OK;
 }
 
@@ -493,11 +535,56 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
     return SYMFT_OK;
 }
 
+// The wave-owned kernel: one 16-wave workgroup per CU, each wave one word of a 16-word tile.
+static symft_status run_frame_wave(symft_program *h, const DevProg &D, uint64_t word_begin, uint64_t n_words,
+                                   uint64_t shots, uint64_t *out, uint64_t stride, uint32_t sections, uint64_t seed,
+                                   uint32_t cap_override, hipStream_t st, const CountArgs *cnt) {
+    const size_t lds = frame_wave_lds_bytes(D);
+    if (lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "frame schedule exceeds the LDS budget of the wave kernel");
+    int per_cu = frame_wave_max_blocks_per_cu(lds, cnt != nullptr);
+    if (per_cu <= 0) per_cu = 1;
+    const uint64_t tiles = (n_words + WV_TILE - 1) / WV_TILE;
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)per_cu * num_cus()));
+    WaveArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.word_entries = cap_override ? cap_override * D.n_cls : h->L.wv_word_entries;
+    A.cap_override = cap_override;
+    void *scratch = nullptr;
+    if (pool_alloc(&scratch, (size_t)grid * WV_TILE * std::max<uint32_t>(1, A.word_entries) * 4, st) != hipSuccess)
+        return set_err(SYMFT_ENOMEM, "frame scratch allocation failed");
+    A.scratch = (uint32_t *)scratch;
+    A.P = D;
+    A.seed = seed;
+    A.word_begin = word_begin;
+    A.n_words = n_words;
+    A.shots = shots;
+    A.out = out;
+    A.row_stride = stride;
+    A.sections = sections;
+    A.store16 = (((uintptr_t)out & 15u) == 0 && (stride & 1u) == 0) ? 1u : 0u;
+    A.lds_bytes = (uint32_t)lds;
+    if (cnt) A.cnt = *cnt;
+    hipError_t e = launch_frame_wave(A, grid, st);
+    hipFreeAsync(scratch, st);
+    if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("frame kernel launch failed: ") + hipGetErrorString(e));
+    return SYMFT_OK;
+}
+
+// frame_kernel: 0 automatic (the wave-owned kernel when its LDS fits, else the
+// step-synchronous one), 1 wave-owned, 2 step-synchronous (tile_words 16 / 32
+// or 0 = automatic); tile_words != 0 implies the step-synchronous kernel.
 static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_begin, uint64_t n_words, uint64_t shots,
                               uint64_t *out, uint64_t stride, uint32_t sections, uint64_t seed, uint32_t cap_override,
-                              hipStream_t st, const CountArgs *cnt = nullptr, uint32_t tile_words = 0) {
+                              hipStream_t st, const CountArgs *cnt = nullptr, uint32_t tile_words = 0,
+                              uint32_t frame_kernel = 0) {
     if (tile_words != 0 && tile_words != 16 && tile_words != 32)
         return set_err(SYMFT_EINVAL, "frame_tile_words must be 0, 16 or 32");
+    if (frame_kernel > 2) return set_err(SYMFT_EINVAL, "frame_kernel must be 0, 1 or 2");
+    if (frame_kernel == 1 && tile_words) return set_err(SYMFT_EINVAL, "frame_tile_words applies to the step kernel only");
+    if (frame_kernel == 1 && !D.wv_ok)
+        return set_err(SYMFT_ECAPACITY, "the wave-owned frame kernel cannot run this schedule (LDS)");
+    if (frame_kernel == 1 || (frame_kernel == 0 && !tile_words && D.wv_ok))
+        return run_frame_wave(h, D, word_begin, n_words, shots, out, stride, sections, seed, cap_override, st, cnt);
     // 32-word tiles halve the barrier steps per word; they need the slots of
     // 32 words in LDS and leave one workgroup per CU, so they are taken only
     // with at least two tiles per CU
@@ -621,6 +708,9 @@ symft_status symft_program_info(const symft_program *p, symft_info *info) {
     info->frame_noise_consumers = p->F.n_flips;
     info->rotations_removed = p->P.rot_removed;
     info->frame_pushes = p->F.n_pushes;
+    info->frame_kernel = p->L.meta.fr_ok ? (p->L.meta.wv_ok ? 1u : 2u) : 0u;
+    info->frame_wave_batches = p->F.w_n_batches;
+    info->frame_wave_flushes = p->F.w_n_flushes;
     for (size_t i = 0; i < p->F.steps.size(); i += FR_STEP_WORDS)
         if (p->F.steps[i] == FR_NOISE) info->frame_noise_steps += 1;
     return SYMFT_OK;
@@ -699,7 +789,7 @@ symft_status symft_sample_ex(const symft_program *pc, const symft_sample_opts *o
     const uint64_t w0 = o.shot_offset / 64;
     if (D.fr_ok)
         return run_frame(p, D, w0, n_words, shots, records_out, stride, sections, seed, o.frame_entry_cap, st,
-                         nullptr, o.frame_tile_words);
+                         nullptr, o.frame_tile_words, o.frame_kernel);
     return run_active(p, D, o.precision == 0, w0, n_words, shots, records_out, stride, sections, nullptr, 0, 0, seed, st);
 }
 
@@ -786,20 +876,33 @@ static symft_status count_tables(symft_program *h, const symft_count_opts &o, Co
 extern "C" {
 
 // Count path 2: the record kernel writes the detector and observable rows of
-// every shot to scratch, and a reduction turns them into the flags.
+// every shot to scratch, and a reduction turns them into the flags.  The range
+// runs in chunks of kViaRecordsChunk words, so the scratch holds the detector
+// and observable rows of one chunk (record rows are never written: the
+// kernel's base pointer is set n_rec rows before the scratch).
 static constexpr uint32_t kViaRecords = 1u << 20;  // count-tuner choice: path 2
+static constexpr uint64_t kViaRecordsChunk = 4096;
 
 static symft_status counts_via_records(symft_program *p, const DevProg &D, bool fp64, uint64_t w0, uint64_t n_words,
                                        uint64_t shots, uint64_t seed, hipStream_t st, const CountArgs &C) {
     const Program &P = p->P;
+    const uint64_t ch = std::min<uint64_t>(n_words, kViaRecordsChunk);
+    const uint64_t drows = std::max<uint64_t>(1, P.n_det + P.n_obs);
     void *buf = nullptr;
-    if (pool_alloc(&buf, (size_t)std::max<uint64_t>(1, P.n_rows()) * n_words * 8, st) != hipSuccess)
+    if (pool_alloc(&buf, (size_t)drows * ch * 8, st) != hipSuccess)
         return set_err(SYMFT_ENOMEM, "count row scratch allocation failed");
-    symft_status rc = run_active(p, D, fp64, w0, n_words, shots, (uint64_t *)buf, n_words, 6u, nullptr, 0, 0, seed, st);
-    if (rc == SYMFT_OK) {
-        hipError_t e = launch_flags_from_rows((const uint64_t *)buf, n_words, shots, P.n_rec, (uint32_t)P.n_det,
-                                              (uint32_t)P.n_obs, C, st);
-        if (e != hipSuccess) rc = set_err(SYMFT_EHIP, std::string("flag reduction launch failed: ") + hipGetErrorString(e));
+    symft_status rc = SYMFT_OK;
+    for (uint64_t c0 = 0; c0 < n_words && rc == SYMFT_OK; c0 += ch) {
+        const uint64_t cw = std::min(ch, n_words - c0);
+        const uint64_t cshots = std::min<uint64_t>(shots - c0 * 64, cw * 64);
+        // rows n_rec .. n_rows - 1 of a [n_rows][cw] array whose first n_rec rows are never touched
+        uint64_t *base = (uint64_t *)((uintptr_t)buf - (uintptr_t)(P.n_rec * cw * 8));
+        rc = run_active(p, D, fp64, w0 + c0, cw, cshots, base, cw, 6u, nullptr, 0, 0, seed, st);
+        if (rc == SYMFT_OK) {
+            hipError_t e = launch_flags_from_rows((const uint64_t *)buf, cw, cshots, 0, (uint32_t)P.n_det,
+                                                  (uint32_t)P.n_obs, C, c0, n_words, st);
+            if (e != hipSuccess) rc = set_err(SYMFT_EHIP, std::string("flag reduction launch failed: ") + hipGetErrorString(e));
+        }
     }
     hipFreeAsync(buf, st);
     return rc;
@@ -833,7 +936,7 @@ symft_status symft_sample_counts(const symft_program *pc, const symft_count_opts
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     const uint64_t w0 = o.shot_offset / 64, n_words = (shots + 63) / 64;
-    if (D.fr_ok) return run_frame(p, D, w0, n_words, shots, nullptr, n_words, 0u, seed, 0, st, &C);
+    if (D.fr_ok) return run_frame(p, D, w0, n_words, shots, nullptr, n_words, 0u, seed, 0, st, &C, 0, o.frame_kernel);
     const bool fp64 = o.precision == 0;
     if (D.k_max < 13 && o.threads_per_shot > 256)
         return set_err(SYMFT_EINVAL, "threads_per_shot above 256 needs peak width >= 13");
@@ -1102,6 +1205,7 @@ symft_status symft_autotune(const symft_program *pc, uint32_t precision, uint32_
 // ------------------------------------------------------------- batching ----
 struct BatchPlan {
     std::vector<const symft_program *> progs;
+    std::vector<uint64_t> serials;  // progs' serial numbers (an address alone may be reused)
     std::vector<uint64_t> shots, seeds;
     std::vector<uint64_t *> outs;
     uint32_t precision = 0;
@@ -1118,7 +1222,9 @@ struct BatchPlan {
               uint32_t prec, int dev) const {
         if (n != progs.size() || prec != precision || dev != device) return false;
         for (size_t i = 0; i < n; ++i)
-            if (p[i] != progs[i] || sh[i] != shots[i] || sd[i] != seeds[i] || o[i] != outs[i]) return false;
+            if (p[i] != progs[i] || (p[i] && p[i]->serial != serials[i]) || sh[i] != shots[i] || sd[i] != seeds[i] ||
+                o[i] != outs[i])
+                return false;
         return true;
     }
     void release() {
@@ -1138,10 +1244,28 @@ struct BatchPlan {
 static std::mutex g_batch_mu;
 static std::vector<BatchPlan *> g_plans;  // most recent first, a few kept
 
+static void drop_batch_plans(const symft_program *p) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (size_t i = 0; i < g_plans.size();) {
+        BatchPlan *B = g_plans[i];
+        bool holds = false;
+        for (size_t k = 0; k < B->progs.size(); ++k) holds |= B->progs[k] == p && B->serials[k] == p->serial;
+        if (holds) {
+            B->release();
+            delete B;
+            g_plans.erase(g_plans.begin() + (ptrdiff_t)i);
+        } else {
+            ++i;
+        }
+    }
+}
+
 static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, const uint64_t *shots,
                                const uint64_t *seeds, uint64_t *const *outs, size_t n, uint32_t precision) {
     const bool fp64 = precision == 0;
     B.progs.assign(progs, progs + n);
+    B.serials.resize(n);
+    for (size_t i = 0; i < n; ++i) B.serials[i] = progs[i] ? progs[i]->serial : 0;
     B.shots.assign(shots, shots + n);
     B.seeds.assign(seeds, seeds + n);
     B.outs.assign(outs, outs + n);

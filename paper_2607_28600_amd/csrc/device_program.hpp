@@ -85,9 +85,18 @@ struct DevProg {
     const uint64_t *fr_fl3;      // flip entries: cnt << 6 | up to three 16-bit slots from bit 16
     const uint32_t *fr_cap;      // per class: flip entries kept per (word, class)
     const uint32_t *fr_capoff;   // per class + 1: prefix of fr_cap
+    // wave-owned pure-frame schedule (sample_frame_wave.hip, launch_args.hpp)
+    const uint32_t *wv_ops;      // ops of 8 words
+    const uint32_t *wv_rows;     // output row of every staged position
+    const uint64_t *wv_fl;       // per (channel, branch): slot flips (inline up to three, else a list)
+    const uint16_t *wv_sl;       // slot lists
+    const uint32_t *wv_rm;       // measurement of every RandomMeas node
+    const uint32_t *wv_cap;      // per class: slot flips kept per word
+    const uint32_t *wv_capoff;   // per class + 1: prefix of wv_cap
     uint32_t n_instr, n_meas, n_rm, n_rec, n_det, n_obs, n_cls, k_max;
     uint32_t fr_n_steps, fr_n_slots, n_sym, fr_ok;   // fr_ok: the pure-frame kernel can run the program
     uint32_t fr_first_emit, fr_first_emit_n, fr_first_noise_cls, n_am;
+    uint32_t wv_n_ops, wv_n_rm, wv_first_noise_cls, wv_first_batch, wv_first_batch_n, wv_ok;
 };
 
 }  // namespace symft

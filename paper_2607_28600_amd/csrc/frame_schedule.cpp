@@ -68,6 +68,122 @@ static std::vector<uint32_t> xor_sets(std::vector<uint32_t> a, const std::vector
 // that folding adds).
 static const size_t FOLD_MAX_PREDS = 64, FOLD_MAX_NOISE = 1024;
 
+namespace {
+struct Node {
+    uint8_t cst = 0, rm = 0, sec = 0;
+    uint32_t row = FR_NO_ROW, rm_t = 0;  // rm_t: the measurement whose RandomMeas word is added
+    std::vector<uint32_t> preds, succs, noise;
+    int emit = -1, first = 1 << 30, slot = -1;
+};
+struct Step {
+    uint32_t kind;
+    uint32_t cls, r0, r1;
+    std::vector<uint32_t> nodes;
+};
+}  // namespace
+
+// The wave-owned schedule from the step schedule.  The steps keep their order
+// (so every slot interval of the colouring holds); consecutive EMIT steps'
+// nodes are packed into batches of up to 64 as long as no node depends on a
+// node already in the batch (a node reads its slot before any push of its
+// batch lands, so a dependency inside a batch would be lost).  A NOISE step
+// ends the batch before it.  Batches are staged in order; a batch that does
+// not fit the rest of the staging buffer first flushes it.
+static void build_wave_ops(const std::vector<Step> &steps, const std::vector<uint32_t> &first_node,
+                           const std::vector<Node> &nd, FrameSchedule &F) {
+    F.wops.clear();
+    F.wrows.clear();
+    std::vector<int64_t> in_batch(nd.size(), -1);
+    int64_t batch_id = 0;
+    uint32_t b_first = 0, b_n = 0, pos = 0, buf = 0, flush_off = 0;
+    std::vector<uint32_t> staged;  // rows staged in the open buffer
+    auto op = [&](std::initializer_list<uint32_t> w) {
+        std::vector<uint32_t> r(w);
+        r.resize(WV_OP_WORDS, 0);
+        F.wops.insert(F.wops.end(), r.begin(), r.end());
+    };
+    auto flush = [&]() {
+        if (staged.empty()) return;
+        op({WV_FLUSH, flush_off, (uint32_t)staged.size(), buf});
+        F.wrows.insert(F.wrows.end(), staged.begin(), staged.end());
+        flush_off += (uint32_t)staged.size();
+        staged.clear();
+        pos = 0;
+        buf ^= 1u;
+        F.w_n_flushes += 1;
+    };
+    auto close = [&]() {
+        if (!b_n) return;
+        if (pos + b_n > WV_STAGE_ROWS) flush();
+        op({WV_BATCH, b_first, b_n, pos, buf, 0, 0});
+        for (uint32_t i = 0; i < b_n; ++i) staged.push_back(0);  // rows filled below
+        pos += b_n;
+        b_n = 0;
+        ++batch_id;
+        F.w_n_batches += 1;
+    };
+    std::vector<uint32_t> rec_of_node(nd.size(), 0);  // node id -> record index
+    for (size_t i = 0; i < steps.size(); ++i) {
+        const Step &st = steps[i];
+        if (st.kind == FR_NOISE) {
+            close();
+            op({WV_NOISE, st.cls, st.r1, 0, 0});  // step index and next class filled below
+            continue;
+        }
+        for (size_t k = 0; k < st.nodes.size(); ++k) {
+            const uint32_t id = st.nodes[k];
+            const uint32_t rec = first_node[i] + (uint32_t)k;
+            rec_of_node[id] = rec;
+            bool dep = false;
+            for (uint32_t u : nd[id].preds) dep |= in_batch[u] == batch_id;
+            if (b_n && (b_n == WV_BATCH_MAX || dep || rec != b_first + b_n)) close();
+            if (!b_n) b_first = rec;
+            in_batch[id] = batch_id;
+            ++b_n;
+        }
+    }
+    close();
+    flush();
+    // staged rows, the NOISE steps' local indices and look-ahead fields
+    std::vector<uint32_t> row_of_rec(F.nodes.size() / 8);
+    for (size_t r = 0; r < row_of_rec.size(); ++r) row_of_rec[r] = F.nodes[8 * r + 1];
+    {
+        size_t fo = 0;
+        std::vector<uint32_t> batch_rows;
+        for (size_t o = 0; o < F.wops.size(); o += WV_OP_WORDS) {
+            const uint32_t *w = &F.wops[o];
+            if (w[0] == WV_BATCH)
+                for (uint32_t q = 0; q < w[2]; ++q) batch_rows.push_back(row_of_rec[w[1] + q]);
+            if (w[0] == WV_FLUSH) {
+                for (uint32_t q = 0; q < w[2]; ++q) F.wrows[fo + q] = batch_rows[q];
+                batch_rows.erase(batch_rows.begin(), batch_rows.begin() + w[2]);
+                fo += w[2];
+            }
+        }
+    }
+    std::map<uint32_t, uint32_t> next_local;
+    for (size_t o = 0; o < F.wops.size(); o += WV_OP_WORDS)
+        if (F.wops[o] == WV_NOISE) F.wops[o + 3] = next_local[F.wops[o + 1]]++;
+    uint32_t nn_cls = FR_NONE, nb_first = 0, nb_n = 0;
+    for (size_t o = F.wops.size(); o >= WV_OP_WORDS;) {
+        o -= WV_OP_WORDS;
+        uint32_t *w = &F.wops[o];
+        if (w[0] == WV_NOISE) {
+            w[4] = nn_cls;
+            nn_cls = w[1];
+        } else if (w[0] == WV_BATCH) {
+            w[5] = nb_first;
+            w[6] = nb_n;
+            nb_first = w[1];
+            nb_n = w[2];
+        }
+    }
+    F.w_first_noise_cls = nn_cls;
+    F.w_first_batch[0] = nb_first;
+    F.w_first_batch[1] = nb_n;
+    F.wave_ok = true;
+}
+
 void build_frame_schedule(const Program &P, FrameSchedule &F) {
     F = FrameSchedule();
     if (P.k_max != 0) return;
@@ -81,12 +197,6 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
     if (thr_total >= (1u << 23)) return;  // channel records hold 23-bit threshold offsets
     const uint32_t M = (uint32_t)P.n_meas, D = (uint32_t)P.n_det, B = (uint32_t)P.n_obs;
     const uint32_t NN = M + D + B;
-    struct Node {
-        uint8_t cst = 0, rm = 0, sec = 0;
-        uint32_t row = FR_NO_ROW, rm_t = 0;  // rm_t: the measurement whose RandomMeas word is added
-        std::vector<uint32_t> preds, succs, noise;
-        int emit = -1, first = 1 << 30, slot = -1;
-    };
     std::vector<Node> nd(NN);
     for (uint32_t t = 0; t < M; ++t) {
         const Instr &I = P.instrs[(size_t)P.meas_instr[t]];
@@ -137,11 +247,6 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
     for (uint32_t b = 0; b < B; ++b) items.push_back({(int64_t)P.n_ops, 3, M + D + b});
 
     // steps
-    struct Step {
-        uint32_t kind;
-        uint32_t cls, r0, r1;
-        std::vector<uint32_t> nodes;
-    };
     std::vector<Step> steps;
     std::vector<int> chan_step(P.chans.size(), -1);
     std::map<uint32_t, std::pair<uint32_t, uint32_t>> seg;  // class -> rank range
@@ -277,6 +382,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
         for (uint32_t s : nd[i].noise) cons[s].push_back((uint32_t)nd[i].slot);
     std::vector<uint64_t> chan_fl(P.chans.size(), 0), chan_thr(P.chans.size(), 0);
     std::vector<double> chan_k1(P.chans.size(), 0), chan_k2(P.chans.size(), 0);  // E[entries], E[entries^2] per event
+    std::vector<double> chan_f1(P.chans.size(), 0), chan_f2(P.chans.size(), 0);  // E[slot flips], E[flips^2] per event
     uint64_t thr_off = 0;
     for (size_t c = 0; c < P.chans.size(); ++c) {
         const Channel &ch = P.chans[c];
@@ -294,6 +400,14 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             F.n_flips += fl.size();
             if ((fl.size() + 2) / 3 > 63) return;  // flip-table words hold 6-bit entry counts
             F.fltab.push_back(pack_flips(fl, F.fl3));
+            if (fl.size() <= 3 && !fl.empty()) {
+                uint64_t w = fl.size();
+                for (size_t q = 0; q < fl.size(); ++q) w |= (uint64_t)fl[q] << (16 + 16 * q);
+                F.wfl.push_back(w);
+            } else {
+                F.wfl.push_back(((uint64_t)fl.size() << 8) | ((uint64_t)F.wsl.size() << 32));
+                for (uint32_t sl : fl) F.wsl.push_back((uint16_t)sl);
+            }
             // branch probability under the draw contract
             double pj = 1.0 / ch.J;
             if (!ch.uniform) {
@@ -303,6 +417,9 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             const double k = (double)((fl.size() + 2) / 3);
             chan_k1[c] += pj * k;
             chan_k2[c] += pj * k * k;
+            const double f = (double)fl.size();
+            chan_f1[c] += pj * f;
+            chan_f2[c] += pj * f * f;
         }
     }
     // step index of every channel within its class
@@ -320,7 +437,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
     // step index << 33 | threshold offset << 41; per-class flip-entry capacity per
     // word: the expected count plus 8 standard deviations (compound Poisson) plus 64
     for (const NoiseClass &nc : P.classes) {
-        double m1 = 0, m2 = 0;
+        double m1 = 0, m2 = 0, f1 = 0, f2 = 0;
         const double p = std::ldexp((double)nc.p32, -32);
         for (int32_t c : nc.chans) {
             const Channel &ch = P.chans[(size_t)c];
@@ -328,10 +445,14 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
                                ((uint64_t)chan_step_local[(size_t)c] << 33) | (chan_thr[(size_t)c] << 41));
             m1 += 64.0 * p * chan_k1[(size_t)c];
             m2 += 64.0 * p * chan_k2[(size_t)c];
+            f1 += 64.0 * p * chan_f1[(size_t)c];
+            f2 += 64.0 * p * chan_f2[(size_t)c];
         }
         F.events_per_word += (double)nc.chans.size() * 64.0 * p;
         const double cap = std::ceil((m1 + 8.0 * std::sqrt(m2) + 64.0) / 64.0) * 64.0;
         F.cls_cap.push_back((uint32_t)std::min(cap, 16777216.0));
+        const double wcap = std::ceil((f1 + 8.0 * std::sqrt(f2) + 64.0) / 64.0) * 64.0;
+        F.wcap.push_back((uint32_t)std::min(wcap, 16777216.0));
     }
     // encode steps (FR_STEP_WORDS per step, see launch_args.hpp) and node records
     std::vector<uint32_t> first_node(steps.size(), 0);
@@ -380,7 +501,8 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             F.nodes.push_back(np > 0 ? (uint32_t)nd[v.succs[0]].slot : 0u);
             F.nodes.push_back(np > 1 ? (uint32_t)nd[v.succs[1]].slot : 0u);
             F.nodes.push_back((uint32_t)F.push.size());  // pushes beyond the first two
-            F.nodes.push_back(0);
+            F.nodes.push_back(v.rm ? (uint32_t)F.rm_meas.size() : 0u);  // RandomMeas index (wave kernel)
+            if (v.rm) F.rm_meas.push_back(v.rm_t);
             for (uint32_t k = 2; k < np; ++k) F.push.push_back((uint32_t)nd[v.succs[k]].slot);
         }
     }
@@ -388,6 +510,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
     for (uint32_t i = 0; i < NN; ++i) F.n_pushes += nd[i].succs.size();
     F.n_steps = steps.size();
     F.ok = F.n_steps > 0;
+    build_wave_ops(steps, first_node, nd, F);
 }
 
 }  // namespace symft

@@ -80,6 +80,24 @@ struct FrameArgs {
     CountArgs cnt;
 };
 
+struct WaveArgs {
+    DevProg P;
+    uint64_t seed;
+    uint64_t word_begin;
+    uint64_t n_words;
+    uint64_t shots;
+    uint64_t *out;
+    uint64_t row_stride;
+    uint32_t *scratch;        // per workgroup: slot flip entries [16 words][word_entries]
+    uint32_t word_entries;    // sum of class capacities
+    uint32_t cap_override;    // nonzero: every class keeps this many slot flips (offsets c * cap_override)
+    uint32_t sections;
+    uint32_t store16;
+    uint32_t lds_bytes;
+    uint32_t pad;
+    CountArgs cnt;
+};
+
 // Pure-frame schedule (programs with peak active width 0); steps run in
 // order, separated by workgroup barriers.  Each step is FR_STEP_WORDS words:
 //   [kind, a, b, c, 0, next EMIT first node, next EMIT node count, next NOISE class]
@@ -103,6 +121,26 @@ static const uint32_t FR_LEVEL_MAX = 128;  // nodes per EMIT step: one (node, 4 
 static const uint32_t FR_STEP_WORDS = 8;
 static const uint32_t FR_NONE = 0xFFFFFFFFu;
 
+// Wave-owned schedule (sample_frame_wave.hip): each wave of a 16-wave
+// workgroup owns one 64-shot word of a 16-word tile for the whole schedule,
+// so nothing but the row staging is shared between waves.  The schedule is a
+// list of ops of WV_OP_WORDS words:
+//   WV_NOISE  [kind, class, rank end, step index within the class, class of the next NOISE op]
+//             XOR the lane bits of the word's flip entries of that step into its slots;
+//   WV_BATCH  [kind, first node, node count <= 64, staging position, staging buffer,
+//              first node of the next BATCH op, its node count]
+//             one node per lane: read and clear the node's slot, add its constant or
+//             RandomMeas word, stage the value, XOR it into the successors' slots;
+//             no node of a batch depends on another node of the same batch;
+//   WV_FLUSH  [kind, offset into the staged-row table, staged rows, staging buffer]
+//             workgroup barrier, then the 16 waves store the staged rows as whole
+//             128-byte lines (buffers alternate, so staging goes on during the stores).
+enum WaveOpKind : uint32_t { WV_NOISE = 1, WV_BATCH = 2, WV_FLUSH = 3 };
+static const uint32_t WV_OP_WORDS = 8;
+static const uint32_t WV_BATCH_MAX = 64;   // nodes per batch: one per lane
+static const uint32_t WV_STAGE_ROWS = 128; // staged rows per buffer: (row, 2 words) per thread of 16 waves
+static const uint32_t WV_TILE = 16;        // words per tile = waves per workgroup
+
 struct FrameSchedule {
     std::vector<uint32_t> steps;      // FR_STEP_WORDS per step
     std::vector<uint32_t> first_emit = {0, 0};  // first EMIT step: first node, node count
@@ -120,6 +158,18 @@ struct FrameSchedule {
     uint64_t n_flips = 0;           // slot flips over all (channel, branch) entries
     double events_per_word = 0;     // expected noise events of one 64-shot word
     bool ok = false;                // the pure-frame kernel can run the program
+    // wave-owned schedule
+    std::vector<uint32_t> wops;     // WV_OP_WORDS per op
+    std::vector<uint32_t> wrows;    // output row of every staged position, by FLUSH offset
+    std::vector<uint64_t> wfl;      // per (channel, branch), indexed like fltab: n (1..3) | slots at bits 16, 32, 48;
+                                    // or 0 | count << 8 | offset into wsl << 32 (count 0: no flips)
+    std::vector<uint16_t> wsl;      // slot lists of the branches that flip more than three
+    std::vector<uint32_t> rm_meas;  // measurement of each RandomMeas node, in node order (node word 7 = index)
+    std::vector<uint32_t> wcap;     // per class: slot flips kept per word
+    uint32_t w_first_noise_cls = 0xFFFFFFFFu;
+    uint32_t w_first_batch[2] = {0, 0};
+    uint64_t w_n_batches = 0, w_n_flushes = 0;
+    bool wave_ok = false;           // the wave-owned schedule was built
 };
 
 void build_frame_schedule(const Program &P, FrameSchedule &F);

@@ -746,7 +746,8 @@ __global__ void reset_counter_kernel(uint32_t *counter) { counter[threadIdx.x] =
 // detectors, logical error = OR of (observable XOR expected) on kept shots.
 // One thread per word; one atomic add per wave and counter.
 __global__ void flags_from_rows_kernel(const uint64_t *rows, uint64_t n_words, uint64_t shots, uint64_t n_rec,
-                                       uint32_t n_det, uint32_t n_obs, CountArgs C) {
+                                       uint32_t n_det, uint32_t n_obs, CountArgs C, uint64_t flag_off,
+                                       uint64_t flag_stride) {
     const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long d = 0, l = 0;
     if (w < n_words) {
@@ -761,8 +762,8 @@ __global__ void flags_from_rows_kernel(const uint64_t *rows, uint64_t n_words, u
         d &= m;
         l &= ~d & m;
         if (C.flags) {
-            C.flags[w] = d;
-            C.flags[n_words + w] = l;
+            C.flags[flag_off + w] = d;
+            C.flags[flag_stride + flag_off + w] = l;
         }
     }
     unsigned long long nd = (unsigned long long)__popcll(d), nl = (unsigned long long)__popcll(l);
@@ -776,11 +777,14 @@ __global__ void flags_from_rows_kernel(const uint64_t *rows, uint64_t n_words, u
     }
 }
 
+// rows: n_rec + n_det + n_obs rows of n_words words (only rows from n_rec on
+// are read); flags row 0 at flags[flag_off ..], row 1 at flags[flag_stride + flag_off ..].
 hipError_t launch_flags_from_rows(const uint64_t *rows, uint64_t n_words, uint64_t shots, uint64_t n_rec,
-                                  uint32_t n_det, uint32_t n_obs, const CountArgs &C, hipStream_t st) {
+                                  uint32_t n_det, uint32_t n_obs, const CountArgs &C, uint64_t flag_off,
+                                  uint64_t flag_stride, hipStream_t st) {
     if (n_words == 0) return hipSuccess;
     hipLaunchKernelGGL(flags_from_rows_kernel, dim3((uint32_t)((n_words + 255) / 256)), dim3(256), 0, st, rows,
-                       n_words, shots, n_rec, n_det, n_obs, C);
+                       n_words, shots, n_rec, n_det, n_obs, C, flag_off, flag_stride);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@
 
 #include <algorithm>
 
+#include "frame_device.hpp"
 #include "launch_args.hpp"
 #include "philox.hpp"
 
@@ -47,46 +48,6 @@ struct Tile {
     static constexpr uint32_t STG_WORDS = FR_LEVEL_MAX * TW;   // staged u64
     static_assert(FR_LEVEL_MAX * QPN == NWC * 64, "one (node, 4 words) per thread");
 };
-
-// Program data read with wave-uniform indices goes through the constant
-// address space, so it is fetched by scalar loads: those are counted apart
-// from vector memory, and never wait behind the row stores in flight.
-template <typename T>
-using cptr = const __attribute__((address_space(4))) T *;
-template <typename T>
-__device__ __forceinline__ cptr<T> uniform(const T *p) {
-    return (cptr<T>)p;
-}
-
-__device__ __forceinline__ GapFast load_fast(const GapFast *p, uint32_t c) {
-    const cptr<uint32_t> q = uniform((const uint32_t *)(p + c));
-    GapFast f;
-    f.invlog2q = __uint_as_float(q[0]);
-    f.A = __uint_as_float(q[1]);
-    f.eps = __uint_as_float(q[2]);
-    f.pad = 0;
-    f.qW = (uint64_t)q[4] | ((uint64_t)q[5] << 32);
-    f.vmin = (uint64_t)q[6] | ((uint64_t)q[7] << 32);
-    return f;
-}
-
-struct FrWord {
-    uint32_t pos, j, e, pad;  // class stream state: next position, draw, event index
-};
-
-__device__ __forceinline__ uint32_t pick4(uint4 r, uint32_t i) {
-    return i == 0 ? r.x : i == 1 ? r.y : i == 2 ? r.z : r.w;
-}
-
-// Channel record: flip-table offset | J << 26 | uniform << 32 | step << 33 | thr_off << 41.
-__device__ __forceinline__ uint32_t branch_of(const uint64_t *thr, uint64_t info, uint32_t bv) {
-    const uint32_t J = (uint32_t)(info >> 26) & 0x3Fu;
-    if ((info >> 32) & 1u) return (uint32_t)(((uint64_t)bv * J) >> 32);
-    const uint64_t t0 = info >> 41;
-    for (uint32_t t = 0; t < J; ++t)
-        if ((uint64_t)bv < thr[t0 + t]) return t;
-    return J - 1;
-}
 
 // Slot array: slot s holds the tile's TW words at s * TW + (w ^ (s & (TW - 1))).
 // The swizzle spreads one word column over the LDS banks (an unswizzled column
@@ -120,31 +81,6 @@ __device__ __forceinline__ void push_quad(unsigned long long *slots, uint32_t s,
     const uint32_t x = s & 3u;
 #pragma unroll
     for (uint32_t i = 0; i < 4; ++i) atomicXor(d + (i ^ x), v[i]);
-}
-
-struct Walk {
-    uint32_t pos, j, e;
-};
-
-// Flip-table word of a (channel, branch): its single flip entry (slot count
-// in bits 6..7, nonzero), or entry count (bits 0..5) | first entry << 8.
-__device__ __forceinline__ bool flip_inline(uint64_t fw) { return ((fw >> 6) & 3u) != 0; }
-__device__ __forceinline__ uint32_t flip_count(uint64_t fw) { return flip_inline(fw) ? 1u : (uint32_t)(fw & 63u); }
-
-// Inclusive prefix sum over the 64 lanes of a wave by DPP: a 4-lane window
-// inside each row of 16 (row shifts 1..3), then banks (row shifts 4 and 8
-// into the upper banks), then rows (broadcasts of lanes 15 and 31).
-__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
-    const int xi = (int)x;
-    uint32_t s = x;
-    s += (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x111, 0xf, 0xf, true);  // row_shr:1
-    s += (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x112, 0xf, 0xf, true);  // row_shr:2
-    s += (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x113, 0xf, 0xf, true);  // row_shr:3
-    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x114, 0xf, 0xe, false);  // row_shr:4, banks 1-3
-    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x118, 0xf, 0xc, false);  // row_shr:8, banks 2-3
-    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x142, 0xa, 0xf, false);  // row_bcast:15, rows 1, 3
-    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x143, 0xc, 0xf, false);  // row_bcast:31, rows 2, 3
-    return s;
 }
 
 // The program tables a walk reads (passed by value, so an out-of-line walk
@@ -322,7 +258,6 @@ __device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const 
     return cutR;
 }
 
-__device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Walk the word's class stream up to the end R of this step, applying events at once.
 template <uint32_t TW>
@@ -341,18 +276,6 @@ __device__ __forceinline__ void noise_direct(WalkTabs T, GapFast F, const uint64
         S->j = st.j;
         S->e = st.e;
     }
-}
-
-__device__ __forceinline__ unsigned long long word_mask(uint64_t wi, uint64_t shots) {
-    const uint64_t s0 = wi * 64;
-    if (s0 + 64 <= shots) return ~0ull;
-    if (s0 >= shots) return 0ull;
-    return (1ull << (shots - s0)) - 1ull;
-}
-
-__device__ __forceinline__ unsigned long long rm_word(uint32_t t, uint64_t w, uint32_t k0, uint32_t k1) {
-    const uint4 o = philox4x32_10(make_uint4(t >> 1, (uint32_t)w, 0u, (3u << 24) | (uint32_t)(w >> 32)), k0, k1);
-    return (t & 1) ? ((uint64_t)o.z | ((uint64_t)o.w << 32)) : ((uint64_t)o.x | ((uint64_t)o.y << 32));
 }
 
 // One (node, 4 words) of an EMIT step: the four slot words are read and

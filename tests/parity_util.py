@@ -112,3 +112,22 @@ def frame_relation(a, b, tol):
         if np.max(np.abs(a - ph * chi * bb)) <= tol:
             return y, s
     return None
+
+
+def p0_error(p0_gpu, oc, seed, shots, tol):
+    """Largest abs(P0_gpu - P0_oracle) over the active measurements of `shots`.
+
+    p0_gpu[i, t] is the kernels' Pr(recorded bit = 0) of measurement t in
+    shots[i].  Each shot is compared up to and including its first active draw
+    within `tol` of the oracle's threshold: past that draw the two sides may
+    take different branches, and their later probabilities need not agree.
+    Returns (worst error, number of probabilities compared)."""
+    worst, n = 0.0, 0
+    for i, s in enumerate(shots):
+        tr = oc.trace(seed, s)
+        for t in np.flatnonzero(tr["meas_kind"] >= 2):
+            worst = max(worst, abs(float(p0_gpu[i, t]) - float(tr["p0"][t])))
+            n += 1
+            if abs(O.active_u(seed, int(t), s) - tr["p0"][t]) < tol:
+                break
+    return worst, n

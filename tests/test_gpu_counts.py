@@ -211,3 +211,27 @@ def test_counts_via_records_path(prec):
     a, _ = p.sample_counts(64 * 7, 33, post=post, precision=prec)
     b, _ = p.sample_counts(64 * 7, 33, post=post, precision=prec, mode=1)
     assert np.array_equal(S.bits_to_numpy(a), S.bits_to_numpy(b))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_count_paths_agree_over_several_chunks(prec):
+    """Count path 2 runs its range in chunks of 4096 words (bounded scratch for the detector and observable
+    rows only): over three and a half chunks at an offset, paths 1 and 2 and the automatic choice give the
+    same flags and counts, equal to those derived from the same kernels' full records."""
+    from workloads.distill import distill_15to1
+    c = distill_15to1(1e-2)
+    p = S.Program(c)
+    post = list(range(c.num_detectors))
+    shots, off, seed = 3 * 4096 * 64 + 64 * 2048 + 37, 64 * 5, 4099
+    print(f"count paths over {shots} shots, {prec}", flush=True)
+    f1, c1 = p.sample_counts(shots, seed, post=post, shot_offset=off, precision=prec, mode=1)
+    f2, c2 = p.sample_counts(shots, seed, post=post, shot_offset=off, precision=prec, mode=2)
+    p.autotune_counts(post, precision=prec)
+    f0, c0 = p.sample_counts(shots, seed, post=post, shot_offset=off, precision=prec, mode=0)
+    a1, a2, a0 = S.bits_to_numpy(f1), S.bits_to_numpy(f2), S.bits_to_numpy(f0)
+    assert np.array_equal(a1, a2) and np.array_equal(a1, a0)
+    assert list(c1.cpu().numpy()) == list(c2.cpu().numpy()) == list(c0.cpu().numpy())
+    rec = S.bits_to_numpy(p.sample(shots, seed, shot_offset=off, precision=prec))
+    own, own_c = count_flags(rec, c.num_records, c.num_detectors, c.num_observables, shots, post, None)
+    assert np.array_equal(a1, own)
+    assert list(c1.cpu().numpy()) == list(own_c)

@@ -145,7 +145,7 @@ def test_c4_programs(i):
         compare_records(got, want, w.circuit, oc, w.seed, 0, TOL[prec])
 
 
-@pytest.mark.parametrize("k,prec", [(14, "fp32"), (14, "fp64"), (16, "fp32")])
+@pytest.mark.parametrize("k,prec", [(14, "fp32"), (14, "fp64"), (16, "fp32"), (16, "fp64")])
 def test_c5_large_active_state(k, prec):
     w = configs.c5(k)
     p = S.Program(w.circuit)

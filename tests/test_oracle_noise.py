@@ -1,6 +1,7 @@
 """Pins of the oracle's noise and measurement draws (draw contract) by statistics.
 
-* the exact-integer geometric table: Q[1] = 2^32 - P32, monotone, ~ 2^32 (1-p)^g;
+* the exact-integer geometric table, element by element against a big-integer
+  recomputation, and within g + 1 of 2^32 (1-p)^g;
 * per-channel firing frequency vs P32 / 2^32 (binomial z-test) and branch
   frequencies (uniform D1/D2, weighted general channels: chi-square);
 * per-detector marginals of a noisy surface code vs the exact value
@@ -18,9 +19,31 @@ from workloads.circuit import Circuit, Op
 from workloads.surface import rotated_memory_z
 
 
+def _exact_table(p32: int):
+    """Q[0] = 2^32, Q[g+1] = floor(Q[g] (2^32 - P32) / 2^32) in Python big integers."""
+    q = [1 << 32]
+    for _ in range(4096):
+        q.append((q[-1] * ((1 << 32) - p32)) >> 32)
+    return q
+
+
+# P32 values of the workloads (p = 1e-3 surface codes and distillation, 5e-4
+# near-Clifford circuits, readout flips 1e-2 and 2e-2, heavy noise 0.3) and the
+# edges of the range: the smallest and largest P32 below 2^32, and 2^32 itself
+# (a channel that always fires).
+_P32S = [int(p * 2 ** 32) for p in (1e-3, 5e-4, 1e-2, 2e-2, 0.3, 0.05, 0.15, 0.09)] + [1, 2, (1 << 32) - 1, 1 << 32]
+
+
 def test_gap_table_exact_integers():
-    for p in (1e-3, 5e-4, 0.3, 1.0):
-        p32 = 1 << 32 if p >= 1 else int(np.floor(p * 2 ** 32))
+    for p32 in _P32S:
+        got = [int(v) for v in oracle.gap_table(p32)]
+        want = _exact_table(p32)
+        assert got == want, p32
+
+
+def test_gap_table_closed_form():
+    # the integer table stays within one unit per step of 2^32 q^g, q = 1 - P32/2^32
+    for p32 in _P32S:
         Q = oracle.gap_table(p32).astype(np.float64)
         assert Q[0] == 2 ** 32
         assert Q[1] == 2 ** 32 - p32

@@ -30,7 +30,7 @@ def test_philox_known_answers():
         for line in f:
             if line.strip() and not line.startswith("#"):
                 rows.append([int(t, 16) for t in line.split()])
-    assert len(rows) == 4
+    assert len(rows) == 3
     for r in rows:
         out = oracle.philox(r[0:4], r[4:6])
         assert [int(v) for v in out] == r[6:10]
@@ -306,3 +306,14 @@ def test_final_state_matches_dense_replay(seed):
             assert abs(abs(np.vdot(psi_o, psi_d)) - 1) < 1e-10
             checked += fs["k"] > 0
     assert checked > 0
+
+
+def test_oracle_rejects_registers_past_its_limit():
+    # the oracle's per-shot Pauli scratch holds 64 words, so at most 4096 qubits
+    c = Circuit(4097)
+    c.append("H", [4096])
+    with pytest.raises(ValueError):
+        OracleCircuit(c)
+    ok = Circuit(4096)
+    ok.append("M", [4095])
+    assert OracleCircuit(ok).sample(1, 64).shape[0] == 1
