@@ -6,17 +6,23 @@ per step on the pure-frame path.  One step = one symft_sample call that
 writes all 2762 bit-packed rows for 2^24 shots, inputs (the compiled program)
 already resident in HBM.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
-                    [--workload c2|c1|c3|c3fp64|c4|c4fp64|c5|c5fp64|c5k16|post|distill]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-extras]
+                    [--workload c2|c1|c3|c3fp64|c4|c4fp64|c5|c5fp64|c5k16|c5k16fp64|post|distill]
 
-Prints one JSON line.  `roofline` prices the dominant kernel against HBM
-bandwidth (record bytes written per launch / average launch time, measured
-with HIP events on the launch stream); `cpu_baseline` times the CPU oracle
-on a bounded sample of the same workload.
+Prints one JSON line.  `roofline` prices the dominant kernel against its
+bound (record bytes written per launch / average launch time for the frame
+kernel, measured with HIP events on the launch stream).  The default line's
+`extra` also carries the batched-FP32 vs per-circuit-FP64 comparison on the
+128-program batch (both sides autotuned) and the step-synchronous frame
+kernel's time.  The oracle leg (`cpu_baseline`, on unless --no-cpu-baseline)
+times the CPU oracle on a bounded sample of the same workload and reports
+the kernels' branch-probability and amplitude errors against the FP64 oracle
+per configuration.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,14 +33,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "shots/s on 1 MI355X (batched FP32 vs plain FP64) + % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-# Measured HBM bytes per launch of the pure-frame kernel on a workload (FETCH_SIZE x 2.000 +
-# WRITE_SIZE x 1.000, the scales read off a 1 GiB device copy), kept only while the kernel is
-# the one the counters were taken on.
-FRAME_TRAFFIC_BYTES = {"surface_d11_r11_p1e-3": (1563095 * 2 + 8400322) * 1024}
-# The same for the active kernel with HBM-resident vectors (FP32, 2^16 shots).
-ACTIVE_TRAFFIC_BYTES = {"near_clifford_n48_k16": (688241884 * 2 + 1133273003) * 1024}
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
+LDS_BYTES = 160 * 1024
+CSRC = os.path.join(ROOT, "paper_2607_28600_amd", "csrc")
+
+# HBM bytes per launch measured with rocprofv3 (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 KiB, the scales
+# read off a 1 GiB device copy; profiles/ holds the runs), with the SHA-256 of the kernel source they
+# were taken on.  A changed source reports traffic null until it is profiled again.
+# The digest covers the kernel's source file and the headers every kernel includes.
+PROFILED_TRAFFIC = {}
+_HEADERS = ["device_program.hpp", "launch_args.hpp", "philox.hpp", "frame_device.hpp"]
+
+
+def _source_sha(name):
+    h = hashlib.sha256()
+    for f in [name] + _HEADERS:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _traffic(workload, source):
+    rec = PROFILED_TRAFFIC.get((workload, source))
+    if rec is None or _source_sha(source)[:16] != rec[0]:
+        return None
+    return rec[1]
 
 
 def _time_launches(fn, steps, warmup, stream):
@@ -47,7 +71,6 @@ def _time_launches(fn, steps, warmup, stream):
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    wall0 = time.perf_counter()
     t0.record(stream)
     for i in range(steps):
         starts[i].record(stream)
@@ -55,46 +78,47 @@ def _time_launches(fn, steps, warmup, stream):
         ends[i].record(stream)
     t1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
     per = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    return t0.elapsed_time(t1) / steps, sum(per) / len(per), wall
+    return t0.elapsed_time(t1) / steps, sum(per) / len(per)
 
 
-LDS_BYTES = 160 * 1024
+def _c4_comparison(S, stream, steps, prec="fp32"):
+    """The 128-program batch in one persistent graph-replayed launch (threads per shot from the batch
+    autotuner) against 128 per-circuit plain FP64 launches, each program autotuned for FP64 first.
+    Both launch configurations are chosen outside the timed region."""
+    import torch
+    from workloads import configs
+    ws = configs.c4()
+    progs = [S.Program(x.circuit) for x in ws]
+    outs = [torch.empty((p.n_rows, (x.shots + 63) // 64), dtype=torch.int64, device="cuda")
+            for p, x in zip(progs, ws)]
+    shots = [x.shots for x in ws]
+    seeds = [x.seed for x in ws]
+    total = sum(shots)
+
+    def batched():
+        S.sample_batch(progs, shots, seeds, outs, precision=prec, graph=True, stream=stream.cuda_stream)
+
+    ms_b, ms_b_kernel = _time_launches(batched, steps, 2, stream)
+    for p in progs:
+        p.autotune("fp64")
+
+    def plain_fp64():
+        for p, x, o in zip(progs, ws, outs):
+            p.sample_into(o, x.shots, x.seed, precision="fp64", stream=stream.cuda_stream)
+
+    ms_64, _ = _time_launches(plain_fp64, max(2, steps // 2), 1, stream)
+    flops = sum(p.info()["dense_flops_per_shot"] * s for p, s in zip(progs, shots))
+    return {
+        "shots": total, "programs": len(ws),
+        f"batched_{prec}": {"ms_per_step": round(ms_b, 3), "shots_per_s": round(total / (ms_b / 1e3), 1),
+                            "tflops": round(flops / (ms_b_kernel / 1e3) / 1e12, 3)},
+        "per_circuit_fp64_autotuned": {"ms_per_step": round(ms_64, 3), "shots_per_s": round(total / (ms_64 / 1e3), 1)},
+        f"batched_{prec}_over_per_circuit_fp64": round(ms_64 / ms_b, 3),
+    }, (progs, ws, flops, ms_b_kernel)
 
 
-def _p0_error(prog, seed, n_shots):
-    """Largest |Pr(m=0)| difference between the FP32 and FP64 kernels over the active
-    measurements of n_shots shots, and how many exceed 1e-5 (the FP64 kernel matches the
-    oracle within 1e-12 in the parity tests; a larger difference can only follow a draw that
-    fell between the two precisions' thresholds, after which both branches are valid)."""
-    import numpy as np
-    a = prog.probe(0, n_shots, seed, precision="fp32")
-    b = prog.probe(0, n_shots, seed, precision="fp64")
-    ok = ~np.isnan(b)
-    d = np.abs(a[ok] - b[ok])
-    return {"max_abs": float(d.max(initial=0.0)), "over_1e-5": int((d > 1e-5).sum()),
-            "measurements": int(d.size), "probed_shots": n_shots}
-
-
-def _amp_error(prog, seed, n_shots):
-    """Largest |amplitude| difference between the FP32 and FP64 kernels over the final active vectors of
-    n_shots shots whose records agree in both precisions (a shot whose draw fell between the two
-    precisions' thresholds took another branch and is left out; the count is reported)."""
-    import numpy as np
-    import paper_2607_28600_amd as S
-    a32 = prog.probe_amplitudes(0, n_shots, seed, precision="fp32")
-    a64 = prog.probe_amplitudes(0, n_shots, seed, precision="fp64")
-    r32 = S.bits_to_numpy(prog.sample(n_shots, seed, precision="fp32"))
-    r64 = S.bits_to_numpy(prog.sample(n_shots, seed, precision="fp64"))
-    same = [s for s in range(n_shots)
-            if np.array_equal((r32[:, s // 64] >> np.uint64(s % 64)) & np.uint64(1),
-                              (r64[:, s // 64] >> np.uint64(s % 64)) & np.uint64(1))]
-    d = np.abs(a32[same] - a64[same]) if same else np.zeros(1)
-    return {"max_abs": float(d.max(initial=0.0)), "shots_compared": len(same), "probed_shots": n_shots,
-            "amplitudes_per_shot": int(a64.shape[1])}
-
-
+# ------------------------------------------------------------------ oracle leg
 def _cpu_baseline(circ, seed, words, threads):
     from oracle import OracleCircuit
     oc = OracleCircuit(circ)
@@ -104,6 +128,61 @@ def _cpu_baseline(circ, seed, words, threads):
     return len(words) * 64 / dt, dt
 
 
+def _errors_vs_oracle(prog, w, n_p0, n_amp):
+    """Branch-probability and final-amplitude errors of the kernels (FP32 and FP64) against the FP64
+    oracle on the first shots of a workload.  Pr(m = 0) is compared on every active measurement up to a
+    shot's first draw within 1e-5 of the oracle's threshold (past it the branches may differ); final
+    amplitudes on shots whose records equal the oracle's, up to the Pauli-frame map the two
+    representations differ by (index shift, sign character, global phase)."""
+    import numpy as np
+    import paper_2607_28600_amd as S
+    from oracle import OracleCircuit
+    from tests.parity_util import frame_match, p0_error
+    oc = OracleCircuit(w.circuit)
+    res = {}
+    s0 = 64 * 3 + 5
+    shots = list(range(s0, s0 + n_p0))
+    want = oc.sample(w.seed, 64)
+    for prec in ("fp32", "fp64"):
+        p0 = prog.probe(s0, n_p0, w.seed, precision=prec)
+        worst, cnt = p0_error(p0, oc, w.seed, shots, 1e-5)
+        amp = prog.probe_amplitudes(0, n_amp, w.seed, precision=prec)
+        rec = S.bits_to_numpy(prog.sample(64, w.seed, precision=prec))
+        amp_err, checked, unmatched = 0.0, 0, 0
+        for s in range(n_amp):
+            bit = np.uint64(s)
+            if not np.array_equal((rec[:, 0] >> bit) & np.uint64(1), (want[:, 0] >> bit) & np.uint64(1)):
+                continue
+            fs = oc.final_state(w.seed, s)
+            m = frame_match(amp[s], fs["alpha"], 1e-4 if prec == "fp32" else 1e-9)
+            if m is None:
+                unmatched += 1
+                continue
+            amp_err = max(amp_err, m[2])
+            checked += 1
+        res[prec] = {"p0_max_abs_err": worst, "p0_compared": cnt, "amp_max_abs_err": amp_err,
+                     "amp_shots": checked, "amp_shots_unmatched": unmatched,
+                     "amplitudes_per_shot": int(amp.shape[1])}
+    return res
+
+
+def _oracle_errors_all(S):
+    """Errors against the FP64 oracle for the near-Clifford configurations: C3, four C4 programs (widths
+    4, 8, 12, 12), C5 at widths 14 and 16."""
+    from workloads import configs
+    out = {}
+    cases = [("c3", configs.c3(), 24, 16)]
+    c4 = configs.c4()
+    cases += [(f"c4_{i}", c4[i], 8, 8) for i in (3, 7, 11, 59)]
+    cases += [("c5_k14", configs.c5(14), 8, 4), ("c5_k16", configs.c5(16), 4, 2)]
+    for name, w, n_p0, n_amp in cases:
+        prog = S.Program(w.circuit)
+        out[name] = _errors_vs_oracle(prog, w, n_p0, n_amp)
+        out[name]["k_max"] = prog.k_max
+    return out
+
+
+# ------------------------------------------------------------------ workloads
 def run(args):
     import torch
     import paper_2607_28600_amd as S
@@ -113,11 +192,15 @@ def run(args):
     stream = torch.cuda.current_stream()
     cores = os.cpu_count() or 1
     extra = {}
+    errors_for = None  # workload whose errors the oracle leg reports
     wl = args.workload
-    if wl in ("c1", "c2", "c3", "c3fp64", "c5", "c5fp64", "c5k16"):
-        w = {"c1": configs.c1, "c2": configs.c2, "c3": configs.c3, "c3fp64": configs.c3,
-             "c5": lambda: configs.c5(14), "c5fp64": lambda: configs.c5(14), "c5k16": lambda: configs.c5(16)}[wl]()
-        prec = "fp32" if wl in ("c3", "c5", "c5k16") else "fp64"
+    single = {"c1": (configs.c1, "fp64"), "c2": (configs.c2, "fp64"), "c3": (configs.c3, "fp32"),
+              "c3fp64": (configs.c3, "fp64"), "c5": (lambda: configs.c5(14), "fp32"),
+              "c5fp64": (lambda: configs.c5(14), "fp64"), "c5k16": (lambda: configs.c5(16), "fp32"),
+              "c5k16fp64": (lambda: configs.c5(16), "fp64")}
+    if wl in single:
+        make, prec = single[wl]
+        w = make()
         prog = S.Program(w.circuit)
         info = prog.info()
         tps = prog.autotune(prec) if info["k_max"] else 0  # launch configuration, outside the timed region
@@ -127,83 +210,75 @@ def run(args):
         def step():
             prog.sample_into(out, w.shots, w.seed, precision=prec, stream=stream.cuda_stream)
 
-        ms_step, ms_kernel, wall = _time_launches(step, args.steps, args.warmup, stream)
+        ms_step, ms_kernel = _time_launches(step, args.steps, args.warmup, stream)
         value = w.shots / (ms_step / 1e3)
         rec_bytes = prog.n_rows * words * 8
+        dtype = "u64" if info["k_max"] == 0 else ("f32" if prec == "fp32" else "f64")
         if info["k_max"] == 0:
+            fk = int(info["frame_kernel"])
+            kname, src = ("frame_wave_kernel", "sample_frame_wave.hip") if fk == 1 else ("frame_kernel", "sample_frame.hip")
             achieved = rec_bytes / (ms_kernel / 1e3) / 1e9
-            traffic = FRAME_TRAFFIC_BYTES.get(w.name) if w.shots == 1 << 24 else None
+            traffic = _traffic(w.name, src) if w.shots == 1 << 24 else None
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": round(traffic / 1e9, 3) if traffic else None, "traffic_unit": "GB/launch",
-                    "kernel": "frame_kernel", "bytes_per_launch": rec_bytes}
-            dtype = "u64"
-        elif (1 << info["k_max"]) * (8 if prec == "fp32" else 16) > LDS_BYTES or (13 <= info["k_max"] <= 14 and tps != 1024):
-            # vectors streamed from HBM scratch (always at peak widths 13 and 14 unless one shot runs per
-            # 1024-thread workgroup): one read and one write of the live vector per instruction
+                    "kernel": kname, "bytes_per_launch": rec_bytes}
+            if args.extras and fk in (1, 2):
+                # the other pure-frame kernel on the same launch, for comparison
+                other = 2 if fk == 1 else 1
+
+                def other_kernel():
+                    prog.sample_into(out, w.shots, w.seed, stream=stream.cuda_stream, frame_kernel=other)
+                key = "step_synchronous_frame_kernel" if other == 2 else "wave_owned_frame_kernel"
+                try:
+                    _, ms_ok = _time_launches(other_kernel, max(2, args.steps // 4), 1, stream)
+                    extra[key] = {"ms_per_launch": round(ms_ok, 4),
+                                  "frac": round(rec_bytes / (ms_ok / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+                except S.SymftError as e:  # the schedule does not fit that kernel
+                    extra[key] = {"unavailable": str(e)}
+        elif (1 << info["k_max"]) * (8 if prec == "fp32" else 16) > LDS_BYTES and info["k_max"] >= 15:
+            # vectors streamed from HBM scratch far beyond the caches: one read and one write of the live
+            # vector per dense instruction
             nbytes = info["dense_bytes_per_shot"] * (1 if prec == "fp32" else 2) * w.shots
             achieved = nbytes / (ms_kernel / 1e3) / 1e9
-            traffic = ACTIVE_TRAFFIC_BYTES.get(w.name) if prec == "fp32" and w.shots == 1 << 16 else None
+            traffic = _traffic(w.name, "sample_active.hip") if prec == "fp32" and w.shots == 1 << 16 else None
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": round(traffic / 1e9, 1) if traffic else None, "traffic_unit": "GB/launch",
                     "kernel": "active_kernel", "bytes_per_launch": nbytes}
-            dtype = "f32" if prec == "fp32" else "f64"
         else:
+            # vectors in LDS, or at widths 13 and 14 in scratch that the L2 and the Infinity Cache hold:
+            # priced against the vector ALU
             flops = info["dense_flops_per_shot"] * w.shots
             achieved = flops / (ms_kernel / 1e3) / 1e12
             peak = FP32_PEAK_TFLOPS if prec == "fp32" else FP64_PEAK_TFLOPS
             roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                     "frac": round(achieved / peak, 4), "traffic": None, "kernel": "active_kernel",
                     "flops_per_launch": flops}
-            dtype = "f32" if prec == "fp32" else "f64"
-        if info["k_max"] and prec == "fp32":
-            extra["p0_fp32_vs_fp64"] = _p0_error(prog, w.seed, 64)
-            extra["amplitude_fp32_vs_fp64"] = _amp_error(prog, w.seed, 64)
         config = {"workload": w.name, "shots": w.shots, "rows": prog.n_rows, "k_max": info["k_max"],
                   "precision": prec if info["k_max"] else "n/a (integer path)"}
         if tps:
             config["threads_per_shot"] = tps
-        n_cpu_words = {"c1": 256, "c2": 24, "c3": 64, "c3fp64": 64, "c5": 8, "c5fp64": 8, "c5k16": 2}[wl]
+        if info["k_max"]:
+            errors_for = (prog, w)
+        n_cpu_words = {"c1": 256, "c2": 24, "c3": 64, "c3fp64": 64, "c5": 8, "c5fp64": 8, "c5k16": 2,
+                       "c5k16fp64": 2}[wl]
         sample_words = [int(i * words / n_cpu_words) for i in range(n_cpu_words)]
         circ, seed = w.circuit, w.seed
+        if wl == "c2" and args.extras:
+            extra["c4_batch"], _ = _c4_comparison(S, stream, 6)
     elif wl in ("c4", "c4fp64"):
-        ws = configs.c4()
-        progs = [S.Program(x.circuit) for x in ws]
-        outs = [torch.empty((p.n_rows, (x.shots + 63) // 64), dtype=torch.int64, device="cuda")
-                for p, x in zip(progs, ws)]
-        shots = [x.shots for x in ws]
-        seeds = [x.seed for x in ws]
         prec = "fp64" if wl == "c4fp64" else "fp32"
-
-        def step():
-            S.sample_batch(progs, shots, seeds, outs, precision=prec, graph=True, stream=stream.cuda_stream)
-
-        ms_step, ms_kernel, wall = _time_launches(step, args.steps, args.warmup, stream)
-        total = sum(shots)
-        value = total / (ms_step / 1e3)
-
-        def plain_fp64():
-            for p, x, o in zip(progs, ws, outs):
-                p.sample_into(o, x.shots, x.seed, precision="fp64", stream=stream.cuda_stream)
-
-        ms64, _, _ = _time_launches(plain_fp64, max(2, args.steps // 4), 1, stream)
-        extra["fp64_per_circuit_launches"] = {"shots_per_s": round(total / (ms64 / 1e3), 1), "ms_per_step": round(ms64, 4)}
-        extra[f"batched_{prec}_over_fp64_plain"] = round(ms64 / ms_step, 3)
-        flops = sum(p.info()["dense_flops_per_shot"] * s for p, s in zip(progs, shots))
+        cmp, (progs, ws, flops, ms_kernel) = _c4_comparison(S, stream, args.steps, prec)
+        ms_step = cmp[f"batched_{prec}"]["ms_per_step"]
+        value = cmp["shots"] / (ms_step / 1e3)
+        extra["c4_batch"] = cmp
         achieved = flops / (ms_kernel / 1e3) / 1e12
         peak = FP32_PEAK_TFLOPS if prec == "fp32" else FP64_PEAK_TFLOPS
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": "active_kernel"}
+                "frac": round(achieved / peak, 4), "traffic": None, "kernel": "batch_kernel"}
         dtype = "f32" if prec == "fp32" else "f64"
-        config = {"workload": "batch_128_near_clifford", "shots": total, "programs": len(ws), "precision": prec}
-        if prec == "fp32":
-            errs = [_p0_error(p, x.seed, 16) for p, x in list(zip(progs, ws))[::16]]
-            extra["p0_fp32_vs_fp64"] = {"max_abs": max(e["max_abs"] for e in errs),
-                                        "over_1e-5": sum(e["over_1e-5"] for e in errs),
-                                        "measurements": sum(e["measurements"] for e in errs),
-                                        "probed_shots": sum(e["probed_shots"] for e in errs),
-                                        "programs": len(errs)}
+        config = {"workload": "batch_128_near_clifford", "shots": cmp["shots"], "programs": len(ws), "precision": prec}
         circ, seed = ws[0].circuit, ws[0].seed
         sample_words = list(range(16))
     elif wl in ("post", "distill"):
@@ -225,7 +300,7 @@ def run(args):
             prog.sample_counts_into(flags, counts, w.shots, w.seed, post=post, precision=prec,
                                     stream=stream.cuda_stream)
 
-        ms_step, ms_kernel, wall = _time_launches(step, args.steps, args.warmup, stream)
+        ms_step, ms_kernel = _time_launches(step, args.steps, args.warmup, stream)
         value = w.shots / (ms_step / 1e3)
         counts.zero_()
         step()
@@ -235,7 +310,7 @@ def run(args):
         def records():
             prog.sample_into(out, w.shots, w.seed, precision=prec, stream=stream.cuda_stream)
 
-        ms_rec, ms_rec_kernel, _ = _time_launches(records, max(2, args.steps // 2), 1, stream)
+        ms_rec, ms_rec_kernel = _time_launches(records, max(2, args.steps // 2), 1, stream)
         del out
         extra["discarded_fraction"] = round(n_disc / w.shots, 5)
         extra["logical_errors_per_kept_shot"] = round(n_log / max(1, w.shots - n_disc), 6)
@@ -255,6 +330,7 @@ def run(args):
         circ, seed = w.circuit, w.seed
         n_cpu_words = 16 if wl == "post" else 8192  # the width-5 distillation oracle runs ~1e5 shots/s
         sample_words = [int(i * words / n_cpu_words) for i in range(n_cpu_words)]
+        errors_for = (prog, w)
     else:
         raise SystemExit(f"unknown workload {wl}")
 
@@ -263,6 +339,11 @@ def run(args):
         cpu = {"value": round(cpu_value, 2), "unit": "shots/s", "cores": cores, "kind": "oracle",
                "sample": f"{len(sample_words)} 64-shot words spread over the workload's shot range "
                          f"({len(sample_words) * 64} shots, {cpu_dt:.1f} s)"}
+        if args.extras:
+            if wl == "c2":
+                extra["errors_vs_fp64_oracle"] = _oracle_errors_all(S)
+            elif errors_for is not None:
+                extra["errors_vs_fp64_oracle"] = _errors_vs_oracle(errors_for[0], errors_for[1], 12, 8)
     else:
         cpu = None
     line = {
@@ -284,6 +365,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="time only the workload itself (no comparisons, no error report)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the sampler runs on one GPU only; shots shard by 64-shot word ranges, "

@@ -129,8 +129,9 @@ typedef struct {
     uint64_t frame_pushes;         /* record-to-consumer XORs over the schedule */
     uint64_t frame_noise_consumers;/* noise-symbol-to-consumer XORs, summed over symbols */
     uint64_t rotations_removed;    /* rotations fused into an earlier one or cancelled (symft_compile_opts) */
-    uint64_t frame_kernel;         /* pure-frame kernel of the automatic choice: 1 wave-owned, 2 step-synchronous;
-                                      0 when the program runs on the active kernel */
+    uint64_t frame_kernel;         /* pure-frame kernel of the automatic choice: 2 step-synchronous, 1 wave-owned
+                                      (schedules whose slots fit only its LDS); 0 when the program runs on the
+                                      active kernel */
     uint64_t frame_wave_batches;   /* wave-owned schedule: node batches (one node per lane) */
     uint64_t frame_wave_flushes;   /* wave-owned schedule: staged-row flushes (workgroup barriers) */
 } symft_info;
@@ -201,9 +202,9 @@ typedef struct {
                                       per CU, when the schedule fits LDS at that width and there are at least
                                       two such tiles per CU; else 16-word tiles); 16 or 32 forces the width
                                       (ECAPACITY if it does not fit; records are unchanged) */
-    uint32_t frame_kernel;         /* pure-frame programs: 0 = automatic (the wave-owned kernel, in which each
-                                      wave of a 16-wave workgroup owns one 64-shot word for the whole schedule,
-                                      when its LDS fits; else the step-synchronous kernel); 1 = wave-owned
+    uint32_t frame_kernel;         /* pure-frame programs: 0 = automatic (the step-synchronous kernel when its
+                                      LDS fits, else the wave-owned kernel, in which each wave of a 16-wave
+                                      workgroup owns one 64-shot word for the whole schedule); 1 = wave-owned
                                       (ECAPACITY if it does not fit); 2 = step-synchronous.  A nonzero
                                       frame_tile_words selects the step-synchronous kernel.  Records are
                                       unchanged */
@@ -265,8 +266,8 @@ typedef struct {
                                       written to scratch by the record kernel, then reduced to the flags (for
                                       programs that reject few shots).  Flags do not depend on it.  Pure-frame
                                       programs always use the frame kernel's flags */
-    uint32_t frame_kernel;         /* pure-frame programs: as in symft_sample_opts (0 automatic, 1 wave-owned,
-                                      2 step-synchronous); flags do not depend on it */
+    uint32_t frame_kernel;         /* pure-frame programs, as in symft_sample_opts: 0 automatic, 1 wave-owned,
+                                      2 step-synchronous; flags do not depend on it */
 } symft_count_opts;
 
 /* Sample `shots` shots and report, per shot, only a discarded flag and a

@@ -57,6 +57,7 @@ static GapFast gap_fast_constants(uint64_t p32, const uint64_t *Q) {
     GapFast f;
     std::memset(&f, 0, sizeof(f));
     f.qW = Q[4096];
+    f.vwin = UINT32_MAX;
     if (p32 == 0 || p32 >= (uint64_t(1) << 32)) {
         f.invlog2q = -0.0f;
         f.vmin = UINT64_MAX;  // P32 = 0: every draw is below Q[4096]; P32 = 2^32: table only
@@ -73,6 +74,12 @@ static GapFast gap_fast_constants(uint64_t p32, const uint64_t *Q) {
     f.A = (float)(1.25 * D / (std::log(2.0) * l));
     f.eps = (float)(2.0 * err_t);
     f.vmin = 1;
+    if (err_t < 0.5) {
+        // G >= floor(t) - 1 needs v (2^32 - P32) / P32 > D; the error bound needs v >= max(Q[4096], 1)
+        const double vw = std::ceil(D * (std::ldexp(1.0, 32) - (double)p32) / (double)p32) + 2.0;
+        const double lo = std::max<double>(vw, (double)std::max<uint64_t>(Q[4096], 1));
+        if (lo < 4294967295.0) f.vwin = (uint32_t)lo;
+    }
     return f;
 }
 
@@ -92,7 +99,7 @@ struct HostLayout {
     // offsets of each array inside blob
     size_t o_instr, o_cmeas, o_am, o_rm, o_recmeas, o_detoff, o_detrows, o_obsoff, o_obsrows, o_clsQ, o_clsoff, o_clschan,
         o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_invlog, o_clsfast, o_frstep, o_frnodes, o_frpush, o_frchinfo,
-        o_frfltab, o_frfl3, o_frcap, o_frcapoff, o_wvops, o_wvrows, o_wvfl, o_wvsl, o_wvrm, o_wvcap, o_wvcapoff;
+        o_frrec, o_frfl3, o_frcap, o_frcapoff, o_wvops, o_wvrows, o_wvfl, o_wvsl, o_wvrm, o_wvcap, o_wvcapoff, o_ci32, o_st8, o_q32;
     uint32_t word_entries = 0;  // flip entries per word over all classes (frame kernel scratch)
     uint32_t wv_word_entries = 0;  // slot flips per word over all classes (wave kernel scratch)
     DevProg meta;  // counts only; pointers filled at upload
@@ -120,11 +127,12 @@ struct symft_program {
     ~symft_program() {
         drop_batch_plans(this);
         auto drop = [](int d, void *ptr) {
+            // a destructor has no caller to report to: failures here are ignored
             int cur = 0;
-            hipGetDevice(&cur);
-            hipSetDevice(d);
-            hipFree(ptr);
-            hipSetDevice(cur);
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(d);
+            (void)hipFree(ptr);
+            (void)hipSetDevice(cur);
         };
         for (auto &kv : dev) drop(kv.first, kv.second);
         for (auto &kv : count_dev) drop(kv.first.first, kv.second);
@@ -276,7 +284,17 @@ static void lower(symft_program *h) {
     L.o_frnodes = put(L.blob, h->F.nodes);
     L.o_frpush = put(L.blob, h->F.push);
     L.o_frchinfo = put(L.blob, h->F.chinfo);
-    L.o_frfltab = put(L.blob, h->F.fltab);
+    L.o_ci32 = put(L.blob, h->F.ci32);
+    L.o_st8 = put(L.blob, h->F.st8);
+    {
+        std::vector<uint32_t> q32;
+        for (auto &c : P.classes)
+            for (size_t g = 0; g < c.Q.size(); ++g) q32.push_back(c.Q[g] >= (uint64_t(1) << 32) ? 0xFFFFFFFFu : (uint32_t)c.Q[g]);
+        // whole 16-byte units for the LDS copy; the walks treat entry 0 (2^32) as above every draw
+        q32.resize((q32.size() + 3) & ~(size_t)3, 0u);
+        L.o_q32 = put(L.blob, q32);
+    }
+    L.o_frrec = put(L.blob, h->F.frec);
     L.o_frfl3 = put(L.blob, h->F.fl3);
     {
         std::vector<uint32_t> capoff(1, 0);
@@ -314,6 +332,15 @@ static void lower(symft_program *h) {
     m.fr_first_emit_n = h->F.first_emit[1];
     m.fr_first_noise_cls = h->F.first_noise_cls;
     m.n_sym = P.n_noise_sym;
+    m.fr_n_cch = (uint32_t)h->F.ci32.size();
+    m.fr_rec_ok = h->F.rec_ok ? 1u : 0u;
+    {
+        // the 32-bit gap tables are exact when every Q[g], g >= 1, is below 2^32
+        bool q_ok = true;
+        for (auto &c : P.classes)
+            for (size_t g = 1; g < c.Q.size(); ++g) q_ok = q_ok && c.Q[g] < (uint64_t(1) << 32);
+        m.fr_ltab = h->F.ltab_ok && q_ok ? 1u : 0u;
+    }
     m.wv_n_ops = (uint32_t)(h->F.wops.size() / WV_OP_WORDS);
     m.wv_n_rm = (uint32_t)h->F.rm_meas.size();
     m.wv_first_noise_cls = h->F.w_first_noise_cls;
@@ -365,7 +392,10 @@ static symft_status device_prog(symft_program *h, DevProg &out) {
     out.fr_nodes = (const uint32_t *)(b + L.o_frnodes);
     out.fr_push = (const uint32_t *)(b + L.o_frpush);
     out.fr_chinfo = (const uint64_t *)(b + L.o_frchinfo);
-    out.fr_fltab = (const uint64_t *)(b + L.o_frfltab);
+    out.fr_ci32 = (const uint32_t *)(b + L.o_ci32);
+    out.fr_st8 = (const uint8_t *)(b + L.o_st8);
+    out.cls_Q32 = (const uint32_t *)(b + L.o_q32);
+    out.fr_frec = (const uint64_t *)(b + L.o_frrec);
     out.fr_fl3 = (const uint64_t *)(b + L.o_frfl3);
     out.fr_cap = (const uint32_t *)(b + L.o_frcap);
     out.fr_capoff = (const uint32_t *)(b + L.o_frcapoff);
@@ -544,13 +574,15 @@ static symft_status run_frame_wave(symft_program *h, const DevProg &D, uint64_t 
     int per_cu = frame_wave_max_blocks_per_cu(lds, cnt != nullptr);
     if (per_cu <= 0) per_cu = 1;
     const uint64_t tiles = (n_words + WV_TILE - 1) / WV_TILE;
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)per_cu * num_cus()));
+    uint64_t cap = (uint64_t)per_cu * num_cus();
     WaveArgs A;
     std::memset(&A, 0, sizeof(A));
     A.word_entries = cap_override ? cap_override * D.n_cls : h->L.wv_word_entries;
     A.cap_override = cap_override;
+    const uint64_t per_wg = (uint64_t)WV_TILE * std::max<uint32_t>(1, A.word_entries) * 4;
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
     void *scratch = nullptr;
-    if (pool_alloc(&scratch, (size_t)grid * WV_TILE * std::max<uint32_t>(1, A.word_entries) * 4, st) != hipSuccess)
+    if (pool_alloc(&scratch, (size_t)grid * per_wg, st) != hipSuccess)
         return set_err(SYMFT_ENOMEM, "frame scratch allocation failed");
     A.scratch = (uint32_t *)scratch;
     A.P = D;
@@ -565,14 +597,14 @@ static symft_status run_frame_wave(symft_program *h, const DevProg &D, uint64_t 
     A.lds_bytes = (uint32_t)lds;
     if (cnt) A.cnt = *cnt;
     hipError_t e = launch_frame_wave(A, grid, st);
-    hipFreeAsync(scratch, st);
+    if (scratch) hipFreeAsync(scratch, st);
     if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("frame kernel launch failed: ") + hipGetErrorString(e));
     return SYMFT_OK;
 }
 
-// frame_kernel: 0 automatic (the wave-owned kernel when its LDS fits, else the
-// step-synchronous one), 1 wave-owned, 2 step-synchronous (tile_words 16 / 32
-// or 0 = automatic); tile_words != 0 implies the step-synchronous kernel.
+// frame_kernel: 0 automatic (the step-synchronous kernel when its LDS fits,
+// else the wave-owned one), 1 wave-owned, 2 step-synchronous (tile_words 16 /
+// 32 or 0 = automatic); tile_words != 0 implies the step-synchronous kernel.
 static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_begin, uint64_t n_words, uint64_t shots,
                               uint64_t *out, uint64_t stride, uint32_t sections, uint64_t seed, uint32_t cap_override,
                               hipStream_t st, const CountArgs *cnt = nullptr, uint32_t tile_words = 0,
@@ -583,7 +615,8 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
     if (frame_kernel == 1 && tile_words) return set_err(SYMFT_EINVAL, "frame_tile_words applies to the step kernel only");
     if (frame_kernel == 1 && !D.wv_ok)
         return set_err(SYMFT_ECAPACITY, "the wave-owned frame kernel cannot run this schedule (LDS)");
-    if (frame_kernel == 1 || (frame_kernel == 0 && !tile_words && D.wv_ok))
+    const bool step_fits = frame_lds_bytes(D, 16) <= kLdsLimit;
+    if (frame_kernel == 1 || (frame_kernel == 0 && !tile_words && !step_fits && D.wv_ok))
         return run_frame_wave(h, D, word_begin, n_words, shots, out, stride, sections, seed, cap_override, st, cnt);
     // 32-word tiles halve the barrier steps per word; they need the slots of
     // 32 words in LDS and leave one workgroup per CU, so they are taken only
@@ -596,16 +629,14 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
     if (per_cu <= 0) per_cu = 1;
     uint64_t tiles = (n_words + tw - 1) / tw;
     uint64_t cap = (uint64_t)per_cu * (uint64_t)num_cus();
-    uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
     FrameArgs A;
     std::memset(&A, 0, sizeof(A));
     A.word_entries = cap_override ? cap_override * D.n_cls : h->L.word_entries;
     A.cap_override = cap_override;
-    A.cap = D.fr_cap;
-    A.cap_off = D.fr_capoff;
-    const size_t scratch_bytes = (size_t)grid * frame_scratch_words(A.word_entries, tw) * 8;
+    const uint64_t per_wg = (uint64_t)frame_scratch_words(A.word_entries, tw) * 8;
+    uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
     void *scratch = nullptr;
-    if (pool_alloc(&scratch, scratch_bytes, st) != hipSuccess)
+    if (pool_alloc(&scratch, (size_t)grid * per_wg, st) != hipSuccess)
         return set_err(SYMFT_ENOMEM, "frame scratch allocation failed");
     A.scratch = (uint64_t *)scratch;
     A.P = D;
@@ -620,7 +651,7 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
     A.lds_bytes = (uint32_t)lds;
     if (cnt) A.cnt = *cnt;
     hipError_t e = launch_frame(A, grid, st, tw);
-    hipFreeAsync(scratch, st);
+    if (scratch) hipFreeAsync(scratch, st);
     if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("frame kernel launch failed: ") + hipGetErrorString(e));
     return SYMFT_OK;
 }
@@ -708,7 +739,7 @@ symft_status symft_program_info(const symft_program *p, symft_info *info) {
     info->frame_noise_consumers = p->F.n_flips;
     info->rotations_removed = p->P.rot_removed;
     info->frame_pushes = p->F.n_pushes;
-    info->frame_kernel = p->L.meta.fr_ok ? (p->L.meta.wv_ok ? 1u : 2u) : 0u;
+    info->frame_kernel = p->L.meta.fr_ok ? (frame_lds_bytes(p->L.meta, 16) <= kLdsLimit ? 2u : 1u) : 0u;
     info->frame_wave_batches = p->F.w_n_batches;
     info->frame_wave_flushes = p->F.w_n_flushes;
     for (size_t i = 0; i < p->F.steps.size(); i += FR_STEP_WORDS)

@@ -45,11 +45,17 @@ struct DevChan {
 // frac(t) > log2(1 + D/v) / |log2 q|, which frac(t) >= A / v with
 // A >= D / (ln 2 |log2 q|) implies.  Then G = floor(t).  eps bounds the FP32
 // error of t; draws outside these margins take the exact table search.
+// Near a boundary the computed t is still within one of the exact one, and
+// G >= floor(t) - 1 once v (1 - q) / q > D (the step from R[floor(t) - 1] down
+// to v exceeds the table's rounding loss), so then G = g0 - 2 + #{k in g0 - 1
+// .. g0 + 1 : v < Q[k]} with g0 = floor(t computed): three independent table
+// reads decide the draws the margins leave (vwin: the least v for which this
+// holds; UINT32_MAX when the error bound does not allow it).
 struct GapFast {
     float invlog2q;   // 1 / log2(q)
     float A;          // margin numerator (inflated)
     float eps;        // bound on |t computed - t|
-    uint32_t pad;
+    uint32_t vwin;    // three-read window decision for v >= vwin
     uint64_t qW;      // Q[4096]: v < qW means G = 4096
     uint64_t vmin;    // fast path only for v >= vmin (1, or never when P32 = 2^32)
 };
@@ -81,8 +87,11 @@ struct DevProg {
     const uint32_t *fr_nodes;    // 8 words per node: slot | flags << 24, row, meas, push count, two successor slots, push offset, 0
     const uint32_t *fr_push;     // successor slots
     const uint64_t *fr_chinfo;   // per (class, rank): flip-table offset | J << 26 | uniform << 32 | step << 33 | thr_off << 41
-    const uint64_t *fr_fltab;    // per (channel, branch): its one flip entry, or entry count | first entry << 8
-    const uint64_t *fr_fl3;      // flip entries: cnt << 6 | up to three 16-bit slots from bit 16
+    const uint64_t *fr_frec;     // per (channel, branch): flip record of four entries (32 bytes, 16-byte aligned)
+    const uint64_t *fr_fl3;      // flip entries of branches with more than four: (k - 1) << 6 | four 12-bit slots
+    const uint32_t *fr_ci32;     // per (class, rank): flip-table offset | J << 20 (for the LDS copy)
+    const uint8_t *fr_st8;       // per (class, rank): NOISE step index within the class
+    const uint32_t *cls_Q32;     // n_cls x 4097: Q[g] as 32 bits (Q[0] = 2^32 stored as 2^32 - 1; walks decide g = 0 without it)
     const uint32_t *fr_cap;      // per class: flip entries kept per (word, class)
     const uint32_t *fr_capoff;   // per class + 1: prefix of fr_cap
     // wave-owned pure-frame schedule (sample_frame_wave.hip, launch_args.hpp)
@@ -97,6 +106,9 @@ struct DevProg {
     uint32_t fr_n_steps, fr_n_slots, n_sym, fr_ok;   // fr_ok: the pure-frame kernel can run the program
     uint32_t fr_first_emit, fr_first_emit_n, fr_first_noise_cls, n_am;
     uint32_t wv_n_ops, wv_n_rm, wv_first_noise_cls, wv_first_batch, wv_first_batch_n, wv_ok;
+    uint32_t fr_n_cch;           // entries of fr_ci32 / fr_st8: channels over all classes, padded to a multiple of 16
+    uint32_t fr_ltab;            // nonzero: phase G copies fr_ci32, fr_st8 and cls_Q32 into LDS
+    uint32_t fr_rec_ok;          // nonzero: slots below 2^12, as the step-synchronous kernel's entries need
 };
 
 }  // namespace symft

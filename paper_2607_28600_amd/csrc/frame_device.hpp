@@ -27,7 +27,7 @@ __device__ __forceinline__ GapFast load_fast(const GapFast *p, uint32_t c) {
     f.invlog2q = __uint_as_float(q[0]);
     f.A = __uint_as_float(q[1]);
     f.eps = __uint_as_float(q[2]);
-    f.pad = 0;
+    f.vwin = q[3];
     f.qW = (uint64_t)q[4] | ((uint64_t)q[5] << 32);
     f.vmin = (uint64_t)q[6] | ((uint64_t)q[7] << 32);
     return f;
@@ -54,11 +54,6 @@ __device__ __forceinline__ uint32_t branch_of(const uint64_t *thr, uint64_t info
 struct Walk {
     uint32_t pos, j, e;
 };
-
-// Flip-table word of a (channel, branch): its single flip entry (slot count
-// in bits 6..7, nonzero), or entry count (bits 0..5) | first entry << 8.
-__device__ __forceinline__ bool flip_inline(uint64_t fw) { return ((fw >> 6) & 3u) != 0; }
-__device__ __forceinline__ uint32_t flip_count(uint64_t fw) { return flip_inline(fw) ? 1u : (uint32_t)(fw & 63u); }
 
 // Inclusive prefix sum over the 64 lanes of a wave by DPP: a 4-lane window
 // inside each row of 16 (row shifts 1..3), then banks (row shifts 4 and 8
@@ -109,19 +104,22 @@ __device__ __forceinline__ bool walk_events(const GapFast &F, const uint64_t *Q,
     const uint4 rr = philox4x32_10(make_uint4((jal >> 2) + lane, wlo, c, (1u << 24) | whi), k0, k1);
     int G[4];
     {
-        bool n[4];
         const uint32_t v[4] = {rr.x, rr.y, rr.z, rr.w};
+        bool need[4], act[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const bool a = jal + 4 * lane + i >= st.j;
-            int g = 0;
-            n[i] = a && !gap_fast(F, v[i], g);
-            G[i] = a ? g : -1;
+            act[i] = jal + 4 * lane + i >= st.j;
+            need[i] = act[i] && !gap_fast_select(F, v[i], G[i]);
         }
-        // exact table search for the draws that fell outside the margins
+        // draws the margins leave: three table reads around the computed gap, or (draws smaller than
+        // the window covers) the table search
+        if (__ballot(need[0] || need[1] || need[2] || need[3])) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (n[i]) G[i] = gap_of(Q, F.invlog2q, v[i]);
+            for (int i = 0; i < 4; ++i)
+                if (need[i]) G[i] = v[i] >= F.vwin ? gap_window(Q, v[i], G[i]) : gap_of(Q, F.invlog2q, v[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) G[i] = act[i] ? G[i] : -1;
     }
     uint32_t inc = 0, nev = 0;
 #pragma unroll
@@ -204,6 +202,329 @@ __device__ __forceinline__ bool walk_events(const GapFast &F, const uint64_t *Q,
     st.pos = n_pos;
     st.e = n_e;
     st.j = n_j;
+    return cutR;
+}
+
+// Slot-flip entry of the frame kernels' scratch: shot lane | step index within
+// the class << 6 | slot << 14.
+__device__ __forceinline__ uint32_t flip_entry(uint32_t lane, uint32_t step, uint32_t slot) {
+    return lane | (step << 6) | (slot << 14);
+}
+
+// One walk of the (class c, word w) stream with every event resolved through
+// its channel record (flip-table offset | J << 26 | uniform << 32 | step << 33
+// | threshold offset << 41) and its branch's slot flips (wv_fl: n | slots, or a
+// list in wv_sl).  Every lane loads a channel record (inactive lanes the
+// class's first), so the loads need no branch; non-uniform channels take
+// their threshold search only when some lane has one.
+// GEN: the flips become entries appended at out[*n_out ..] (those past cap
+// are dropped, *n_out still counts them).  Otherwise apply(slot, lane bit) is
+// called for each flip.  Returns whether the walk stopped at R.
+template <bool GEN, typename Apply>
+__device__ __forceinline__ bool walk_resolved(const DevProg &P, const GapFast &F, uint32_t c, uint32_t coff, uint64_t w,
+                                              Walk &st, uint32_t R, uint32_t *tmp, uint32_t *out, uint32_t cap,
+                                              uint32_t *n_out, uint32_t k0, uint32_t k1, Apply apply) {
+    bool ok[4];
+    uint32_t at[4], bv[4];
+    const bool cut = walk_events(F, P.cls_Q + (size_t)c * 4097, c, (uint32_t)w, (uint32_t)(w >> 32), st, R, tmp, k0,
+                                 k1, ok, at, bv);
+    uint64_t info[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) info[i] = P.fr_chinfo[coff + (ok[i] ? at[i] >> 6 : 0u)];
+    uint32_t br[4];
+    bool nonuni = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t J = (uint32_t)(info[i] >> 26) & 0x3Fu;
+        br[i] = (uint32_t)(((uint64_t)bv[i] * J) >> 32);
+        nonuni |= ok[i] && !((info[i] >> 32) & 1u);
+    }
+    if (__ballot(nonuni)) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (ok[i] && !((info[i] >> 32) & 1u)) br[i] = branch_of(P.thr, info[i], bv[i]);
+    }
+    uint64_t fw[4];
+    uint32_t nfl[4], k_lane = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        fw[i] = P.wv_fl[(uint32_t)(info[i] & 0x3FFFFFFu) + br[i]];
+        const uint32_t n = (fw[i] & 3u) ? (uint32_t)(fw[i] & 3u) : (uint32_t)(fw[i] >> 8) & 0xFFFFFFu;
+        nfl[i] = ok[i] ? n : 0u;
+        k_lane += nfl[i];
+    }
+    if (GEN) {
+        // flips of this lane's events go after those of the lanes below it
+        const uint32_t xs = wave_incl_sum(k_lane);
+        const uint32_t ktot = (uint32_t)__builtin_amdgcn_readlane((int)xs, 63);
+        uint32_t o = *n_out + xs - k_lane;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t sh = at[i] & 63u, stp = (uint32_t)(info[i] >> 33) & 0xFFu;
+            if (fw[i] & 3u) {
+#pragma unroll
+                for (uint32_t q = 0; q < 3; ++q)
+                    if (q < nfl[i] && o + q < cap)
+                        out[o + q] = flip_entry(sh, stp, (uint32_t)(fw[i] >> (16 + 16 * q)) & 0xFFFFu);
+            } else if (nfl[i]) {
+                const uint16_t *sl = P.wv_sl + (fw[i] >> 32);
+                for (uint32_t q = 0; q < nfl[i]; ++q)
+                    if (o + q < cap) out[o + q] = flip_entry(sh, stp, sl[q]);
+            }
+            o += nfl[i];
+        }
+        *n_out += ktot;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const unsigned long long bit = 1ull << (at[i] & 63u);
+            if (fw[i] & 3u) {
+#pragma unroll
+                for (uint32_t q = 0; q < 3; ++q)
+                    if (q < nfl[i]) apply((uint32_t)(fw[i] >> (16 + 16 * q)) & 0xFFFFu, bit);
+            } else if (nfl[i]) {
+                const uint16_t *sl = P.wv_sl + (fw[i] >> 32);
+                for (uint32_t q = 0; q < nfl[i]; ++q) apply((uint32_t)sl[q], bit);
+            }
+        }
+    }
+    return cut;
+}
+
+// Tables of the walk.  LT: LDS copies (compact channel records ci32 =
+// flip-table offset | J << 20 of uniform channels, step bytes st8, and the
+// gap table as 32-bit words q32), which phase G keeps in the slot region;
+// otherwise the device program's global tables.
+struct WalkLds {
+    const uint32_t *ci32;
+    const uint8_t *st8;
+    const uint32_t *q32;
+};
+
+// Step-kernel flip entry: shot lane | (k - 1) << 6 | step << 8 | k slots of
+// 12 bits from bit 16 (k = 1..4).
+__device__ __forceinline__ uint32_t entry_slots(uint64_t e) { return ((uint32_t)(e >> 6) & 3u) + 1u; }
+__device__ __forceinline__ uint32_t entry_slot(uint64_t e, uint32_t q) { return (uint32_t)(e >> (16 + 12 * q)) & 0xFFFu; }
+
+// Lean walk of the (class c, word w) stream: the draws, gaps and positions of
+// walk_events, each event resolved through its channel record and branch into
+// its flip record (four pre-packed entries, the count in the first one's lane
+// bits), all four records of a lane loaded together.  Straight-line code
+// except where some lane takes the table search or a branch with more than
+// four entries.  GEN: the entries, tagged with shot lane and step, appended at
+// out[n_out ..] (those past cap dropped, n_out still counts them); otherwise
+// apply(entry) per entry.  Returns whether the walk stopped at R.
+template <bool GEN, bool LT, typename Apply>
+__device__ __forceinline__ bool walk_entries(const DevProg &P, const WalkLds &T, const GapFast &F, uint32_t c,
+                                             uint32_t coff, uint64_t w, Walk &st, uint32_t R, uint32_t *tmp,
+                                             uint64_t *out, uint32_t cap, uint32_t &n_out, uint32_t k0, uint32_t k1,
+                                             Apply apply) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wlo = (uint32_t)w, whi = (uint32_t)(w >> 32);
+    const uint64_t *Q = P.cls_Q + (size_t)c * 4097;
+    const uint32_t jal = st.j & ~3u;
+    const uint4 rr = philox4x32_10(make_uint4((jal >> 2) + lane, wlo, c, (1u << 24) | whi), k0, k1);
+    const uint32_t v[4] = {rr.x, rr.y, rr.z, rr.w};
+    // G[i] = -1: a draw before the stream's position (only lane 0's first draws can be)
+    int G[4];
+    bool need[4], act[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        act[i] = lane != 0 || (uint32_t)i >= st.j - jal;
+        const bool fast = gap_fast_lean(F, v[i], G[i]);
+        need[i] = act[i] & !fast;
+    }
+    if (__ballot(need[0] | need[1] | need[2] | need[3])) {
+        // the window's three table reads for every draw, issued together (indices clamped into the
+        // table), then the draws the window does not cover take the table search
+        uint64_t q[4][3];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int k = min(max(G[i] - 1 + d, 0), 4096);
+                q[i][d] = LT ? (uint64_t)T.q32[(size_t)c * 4097 + k] : Q[k];
+            }
+        bool slow = false;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int g = G[i] - 2;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int k = G[i] - 1 + d;
+                g += (k <= 0 || (k <= 4096 && (uint64_t)v[i] < q[i][d])) ? 1 : 0;
+            }
+            const bool win = v[i] >= F.vwin;
+            G[i] = need[i] && win ? g : G[i];
+            need[i] = need[i] && !win;
+            slow |= need[i];
+        }
+        if (__ballot(slow)) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (need[i]) G[i] = gap_of(Q, F.invlog2q, v[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) G[i] = act[i] ? G[i] : -1;
+    // advance of each draw (0 for inactive ones) and whether it is an event
+    uint32_t adv[4], isev[4], inc = 0, nev = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        isev[i] = (G[i] >= 0 && G[i] < 4096) ? 1u : 0u;
+        adv[i] = G[i] < 0 ? 0u : (G[i] == 4096 ? 4096u : (uint32_t)G[i] + 1u);
+        inc += adv[i];
+        nev += isev[i];
+    }
+    // (events << 23 | advance): a walk advances at most 2^20 positions and finds at most 256 events
+    const uint32_t mine = (nev << 23) | inc;
+    const uint32_t x = wave_incl_sum(mine);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+    const uint32_t ex = x - mine;
+    const uint32_t eb = st.e & ~3u, elim = eb + 256u;
+    // per draw: the stream position before it, its event position and its event index
+    uint32_t base[4], evi[4], cutm = 0;
+    {
+        uint32_t pp = st.pos + (ex & 0x7FFFFFu), ee = st.e + (ex >> 23);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            base[i] = pp;
+            evi[i] = ee;
+            const uint32_t at = pp + (uint32_t)(G[i] < 0 ? 0 : G[i]);
+            cutm |= (isev[i] && (at >= R || ee >= elim)) ? (1u << i) : 0u;
+            ee += isev[i];
+            pp += adv[i];
+        }
+    }
+    const uint32_t ci = cutm ? (uint32_t)__ffs(cutm) - 1u : 0u;  // this lane's first cut draw
+    const uint64_t bal = __ballot(cutm != 0);
+    uint32_t n_pos, n_e, n_j;
+    bool cutR;
+    if (bal) {
+        const uint32_t cl = (uint32_t)(__ffsll((long long)bal) - 1);
+        const uint32_t cp = ci == 0 ? base[0] : ci == 1 ? base[1] : ci == 2 ? base[2] : base[3];
+        const uint32_t ce = ci == 0 ? evi[0] : ci == 1 ? evi[1] : ci == 2 ? evi[2] : evi[3];
+        const int cg = ci == 0 ? G[0] : ci == 1 ? G[1] : ci == 2 ? G[2] : G[3];
+        n_pos = (uint32_t)__builtin_amdgcn_readlane((int)cp, (int)cl);
+        n_e = (uint32_t)__builtin_amdgcn_readlane((int)ce, (int)cl);
+        n_j = jal + 4 * cl + (uint32_t)__builtin_amdgcn_readlane((int)ci, (int)cl);
+        cutR = n_pos + (uint32_t)__builtin_amdgcn_readlane(cg, (int)cl) >= R;
+    } else {
+        n_pos = st.pos + (total & 0x7FFFFFu);
+        n_e = st.e + (total >> 23);
+        n_j = jal + 256;
+        cutR = false;
+    }
+    // positions of the kept events (before the cut), by event index
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (isev[i] && evi[i] < n_e) tmp[evi[i] - eb] = base[i] + (uint32_t)G[i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // branch draws: lane l owns events eb + 4l .. eb + 4l + 3, one Philox block
+    const uint4 bb = philox4x32_10(make_uint4((eb >> 2) + lane, wlo, c, (2u << 24) | whi), k0, k1);
+    const uint32_t bw[4] = {bb.x, bb.y, bb.z, bb.w};
+    bool ok[4];
+    uint32_t at[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t ev = eb + 4 * lane + i;
+        ok[i] = ev >= st.e && ev < n_e;
+        at[i] = tmp[4 * lane + i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    st.pos = n_pos;
+    st.e = n_e;
+    st.j = n_j;
+    // resolve: channel record (inactive lanes read the class's first), branch, flip record index
+    uint32_t fi[4], stp[4];
+    if (LT) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t rk = coff + (ok[i] ? at[i] >> 6 : 0u);
+            const uint32_t ci32 = T.ci32[rk];
+            stp[i] = T.st8[rk];
+            fi[i] = (ci32 & 0xFFFFFu) + (uint32_t)(((uint64_t)bw[i] * (ci32 >> 20)) >> 32);
+        }
+    } else {
+        uint64_t info[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) info[i] = P.fr_chinfo[coff + (ok[i] ? at[i] >> 6 : 0u)];
+        uint32_t br[4];
+        bool nonuni = false;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            br[i] = (uint32_t)(((uint64_t)bw[i] * ((uint32_t)(info[i] >> 26) & 0x3Fu)) >> 32);
+            nonuni |= ok[i] && !((info[i] >> 32) & 1u);
+        }
+        if (__ballot(nonuni)) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (ok[i] && !((info[i] >> 32) & 1u)) br[i] = branch_of(P.thr, info[i], bw[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            fi[i] = (uint32_t)(info[i] & 0x3FFFFFFu) + br[i];
+            stp[i] = (uint32_t)(info[i] >> 33) & 0xFFu;
+        }
+    }
+    // the four flip records of the lane, 32 bytes each, loaded together
+    uint4 ra[4], rb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint4 *rp = (const uint4 *)(P.fr_frec + 4 * (size_t)fi[i]);
+        ra[i] = rp[0];
+        rb[i] = rp[1];
+    }
+    // entries per event: the record's count, or (63) a list's count in its third word
+    uint32_t m[4], k_lane = 0, ovm = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t cnt = ra[i].x & 63u;
+        const bool ov = cnt == 63u;
+        m[i] = ok[i] ? (ov ? rb[i].x : cnt) : 0u;
+        ovm |= (ok[i] && ov) ? (1u << i) : 0u;
+        k_lane += m[i];
+    }
+    const bool lists = __ballot(ovm != 0) != 0;
+    uint32_t o = 0;
+    if (GEN) {
+        const uint32_t xs = wave_incl_sum(k_lane);
+        const uint32_t ktot = (uint32_t)__builtin_amdgcn_readlane((int)xs, 63);
+        o = n_out + xs - k_lane;
+        n_out += ktot;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t tag = (uint64_t)(at[i] & 63u) | ((uint64_t)stp[i] << 8);
+        const uint64_t e[4] = {(((uint64_t)ra[i].y << 32) | ra[i].x) & ~63ull, ((uint64_t)ra[i].w << 32) | ra[i].z,
+                               ((uint64_t)rb[i].y << 32) | rb[i].x, ((uint64_t)rb[i].w << 32) | rb[i].z};
+        const bool in_rec = !((ovm >> i) & 1u);
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            if (in_rec && q < m[i]) {
+                if (GEN) {
+                    if (o + q < cap) out[o + q] = e[q] | tag;
+                } else {
+                    apply(e[q] | tag);
+                }
+            }
+        }
+        if (lists && !in_rec) {
+            const uint64_t *l = P.fr_fl3 + e[1];
+            for (uint32_t q = 0; q < m[i]; ++q) {
+                if (GEN) {
+                    if (o + q < cap) out[o + q] = l[q] | tag;
+                } else {
+                    apply(l[q] | tag);
+                }
+            }
+        }
+        o += m[i];
+    }
     return cutR;
 }
 

@@ -30,23 +30,33 @@
 
 namespace symft {
 
-// Flip entries of one (channel, branch): ceil(n / 3) entries
-// cnt << 6 | s0 << 16 | s1 << 32 | s2 << 48 (cnt = slots in the entry, 1..3).
-// Returns the flip-table word: the entry itself when there is exactly one
-// (bits 6..7 nonzero), else entry count | first entry << 8 (bits 6..7 zero,
-// count < 64), so the common single-entry event needs no second lookup.
-static uint64_t pack_flips(const std::vector<uint32_t> &fl, std::vector<uint64_t> &fl3) {
+// Flip entries of one (channel, branch): ceil(n / 4) entries
+// (k - 1) << 6 | s0 << 16 | s1 << 28 | s2 << 40 | s3 << 52 (k = slots in the
+// entry, 1..4; slots below 2^12, which every schedule that fits the
+// step-synchronous kernel's LDS satisfies).  The branch's flip record holds
+// four such entries, the entry count in the lane bits (0..5) of the first; a
+// branch with more than four entries keeps them in fl3 instead, its record
+// holding 63 (first), the list offset (second) and the entry count (third).
+// The lane and step bits of every stored entry are zero.
+static void pack_record(const std::vector<uint32_t> &fl, std::vector<uint64_t> &rec, std::vector<uint64_t> &fl3) {
     std::vector<uint64_t> es;
-    for (size_t i = 0; i < fl.size(); i += 3) {
-        const size_t cnt = std::min<size_t>(3, fl.size() - i);
-        uint64_t e = (uint64_t)cnt << 6;
-        for (size_t q = 0; q < cnt; ++q) e |= (uint64_t)fl[i + q] << (16 + 16 * q);
+    for (size_t i = 0; i < fl.size(); i += 4) {
+        const size_t cnt = std::min<size_t>(4, fl.size() - i);
+        uint64_t e = (uint64_t)(cnt - 1) << 6;
+        for (size_t q = 0; q < cnt; ++q) e |= (uint64_t)(fl[i + q] & 0xFFFu) << (16 + 12 * q);
         es.push_back(e);
     }
-    if (es.size() == 1) return es[0];
-    const uint64_t off = fl3.size();
-    fl3.insert(fl3.end(), es.begin(), es.end());
-    return (uint64_t)es.size() | (off << 8);
+    uint64_t r[4] = {0, 0, 0, 0};
+    if (es.size() <= 4) {
+        for (size_t q = 0; q < es.size(); ++q) r[q] = es[q];
+        r[0] |= (uint64_t)es.size();
+    } else {
+        r[0] = 63;
+        r[1] = fl3.size();
+        r[2] = es.size();
+        fl3.insert(fl3.end(), es.begin(), es.end());
+    }
+    rec.insert(rec.end(), r, r + 4);
 }
 
 // Elements of odd total multiplicity in a and b: the sum over GF(2) of two
@@ -316,16 +326,42 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
         F.max_level = std::max<uint32_t>(F.max_level, (uint32_t)level.size());
         level.clear();
     };
+    // Channels wait (pending) until a node that reads one of them arrives: a
+    // class's stream is consumed in rank order, so the pending channels of a
+    // class are a contiguous rank range, and nodes that read none of them
+    // (detectors, records of other qubits) join the open level.  When a node
+    // reads a pending channel, the open level is emitted and the NOISE steps
+    // follow -- unless no node of the level takes any contribution (random
+    // outcomes with nothing added): such a level holds no slots, so it stays
+    // open behind the NOISE steps, which its nodes do not read.
+    std::vector<int32_t> sym_chan_of(P.n_noise_sym, -1);
+    for (uint32_t c = 0; c < P.chans.size(); ++c)
+        for (uint32_t k = 0; k < P.chans[c].nsym; ++k) sym_chan_of[P.chans[c].sym0 + k] = (int32_t)c;
+    std::vector<uint8_t> pending(P.chans.size(), 0);
+    auto flush_pending = [&]() {
+        for (uint32_t c : seg_chans) pending[c] = 0;
+        flush_noise();
+    };
     for (const Item &it : items) {
         if (it.kind == 0) {
-            flush_level();
             const Channel &ch = P.chans[it.id];
             auto f = seg.find((uint32_t)ch.cls);
             if (f == seg.end()) seg[(uint32_t)ch.cls] = {(uint32_t)ch.rank, (uint32_t)ch.rank + 1};
             else f->second.second = (uint32_t)ch.rank + 1;
             seg_chans.push_back(it.id);
+            pending[it.id] = 1;
         } else {
-            flush_noise();
+            bool reads = false;
+            for (uint32_t sy : nd[it.id].noise) {
+                const int32_t c = sym_chan_of[sy];
+                reads |= c >= 0 && pending[(size_t)c];
+            }
+            if (reads) {
+                bool holds = false;
+                for (uint32_t u : level) holds |= !nd[u].preds.empty() || !nd[u].noise.empty();
+                if (holds) flush_level();
+                flush_pending();
+            }
             bool dep = false;
             for (uint32_t u : nd[it.id].preds) dep |= in_level[u] != 0;
             if (dep && !fold(nd[it.id])) flush_level();
@@ -333,8 +369,8 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             in_level[it.id] = 1;
         }
     }
-    flush_noise();
     flush_level();
+    flush_pending();
     for (uint32_t i = 0; i < NN; ++i)
         for (uint32_t u : nd[i].preds) nd[u].succs.push_back(i);
 
@@ -376,6 +412,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
     }
     F.n_slots = n_slots;
     if (n_slots >= (1u << 16)) return;  // flip entries hold 16-bit slots
+    F.rec_ok = n_slots < (1u << 12);  // the step kernel's entries hold 12-bit slots
     // noise symbol -> consumer slots; (channel, branch) -> slots flipped
     std::vector<std::vector<uint32_t>> cons(P.n_noise_sym);
     for (uint32_t i = 0; i < NN; ++i)
@@ -388,7 +425,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
         const Channel &ch = P.chans[c];
         chan_thr[c] = thr_off;
         thr_off += ch.thr.size();
-        chan_fl[c] = F.fltab.size();
+        chan_fl[c] = F.frec.size() / 4;
         for (uint32_t j = 0; j < ch.J; ++j) {
             std::map<uint32_t, int> par;
             for (uint32_t i = 0; i < ch.nsym; ++i)
@@ -398,8 +435,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             for (auto &kv : par)
                 if (kv.second) fl.push_back(kv.first);
             F.n_flips += fl.size();
-            if ((fl.size() + 2) / 3 > 63) return;  // flip-table words hold 6-bit entry counts
-            F.fltab.push_back(pack_flips(fl, F.fl3));
+            pack_record(fl, F.frec, F.fl3);
             if (fl.size() <= 3 && !fl.empty()) {
                 uint64_t w = fl.size();
                 for (size_t q = 0; q < fl.size(); ++q) w |= (uint64_t)fl[q] << (16 + 16 * q);
@@ -414,7 +450,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
                 const double lo = j ? (double)ch.thr[j - 1] : 0.0;
                 pj = ((double)ch.thr[j] - lo) / 4294967296.0;
             }
-            const double k = (double)((fl.size() + 2) / 3);
+            const double k = (double)((fl.size() + 3) / 4);
             chan_k1[c] += pj * k;
             chan_k2[c] += pj * k * k;
             const double f = (double)fl.size();
@@ -433,6 +469,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             for (uint32_t r = st.r0; r < st.r1; ++r) chan_step_local[(size_t)P.classes[st.cls].chans[r]] = sl;
         }
     }
+    F.ltab_ok = true;
     // channel record per (class, rank): flip-table offset | J << 26 | uniform << 32 |
     // step index << 33 | threshold offset << 41; per-class flip-entry capacity per
     // word: the expected count plus 8 standard deviations (compound Poisson) plus 64
@@ -443,6 +480,10 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             const Channel &ch = P.chans[(size_t)c];
             F.chinfo.push_back(chan_fl[(size_t)c] | ((uint64_t)ch.J << 26) | ((uint64_t)ch.uniform << 32) |
                                ((uint64_t)chan_step_local[(size_t)c] << 33) | (chan_thr[(size_t)c] << 41));
+            // compact record for the LDS copy of the walk tables: flip-table offset | J << 20
+            F.ltab_ok = F.ltab_ok && ch.uniform && chan_fl[(size_t)c] < (1u << 20) && ch.J < 64;
+            F.ci32.push_back((uint32_t)(chan_fl[(size_t)c] & 0xFFFFFu) | ((uint32_t)ch.J << 20));
+            F.st8.push_back((uint8_t)chan_step_local[(size_t)c]);
             m1 += 64.0 * p * chan_k1[(size_t)c];
             m2 += 64.0 * p * chan_k2[(size_t)c];
             f1 += 64.0 * p * chan_f1[(size_t)c];
@@ -454,6 +495,9 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
         const double wcap = std::ceil((f1 + 8.0 * std::sqrt(f2) + 64.0) / 64.0) * 64.0;
         F.wcap.push_back((uint32_t)std::min(wcap, 16777216.0));
     }
+    // the LDS copy moves whole 16-byte units: both compact arrays padded to a multiple of 16 channels
+    F.ci32.resize((F.ci32.size() + 15) & ~(size_t)15, 0u);
+    F.st8.resize(F.ci32.size(), 0u);
     // encode steps (FR_STEP_WORDS per step, see launch_args.hpp) and node records
     std::vector<uint32_t> first_node(steps.size(), 0);
     uint32_t nodes_so_far = 0;

@@ -68,10 +68,8 @@ struct FrameArgs {
     uint64_t shots;
     uint64_t *out;
     uint64_t row_stride;
-    uint64_t *scratch;        // per workgroup: flip entries [16 words][sum of class capacities], fallback walk positions
-    const uint32_t *cap;      // per class: flip entries kept per word (device)
-    const uint32_t *cap_off;  // per class: offset of the class within a word's region (device)
-    uint32_t word_entries;    // sum of class capacities
+    uint64_t *scratch;        // per workgroup: flip entries [TW words][sum of class capacities], fallback walk positions
+    uint32_t word_entries;    // sum of class capacities (flip entries per word)
     uint32_t cap_override;    // nonzero: every class keeps this many entries (offsets c * cap_override)
     uint32_t sections;
     uint32_t store16;         // output rows may be stored 16 bytes at a time
@@ -117,7 +115,7 @@ struct WaveArgs {
 // successors in the push list, 0.
 enum FrameStepKind : uint32_t { FR_NOISE = 1, FR_EMIT = 2 };
 static const uint32_t FR_NO_ROW = 0xFFFFFFFFu;
-static const uint32_t FR_LEVEL_MAX = 128;  // nodes per EMIT step: one (node, 4 words) per thread of 8 waves
+static const uint32_t FR_LEVEL_MAX = 256;  // nodes per EMIT step: two (node, 4 words) tasks per thread
 static const uint32_t FR_STEP_WORDS = 8;
 static const uint32_t FR_NONE = 0xFFFFFFFFu;
 
@@ -148,9 +146,13 @@ struct FrameSchedule {
     std::vector<uint32_t> nodes;    // 8 per node
     std::vector<uint32_t> push;
     std::vector<uint64_t> chinfo;   // indexed by class offset + rank
-    std::vector<uint64_t> fltab;    // per (channel, branch): its one flip entry, or entry count | first entry << 8
-    std::vector<uint64_t> fl3;      // flip entries: cnt << 6 | three 16-bit slots from bit 16
+    std::vector<uint64_t> frec;     // per (channel, branch): flip record, four entries (see pack_record)
+    std::vector<uint64_t> fl3;      // flip entries of branches with more than four: (k - 1) << 6 | four 12-bit slots
+    bool rec_ok = false;            // slots below 2^12 (the step kernel's entries)
     std::vector<uint32_t> cls_cap;  // flip entries kept per (word, class)
+    std::vector<uint32_t> ci32;     // per (class, rank): flip-table offset | J << 20 (uniform channels)
+    std::vector<uint8_t> st8;       // per (class, rank): NOISE step index within the class
+    bool ltab_ok = false;           // every channel uniform, flip-table offsets below 2^20
     uint32_t n_slots = 0;
     size_t n_steps = 0;
     uint32_t max_level = 0;

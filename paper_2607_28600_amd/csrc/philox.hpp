@@ -45,6 +45,51 @@ __device__ __forceinline__ int gap_of(const uint64_t *__restrict__ Q, float invl
     return lo;
 }
 
+// The same decision without branches (every lane evaluates every term, so a
+// wave decides its 4 x 64 draws in straight-line code): G is the gap and the
+// result says whether the margins decided it; lanes it does not decide take
+// the table search.
+__device__ __forceinline__ bool gap_fast_select(const GapFast &F, uint32_t v, int &G) {
+    const float vf = (float)v;
+    const float t = __log2f(vf * 2.3283064365386963e-10f) * F.invlog2q;
+    const int g0 = (int)t;
+    const float fr = t - (float)g0;
+    const bool margin = fr >= F.A * __builtin_amdgcn_rcpf(vf) + F.eps && fr < 1.0f - F.eps;
+    const bool below = (uint64_t)v < F.qW;
+    const bool ok = (uint64_t)v >= F.vmin && g0 < 4096 && margin;
+    G = below ? 4096 : g0;
+    return below || ok;
+}
+
+// The decision the walks take: gap_fast_select with the margin test
+// frac(t) >= A / v + eps rewritten as frac(t) v >= A + eps v (no reciprocal;
+// the rounding of the two products is far inside the 1.25 inflation of A).
+// Draws of 0 fail it (0 >= A), which the table then decides.
+__device__ __forceinline__ bool gap_fast_lean(const GapFast &F, uint32_t v, int &G) {
+    const float vf = (float)v;
+    const float t = __log2f(vf * 2.3283064365386963e-10f) * F.invlog2q;
+    const int g0 = (int)t;
+    const float fr = t - (float)g0;
+    const bool margin = fr * vf >= __builtin_fmaf(F.eps, vf, F.A) && fr < 1.0f - F.eps;
+    const bool below = (uint64_t)v < F.qW;
+    const bool ok = (uint64_t)v >= F.vmin && g0 < 4096 && margin;
+    G = below ? 4096 : g0;
+    return below || ok;
+}
+
+// G from the computed g0 = floor(t) by the window rule of GapFast (v >= vwin):
+// Q[k] for k < 0 counts as above every draw, for k > 4096 as 0.
+__device__ __forceinline__ int gap_window(const uint64_t *__restrict__ Q, uint32_t v, int g0) {
+    int G = g0 - 2;
+#pragma unroll
+    for (int d = -1; d <= 1; ++d) {
+        const int k = g0 + d;
+        const uint64_t q = k < 0 ? ~0ull : k > 4096 ? 0ull : Q[k];
+        G += (uint64_t)v < q ? 1 : 0;
+    }
+    return G;
+}
+
 __device__ __forceinline__ bool gap_fast(const GapFast &F, uint32_t v, int &G) {
     if ((uint64_t)v < F.qW) {
         G = 4096;

@@ -10,9 +10,14 @@
 //    draw contract -- walks of 64 lanes x 4 gap draws decided without the
 //    table except near a boundary, a 32-bit wave scan turning gaps into
 //    positions, one branch-draw Philox block per lane -- and turn each event
-//    into its pre-packed flip entries (shot lane, NOISE step, up to three
-//    slots), written in stream order to the workgroup's scratch, which stays
-//    in L2 / the Infinity Cache;
+//    into its pre-packed flip entries (shot lane, NOISE step, up to four
+//    12-bit slots each; a branch's entries sit in one 32-byte flip record, so
+//    a lane loads the records of its four events together), written in
+//    stream order to the workgroup's scratch, which stays in L2 / the
+//    Infinity Cache.  The slot region is free in this phase: when they fit,
+//    it holds LDS copies of the walk's tables (32-bit gap table, compact
+//    channel records, step bytes), which leaves the flip records as the
+//    walk's only global loads, and is cleared again before phase S;
 //  * phase S: the push-based schedule (launch_args.hpp), a barrier after
 //    every step.  NOISE: each wave streams its words' entries of the step and
 //    XORs the lane bits into the slots.  EMIT: lanes take (node, 4 words),
@@ -29,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "frame_device.hpp"
 #include "launch_args.hpp"
@@ -38,15 +44,16 @@ namespace symft {
 
 // Tile shape, by tile width TW (16 or 32 words): TW / 2 waves, each walking
 // two words in phase G and streaming two words' entries in NOISE steps; an
-// EMIT step gives each thread one (node, 4 words) of up to FR_LEVEL_MAX nodes.
+// EMIT step of up to FR_LEVEL_MAX nodes gives each thread two (node, 4 words)
+// tasks, q and q + the thread count.
 template <uint32_t TW>
 struct Tile {
     static_assert(TW == 16 || TW == 32, "tile of 16 or 32 words");
     static constexpr uint32_t NWC = TW / 2;                    // waves
+    static constexpr uint32_t NT = NWC * 64;                   // threads
     static constexpr uint32_t WPW = TW / NWC;                  // words per wave in NOISE steps
     static constexpr uint32_t QPN = TW / 4;                    // word quads per node
-    static constexpr uint32_t STG_WORDS = FR_LEVEL_MAX * TW;   // staged u64
-    static_assert(FR_LEVEL_MAX * QPN == NWC * 64, "one (node, 4 words) per thread");
+    static_assert(FR_LEVEL_MAX * QPN == 2 * NT, "two (node, 4 words) tasks per thread");
 };
 
 // Slot array: slot s holds the tile's TW words at s * TW + (w ^ (s & (TW - 1))).
@@ -63,15 +70,15 @@ __device__ __forceinline__ unsigned long long *slot_quad(unsigned long long *slo
     return &slots[(size_t)s * TW + (wl ^ (s & (TW - 4)))];
 }
 
-// Flip entry: lane | cnt << 6 | step << 8 | s0 << 16 | s1 << 32 | s2 << 48,
+// Flip entry (lane | (k - 1) << 6 | step << 8 | k 12-bit slots from bit 16)
 // applied to word wl of the tile.
 template <uint32_t TW>
 __device__ __forceinline__ void apply_entry(uint64_t e, unsigned long long *slots, uint32_t wl) {
     const unsigned long long bit = 1ull << (e & 63u);
-    const uint32_t cnt = (uint32_t)(e >> 6) & 3u;
-    atomicXor(slot_word<TW>(slots, (uint32_t)(e >> 16) & 0xFFFFu, wl), bit);
-    if (cnt > 1) atomicXor(slot_word<TW>(slots, (uint32_t)(e >> 32) & 0xFFFFu, wl), bit);
-    if (cnt > 2) atomicXor(slot_word<TW>(slots, (uint32_t)(e >> 48), wl), bit);
+    const uint32_t k = entry_slots(e);
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q)
+        if (q < k) atomicXor(slot_word<TW>(slots, entry_slot(e, q), wl), bit);
 }
 
 // XOR v[0 .. 3] into words wl .. wl + 3 of slot s.
@@ -83,193 +90,19 @@ __device__ __forceinline__ void push_quad(unsigned long long *slots, uint32_t s,
     for (uint32_t i = 0; i < 4; ++i) atomicXor(d + (i ^ x), v[i]);
 }
 
-// The program tables a walk reads (passed by value, so an out-of-line walk
-// needs no copy of the whole program descriptor).
-struct WalkTabs {
-    const uint64_t *chinfo, *fltab, *fl3, *thr;
-};
-
-__device__ __forceinline__ WalkTabs walk_tabs(const DevProg &P) { return WalkTabs{P.fr_chinfo, P.fr_fltab, P.fr_fl3, P.thr}; }
-
-// One walk of the stream (class c, word w): the 256 gap draws from st.j
-// (aligned down to a Philox block), cut before the first event at a position
-// >= R or with an index past the 64 branch blocks that start at st.e & ~3.
-// tmp (256 words, private to the wave) carries event positions between the
-// two phases.  Each event becomes its flip entries: GEN appends them to
-// out[*n_out ...] (those past `cap` are dropped, *n_out still counts them);
-// otherwise they are applied to the word's slot column.  Returns whether the
-// walk stopped at R.
-template <uint32_t TW, bool GEN>
-__device__ __forceinline__ bool walk(const WalkTabs &T, const GapFast &F, const uint64_t *Q, uint32_t c, uint32_t coff, uint32_t wlo,
-                     uint32_t whi, Walk &st, uint32_t R, uint32_t *tmp, uint64_t *out, uint32_t cap,
-                     uint32_t *n_out, unsigned long long *slots, uint32_t wl, uint32_t k0, uint32_t k1) {
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t jal = st.j & ~3u;
-    const uint4 rr = philox4x32_10(make_uint4((jal >> 2) + lane, wlo, c, (1u << 24) | whi), k0, k1);
-    int G0, G1, G2, G3;
-    bool n0, n1, n2, n3;
-    {
-        const uint32_t jl = jal + 4 * lane;
-        const bool a0 = jl + 0 >= st.j, a1 = jl + 1 >= st.j, a2 = jl + 2 >= st.j, a3 = jl + 3 >= st.j;
-        int g0 = 0, g1 = 0, g2 = 0, g3 = 0;
-        n0 = a0 && !gap_fast(F, rr.x, g0);
-        n1 = a1 && !gap_fast(F, rr.y, g1);
-        n2 = a2 && !gap_fast(F, rr.z, g2);
-        n3 = a3 && !gap_fast(F, rr.w, g3);
-        G0 = a0 ? g0 : -1;
-        G1 = a1 ? g1 : -1;
-        G2 = a2 ? g2 : -1;
-        G3 = a3 ? g3 : -1;
-    }
-    // exact table search for the draws that fell outside the margins
-    while (n0 || n1 || n2 || n3) {
-        const uint32_t v = n0 ? rr.x : n1 ? rr.y : n2 ? rr.z : rr.w;
-        const int g = gap_of(Q, F.invlog2q, v);
-        if (n0) {
-            G0 = g;
-            n0 = false;
-        } else if (n1) {
-            G1 = g;
-            n1 = false;
-        } else if (n2) {
-            G2 = g;
-            n2 = false;
-        } else {
-            G3 = g;
-            n3 = false;
-        }
-    }
-    const int G[4] = {G0, G1, G2, G3};
-    uint32_t inc = 0, nev = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (G[i] >= 0) {
-            inc += G[i] == 4096 ? 4096u : (uint32_t)G[i] + 1u;
-            nev += G[i] < 4096 ? 1u : 0u;
-        }
-    }
-    // (events << 23 | advance): a walk advances at most 2^20 positions and finds at most 256 events
-    const uint32_t mine = (nev << 23) | inc;
-    const uint32_t x = wave_incl_sum(mine);
-    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-    const uint32_t ex = x - mine;
-    const uint32_t p = st.pos + (ex & 0x7FFFFFu), e = st.e + (ex >> 23);
-    const uint32_t eb = st.e & ~3u, elim = eb + 256u;
-    int cut_i = 4;
-    uint32_t cut_p = 0, cut_e = 0, cut_r = 0;
-    {
-        uint32_t pp = p, ee = e;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (G[i] >= 0) {
-                if (G[i] < 4096 && cut_i == 4 && (pp + (uint32_t)G[i] >= R || ee >= elim)) {
-                    cut_i = i;
-                    cut_p = pp;
-                    cut_e = ee;
-                    cut_r = pp + (uint32_t)G[i] >= R ? 1u : 0u;
-                }
-                if (G[i] < 4096) ++ee;
-                pp += G[i] == 4096 ? 4096u : (uint32_t)G[i] + 1u;
-            }
-        }
-    }
-    const uint64_t bal = __ballot(cut_i < 4);
-    const uint32_t cut_lane = bal ? (uint32_t)(__ffsll((long long)bal) - 1) : 64u;
-    uint32_t n_pos, n_e, n_j;
-    bool cutR;
-    if (cut_lane < 64) {
-        n_pos = (uint32_t)__builtin_amdgcn_readlane((int)cut_p, (int)cut_lane);
-        n_e = (uint32_t)__builtin_amdgcn_readlane((int)cut_e, (int)cut_lane);
-        n_j = jal + 4 * cut_lane + (uint32_t)__builtin_amdgcn_readlane(cut_i, (int)cut_lane);
-        cutR = __builtin_amdgcn_readlane((int)cut_r, (int)cut_lane) != 0;
-    } else {
-        n_pos = st.pos + (total & 0x7FFFFFu);
-        n_e = st.e + (total >> 23);
-        n_j = jal + 256;
-        cutR = false;
-    }
-    // positions of the kept events, by event index
-    {
-        uint32_t pp = p, ee = e;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (G[i] >= 0) {
-                const bool before = lane < cut_lane || (lane == cut_lane && i < cut_i);
-                if (before && G[i] < 4096) tmp[ee - eb] = pp + (uint32_t)G[i];
-                if (G[i] < 4096) ++ee;
-                pp += G[i] == 4096 ? 4096u : (uint32_t)G[i] + 1u;
-            }
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // branch draws: lane l owns events eb + 4l .. eb + 4l + 3, one Philox block
-    const uint4 bb = philox4x32_10(make_uint4((eb >> 2) + lane, wlo, c, (2u << 24) | whi), k0, k1);
-    uint64_t fw[4], tag[4];
-    uint32_t k_lane = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < 4; ++i) {
-        const uint32_t ev = eb + 4 * lane + i;
-        fw[i] = 0;
-        tag[i] = 0;
-        if (ev >= st.e && ev < n_e) {
-            const uint32_t at = tmp[4 * lane + i];
-            const uint64_t info = T.chinfo[coff + (at >> 6)];
-            const uint32_t fi = (uint32_t)(info & 0x3FFFFFFu) + branch_of(T.thr, info, pick4(bb, i));
-            fw[i] = T.fltab[fi];
-            tag[i] = (uint64_t)(at & 63u) | (((info >> 33) & 0xFFu) << 8);
-            k_lane += flip_count(fw[i]);
-        }
-    }
-    if (GEN) {
-        // entries of this lane's events go after those of the lanes below it
-        const uint32_t xs = wave_incl_sum(k_lane);
-        const uint32_t ktot = (uint32_t)__builtin_amdgcn_readlane((int)xs, 63);
-        uint32_t o = *n_out + xs - k_lane;
-#pragma unroll
-        for (uint32_t i = 0; i < 4; ++i) {
-            if (flip_inline(fw[i])) {
-                if (o < cap) out[o] = fw[i] | tag[i];
-                ++o;
-                continue;
-            }
-            const uint32_t k = flip_count(fw[i]);
-            const uint64_t f0 = fw[i] >> 8;
-            for (uint32_t q = 0; q < k; ++q, ++o)
-                if (o < cap) out[o] = T.fl3[f0 + q] | tag[i];
-        }
-        *n_out += ktot;
-    } else {
-#pragma unroll
-        for (uint32_t i = 0; i < 4; ++i) {
-            if (flip_inline(fw[i])) {
-                apply_entry<TW>(fw[i] | tag[i], slots, wl);
-                continue;
-            }
-            const uint32_t k = flip_count(fw[i]);
-            const uint64_t f0 = fw[i] >> 8;
-            for (uint32_t q = 0; q < k; ++q) apply_entry<TW>(T.fl3[f0 + q] | tag[i], slots, wl);
-        }
-    }
-    st.pos = n_pos;
-    st.e = n_e;
-    st.j = n_j;
-    return cutR;
-}
-
-
 // Walk the word's class stream up to the end R of this step, applying events at once.
 template <uint32_t TW>
-__device__ __forceinline__ void noise_direct(WalkTabs T, GapFast F, const uint64_t *Q, uint32_t c, uint32_t coff,
-                                          uint32_t R, uint64_t w, FrWord *S, uint32_t *tmp, unsigned long long *slots,
-                                          uint32_t wl,
-                                          uint32_t k0, uint32_t k1) {
+__device__ __forceinline__ void noise_direct(const DevProg &P, uint32_t c, uint32_t R, uint64_t w, FrWord *S,
+                                             uint32_t *tmp, unsigned long long *slots, uint32_t wl, uint32_t k0,
+                                             uint32_t k1) {
     Walk st = {rfl(S->pos), rfl(S->j), rfl(S->e)};
     if (st.pos >= R) return;
-    while (!walk<TW, false>(T, F, Q, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st, R, tmp, nullptr, 0, nullptr, slots, wl,
-                        k0, k1) &&
-           st.pos < R) {
+    const GapFast F = load_fast(P.cls_fast, c);
+    const uint32_t coff = uniform(P.cls_off)[c];
+    auto flip = [slots, wl](uint64_t e) { apply_entry<TW>(e, slots, wl); };
+    uint32_t none = 0;
+    const WalkLds T = {nullptr, nullptr, nullptr};
+    while (!walk_entries<false, false>(P, T, F, c, coff, w, st, R, tmp, nullptr, 0, none, k0, k1, flip) && st.pos < R) {
     }
     if ((threadIdx.x & 63u) == 0) {
         S->pos = st.pos;
@@ -278,17 +111,15 @@ __device__ __forceinline__ void noise_direct(WalkTabs T, GapFast F, const uint64
     }
 }
 
-// One (node, 4 words) of an EMIT step: the four slot words are read and
-// cleared, the node's constant and RandomMeas words added, the values staged
-// for the next step's stores (with the node's row, or FR_NO_ROW when the row
-// is not written) and XOR-ed into the successors' slots.  Thread q always
-// stages at the same place, so it stores the previous step's chunk and
-// stages the next one in program order without a second buffer.
+// One (node, 4 words) task of an EMIT step: the four slot words are read and
+// cleared, the node's constant and RandomMeas words added, the 32 bytes of its
+// row stored (the node's QPN tasks are adjacent threads, so a row of the tile
+// goes out as whole lines) and the values XOR-ed into the successors' slots.
 template <uint32_t TW>
 __device__ __forceinline__ void emit_quad(const DevProg &P, const FrameArgs &A, uint4 ra, uint4 rb, uint32_t q,
-                                          uint64_t wt, unsigned long long *slots, unsigned long long *stg,
-                                          uint32_t *rows, unsigned long long *fl, uint32_t k0, uint32_t k1) {
-    const uint32_t vi = q / Tile<TW>::QPN, wl = 4 * (q % Tile<TW>::QPN);
+                                          uint64_t wt, bool full, unsigned long long *slots, unsigned long long *fl,
+                                          uint32_t k0, uint32_t k1) {
+    const uint32_t wl = 4 * (q % Tile<TW>::QPN);
     const uint32_t flags = ra.x >> 24;
     const unsigned long long c = (flags & 1u) ? ~0ull : 0ull;
     unsigned long long v[4] = {c, c, c, c};
@@ -315,10 +146,10 @@ __device__ __forceinline__ void emit_quad(const DevProg &P, const FrameArgs &A, 
             v[3] = t;
         }
     }
+    const uint32_t sec = (flags >> 4) & 3u;
     if (A.cnt.on) {
         // aggregate counts: a postselected detector ORs into the discarded
         // flags, an observable (XOR its expected value) into the logical ones
-        const uint32_t sec = (flags >> 4) & 3u;
         if (sec == 2u) {
             const uint32_t d = ra.y - P.n_rec;
             if ((A.cnt.post[d >> 5] >> (d & 31u)) & 1u) {
@@ -331,13 +162,29 @@ __device__ __forceinline__ void emit_quad(const DevProg &P, const FrameArgs &A, 
 #pragma unroll
             for (uint32_t i = 0; i < 4; ++i) atomicOr(&fl[TW + wl + i], v[i] ^ x);
         }
-    }
-    ((ulonglong2 *)&stg[vi * TW + wl])[0] = make_ulonglong2(v[0], v[1]);
-    ((ulonglong2 *)&stg[vi * TW + wl])[1] = make_ulonglong2(v[2], v[3]);
-    {
-        // every lane of the node writes the same row index
-        const uint32_t sec = (flags >> 4) & 3u;
-        rows[vi] = (ra.y != FR_NO_ROW && sec && ((A.sections >> (sec - 1)) & 1u)) ? ra.y : FR_NO_ROW;
+    } else if (ra.y != FR_NO_ROW && sec && ((A.sections >> (sec - 1)) & 1u)) {
+        const uint64_t wi = wt + wl;
+        unsigned long long *dst = (unsigned long long *)A.out + (uint64_t)ra.y * A.row_stride + wi;
+        if (full) {
+            // every word of the tile is whole and 16-byte stores are allowed
+            ((ulonglong2 *)dst)[0] = make_ulonglong2(v[0], v[1]);
+            ((ulonglong2 *)dst)[1] = make_ulonglong2(v[2], v[3]);
+        } else {
+#pragma unroll
+            for (uint32_t h = 0; h < 2; ++h) {
+                const uint64_t wh = wi + 2 * h;
+                if (wh < A.n_words) {
+                    const unsigned long long m0 = word_mask(wh, A.shots), m1 = word_mask(wh + 1, A.shots);
+                    unsigned long long *d = dst + 2 * h;
+                    if (A.store16 && wh + 1 < A.n_words) {
+                        *(ulonglong2 *)d = make_ulonglong2(v[2 * h] & m0, v[2 * h + 1] & m1);
+                    } else {
+                        d[0] = v[2 * h] & m0;
+                        if (wh + 1 < A.n_words) d[1] = v[2 * h + 1] & m1;
+                    }
+                }
+            }
+        }
     }
     const uint32_t np = ra.w;
     if (np > 0) push_quad<TW>(slots, rb.x, wl, v);
@@ -345,57 +192,51 @@ __device__ __forceinline__ void emit_quad(const DevProg &P, const FrameArgs &A, 
     for (uint32_t k = 2; k < np; ++k) push_quad<TW>(slots, P.fr_push[rb.z + k - 2], wl, v);
 }
 
-// One 32-byte chunk (node q / 4, words 4 (q % 4) .. + 3) of the rows staged
-// by an EMIT step.
-template <uint32_t TW>
-__device__ __forceinline__ void store_chunk(const FrameArgs &A, const unsigned long long *stg, const uint32_t *rows,
-                                            uint32_t q, uint64_t wt, bool full) {
-    const uint32_t v = q / Tile<TW>::QPN, pw = 4 * (q % Tile<TW>::QPN);
-    const uint32_t row = rows[v];
-    const uint64_t wi = wt + pw;
-    const ulonglong2 *src = (const ulonglong2 *)&stg[v * TW + pw];
-    if (full) {
-        // every word of the tile is whole and 16-byte stores are allowed
-        if (row == FR_NO_ROW) return;
-        ulonglong2 *dst = (ulonglong2 *)((unsigned long long *)A.out + (uint64_t)row * A.row_stride + wi);
-        const ulonglong2 a = src[0], b = src[1];
-        dst[0] = a;
-        dst[1] = b;
-        return;
-    }
-    if (row == FR_NO_ROW) return;
-#pragma unroll
-    for (uint32_t h = 0; h < 2; ++h) {
-        const uint64_t wh = wi + 2 * h;
-        if (wh >= A.n_words) return;
-        const ulonglong2 val = src[h];
-        const unsigned long long m0 = word_mask(wh, A.shots), m1 = word_mask(wh + 1, A.shots);
-        unsigned long long *dst = (unsigned long long *)A.out + (uint64_t)row * A.row_stride + wh;
-        if (A.store16 && wh + 1 < A.n_words) {
-            *(ulonglong2 *)dst = make_ulonglong2(val.x & m0, val.y & m1);
-        } else {
-            dst[0] = val.x & m0;
-            if (wh + 1 < A.n_words) dst[1] = val.y & m1;
+// Phase G of one tile: each wave walks the streams of its words, class by
+// class, into the workgroup's scratch; a stream past its capacity marks its
+// word for the fallback.  LT: the walk tables are in LDS (T).
+template <uint32_t TW, bool LT>
+__device__ __forceinline__ void phase_g(const DevProg &P, const FrameArgs &A, const WalkLds &T, uint64_t wt,
+                                        uint64_t *scr, uint32_t *tmp, uint32_t *cnt, uint32_t *ovf, uint32_t k0,
+                                        uint32_t k1) {
+    constexpr uint32_t NWC = Tile<TW>::NWC;
+    const uint32_t NC = P.n_cls, wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    for (uint32_t wl = wave; wl < TW && wt + wl < A.n_words; wl += NWC) {
+        const uint64_t w = A.word_begin + wt + wl;
+        bool over = false;
+        for (uint32_t c = 0; c < NC && !over; ++c) {
+            const uint32_t coff = uniform(P.cls_off)[c], cend = (uniform(P.cls_off)[c + 1] - coff) * 64u;
+            const GapFast F = load_fast(P.cls_fast, c);
+            const uint32_t cap = A.cap_override ? A.cap_override : uniform(P.fr_cap)[c];
+            uint64_t *out =
+                scr + (size_t)wl * A.word_entries + (A.cap_override ? c * A.cap_override : uniform(P.fr_capoff)[c]);
+            Walk st = {0, 0, 0};
+            uint32_t n = 0;
+            auto none = [](uint64_t) {};
+            while (!walk_entries<true, LT>(P, T, F, c, coff, w, st, cend, tmp, out, cap, n, k0, k1, none) &&
+                   st.pos < cend && n <= cap) {
+            }
+            over = n > cap;
+            if (lane == 0) cnt[wl * NC + c] = n;
         }
+        if (lane == 0 && over) ovf[wl] = 1;
     }
 }
 
 // Workgroup: TW / 2 waves.  LDS: slots [NS][TW] u64 | stream states [TW][NC] |
 // entry cursors and counts [TW][NC] | overflow flags [TW] | aggregate-count
-// flags [2][TW] u64 (discarded, logical error) | one region used by
-// phase G as walk positions [NWC][256] and by phase S as the staging buffer
-// ([FR_LEVEL_MAX][TW] u64 + [FR_LEVEL_MAX] rows).
-// Phase S orders each step so that nothing it waits for was issued in the
-// same step: the rows staged by the previous EMIT step are stored first (one
-// 32-byte chunk per thread), node records were fetched one EMIT step ahead
-// and the first flip entries of a NOISE step right after the previous NOISE
-// step; a step record (one scalar load) names what the next steps need.  (Vector loads and stores share one completion counter, so a load
-// issued behind fresh stores would wait for them.)  Every slot is zero
-// between tiles: each one that receives a contribution is read and cleared by
-// the node that owns it, and every node is emitted.
+// flags [2][TW] u64 (discarded, logical error) | walk positions [NWC][256].
+// Phase S fetches each step's data before the stores of the step before it
+// are issued: node records one EMIT step ahead (both tasks of a thread), the
+// first flip entries of a NOISE step right after the previous NOISE step; a
+// step record (scalar loads) names what the next steps need.  (Vector loads
+// and stores share one completion counter, so a load issued behind fresh
+// stores would wait for them.)  Every slot is zero between tiles: each one
+// that receives a contribution is read and cleared by the node that owns it,
+// and every node is emitted.
 template <uint32_t TW>
 __global__ void __launch_bounds__(TW * 32) __attribute__((amdgpu_waves_per_eu(4))) frame_kernel(FrameArgs A) {
-    constexpr uint32_t NWC = Tile<TW>::NWC, WPW = Tile<TW>::WPW, QPN = Tile<TW>::QPN, STG_WORDS = Tile<TW>::STG_WORDS;
+    constexpr uint32_t NWC = Tile<TW>::NWC, NT = Tile<TW>::NT, WPW = Tile<TW>::WPW, QPN = Tile<TW>::QPN;
     extern __shared__ __align__(16) unsigned char smem[];
     const DevProg &P = A.P;
     const uint32_t NC = P.n_cls, NS = P.fr_n_slots, n_steps = P.fr_n_steps;
@@ -411,12 +252,16 @@ __global__ void __launch_bounds__(TW * 32) __attribute__((amdgpu_waves_per_eu(4)
     unsigned long long *fl = (unsigned long long *)(smem + ((((unsigned char *)(ovf + TW) - smem) + 15) & ~(ptrdiff_t)15));
     unsigned char *region = (unsigned char *)(fl + 2 * TW);
     uint32_t *tmp = (uint32_t *)region + (size_t)wave * 256;
-    unsigned long long *stg = (unsigned long long *)region;         // [STG_WORDS]
-    uint32_t *rows = (uint32_t *)(stg + STG_WORDS);                  // [FR_LEVEL_MAX]
     const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
     const uint64_t n_tiles = (A.n_words + TW - 1) / TW;
     uint64_t *scr = A.scratch + (size_t)blockIdx.x * (TW * A.word_entries + NWC * 128);
     uint32_t *gtmp = (uint32_t *)(scr + (size_t)TW * A.word_entries) + (size_t)wave * 256;  // fallback walks
+    // LDS copies of the walk tables (channel records, step bytes, 32-bit gap tables), in 16-byte units
+    // (the device program pads each array to 16 bytes), when they fit the slot region
+    const uint32_t lt_ci16 = P.fr_n_cch / 4, lt_st16 = P.fr_n_cch / 16, lt_q16 = (NC * 4097 + 3) / 4;
+    const bool ltab = P.fr_ltab && (size_t)(lt_ci16 + lt_q16 + lt_st16) * 16 <= (size_t)(NS + 1) * TW * 8;
+    const WalkLds LT = {(const uint32_t *)slots, (const uint8_t *)(slots + 2 * (size_t)(lt_ci16 + lt_q16)),
+                        (const uint32_t *)(slots + 2 * (size_t)lt_ci16)};
     for (uint32_t i = tid; i < (NS + 1) * TW; i += NWC * 64) slots[i] = 0ull;
     if (tid < 2 * TW) fl[tid] = 0ull;
     unsigned long long n_disc = 0, n_logic = 0;  // aggregate counts of this workgroup (threads < TW)
@@ -430,34 +275,30 @@ __global__ void __launch_bounds__(TW * 32) __attribute__((amdgpu_waves_per_eu(4)
         if (tid < TW) ovf[tid] = 0;
         __syncthreads();
         // phase G: every event of every (word, class) stream of the tile
-        for (uint32_t wl = wave; wl < TW && wt + wl < A.n_words; wl += NWC) {
-            const uint64_t w = A.word_begin + wt + wl;
-            bool over = false;
-            for (uint32_t c = 0; c < NC && !over; ++c) {
-                const uint32_t coff = uniform(P.cls_off)[c], cend = (uniform(P.cls_off)[c + 1] - coff) * 64u;
-                const GapFast F = load_fast(P.cls_fast, c);
-                const uint32_t cap = A.cap_override ? A.cap_override : uniform(A.cap)[c];
-                uint64_t *out =
-                    scr + (size_t)wl * A.word_entries + (A.cap_override ? c * A.cap_override : uniform(A.cap_off)[c]);
-                Walk st = {0, 0, 0};
-                uint32_t n = 0;
-                while (!walk<TW, true>(walk_tabs(P), F, P.cls_Q + (size_t)c * 4097, c, coff, (uint32_t)w, (uint32_t)(w >> 32), st,
-                                   cend, tmp, out, cap, &n, nullptr, 0, k0, k1) &&
-                       st.pos < cend && n <= cap) {
-                }
-                over = n > cap;
-                if (lane == 0) cnt[wl * NC + c] = n;
-            }
-            if (lane == 0 && over) ovf[wl] = 1;
+        if (ltab) {
+            // the walk tables into the slot region, which phase S needs only from the next barrier on
+            uint4 *d = (uint4 *)slots;
+            for (uint32_t i = tid; i < lt_ci16; i += NT) d[i] = ((const uint4 *)P.fr_ci32)[i];
+            for (uint32_t i = tid; i < lt_q16; i += NT) d[lt_ci16 + i] = ((const uint4 *)P.cls_Q32)[i];
+            for (uint32_t i = tid; i < lt_st16; i += NT) d[lt_ci16 + lt_q16 + i] = ((const uint4 *)P.fr_st8)[i];
+            __syncthreads();
+            phase_g<TW, true>(P, A, LT, wt, scr, tmp, cnt, ovf, k0, k1);
+        } else {
+            phase_g<TW, false>(P, A, LT, wt, scr, tmp, cnt, ovf, k0, k1);
         }
         // each wave reads back only the entries it wrote (through other lanes); a
         // workgroup-scope fence orders them, all waves of a workgroup sharing one L1
         __threadfence_block();
-        __syncthreads();
+        const bool any_ovf = __syncthreads_or(tid < TW && ovf[tid]) != 0;
+        if (ltab) {
+            // the slot region back to zero
+            uint4 *d = (uint4 *)slots;
+            for (uint32_t i = tid; i < lt_ci16 + lt_q16 + lt_st16; i += NT) d[i] = make_uint4(0, 0, 0, 0);
+            __syncthreads();
+        }
         // phase S
         const cptr<uint32_t> stp = uniform(P.fr_step);
-        uint32_t pend_n = 0;
-        uint4 pa = make_uint4(0, 0, 0, 0), pb = pa;
+        uint4 pa = make_uint4(0, 0, 0, 0), pb = pa, pa2 = pa, pb2 = pa;
         uint64_t pe[WPW];
         uint32_t pk[WPW];
         auto fetch_records = [&](uint32_t first, uint32_t n) {
@@ -466,15 +307,20 @@ __global__ void __launch_bounds__(TW * 32) __attribute__((amdgpu_waves_per_eu(4)
                 pa = rec[0];
                 pb = rec[1];
             }
+            if (tid + NT < n * QPN) {
+                const uint4 *rec = (const uint4 *)(P.fr_nodes + 8 * (size_t)(first + (tid + NT) / QPN));
+                pa2 = rec[0];
+                pb2 = rec[1];
+            }
         };
         auto fetch_entries = [&](uint32_t c) {
 #pragma unroll
             for (uint32_t i = 0; i < WPW; ++i) {
-                pe[i] = 0;
+                pe[i] = 0ull;
                 pk[i] = FR_NONE;
             }
             if (c == FR_NONE) return;
-            const uint32_t coff = A.cap_override ? c * A.cap_override : uniform(A.cap_off)[c];
+            const uint32_t coff = A.cap_override ? c * A.cap_override : uniform(P.fr_capoff)[c];
 #pragma unroll
             for (uint32_t i = 0; i < WPW; ++i) {
                 const uint32_t wl = wave + i * NWC;
@@ -486,17 +332,17 @@ __global__ void __launch_bounds__(TW * 32) __attribute__((amdgpu_waves_per_eu(4)
         };
         fetch_records(P.fr_first_emit, P.fr_first_emit_n);
         fetch_entries(P.fr_first_noise_cls);
-        auto noise_step = [&](cptr<uint32_t> r) {
+        // SLOW: some word of the tile overflowed its capacity and walks afresh at each NOISE step (a copy
+        // of the step loop of its own, so that the common loop carries none of that walk's registers)
+        auto noise_step = [&](cptr<uint32_t> r, auto slow) {
             const uint32_t c = r[1], r1 = r[2], sl = r[3];
-            const uint32_t coff = A.cap_override ? c * A.cap_override : uniform(A.cap_off)[c];
+            const uint32_t coff = A.cap_override ? c * A.cap_override : uniform(P.fr_capoff)[c];
 #pragma unroll
             for (uint32_t i = 0; i < WPW; ++i) {
                 const uint32_t wl = wave + i * NWC;
                 if (wt + wl >= A.n_words) continue;
-                if (rfl(ovf[wl])) {
-                    noise_direct<TW>(walk_tabs(P), load_fast(P.cls_fast, c), P.cls_Q + (size_t)c * 4097, c,
-                                 uniform(P.cls_off)[c], r1 * 64u, A.word_begin + wt + wl, &wst[wl * NC + c], gtmp,
-                                 slots, wl, k0, k1);
+                if (decltype(slow)::value && rfl(ovf[wl])) {
+                    noise_direct<TW>(P, c, r1 * 64u, A.word_begin + wt + wl, &wst[wl * NC + c], gtmp, slots, wl, k0, k1);
                     continue;
                 }
                 const uint64_t *src = scr + (size_t)wl * A.word_entries + coff;
@@ -517,34 +363,31 @@ __global__ void __launch_bounds__(TW * 32) __attribute__((amdgpu_waves_per_eu(4)
             }
             fetch_entries(r[7]);
         };
+        auto run_steps = [&](auto slow) {
         for (uint32_t step = 0; step < n_steps; ++step) {
             const cptr<uint32_t> r = stp + (size_t)step * FR_STEP_WORDS;
             const bool is_emit = r[0] == FR_EMIT;
             // Take the data fetched for this step before issuing any store: a wait
             // on vector memory covers every operation issued before it, so a load
             // consumed behind fresh stores would wait for the stores as well.
-            const uint4 ra = pa, rb = pb;
-            if (is_emit) {
-                asm volatile("" : : "v"(ra.x), "v"(ra.y), "v"(ra.z), "v"(ra.w), "v"(rb.x), "v"(rb.y), "v"(rb.z));
-            } else {
-#pragma unroll
-                for (uint32_t i = 0; i < WPW; ++i) asm volatile("" : : "v"(pe[i]));
-            }
-            // rows staged by the previous step (if it was an EMIT step)
-            if (tid < pend_n * QPN) store_chunk<TW>(A, stg, rows, tid, wt, full);
-            pend_n = 0;
+            const uint4 ra = pa, rb = pb, ra2 = pa2, rb2 = pb2;
             if (is_emit) {
                 const uint32_t n = r[2];
                 fetch_records(r[5], r[6]);
-                if (tid < n * QPN) emit_quad<TW>(P, A, ra, rb, tid, wt, slots, stg, rows, fl, k0, k1);
-                pend_n = n;
+                if (tid < n * QPN) emit_quad<TW>(P, A, ra, rb, tid, wt, full, slots, fl, k0, k1);
+                if (tid + NT < n * QPN) emit_quad<TW>(P, A, ra2, rb2, tid + NT, wt, full, slots, fl, k0, k1);
             } else {
-                noise_step(r);
+#pragma unroll
+                for (uint32_t i = 0; i < WPW; ++i) asm volatile("" : : "v"(pe[i]));
+                noise_step(r, slow);
             }
             __syncthreads();
         }
-        if (tid < pend_n * QPN) store_chunk<TW>(A, stg, rows, tid, wt, full);
-        __syncthreads();
+        };
+        if (any_ovf)
+            run_steps(std::true_type());
+        else
+            run_steps(std::false_type());
         if (A.cnt.on && tid < TW) {
             // the tile's flags: kept shots only can have a logical error; bits past the shot count are 0
             const uint64_t wi = wt + tid;
@@ -575,22 +418,22 @@ __global__ void __launch_bounds__(TW * 32) __attribute__((amdgpu_waves_per_eu(4)
     }
 }
 
-// Gap decisions exactly as the walk takes them (fast margins, else the table).
+// Gap decisions exactly as the walks take them (fast margins, else the three-read window, else the table).
 __global__ void gap_check_kernel(GapFast F, const uint64_t *Q, const uint32_t *v, int32_t *g, uint64_t n) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int G = 0;
-    if (!gap_fast(F, v[i], G)) G = gap_of(Q, F.invlog2q, v[i]);
+    if (!gap_fast_lean(F, v[i], G)) G = v[i] >= F.vwin ? gap_window(Q, v[i], G) : gap_of(Q, F.invlog2q, v[i]);
     g[i] = G;
 }
 
 template <uint32_t TW>
 static size_t lds_bytes_of(const DevProg &P) {
-    // slots | stream states | cursors and counts | overflow flags | count flags | (walk positions or staging)
+    if (!P.fr_rec_ok) return SIZE_MAX;  // slots past the entries' 12 bits: the kernel cannot run the schedule
+    // slots | stream states | cursors and counts | overflow flags | count flags | walk positions
     const size_t head = (size_t)(P.fr_n_slots + 1) * TW * 8 + (size_t)TW * P.n_cls * (sizeof(FrWord) + 8) + TW * 4;
     const size_t flags = 2 * TW * 8;
-    const size_t region =
-        std::max<size_t>((size_t)Tile<TW>::NWC * 256 * 4, Tile<TW>::STG_WORDS * 8 + FR_LEVEL_MAX * 4);
+    const size_t region = (size_t)Tile<TW>::NWC * 256 * 4;
     return ((head + 15) & ~(size_t)15) + flags + region;
 }
 

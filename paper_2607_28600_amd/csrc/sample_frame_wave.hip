@@ -41,83 +41,6 @@ namespace symft {
 
 static constexpr uint32_t WV_THREADS = WV_TILE * 64;
 
-// Flip entry of the wave kernel: shot lane | step index within the class << 6 | slot << 14.
-__device__ __forceinline__ uint32_t wv_entry(uint32_t lane, uint32_t step, uint32_t slot) {
-    return lane | (step << 6) | (slot << 14);
-}
-
-// One walk of the word's class-c stream with every event resolved to its
-// slot flips.  GEN: the flips become entries appended at out[*n_out ..]
-// (those past cap are dropped; *n_out still counts them).  Otherwise they are
-// XOR-ed at once into the wave's slot column col.
-template <bool GEN>
-__device__ __forceinline__ bool wv_walk(const WaveArgs &A, const GapFast &F, uint32_t c, uint32_t coff, uint64_t w,
-                                        Walk &st, uint32_t R, uint32_t *tmp, uint32_t *out, uint32_t cap,
-                                        uint32_t *n_out, unsigned long long *col, uint32_t k0, uint32_t k1) {
-    const DevProg &P = A.P;
-    bool ok[4];
-    uint32_t at[4], bv[4];
-    const bool cut = walk_events(F, P.cls_Q + (size_t)c * 4097, c, (uint32_t)w, (uint32_t)(w >> 32), st, R, tmp, k0,
-                                 k1, ok, at, bv);
-    uint64_t fw[4];
-    uint32_t stp[4], nfl[4], k_lane = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        fw[i] = 0;
-        stp[i] = 0;
-        nfl[i] = 0;
-        if (ok[i]) {
-            const uint64_t info = P.fr_chinfo[coff + (at[i] >> 6)];
-            const uint32_t fi = (uint32_t)(info & 0x3FFFFFFu) + branch_of(P.thr, info, bv[i]);
-            fw[i] = P.wv_fl[fi];
-            stp[i] = (uint32_t)(info >> 33) & 0xFFu;
-            nfl[i] = (fw[i] & 3u) ? (uint32_t)(fw[i] & 3u) : (uint32_t)(fw[i] >> 8) & 0xFFFFFFu;
-            k_lane += nfl[i];
-        }
-    }
-    const uint32_t lane = threadIdx.x & 63u;
-    if (GEN) {
-        // flips of this lane's events go after those of the lanes below it
-        const uint32_t xs = wave_incl_sum(k_lane);
-        const uint32_t ktot = (uint32_t)__builtin_amdgcn_readlane((int)xs, 63);
-        uint32_t o = *n_out + xs - k_lane;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (!nfl[i]) continue;
-            const uint32_t sh = at[i] & 63u;
-            if (fw[i] & 3u) {
-#pragma unroll
-                for (uint32_t q = 0; q < 3; ++q)
-                    if (q < nfl[i]) {
-                        if (o < cap) out[o] = wv_entry(sh, stp[i], (uint32_t)(fw[i] >> (16 + 16 * q)) & 0xFFFFu);
-                        ++o;
-                    }
-            } else {
-                const uint16_t *sl = P.wv_sl + (fw[i] >> 32);
-                for (uint32_t q = 0; q < nfl[i]; ++q, ++o)
-                    if (o < cap) out[o] = wv_entry(sh, stp[i], sl[q]);
-            }
-        }
-        *n_out += ktot;
-    } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (!nfl[i]) continue;
-            const unsigned long long bit = 1ull << (at[i] & 63u);
-            if (fw[i] & 3u) {
-#pragma unroll
-                for (uint32_t q = 0; q < 3; ++q)
-                    if (q < nfl[i]) atomicXor(col + ((fw[i] >> (16 + 16 * q)) & 0xFFFFu), bit);
-            } else {
-                const uint16_t *sl = P.wv_sl + (fw[i] >> 32);
-                for (uint32_t q = 0; q < nfl[i]; ++q) atomicXor(col + sl[q], bit);
-            }
-        }
-        (void)lane;
-    }
-    return cut;
-}
-
 // LDS layout: slots [16][NS + 1] u64 (wave w's column; slot NS stays 0) |
 // RandomMeas words [16][n_rm] u64 | staging [2][128][16] u64 | walk positions
 // [16][256] u32 | stream states [16][NC] | entry cursors, counts [16][NC] u32 |
@@ -214,8 +137,9 @@ __global__ void __launch_bounds__(WV_THREADS) frame_wave_kernel(WaveArgs A) {
             if (live && !over) {
                 const GapFast F = load_fast(P.cls_fast, c);
                 Walk st = {0, 0, 0};
-                while (!wv_walk<true>(A, F, c, coff, w, st, cend, tmp, out, cap, &n, nullptr, k0, k1) && st.pos < cend &&
-                       n <= cap) {
+                auto none = [](uint32_t, unsigned long long) {};
+                while (!walk_resolved<true>(P, F, c, coff, w, st, cend, tmp, out, cap, &n, k0, k1, none) &&
+                       st.pos < cend && n <= cap) {
                 }
                 over = n > cap;
             }
@@ -269,7 +193,9 @@ __global__ void __launch_bounds__(WV_THREADS) frame_wave_kernel(WaveArgs A) {
                         if (st.pos < R) {
                             const GapFast F = load_fast(P.cls_fast, c);
                             const uint32_t coff = uniform(P.cls_off)[c];
-                            while (!wv_walk<false>(A, F, c, coff, w, st, R, tmp, nullptr, 0, nullptr, col, k0, k1) &&
+                            auto flip = [col](uint32_t sl, unsigned long long bit) { atomicXor(col + sl, bit); };
+                            while (!walk_resolved<false>(P, F, c, coff, w, st, R, tmp, nullptr, 0, nullptr, k0, k1,
+                                                         flip) &&
                                    st.pos < R) {
                             }
                             if (lane == 0) wst[c] = FrWord{st.pos, st.j, st.e, 0};

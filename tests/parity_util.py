@@ -66,6 +66,13 @@ def frame_relation(a, b, tol):
     frame F = i^e Xbar^y Zbar^s' (times dormant factors) sends
     sum_x alpha_x Xbar^x |0bar> to i^e sum_x (-1)^{s'.x} alpha_x Xbar^(x XOR y) |0bar>,
     and sign conventions of the generators add further characters."""
+    m = frame_match(a, b, tol)
+    return None if m is None else m[:2]
+
+
+def frame_match(a, b, tol):
+    """As frame_relation, returning (y, s, err) with err the largest
+    abs(a_x - e^{i phi} (-1)^{s.x} b_{x XOR y}) of the match, or None."""
     a = np.asarray(a, dtype=complex)
     b = np.asarray(b, dtype=complex)
     if a.shape != b.shape:
@@ -109,8 +116,9 @@ def frame_relation(a, b, tol):
             if v ^ par:
                 s |= 1 << p
         chi = np.array([(-1) ** (bin(s & (x ^ r)).count("1") & 1) for x in range(N)])
-        if np.max(np.abs(a - ph * chi * bb)) <= tol:
-            return y, s
+        err = float(np.max(np.abs(a - ph * chi * bb)))
+        if err <= tol:
+            return y, s, err
     return None
 
 

@@ -38,9 +38,9 @@ def c2():
     return w, S.Program(w.circuit), OracleCircuit(w.circuit)
 
 
-def test_automatic_choice_is_the_wave_kernel(c1, c2):
-    assert c1[1].info()["frame_kernel"] == 1
-    assert c2[1].info()["frame_kernel"] == 1
+def test_automatic_choice_is_the_step_kernel(c1, c2):
+    assert c1[1].info()["frame_kernel"] == 2
+    assert c2[1].info()["frame_kernel"] == 2
 
 
 @pytest.mark.parametrize("fk", [1, 2])
@@ -98,7 +98,7 @@ def test_wave_kernel_multiclass(k, cap):
     from tests.test_gpu_parity import _multiclass_surface
     c = _multiclass_surface(5, 4, k)
     p = S.Program(c)
-    assert p.info()["frame_kernel"] == 1
+    assert p.info()["frame_kernel"] == 2
     oc = OracleCircuit(c)
     seed = 0xC1A55 + k
     n = 64 * 40 + 17
