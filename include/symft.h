@@ -223,6 +223,27 @@ symft_status symft_sample(const symft_program *p, uint64_t shots, uint64_t seed,
 symft_status symft_sample_ex(const symft_program *p, const symft_sample_opts *opts, uint64_t shots, uint64_t seed,
                              uint64_t *records_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): symft_sample_ex
+ * with every kernel's scratch taken from a fixed device array of the library
+ * (64 MiB per device, held until the process ends) and no allocation by the
+ * library.  Arguments, layout and records are those of symft_sample_ex, and
+ * the records are identical; to fit the fixed scratch a launch may run fewer
+ * workgroups (the pure-frame kernels' flip entries, the active kernel's
+ * vector slices when vectors do not fit LDS).
+ *   - The program must already be resident on the current device (uploaded
+ *     by an earlier symft_sample / symft_sample_ex call there): EINVAL
+ *     otherwise.
+ *   - ECAPACITY when a single workgroup's scratch exceeds 64 MiB (for
+ *     example a peak active width of 23 and above in FP64).
+ *   - Every call on one device shares that device's array, which keeps the
+ *     last call's contents (nothing in it needs to start at zero: every
+ *     region is written before it is read).  Calls that overlap on one device
+ *     -- on different streams, or from several threads -- race; serialise
+ *     them on one stream. */
+symft_status symft_sample_noalloc(const symft_program *p, const symft_sample_opts *opts, uint64_t shots, uint64_t seed,
+                                  uint64_t *records_out, void *stream);
+
 /* Sample n programs in one persistent launch (paper Sec. 6 batching across
  * shots, here also across programs): a work queue over (program, word range)
  * items ordered by decreasing cost.  records_out[i] (device, n_rows(i) x

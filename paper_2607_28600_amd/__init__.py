@@ -90,6 +90,9 @@ _lib.symft_sample.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p, C.
 _lib.symft_sample_ex.restype = C.c_int32
 _lib.symft_sample_ex.argtypes = [C.c_void_p, C.POINTER(symft_sample_opts), C.c_uint64, C.c_uint64, C.c_void_p,
                                  C.c_void_p]
+_lib.symft_sample_noalloc.restype = C.c_int32
+_lib.symft_sample_noalloc.argtypes = [C.c_void_p, C.POINTER(symft_sample_opts), C.c_uint64, C.c_uint64, C.c_void_p,
+                                      C.c_void_p]
 _lib.symft_sample_counts.restype = C.c_int32
 _lib.symft_sample_counts.argtypes = [C.c_void_p, C.POINTER(symft_count_opts), C.c_uint64, C.c_uint64, C.c_void_p,
                                      C.c_void_p, C.c_void_p]
@@ -115,7 +118,7 @@ _lib.symft_last_error.restype = C.c_char_p
 
 EXPORTED = ["symft_compile", "symft_program_info", "symft_program_plan", "symft_program_export",
             "symft_sample", "symft_sample_ex", "symft_sample_counts", "symft_autotune_counts",
-            "symft_sample_batch", "symft_autotune", "symft_probe", "symft_probe_amplitudes", "symft_gap_check", "symft_program_free",
+            "symft_sample_noalloc", "symft_sample_batch", "symft_autotune", "symft_probe", "symft_probe_amplitudes", "symft_gap_check", "symft_program_free",
             "symft_last_error"]
 
 
@@ -248,6 +251,19 @@ class Program:
                               frame_entry_cap, frame_tile_words, frame_kernel)
         _check(_lib.symft_sample_ex(self._h, C.byref(o), shots, seed, C.c_void_p(ptr), C.c_void_p(stream)),
                "symft_sample_ex")
+
+    def sample_noalloc_into(self, out, shots: int, seed: int, shot_offset: int = 0, precision: str = "fp64",
+                            sections: int = 0, row_stride_words: int = 0, stream=None, frame_kernel: int = 0) -> None:
+        """symft_sample_noalloc: as sample_into, with the kernels' scratch in the library's fixed device array
+        (the program must have been sampled once on this device)."""
+        import torch
+        ptr = out.data_ptr() if hasattr(out, "data_ptr") else int(out)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        o = symft_sample_opts(shot_offset, 0 if precision == "fp64" else 1, sections, row_stride_words, 0, 0,
+                              frame_kernel)
+        _check(_lib.symft_sample_noalloc(self._h, C.byref(o), shots, seed, C.c_void_p(ptr), C.c_void_p(stream)),
+               "symft_sample_noalloc")
 
     def sample(self, shots: int, seed: int, shot_offset: int = 0, precision: str = "fp64", device="cuda",
                frame_entry_cap: int = 0, frame_tile_words: int = 0, frame_kernel: int = 0):

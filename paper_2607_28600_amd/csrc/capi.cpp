@@ -350,12 +350,23 @@ static void lower(symft_program *h) {
     m.fr_ok = h->F.ok && (m.wv_ok || frame_lds_bytes(m, 16) <= kLdsLimit) ? 1u : 0u;
 }
 
-static symft_status device_prog(symft_program *h, DevProg &out) {
+// Scratch memory handed in by the caller of a launch instead of taken from the
+// pool: the launch caps its grid so that its scratch fits `bytes`.
+struct FixedScratch {
+    void *ptr;
+    size_t bytes;
+};
+
+// upload = false: fail instead of uploading a program that is not resident on
+// the current device (the allocation-free entry point allocates nothing).
+static symft_status device_prog(symft_program *h, DevProg &out, bool upload = true) {
     int dev = 0;
     if (const hipError_t e = hipGetDevice(&dev)) return hip_err("hipGetDevice failed", e);
     std::lock_guard<std::mutex> lk(h->mu);
     void *base = nullptr;
     auto it = h->dev.find(dev);
+    if (it == h->dev.end() && !upload)
+        return set_err(SYMFT_EINVAL, "the program is not resident on this device (sample it once with symft_sample_ex)");
     if (it == h->dev.end()) {
         if (hipMalloc(&base, h->L.blob.size()) != hipSuccess) return set_err(SYMFT_ENOMEM, "device program allocation failed");
         if (hipMemcpy(base, h->L.blob.data(), h->L.blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
@@ -523,7 +534,7 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
                                uint64_t shots, uint64_t *out, uint64_t stride, uint32_t sections, double *p0,
                                uint64_t probe_shot0, uint64_t probe_n, uint64_t seed, hipStream_t st,
                                uint32_t force_tps = 0, const CountArgs *cnt = nullptr, double *amp = nullptr,
-                               uint32_t amp_k = 0) {
+                               uint32_t amp_k = 0, const FixedScratch *fixed = nullptr) {
     ActiveConfig c = choose_active(D, fp64, force_tps, 0, cnt != nullptr);
     if (c.lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "program tables exceed the LDS budget of the active kernel");
     int per_cu = active_max_blocks_per_cu(fp64, c.bs, c.lds_vec, c.lds, cnt != nullptr);
@@ -531,6 +542,14 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
     uint64_t cap = (uint64_t)per_cu * (uint64_t)num_cus();
     // HBM-resident vectors: about 1024 threads of shot groups per CU
     if (!c.lds_vec) cap = std::min<uint64_t>(cap, (uint64_t)num_cus() * std::max<uint32_t>(2u, 1024u / c.bs));
+    if (fixed && !c.lds_vec) {
+        // the vector slices of every workgroup must fit the caller's scratch
+        const uint64_t per_wg = (uint64_t)(c.bs / c.tps) * ((uint64_t)1 << D.k_max) * (fp64 ? 16 : 8);
+        if (per_wg > fixed->bytes)
+            return set_err(SYMFT_ECAPACITY, "one workgroup's vector scratch exceeds the fixed scratch (" +
+                                                std::to_string(per_wg) + " > " + std::to_string(fixed->bytes) + " bytes)");
+        cap = std::min<uint64_t>(cap, fixed->bytes / per_wg);
+    }
     uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_words, cap));
     ActiveArgs A;
     std::memset(&A, 0, sizeof(A));
@@ -556,8 +575,12 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
         const uint32_t G = c.bs / c.tps;
         A.scratch_stride = (uint64_t)1 << D.k_max;
         size_t bytes = (size_t)grid * G * A.scratch_stride * (fp64 ? 16 : 8);
-        if (pool_alloc(&scratch, bytes, st) != hipSuccess) return set_err(SYMFT_ENOMEM, "vector scratch allocation failed");
-        A.scratch = scratch;
+        if (fixed) {
+            A.scratch = fixed->ptr;
+        } else {
+            if (pool_alloc(&scratch, bytes, st) != hipSuccess) return set_err(SYMFT_ENOMEM, "vector scratch allocation failed");
+            A.scratch = scratch;
+        }
     }
     hipError_t e = launch_active(A, fp64, c.bs, grid, st);
     if (scratch) hipFreeAsync(scratch, st);
@@ -568,7 +591,8 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
 // The wave-owned kernel: one 16-wave workgroup per CU, each wave one word of a 16-word tile.
 static symft_status run_frame_wave(symft_program *h, const DevProg &D, uint64_t word_begin, uint64_t n_words,
                                    uint64_t shots, uint64_t *out, uint64_t stride, uint32_t sections, uint64_t seed,
-                                   uint32_t cap_override, hipStream_t st, const CountArgs *cnt) {
+                                   uint32_t cap_override, hipStream_t st, const CountArgs *cnt,
+                                   const FixedScratch *fixed = nullptr) {
     const size_t lds = frame_wave_lds_bytes(D);
     if (lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "frame schedule exceeds the LDS budget of the wave kernel");
     int per_cu = frame_wave_max_blocks_per_cu(lds, cnt != nullptr);
@@ -580,11 +604,21 @@ static symft_status run_frame_wave(symft_program *h, const DevProg &D, uint64_t 
     A.word_entries = cap_override ? cap_override * D.n_cls : h->L.wv_word_entries;
     A.cap_override = cap_override;
     const uint64_t per_wg = (uint64_t)WV_TILE * std::max<uint32_t>(1, A.word_entries) * 4;
+    if (fixed) {
+        if (per_wg > fixed->bytes)
+            return set_err(SYMFT_ECAPACITY, "one workgroup's flip-entry scratch exceeds the fixed scratch (" +
+                                                std::to_string(per_wg) + " > " + std::to_string(fixed->bytes) + " bytes)");
+        cap = std::min<uint64_t>(cap, fixed->bytes / per_wg);
+    }
     const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
     void *scratch = nullptr;
-    if (pool_alloc(&scratch, (size_t)grid * per_wg, st) != hipSuccess)
-        return set_err(SYMFT_ENOMEM, "frame scratch allocation failed");
-    A.scratch = (uint32_t *)scratch;
+    if (fixed) {
+        A.scratch = (uint32_t *)fixed->ptr;
+    } else {
+        if (pool_alloc(&scratch, (size_t)grid * per_wg, st) != hipSuccess)
+            return set_err(SYMFT_ENOMEM, "frame scratch allocation failed");
+        A.scratch = (uint32_t *)scratch;
+    }
     A.P = D;
     A.seed = seed;
     A.word_begin = word_begin;
@@ -608,7 +642,7 @@ static symft_status run_frame_wave(symft_program *h, const DevProg &D, uint64_t 
 static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_begin, uint64_t n_words, uint64_t shots,
                               uint64_t *out, uint64_t stride, uint32_t sections, uint64_t seed, uint32_t cap_override,
                               hipStream_t st, const CountArgs *cnt = nullptr, uint32_t tile_words = 0,
-                              uint32_t frame_kernel = 0) {
+                              uint32_t frame_kernel = 0, const FixedScratch *fixed = nullptr) {
     if (tile_words != 0 && tile_words != 16 && tile_words != 32)
         return set_err(SYMFT_EINVAL, "frame_tile_words must be 0, 16 or 32");
     if (frame_kernel > 2) return set_err(SYMFT_EINVAL, "frame_kernel must be 0, 1 or 2");
@@ -617,7 +651,8 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
         return set_err(SYMFT_ECAPACITY, "the wave-owned frame kernel cannot run this schedule (LDS)");
     const bool step_fits = frame_lds_bytes(D, 16) <= kLdsLimit;
     if (frame_kernel == 1 || (frame_kernel == 0 && !tile_words && !step_fits && D.wv_ok))
-        return run_frame_wave(h, D, word_begin, n_words, shots, out, stride, sections, seed, cap_override, st, cnt);
+        return run_frame_wave(h, D, word_begin, n_words, shots, out, stride, sections, seed, cap_override, st, cnt,
+                              fixed);
     // 32-word tiles halve the barrier steps per word; they need the slots of
     // 32 words in LDS and leave one workgroup per CU, so they are taken only
     // with at least two tiles per CU
@@ -634,11 +669,21 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
     A.word_entries = cap_override ? cap_override * D.n_cls : h->L.word_entries;
     A.cap_override = cap_override;
     const uint64_t per_wg = (uint64_t)frame_scratch_words(A.word_entries, tw) * 8;
+    if (fixed) {
+        if (per_wg > fixed->bytes)
+            return set_err(SYMFT_ECAPACITY, "one workgroup's flip-entry scratch exceeds the fixed scratch (" +
+                                                std::to_string(per_wg) + " > " + std::to_string(fixed->bytes) + " bytes)");
+        cap = std::min<uint64_t>(cap, fixed->bytes / per_wg);
+    }
     uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
     void *scratch = nullptr;
-    if (pool_alloc(&scratch, (size_t)grid * per_wg, st) != hipSuccess)
-        return set_err(SYMFT_ENOMEM, "frame scratch allocation failed");
-    A.scratch = (uint64_t *)scratch;
+    if (fixed) {
+        A.scratch = (uint64_t *)fixed->ptr;
+    } else {
+        if (pool_alloc(&scratch, (size_t)grid * per_wg, st) != hipSuccess)
+            return set_err(SYMFT_ENOMEM, "frame scratch allocation failed");
+        A.scratch = (uint64_t *)scratch;
+    }
     A.P = D;
     A.seed = seed;
     A.word_begin = word_begin;
@@ -826,6 +871,73 @@ symft_status symft_sample_ex(const symft_program *pc, const symft_sample_opts *o
 
 symft_status symft_sample(const symft_program *p, uint64_t shots, uint64_t seed, uint64_t *records_out, void *stream) {
     return symft_sample_ex(p, nullptr, shots, seed, records_out, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- allocation-free sampling
+// The scratch of symft_sample_noalloc: every launch of that entry point takes
+// its kernels' scratch (flip entries of the frame kernels, HBM vector slices
+// of the active kernel) from this array instead of allocating, and caps its
+// grid to fit.  Each device holds its own copy for the life of the process.
+// In host code the name `scratch` stands for the host-side shadow of the
+// symbol, not a device address: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is passed on.
+static constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static constexpr int kNoAllocMaxDevices = 64;
+static void *g_scratch_dev[kNoAllocMaxDevices];
+static std::mutex g_scratch_mu;
+
+// The device address of `scratch` on the current device, looked up on the
+// first call on that device.
+static symft_status noalloc_scratch(FixedScratch &out) {
+    int dev = 0;
+    if (const hipError_t e = hipGetDevice(&dev)) return hip_err("hipGetDevice failed", e);
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return set_err(SYMFT_ECAPACITY, "device index past the fixed scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_err("hipGetSymbolAddress of the fixed scratch failed", e);
+        if (!ptr) return set_err(SYMFT_EHIP, "hipGetSymbolAddress returned no address for the fixed scratch");
+        g_scratch_dev[dev] = ptr;
+    }
+    out.ptr = g_scratch_dev[dev];
+    out.bytes = kNoAllocScratchBytes;
+    return SYMFT_OK;
+}
+
+extern "C" {
+
+symft_status symft_sample_noalloc(const symft_program *pc, const symft_sample_opts *opts, uint64_t shots,
+                                  uint64_t seed, uint64_t *records_out, void *stream) {
+    symft_program *p = const_cast<symft_program *>(pc);
+    if (!p) return set_err(SYMFT_EINVAL, "NULL program");
+    symft_sample_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (o.shot_offset % 64) return set_err(SYMFT_EINVAL, "shot_offset must be a multiple of 64");
+    if (o.precision > 1) return set_err(SYMFT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+    if (shots == 0 || p->P.n_rows() == 0) return SYMFT_OK;
+    if (!records_out) return set_err(SYMFT_EINVAL, "records_out is NULL");
+    const uint64_t n_words = (shots + 63) / 64;
+    const uint64_t stride = o.row_stride_words ? o.row_stride_words : n_words;
+    if (stride < n_words) return set_err(SYMFT_EINVAL, "row_stride_words smaller than the shot words");
+    const uint32_t sections = o.sections ? o.sections : 7u;
+    FixedScratch fx;
+    symft_status rc = noalloc_scratch(fx);
+    if (rc) return rc;
+    DevProg D;
+    rc = device_prog(p, D, false);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t w0 = o.shot_offset / 64;
+    if (D.fr_ok)
+        return run_frame(p, D, w0, n_words, shots, records_out, stride, sections, seed, o.frame_entry_cap, st,
+                         nullptr, o.frame_tile_words, o.frame_kernel, &fx);
+    return run_active(p, D, o.precision == 0, w0, n_words, shots, records_out, stride, sections, nullptr, 0, 0, seed,
+                      st, 0, nullptr, nullptr, 0, &fx);
 }
 
 }  // extern "C"
