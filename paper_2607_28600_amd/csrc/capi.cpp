@@ -370,7 +370,7 @@ static symft_status device_prog(symft_program *h, DevProg &out, bool upload = tr
     if (it == h->dev.end()) {
         if (hipMalloc(&base, h->L.blob.size()) != hipSuccess) return set_err(SYMFT_ENOMEM, "device program allocation failed");
         if (hipMemcpy(base, h->L.blob.data(), h->L.blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
-            hipFree(base);
+            (void)hipFree(base);
             return set_err(SYMFT_EHIP, "device program upload failed");
         }
         h->dev[dev] = base;
@@ -443,7 +443,7 @@ static hipError_t pool_alloc(void **p, size_t bytes, hipStream_t st) {
             e = hipMemPoolCreate(&pool, &pr);
             if (e != hipSuccess) return e;
             uint64_t thr = UINT64_MAX;
-            hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
             g_pools[dev] = pool;
         } else {
             pool = it->second;
@@ -456,7 +456,7 @@ static int g_num_cus = 0;
 static int num_cus() {
     if (!g_num_cus) {
         int dev = 0;
-        hipGetDevice(&dev);
+        (void)hipGetDevice(&dev);
         hipDeviceProp_t pr;
         if (hipGetDeviceProperties(&pr, dev) == hipSuccess) g_num_cus = pr.multiProcessorCount;
         if (g_num_cus <= 0) g_num_cus = 256;
@@ -583,7 +583,7 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
         }
     }
     hipError_t e = launch_active(A, fp64, c.bs, grid, st);
-    if (scratch) hipFreeAsync(scratch, st);
+    if (scratch) (void)hipFreeAsync(scratch, st);
     if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("active kernel launch failed: ") + hipGetErrorString(e));
     return SYMFT_OK;
 }
@@ -631,7 +631,7 @@ static symft_status run_frame_wave(symft_program *h, const DevProg &D, uint64_t 
     A.lds_bytes = (uint32_t)lds;
     if (cnt) A.cnt = *cnt;
     hipError_t e = launch_frame_wave(A, grid, st);
-    if (scratch) hipFreeAsync(scratch, st);
+    if (scratch) (void)hipFreeAsync(scratch, st);
     if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("frame kernel launch failed: ") + hipGetErrorString(e));
     return SYMFT_OK;
 }
@@ -696,7 +696,7 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
     A.lds_bytes = (uint32_t)lds;
     if (cnt) A.cnt = *cnt;
     hipError_t e = launch_frame(A, grid, st, tw);
-    if (scratch) hipFreeAsync(scratch, st);
+    if (scratch) (void)hipFreeAsync(scratch, st);
     if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("frame kernel launch failed: ") + hipGetErrorString(e));
     return SYMFT_OK;
 }
@@ -795,9 +795,11 @@ symft_status symft_program_info(const symft_program *p, symft_info *info) {
 symft_status symft_program_plan(const symft_program *p, int16_t *k_after_op, int8_t *meas_kind, int8_t *rot_kind) {
     if (!p) return set_err(SYMFT_EINVAL, "NULL program");
     const Program &P = p->P;
-    if (k_after_op) std::memcpy(k_after_op, P.k_after_op.data(), P.k_after_op.size() * sizeof(int16_t));
-    if (meas_kind) std::memcpy(meas_kind, P.meas_kind.data(), P.meas_kind.size());
-    if (rot_kind) std::memcpy(rot_kind, P.rot_kind.data(), P.rot_kind.size());
+    // (an empty vector may hand out a null pointer, which memcpy must not see even for 0 bytes)
+    if (k_after_op && !P.k_after_op.empty())
+        std::memcpy(k_after_op, P.k_after_op.data(), P.k_after_op.size() * sizeof(int16_t));
+    if (meas_kind && !P.meas_kind.empty()) std::memcpy(meas_kind, P.meas_kind.data(), P.meas_kind.size());
+    if (rot_kind && !P.rot_kind.empty()) std::memcpy(rot_kind, P.rot_kind.data(), P.rot_kind.size());
     return SYMFT_OK;
 }
 
@@ -999,7 +1001,7 @@ static symft_status count_tables(symft_program *h, const symft_count_opts &o, Co
         } else {
             if (hipMalloc(&base, tab.size() * 4) != hipSuccess) return set_err(SYMFT_ENOMEM, "count table allocation failed");
             if (hipMemcpy(base, tab.data(), tab.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
-                hipFree(base);
+                (void)hipFree(base);
                 return set_err(SYMFT_EHIP, "count table upload failed");
             }
             h->count_dev[key] = base;
@@ -1047,7 +1049,7 @@ static symft_status counts_via_records(symft_program *p, const DevProg &D, bool 
             if (e != hipSuccess) rc = set_err(SYMFT_EHIP, std::string("flag reduction launch failed: ") + hipGetErrorString(e));
         }
     }
-    hipFreeAsync(buf, st);
+    (void)hipFreeAsync(buf, st);
     return rc;
 }
 
@@ -1127,12 +1129,12 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
     C.counts = cnt;
     hipStream_t st;
     if (hipStreamCreate(&st) != hipSuccess) {
-        hipFree(cnt);
+        (void)hipFree(cnt);
         return set_err(SYMFT_EHIP, "stream creation failed");
     }
     hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
     float best = 1e30f;
     uint32_t best_tps = 0;
     for (uint32_t cand : {4u, 8u, 16u, 32u, 64u, 128u, 256u, 1024u, 64u | kHbmVec, 128u | kHbmVec, 256u | kHbmVec}) {
@@ -1143,11 +1145,11 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
         if (!wide && !(cand & kHbmVec) && active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
         float ms = 0;
         for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
-            hipEventRecord(e0, st);
+            (void)hipEventRecord(e0, st);
             rc = run_active(p, D, fp64, 0, words, words * 64, nullptr, words, 0u, nullptr, 0, 0, 0x7E57ull, st, cand, &C);
-            hipEventRecord(e1, st);
-            hipEventSynchronize(e1);
-            hipEventElapsedTime(&ms, e0, e1);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
         }
         if (rc) break;
         if (ms < best) {
@@ -1159,21 +1161,21 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
     if (rc == SYMFT_OK && best_tps) {
         float ms = 0;
         for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
-            hipEventRecord(e0, st);
+            (void)hipEventRecord(e0, st);
             rc = counts_via_records(p, D, fp64, 0, words, words * 64, 0x7E57ull, st, C);
-            hipEventRecord(e1, st);
-            hipEventSynchronize(e1);
-            hipEventElapsedTime(&ms, e0, e1);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
         }
         if (rc == SYMFT_OK && ms < best) {
             best = ms;
             best_tps = choose_active(D, fp64, 0, 0, false).tps | kViaRecords;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipStreamDestroy(st);
-    hipFree(cnt);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    (void)hipFree(cnt);
     if (rc) return rc;
     if (best_tps) {
         std::lock_guard<std::mutex> lk(p->mu);
@@ -1200,18 +1202,18 @@ symft_status symft_probe(const symft_program *pc, uint64_t shot_begin, uint32_t 
     const uint64_t rows = std::max<uint64_t>(1, p->P.n_rows());
     if (hipMalloc(&dp0, sizeof(double) * nm * n_shots) != hipSuccess) return set_err(SYMFT_ENOMEM, "probe allocation failed");
     if (hipMalloc(&drec, 8 * rows * nw) != hipSuccess) {
-        hipFree(dp0);
+        (void)hipFree(dp0);
         return set_err(SYMFT_ENOMEM, "probe allocation failed");
     }
-    hipMemset(dp0, 0xff, sizeof(double) * nm * n_shots);  // NaN pattern
+    (void)hipMemset(dp0, 0xff, sizeof(double) * nm * n_shots);  // NaN pattern
     rc = run_active(p, D, precision == 0, w0, nw, nw * 64, drec, nw, 7u, dp0, shot_begin, n_shots, seed, nullptr);
     if (rc == SYMFT_OK) {
         if (hipDeviceSynchronize() != hipSuccess ||
             hipMemcpy(p0_host, dp0, sizeof(double) * nm * n_shots, hipMemcpyDeviceToHost) != hipSuccess)
             rc = set_err(SYMFT_EHIP, "probe copy failed");
     }
-    hipFree(dp0);
-    hipFree(drec);
+    (void)hipFree(dp0);
+    (void)hipFree(drec);
     return rc;
 }
 
@@ -1241,7 +1243,7 @@ symft_status symft_probe_amplitudes(const symft_program *pc, uint64_t shot_begin
     const uint64_t rows = std::max<uint64_t>(1, p->P.n_rows());
     if (hipMalloc(&damp, sizeof(double) * namp) != hipSuccess) return set_err(SYMFT_ENOMEM, "probe allocation failed");
     if (hipMalloc(&drec, 8 * rows * nw) != hipSuccess) {
-        hipFree(damp);
+        (void)hipFree(damp);
         return set_err(SYMFT_ENOMEM, "probe allocation failed");
     }
     rc = run_active(p, D, precision == 0, w0, nw, nw * 64, drec, nw, 7u, nullptr, shot_begin, n_shots, seed, nullptr, 0,
@@ -1251,8 +1253,8 @@ symft_status symft_probe_amplitudes(const symft_program *pc, uint64_t shot_begin
             hipMemcpy(amp_host, damp, sizeof(double) * namp, hipMemcpyDeviceToHost) != hipSuccess)
             rc = set_err(SYMFT_EHIP, "probe copy failed");
     }
-    hipFree(damp);
-    hipFree(drec);
+    (void)hipFree(damp);
+    (void)hipFree(drec);
     return rc;
 }
 
@@ -1270,7 +1272,7 @@ symft_status symft_gap_check(uint64_t p32, const uint32_t *v, int32_t *g_out, ui
     if (hipMemcpy(dQ, Q.data(), Q.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
         launch_gap_check(F, dQ, v, g_out, n, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
         rc = set_err(SYMFT_EHIP, "gap check failed");
-    hipFree(dQ);
+    (void)hipFree(dQ);
     return rc;
 }
 
@@ -1292,12 +1294,12 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
     if (hipMalloc(&out, 8 * rows * words) != hipSuccess) return set_err(SYMFT_ENOMEM, "autotune buffer allocation failed");
     hipStream_t st;
     if (hipStreamCreate(&st) != hipSuccess) {
-        hipFree(out);
+        (void)hipFree(out);
         return set_err(SYMFT_EHIP, "stream creation failed");
     }
     hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
     float best = 1e30f;
     uint32_t best_tps = default_tps(D.k_max, fp64);
     symft_status rc = SYMFT_OK;
@@ -1310,11 +1312,11 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
         if (!wide && !(cand & kHbmVec) && active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
         float ms = 0;
         for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
-            hipEventRecord(e0, st);
+            (void)hipEventRecord(e0, st);
             rc = run_active(p, D, fp64, 0, words, words * 64, out, words, 7u, nullptr, 0, 0, 0x7E57ull, st, cand);
-            hipEventRecord(e1, st);
-            hipEventSynchronize(e1);
-            hipEventElapsedTime(&ms, e0, e1);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
         }
         if (rc) break;
         if (ms < best) {
@@ -1322,10 +1324,10 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
             best_tps = cand;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipStreamDestroy(st);
-    hipFree(out);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    (void)hipFree(out);
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1371,11 +1373,11 @@ struct BatchPlan {
         return true;
     }
     void release() {
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
-        hipFree(d_calls);
-        hipFree(d_items);
-        hipFree(d_counter);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipFree(d_calls);
+        (void)hipFree(d_items);
+        (void)hipFree(d_counter);
         exec = nullptr;
         graph = nullptr;
         d_calls = nullptr;
@@ -1413,7 +1415,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
     B.seeds.assign(seeds, seeds + n);
     B.outs.assign(outs, outs + n);
     B.precision = precision;
-    hipGetDevice(&B.device);
+    (void)hipGetDevice(&B.device);
     std::vector<ActiveArgs> calls;
     std::vector<double> cost;
     std::vector<uint64_t> words_of;
@@ -1509,7 +1511,7 @@ symft_status symft_sample_batch(const symft_program *const *progs, const uint64_
     if (precision > 1) return set_err(SYMFT_EINVAL, "precision must be 0 or 1");
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
-    hipGetDevice(&dev);
+    (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> lk(g_batch_mu);
     BatchPlan *B = nullptr;
     for (size_t i = 0; i < g_plans.size(); ++i)
@@ -1546,7 +1548,7 @@ symft_status symft_sample_batch(const symft_program *const *progs, const uint64_
                 if (e == hipSuccess) e = e2;
                 if (e == hipSuccess) e = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
                 B->graph = g;
-                hipStreamDestroy(cs);
+                (void)hipStreamDestroy(cs);
                 if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("batch graph capture failed: ") + hipGetErrorString(e));
             }
             hipError_t e = hipGraphLaunch(B->exec, st);
