@@ -87,8 +87,8 @@ struct DevProg {
     const uint32_t *fr_nodes;    // 8 words per node: slot | flags << 24, row, meas, push count, two successor slots, push offset, 0
     const uint32_t *fr_push;     // successor slots
     const uint64_t *fr_chinfo;   // per (class, rank): flip-table offset | J << 26 | uniform << 32 | step << 33 | thr_off << 41
-    const uint64_t *fr_frec;     // per (channel, branch): flip record of four entries (32 bytes, 16-byte aligned)
-    const uint64_t *fr_fl3;      // flip entries of branches with more than four: (k - 1) << 6 | four 12-bit slots
+    const uint64_t *fr_frec;     // per (channel, branch): flip record of two entries (16 bytes, 16-byte aligned)
+    const uint64_t *fr_fl3;      // flip entries past a record's two, from an even index (16-byte aligned)
     const uint32_t *fr_ci32;     // per (class, rank): flip-table offset | J << 20 (for the LDS copy)
     const uint8_t *fr_st8;       // per (class, rank): NOISE step index within the class
     const uint32_t *cls_Q32;     // n_cls x 4097: Q[g] as 32 bits (Q[0] = 2^32 stored as 2^32 - 1; walks decide g = 0 without it)

@@ -308,12 +308,14 @@ __device__ __forceinline__ uint32_t entry_slot(uint64_t e, uint32_t q) { return 
 
 // Lean walk of the (class c, word w) stream: the draws, gaps and positions of
 // walk_events, each event resolved through its channel record and branch into
-// its flip record (four pre-packed entries, the count in the first one's lane
-// bits), all four records of a lane loaded together.  Straight-line code
-// except where some lane takes the table search or a branch with more than
-// four entries.  GEN: the entries, tagged with shot lane and step, appended at
-// out[n_out ..] (those past cap dropped, n_out still counts them); otherwise
-// apply(entry) per entry.  Returns whether the walk stopped at R.
+// its 16-byte flip record (the first two pre-packed entries, the count in the
+// first one's lane bits), the four records of a lane loaded together; a lane
+// whose event has more entries loads the next two from the extension, and
+// past four (rare) one at a time.  Straight-line code except where some lane
+// takes the table search or more than two entries.  GEN: the entries, tagged
+// with shot lane and step, appended at out[n_out ..] (those past cap
+// dropped, n_out still counts them); otherwise apply(entry) per entry.
+// Returns whether the walk stopped at R.
 template <bool GEN, bool LT, typename Apply>
 __device__ __forceinline__ bool walk_entries(const DevProg &P, const WalkLds &T, const GapFast &F, uint32_t c,
                                              uint32_t coff, uint64_t w, Walk &st, uint32_t R, uint32_t *tmp,
@@ -471,25 +473,30 @@ __device__ __forceinline__ bool walk_entries(const DevProg &P, const WalkLds &T,
             stp[i] = (uint32_t)(info[i] >> 33) & 0xFFu;
         }
     }
-    // the four flip records of the lane, 32 bytes each, loaded together
-    uint4 ra[4], rb[4];
+    // the four flip records of the lane, 16 bytes each, loaded together
+    uint4 ra[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ra[i] = ((const uint4 *)P.fr_frec)[fi[i]];
+    // entries per event; past two, the extension offset (in 16-byte units) held in the records' idle bits
+    uint32_t m[4], k_lane = 0, xm = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const uint4 *rp = (const uint4 *)(P.fr_frec + 4 * (size_t)fi[i]);
-        ra[i] = rp[0];
-        rb[i] = rp[1];
-    }
-    // entries per event: the record's count, or (63) a list's count in its third word
-    uint32_t m[4], k_lane = 0, ovm = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t cnt = ra[i].x & 63u;
-        const bool ov = cnt == 63u;
-        m[i] = ok[i] ? (ov ? rb[i].x : cnt) : 0u;
-        ovm |= (ok[i] && ov) ? (1u << i) : 0u;
+        m[i] = ok[i] ? (ra[i].x & 63u) : 0u;
+        xm |= m[i] > 2 ? (1u << i) : 0u;
         k_lane += m[i];
     }
-    const bool lists = __ballot(ovm != 0) != 0;
+    uint4 rb[4];
+    const bool more = __ballot(xm != 0) != 0;
+    if (more) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            rb[i] = make_uint4(0, 0, 0, 0);
+            if ((xm >> i) & 1u) {
+                const uint32_t x = ((ra[i].x >> 8) & 0xFFu) | ((ra[i].z & 63u) << 8) | (((ra[i].z >> 8) & 0xFFu) << 14);
+                rb[i] = ((const uint4 *)P.fr_fl3)[x];
+            }
+        }
+    }
     uint32_t o = 0;
     if (GEN) {
         const uint32_t xs = wave_incl_sum(k_lane);
@@ -497,29 +504,35 @@ __device__ __forceinline__ bool walk_entries(const DevProg &P, const WalkLds &T,
         o = n_out + xs - k_lane;
         n_out += ktot;
     }
+    // bits 0..5 and 8..15 of a stored entry (count, extension offset) give way to the tag
+    const uint64_t keep = ~0xFF3Full;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const uint64_t tag = (uint64_t)(at[i] & 63u) | ((uint64_t)stp[i] << 8);
-        const uint64_t e[4] = {(((uint64_t)ra[i].y << 32) | ra[i].x) & ~63ull, ((uint64_t)ra[i].w << 32) | ra[i].z,
-                               ((uint64_t)rb[i].y << 32) | rb[i].x, ((uint64_t)rb[i].w << 32) | rb[i].z};
-        const bool in_rec = !((ovm >> i) & 1u);
+        uint64_t e[4] = {((((uint64_t)ra[i].y << 32) | ra[i].x) & keep) | tag,
+                         ((((uint64_t)ra[i].w << 32) | ra[i].z) & keep) | tag, 0, 0};
+        if (more) {
+            e[2] = (((uint64_t)rb[i].y << 32) | rb[i].x) | tag;
+            e[3] = (((uint64_t)rb[i].w << 32) | rb[i].z) | tag;
+        }
 #pragma unroll
         for (uint32_t q = 0; q < 4; ++q) {
-            if (in_rec && q < m[i]) {
+            if (q < m[i]) {
                 if (GEN) {
-                    if (o + q < cap) out[o + q] = e[q] | tag;
+                    if (o + q < cap) out[o + q] = e[q];
                 } else {
-                    apply(e[q] | tag);
+                    apply(e[q]);
                 }
             }
         }
-        if (lists && !in_rec) {
-            const uint64_t *l = P.fr_fl3 + e[1];
-            for (uint32_t q = 0; q < m[i]; ++q) {
+        if (more && m[i] > 4) {
+            const uint32_t x = ((ra[i].x >> 8) & 0xFFu) | ((ra[i].z & 63u) << 8) | (((ra[i].z >> 8) & 0xFFu) << 14);
+            const uint64_t *l = P.fr_fl3 + 2 * (size_t)x;
+            for (uint32_t q = 4; q < m[i]; ++q) {
                 if (GEN) {
-                    if (o + q < cap) out[o + q] = l[q] | tag;
+                    if (o + q < cap) out[o + q] = l[q - 2] | tag;
                 } else {
-                    apply(l[q] | tag);
+                    apply(l[q - 2] | tag);
                 }
             }
         }

@@ -33,12 +33,13 @@ namespace symft {
 // Flip entries of one (channel, branch): ceil(n / 4) entries
 // (k - 1) << 6 | s0 << 16 | s1 << 28 | s2 << 40 | s3 << 52 (k = slots in the
 // entry, 1..4; slots below 2^12, which every schedule that fits the
-// step-synchronous kernel's LDS satisfies).  The branch's flip record holds
-// four such entries, the entry count in the lane bits (0..5) of the first; a
-// branch with more than four entries keeps them in fl3 instead, its record
-// holding 63 (first), the list offset (second) and the entry count (third).
-// The lane and step bits of every stored entry are zero.
-static void pack_record(const std::vector<uint32_t> &fl, std::vector<uint64_t> &rec, std::vector<uint64_t> &fl3) {
+// step-synchronous kernel's LDS satisfies).  The branch's 16-byte flip record
+// holds the first two entries, the entry count m < 64 in the lane bits
+// (0..5) of the first; with m > 2 the others sit in ext from entry 2 X on
+// (X even, so a 16-byte load reads two), X stored in the bits that are zero in
+// entries at rest: step bits (8..15) of the first entry, lane and step bits of
+// the second.  Returns false when a branch has 64 entries or more.
+static bool pack_record(const std::vector<uint32_t> &fl, std::vector<uint64_t> &rec, std::vector<uint64_t> &ext) {
     std::vector<uint64_t> es;
     for (size_t i = 0; i < fl.size(); i += 4) {
         const size_t cnt = std::min<size_t>(4, fl.size() - i);
@@ -46,17 +47,20 @@ static void pack_record(const std::vector<uint32_t> &fl, std::vector<uint64_t> &
         for (size_t q = 0; q < cnt; ++q) e |= (uint64_t)(fl[i + q] & 0xFFFu) << (16 + 12 * q);
         es.push_back(e);
     }
-    uint64_t r[4] = {0, 0, 0, 0};
-    if (es.size() <= 4) {
-        for (size_t q = 0; q < es.size(); ++q) r[q] = es[q];
-        r[0] |= (uint64_t)es.size();
-    } else {
-        r[0] = 63;
-        r[1] = fl3.size();
-        r[2] = es.size();
-        fl3.insert(fl3.end(), es.begin(), es.end());
+    if (es.size() >= 64) return false;
+    uint64_t r0 = es.empty() ? 0 : es[0], r1 = es.size() > 1 ? es[1] : 0;
+    r0 |= (uint64_t)es.size();
+    if (es.size() > 2) {
+        const uint64_t x = ext.size() / 2;  // in 16-byte units
+        if (x >= (1u << 22)) return false;
+        ext.insert(ext.end(), es.begin() + 2, es.end());
+        if (ext.size() & 1) ext.push_back(0);
+        r0 |= (x & 0xFFu) << 8;
+        r1 |= ((x >> 8) & 63u) | (((x >> 14) & 0xFFu) << 8);
     }
-    rec.insert(rec.end(), r, r + 4);
+    rec.push_back(r0);
+    rec.push_back(r1);
+    return true;
 }
 
 // Elements of odd total multiplicity in a and b: the sum over GF(2) of two
@@ -425,7 +429,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
         const Channel &ch = P.chans[c];
         chan_thr[c] = thr_off;
         thr_off += ch.thr.size();
-        chan_fl[c] = F.frec.size() / 4;
+        chan_fl[c] = F.frec.size() / 2;
         for (uint32_t j = 0; j < ch.J; ++j) {
             std::map<uint32_t, int> par;
             for (uint32_t i = 0; i < ch.nsym; ++i)
@@ -435,7 +439,7 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             for (auto &kv : par)
                 if (kv.second) fl.push_back(kv.first);
             F.n_flips += fl.size();
-            pack_record(fl, F.frec, F.fl3);
+            if (!pack_record(fl, F.frec, F.fl3)) return;
             if (fl.size() <= 3 && !fl.empty()) {
                 uint64_t w = fl.size();
                 for (size_t q = 0; q < fl.size(); ++q) w |= (uint64_t)fl[q] << (16 + 16 * q);

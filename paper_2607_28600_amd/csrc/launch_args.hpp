@@ -146,8 +146,8 @@ struct FrameSchedule {
     std::vector<uint32_t> nodes;    // 8 per node
     std::vector<uint32_t> push;
     std::vector<uint64_t> chinfo;   // indexed by class offset + rank
-    std::vector<uint64_t> frec;     // per (channel, branch): flip record, four entries (see pack_record)
-    std::vector<uint64_t> fl3;      // flip entries of branches with more than four: (k - 1) << 6 | four 12-bit slots
+    std::vector<uint64_t> frec;     // per (channel, branch): 16-byte flip record, two entries (see pack_record)
+    std::vector<uint64_t> fl3;      // flip entries past a record's two: (k - 1) << 6 | four 12-bit slots
     bool rec_ok = false;            // slots below 2^12 (the step kernel's entries)
     std::vector<uint32_t> cls_cap;  // flip entries kept per (word, class)
     std::vector<uint32_t> ci32;     // per (class, rank): flip-table offset | J << 20 (uniform channels)
