@@ -323,6 +323,28 @@ symft_status symft_sample_counts(const symft_program *p, const symft_count_opts 
  * programs).  Errors as symft_sample_counts. */
 symft_status symft_autotune_counts(const symft_program *p, const symft_count_opts *opts, uint32_t *tps_out);
 
+/* Aggregate counts for n programs in one persistent launch (paper Sec. 6:
+ * detector postselection in the batch sampler): symft_sample_counts run
+ * inside symft_sample_batch's work queue.  Program i samples shots[i] shots
+ * with seeds[i] under opts[i] (host array of n, or NULL: nothing
+ * postselected, every observable expected 0); of opts[i] only shot_offset,
+ * n_post, post and obs_expected are used (precision is the batch's; the
+ * launch configuration is the batch's own).
+ *   flags_out   host array of n device pointers, or NULL; an entry is NULL
+ *               or 2 x ceil(shots[i]/64) words, as in symft_sample_counts.
+ *   counts_out  device, 2n uint64, or NULL: program i's discarded and
+ *               logical-error counts are ADDED to counts_out[2i], [2i + 1].
+ * A shot group leaves the instruction stream at its rejecting detector, and
+ * a work item's groups leave it once all of them are rejected.  Programs
+ * that need their own kernel (pure frame, or vectors that do not fit LDS)
+ * run as symft_sample_counts calls on the same stream.  `graph`, plan
+ * caching and the no-overlap rule as in symft_sample_batch (a replayed graph
+ * adds to the counters again).  Errors as symft_sample_counts, plus EINVAL
+ * for a NULL program. */
+symft_status symft_sample_counts_batch(const symft_program *const *progs, const uint64_t *shots, const uint64_t *seeds,
+                                       const symft_count_opts *opts, uint64_t *const *flags_out, uint64_t *counts_out,
+                                       size_t n, uint32_t precision, uint32_t graph, void *stream);
+
 /* Autotuner: times each threads-per-shot configuration (4 .. 256) of the
  * active-state kernel that fits LDS on 4096 words of this program (at peak
  * widths 13 and 14: 64 .. 256 with vectors in HBM, and 1024, on 1024 words; at

@@ -101,6 +101,10 @@ _lib.symft_autotune_counts.argtypes = [C.c_void_p, C.POINTER(symft_count_opts), 
 _lib.symft_sample_batch.restype = C.c_int32
 _lib.symft_sample_batch.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                     C.POINTER(C.c_void_p), C.c_size_t, C.c_uint32, C.c_uint32, C.c_void_p]
+_lib.symft_sample_counts_batch.restype = C.c_int32
+_lib.symft_sample_counts_batch.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                           C.POINTER(symft_count_opts), C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t,
+                                           C.c_uint32, C.c_uint32, C.c_void_p]
 _lib.symft_autotune.restype = C.c_int32
 _lib.symft_autotune.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32)]
 _lib.symft_gap_check.restype = C.c_int32
@@ -118,7 +122,7 @@ _lib.symft_last_error.restype = C.c_char_p
 
 EXPORTED = ["symft_compile", "symft_program_info", "symft_program_plan", "symft_program_export",
             "symft_sample", "symft_sample_ex", "symft_sample_counts", "symft_autotune_counts",
-            "symft_sample_noalloc", "symft_sample_batch", "symft_autotune", "symft_probe", "symft_probe_amplitudes", "symft_gap_check", "symft_program_free",
+            "symft_sample_noalloc", "symft_sample_batch", "symft_sample_counts_batch", "symft_autotune", "symft_probe", "symft_probe_amplitudes", "symft_gap_check", "symft_program_free",
             "symft_last_error"]
 
 
@@ -378,6 +382,33 @@ def sample_batch(programs: Sequence[Program], shots: Sequence[int], seeds: Seque
         stream = torch.cuda.current_stream().cuda_stream
     _check(_lib.symft_sample_batch(hs, sh, sd, op, n, 0 if precision == "fp64" else 1, 1 if graph else 0,
                                    C.c_void_p(stream)), "symft_sample_batch")
+
+
+def sample_counts_batch(programs: Sequence[Program], shots: Sequence[int], seeds: Sequence[int], posts, flags,
+                        counts, obs_expected=None, shot_offsets=None, precision: str = "fp32", graph: bool = False,
+                        stream=None) -> None:
+    """symft_sample_counts_batch: posts[i] (detector indices) and obs_expected[i] (or None) per program; flags
+    (list of device [2, ceil(shots[i]/64)] tensors or None) and counts (device [2n] int64 tensor or None)."""
+    import torch
+    n = len(programs)
+    hs = (C.c_void_p * n)(*[p.handle.value for p in programs])
+    sh = (C.c_uint64 * n)(*[int(s) for s in shots])
+    sd = (C.c_uint64 * n)(*[int(s) for s in seeds])
+    opts = (symft_count_opts * n)()
+    keep = []
+    for i, p in enumerate(programs):
+        o, k = p._count_opts(posts[i], None if obs_expected is None else obs_expected[i],
+                             0 if shot_offsets is None else int(shot_offsets[i]), precision, 0)
+        opts[i] = o
+        keep.append(k)
+    fp = None
+    if flags is not None:
+        fp = (C.c_void_p * n)(*[None if f is None else f.data_ptr() for f in flags])
+    cp = None if counts is None else counts.data_ptr()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(_lib.symft_sample_counts_batch(hs, sh, sd, opts, fp, C.c_void_p(cp), n, 0 if precision == "fp64" else 1,
+                                          1 if graph else 0, C.c_void_p(stream)), "symft_sample_counts_batch")
 
 
 def bits_to_numpy(t) -> np.ndarray:

@@ -24,8 +24,8 @@ struct FrameArgs;
 struct CountArgs;
 hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st, uint32_t tw);
 struct BatchArgs;
-hipError_t launch_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t lds, hipStream_t st);
-int batch_max_blocks_per_cu(bool fp64, size_t lds);
+hipError_t launch_batch(const BatchArgs &B, bool fp64, bool cm, uint32_t grid, uint32_t lds, hipStream_t st);
+int batch_max_blocks_per_cu(bool fp64, bool cm, size_t lds);
 size_t frame_lds_bytes(const DevProg &P, uint32_t tw);
 hipError_t launch_flags_from_rows(const uint64_t *rows, uint64_t n_words, uint64_t shots, uint64_t n_rec,
                                   uint32_t n_det, uint32_t n_obs, const CountArgs &C, uint64_t flag_off,
@@ -1361,11 +1361,14 @@ struct BatchPlan {
     BatchArgs args;
     uint32_t grid = 0, lds = 0;
     std::vector<size_t> others;  // programs sampled by their own launches
+    // aggregate-count plans: the count tables' contents and the counters, compared with sig
+    bool cm = false;
+    std::vector<uint64_t> sig;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     bool same(const symft_program *const *p, const uint64_t *sh, const uint64_t *sd, uint64_t *const *o, size_t n,
               uint32_t prec, int dev) const {
-        if (n != progs.size() || prec != precision || dev != device) return false;
+        if (cm || n != progs.size() || prec != precision || dev != device) return false;
         for (size_t i = 0; i < n; ++i)
             if (p[i] != progs[i] || (p[i] && p[i]->serial != serials[i]) || sh[i] != shots[i] || sd[i] != seeds[i] ||
                 o[i] != outs[i])
@@ -1405,15 +1408,19 @@ static void drop_batch_plans(const symft_program *p) {
     }
 }
 
+// cnt (count plans): per program its count tables, flags and counters, and
+// its first word; outs is then unused.
 static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, const uint64_t *shots,
-                               const uint64_t *seeds, uint64_t *const *outs, size_t n, uint32_t precision) {
+                               const uint64_t *seeds, uint64_t *const *outs, size_t n, uint32_t precision,
+                               const CountArgs *cnt = nullptr, const uint64_t *word0 = nullptr) {
     const bool fp64 = precision == 0;
+    B.cm = cnt != nullptr;
     B.progs.assign(progs, progs + n);
     B.serials.resize(n);
     for (size_t i = 0; i < n; ++i) B.serials[i] = progs[i] ? progs[i]->serial : 0;
     B.shots.assign(shots, shots + n);
     B.seeds.assign(seeds, seeds + n);
-    B.outs.assign(outs, outs + n);
+    if (!cnt) B.outs.assign(outs, outs + n);
     B.precision = precision;
     (void)hipGetDevice(&B.device);
     std::vector<ActiveArgs> calls;
@@ -1422,7 +1429,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
     size_t lds = 0;
     for (size_t i = 0; i < n; ++i) {
         symft_program *p = const_cast<symft_program *>(progs[i]);
-        if (!p || (shots[i] && !outs[i])) return set_err(SYMFT_EINVAL, "NULL program or output in batch");
+        if (!p || (!cnt && shots[i] && !outs[i])) return set_err(SYMFT_EINVAL, "NULL program or output in batch");
         DevProg D;
         symft_status rc = device_prog(p, D);
         if (rc) return rc;
@@ -1449,12 +1456,13 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         std::memset(&A, 0, sizeof(A));
         A.P = D;
         A.seed = seeds[i];
-        A.word_begin = 0;
+        A.word_begin = word0 ? word0[i] : 0;
         A.n_words = (shots[i] + 63) / 64;
         A.shots = shots[i];
-        A.out = outs[i];
+        A.out = cnt ? nullptr : outs[i];
         A.row_stride = A.n_words;
-        A.sections = 7u;
+        A.sections = cnt ? 0u : 7u;
+        if (cnt) A.cnt = cnt[i];
         A.tps = c.tps;
         A.lds_vec = 1;
         A.lds_bytes = (uint32_t)c.lds;
@@ -1467,7 +1475,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
     }
     std::vector<BatchItem> items;
     if (!calls.empty()) {
-        int per_cu = std::max(1, batch_max_blocks_per_cu(fp64, lds));
+        int per_cu = std::max(1, batch_max_blocks_per_cu(fp64, B.cm, lds));
         B.grid = (uint32_t)(per_cu * num_cus());
         uint64_t total_words = 0;
         for (uint64_t w : words_of) total_words += w;
@@ -1503,6 +1511,44 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
     return SYMFT_OK;
 }
 
+// The plan's persistent kernel (after its counter reset), launched directly or
+// through its captured graph.
+static symft_status run_plan(BatchPlan &B, bool fp64, uint32_t graph, hipStream_t st) {
+    if (!B.args.n_items) return SYMFT_OK;
+    if (graph) {
+        if (!B.exec) {
+            // capture [counter reset, persistent kernel] once on a private stream
+            hipStream_t cs;
+            if (hipStreamCreate(&cs) != hipSuccess) return set_err(SYMFT_EHIP, "stream creation failed");
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) e = launch_batch(B.args, fp64, B.cm, B.grid, B.lds, cs);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(cs, &g);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&B.exec, g, nullptr, nullptr, 0);
+            B.graph = g;
+            (void)hipStreamDestroy(cs);
+            if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("batch graph capture failed: ") + hipGetErrorString(e));
+        }
+        hipError_t e = hipGraphLaunch(B.exec, st);
+        if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("batch graph launch failed: ") + hipGetErrorString(e));
+    } else {
+        hipError_t e = launch_batch(B.args, fp64, B.cm, B.grid, B.lds, st);
+        if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("batch kernel launch failed: ") + hipGetErrorString(e));
+    }
+    return SYMFT_OK;
+}
+
+// A new plan at the front of the cache, which keeps the four most recent.
+static void keep_plan(BatchPlan *B) {
+    g_plans.insert(g_plans.begin(), B);
+    while (g_plans.size() > 4) {
+        g_plans.back()->release();
+        delete g_plans.back();
+        g_plans.pop_back();
+    }
+}
+
 symft_status symft_sample_batch(const symft_program *const *progs, const uint64_t *shots, const uint64_t *seeds,
                                 uint64_t *const *records_out, size_t n, uint32_t precision, uint32_t graph,
                                 void *stream) {
@@ -1527,43 +1573,83 @@ symft_status symft_sample_batch(const symft_program *const *progs, const uint64_
             delete B;
             return rc;
         }
-        g_plans.insert(g_plans.begin(), B);
-        while (g_plans.size() > 4) {
-            g_plans.back()->release();
-            delete g_plans.back();
-            g_plans.pop_back();
-        }
+        keep_plan(B);
     }
-    const bool fp64 = precision == 0;
-    if (B->args.n_items) {
-        if (graph) {
-            if (!B->exec) {
-                // capture [counter reset, persistent kernel] once on a private stream
-                hipStream_t cs;
-                if (hipStreamCreate(&cs) != hipSuccess) return set_err(SYMFT_EHIP, "stream creation failed");
-                hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-                if (e == hipSuccess) e = launch_batch(B->args, fp64, B->grid, B->lds, cs);
-                hipGraph_t g = nullptr;
-                hipError_t e2 = hipStreamEndCapture(cs, &g);
-                if (e == hipSuccess) e = e2;
-                if (e == hipSuccess) e = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
-                B->graph = g;
-                (void)hipStreamDestroy(cs);
-                if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("batch graph capture failed: ") + hipGetErrorString(e));
-            }
-            hipError_t e = hipGraphLaunch(B->exec, st);
-            if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("batch graph launch failed: ") + hipGetErrorString(e));
-        } else {
-            hipError_t e = launch_batch(B->args, fp64, B->grid, B->lds, st);
-            if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("batch kernel launch failed: ") + hipGetErrorString(e));
-        }
-    }
+    const symft_status rc = run_plan(*B, precision == 0, graph, st);
+    if (rc) return rc;
     for (size_t i : B->others) {
         symft_sample_opts o;
         std::memset(&o, 0, sizeof(o));
         o.precision = precision;
         symft_status rc = symft_sample_ex(progs[i], &o, shots[i], seeds[i], records_out[i], stream);
         if (rc) return rc;
+    }
+    return SYMFT_OK;
+}
+
+symft_status symft_sample_counts_batch(const symft_program *const *progs, const uint64_t *shots, const uint64_t *seeds,
+                                       const symft_count_opts *opts, uint64_t *const *flags_out, uint64_t *counts_out,
+                                       size_t n, uint32_t precision, uint32_t graph, void *stream) {
+    if (n == 0) return SYMFT_OK;
+    if (!progs || !shots || !seeds) return set_err(SYMFT_EINVAL, "NULL argument");
+    if (precision > 1) return set_err(SYMFT_EINVAL, "precision must be 0 or 1");
+    std::vector<CountArgs> cnt(n);
+    std::vector<uint64_t> word0(n, 0);
+    std::vector<uint64_t> sig;
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    sig.push_back(n);
+    sig.push_back(precision);
+    sig.push_back((uint64_t)dev);
+    for (size_t i = 0; i < n; ++i) {
+        symft_program *p = const_cast<symft_program *>(progs[i]);
+        if (!p) return set_err(SYMFT_EINVAL, "NULL program in batch");
+        symft_count_opts o;
+        std::memset(&o, 0, sizeof(o));
+        if (opts) o = opts[i];
+        if (o.shot_offset % 64) return set_err(SYMFT_EINVAL, "shot_offset must be a multiple of 64");
+        if (o.n_post && !o.post) return set_err(SYMFT_EINVAL, "post is NULL");
+        std::memset(&cnt[i], 0, sizeof(CountArgs));
+        std::vector<uint32_t> key;
+        symft_status rc = count_tables(p, o, cnt[i], &key);
+        if (rc) return rc;
+        cnt[i].flags = flags_out ? flags_out[i] : nullptr;
+        cnt[i].counts = counts_out ? (unsigned long long *)(counts_out + 2 * i) : nullptr;
+        word0[i] = o.shot_offset / 64;
+        sig.insert(sig.end(), {(uint64_t)(uintptr_t)p, p->serial, shots[i], seeds[i],
+                               (uint64_t)(uintptr_t)cnt[i].flags, (uint64_t)(uintptr_t)cnt[i].counts, word0[i],
+                               (uint64_t)key.size()});
+        sig.insert(sig.end(), key.begin(), key.end());
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchPlan *B = nullptr;
+    for (size_t i = 0; i < g_plans.size(); ++i)
+        if (g_plans[i]->cm && g_plans[i]->sig == sig) {
+            B = g_plans[i];
+            break;
+        }
+    if (!B) {
+        B = new BatchPlan();
+        symft_status rc = build_plan(*B, progs, shots, seeds, nullptr, n, precision, cnt.data(), word0.data());
+        if (rc) {
+            B->release();
+            delete B;
+            return rc;
+        }
+        B->sig = sig;
+        keep_plan(B);
+    }
+    const symft_status rc = run_plan(*B, precision == 0, graph, st);
+    if (rc) return rc;
+    for (size_t i : B->others) {
+        symft_count_opts o;
+        std::memset(&o, 0, sizeof(o));
+        if (opts) o = opts[i];
+        o.precision = precision;
+        symft_status r2 = symft_sample_counts(progs[i], &o, shots[i], seeds[i], flags_out ? flags_out[i] : nullptr,
+                                              counts_out ? counts_out + 2 * i : nullptr, stream);
+        if (r2) return r2;
     }
     return SYMFT_OK;
 }

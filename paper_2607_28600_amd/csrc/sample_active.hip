@@ -724,7 +724,7 @@ __global__ void __launch_bounds__(BS) active_kernel(ActiveArgs A) {
 // Persistent work queue over (program, word range) items: every workgroup
 // takes the next item index with a global atomic until the list is exhausted,
 // so every wave reaches the exit.  Items are ordered by decreasing cost.
-template <typename T, int BS>
+template <typename T, int BS, bool CM>
 __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs B) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_idx;
@@ -735,7 +735,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs B) {
         __syncthreads();
         if (idx >= B.n_items) break;
         const BatchItem it = B.items[idx];
-        run_active_words<T, BS, true, false>(B.calls[it.call], it.w0, it.w1, 1, blockIdx.x, smem);
+        run_active_words<T, BS, true, CM>(B.calls[it.call], it.w0, it.w1, 1, blockIdx.x, smem);
     }
 }
 
@@ -850,9 +850,9 @@ int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds, b
     return dispatch<BlocksPerCu>(fp64, bs, lds_vec, cm, lds);
 }
 
-template <typename T>
+template <typename T, bool CM>
 static hipError_t launch_batch_t(const BatchArgs &B, uint32_t grid, uint32_t lds, hipStream_t st) {
-    auto kfn = batch_kernel<T, 256>;
+    auto kfn = batch_kernel<T, 256, CM>;
     hipError_t e = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, B.counter);
@@ -860,14 +860,16 @@ static hipError_t launch_batch_t(const BatchArgs &B, uint32_t grid, uint32_t lds
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t lds, hipStream_t st) {
-    return fp64 ? launch_batch_t<double>(B, grid, lds, st) : launch_batch_t<float>(B, grid, lds, st);
+hipError_t launch_batch(const BatchArgs &B, bool fp64, bool cm, uint32_t grid, uint32_t lds, hipStream_t st) {
+    if (cm) return fp64 ? launch_batch_t<double, true>(B, grid, lds, st) : launch_batch_t<float, true>(B, grid, lds, st);
+    return fp64 ? launch_batch_t<double, false>(B, grid, lds, st) : launch_batch_t<float, false>(B, grid, lds, st);
 }
 
-int batch_max_blocks_per_cu(bool fp64, size_t lds) {
+int batch_max_blocks_per_cu(bool fp64, bool cm, size_t lds) {
     int nb = 0;
-    hipError_t e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<double, 256>, 256, lds)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<float, 256>, 256, lds);
+    const void *k = cm ? (fp64 ? (const void *)batch_kernel<double, 256, true> : (const void *)batch_kernel<float, 256, true>)
+                       : (fp64 ? (const void *)batch_kernel<double, 256, false> : (const void *)batch_kernel<float, 256, false>);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, lds);
     return e == hipSuccess ? nb : 1;
 }
 
