@@ -98,7 +98,7 @@ struct HostLayout {
     std::vector<uint8_t> blob;
     // offsets of each array inside blob
     size_t o_instr, o_cmeas, o_am, o_rm, o_recmeas, o_detoff, o_detrows, o_obsoff, o_obsrows, o_clsQ, o_clsoff, o_clschan,
-        o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_invlog, o_clsfast, o_frstep, o_frnodes, o_frpush, o_frchinfo,
+        o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_invlog, o_clsfast, o_frstep, o_frnodes, o_frpush, o_frnodes16, o_frpush16, o_frchinfo,
         o_frrec, o_frfl3, o_frcap, o_frcapoff, o_wvops, o_wvrows, o_wvfl, o_wvsl, o_wvrm, o_wvcap, o_wvcapoff, o_ci32, o_st8, o_q32;
     uint32_t word_entries = 0;  // flip entries per word over all classes (frame kernel scratch)
     uint32_t wv_word_entries = 0;  // slot flips per word over all classes (wave kernel scratch)
@@ -283,6 +283,8 @@ static void lower(symft_program *h) {
     L.o_frstep = put(L.blob, h->F.steps);
     L.o_frnodes = put(L.blob, h->F.nodes);
     L.o_frpush = put(L.blob, h->F.push);
+    L.o_frnodes16 = put(L.blob, h->F.nodes16);
+    L.o_frpush16 = put(L.blob, h->F.push16);
     L.o_frchinfo = put(L.blob, h->F.chinfo);
     L.o_ci32 = put(L.blob, h->F.ci32);
     L.o_st8 = put(L.blob, h->F.st8);
@@ -402,6 +404,8 @@ static symft_status device_prog(symft_program *h, DevProg &out, bool upload = tr
     out.fr_step = (const uint32_t *)(b + L.o_frstep);
     out.fr_nodes = (const uint32_t *)(b + L.o_frnodes);
     out.fr_push = (const uint32_t *)(b + L.o_frpush);
+    out.fr_nodes16 = (const uint32_t *)(b + L.o_frnodes16);
+    out.fr_push16 = (const uint32_t *)(b + L.o_frpush16);
     out.fr_chinfo = (const uint64_t *)(b + L.o_frchinfo);
     out.fr_ci32 = (const uint32_t *)(b + L.o_ci32);
     out.fr_st8 = (const uint8_t *)(b + L.o_st8);

@@ -86,6 +86,9 @@ struct DevProg {
     const uint32_t *fr_step;     // 8 words per step (launch_args.hpp)
     const uint32_t *fr_nodes;    // 8 words per node: slot | flags << 24, row, meas, push count, two successor slots, push offset, 0
     const uint32_t *fr_push;     // successor slots
+    const uint32_t *fr_nodes16;  // 4 words per node: slot | flags << 12 | push count << 20, row,
+                                 // successor slots s0 | s1 << 12, offset into fr_push16
+    const uint32_t *fr_push16;   // per node: its measurement if RandomMeas, then successor slots past two
     const uint64_t *fr_chinfo;   // per (class, rank): flip-table offset | J << 26 | uniform << 32 | step << 33 | thr_off << 41
     const uint64_t *fr_frec;     // per (channel, branch): flip record of two entries (16 bytes, 16-byte aligned)
     const uint64_t *fr_fl3;      // flip entries past a record's two, from an even index (16-byte aligned)

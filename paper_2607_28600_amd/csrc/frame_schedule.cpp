@@ -552,6 +552,18 @@ void build_frame_schedule(const Program &P, FrameSchedule &F) {
             F.nodes.push_back(v.rm ? (uint32_t)F.rm_meas.size() : 0u);  // RandomMeas index (wave kernel)
             if (v.rm) F.rm_meas.push_back(v.rm_t);
             for (uint32_t k = 2; k < np; ++k) F.push.push_back((uint32_t)nd[v.succs[k]].slot);
+            // compact record (step-synchronous kernel), 4 words: slot | flags << 12 | push count << 20, row,
+            // two successor slots (12 bits each), offset into push16 (a RandomMeas node's measurement first,
+            // then its successors past the first two)
+            const uint32_t sl = v.slot >= 0 ? (uint32_t)v.slot : F.n_slots;
+            if (sl >= (1u << 12) || np >= (1u << 12)) F.rec_ok = false;
+            F.nodes16.push_back(sl | (flags << 12) | (np << 20));
+            F.nodes16.push_back(v.row);
+            F.nodes16.push_back((np > 0 ? (uint32_t)nd[v.succs[0]].slot : 0u) |
+                                ((np > 1 ? (uint32_t)nd[v.succs[1]].slot : 0u) << 12));
+            F.nodes16.push_back((uint32_t)F.push16.size());
+            if (v.rm) F.push16.push_back(v.rm_t);
+            for (uint32_t k = 2; k < np; ++k) F.push16.push_back((uint32_t)nd[v.succs[k]].slot);
         }
     }
     F.n_pushes = 0;

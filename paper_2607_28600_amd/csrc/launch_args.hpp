@@ -145,6 +145,8 @@ struct FrameSchedule {
     uint32_t first_noise_cls = 0xFFFFFFFFu;     // class of the first NOISE step
     std::vector<uint32_t> nodes;    // 8 per node
     std::vector<uint32_t> push;
+    std::vector<uint32_t> nodes16;  // 4 per node, the step-synchronous kernel's compact records
+    std::vector<uint32_t> push16;   // their lists: a RandomMeas node's measurement, then successor slots
     std::vector<uint64_t> chinfo;   // indexed by class offset + rank
     std::vector<uint64_t> frec;     // per (channel, branch): 16-byte flip record, two entries (see pack_record)
     std::vector<uint64_t> fl3;      // flip entries past a record's two: (k - 1) << 6 | four 12-bit slots

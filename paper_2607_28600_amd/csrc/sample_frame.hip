@@ -116,16 +116,16 @@ __device__ __forceinline__ void noise_direct(const DevProg &P, uint32_t c, uint3
 // row stored (the node's QPN tasks are adjacent threads, so a row of the tile
 // goes out as whole lines) and the values XOR-ed into the successors' slots.
 template <uint32_t TW>
-__device__ __forceinline__ void emit_quad(const DevProg &P, const FrameArgs &A, uint4 ra, uint4 rb, uint32_t q,
+__device__ __forceinline__ void emit_quad(const DevProg &P, const FrameArgs &A, uint4 ra, uint32_t q,
                                           uint64_t wt, bool full, unsigned long long *slots, unsigned long long *fl,
                                           uint32_t k0, uint32_t k1) {
     const uint32_t wl = 4 * (q % Tile<TW>::QPN);
-    const uint32_t flags = ra.x >> 24;
+    const uint32_t flags = (ra.x >> 12) & 0xFFu;
     const unsigned long long c = (flags & 1u) ? ~0ull : 0ull;
     unsigned long long v[4] = {c, c, c, c};
     {
         // a node with no contributions reads the extra slot past the schedule's, which stays zero
-        const uint32_t sl = ra.x & 0xFFFFFFu, x = sl & 3u;
+        const uint32_t sl = ra.x & 0xFFFu, x = sl & 3u;
         unsigned long long *sp = slot_quad<TW>(slots, sl, wl);
 #pragma unroll
         for (uint32_t i = 0; i < 4; ++i) v[i] ^= sp[i ^ x];
@@ -137,9 +137,10 @@ __device__ __forceinline__ void emit_quad(const DevProg &P, const FrameArgs &A, 
         // each pass adds the word to v[0] and rotates, which after four passes
         // leaves every word back in place
         const uint64_t w = A.word_begin + wt + wl;
+        const uint32_t rm_t = P.fr_push16[ra.w];
 #pragma unroll 1
         for (uint32_t i = 0; i < 4; ++i) {
-            const unsigned long long t = v[0] ^ rm_word(ra.z, w + i, k0, k1);
+            const unsigned long long t = v[0] ^ rm_word(rm_t, w + i, k0, k1);
             v[0] = v[1];
             v[1] = v[2];
             v[2] = v[3];
@@ -186,10 +187,11 @@ __device__ __forceinline__ void emit_quad(const DevProg &P, const FrameArgs &A, 
             }
         }
     }
-    const uint32_t np = ra.w;
-    if (np > 0) push_quad<TW>(slots, rb.x, wl, v);
-    if (np > 1) push_quad<TW>(slots, rb.y, wl, v);
-    for (uint32_t k = 2; k < np; ++k) push_quad<TW>(slots, P.fr_push[rb.z + k - 2], wl, v);
+    const uint32_t np = ra.x >> 20;
+    if (np > 0) push_quad<TW>(slots, ra.z & 0xFFFu, wl, v);
+    if (np > 1) push_quad<TW>(slots, (ra.z >> 12) & 0xFFFu, wl, v);
+    const uint32_t lb = ra.w + ((flags >> 2) & 1u);  // past a RandomMeas node's measurement
+    for (uint32_t k = 2; k < np; ++k) push_quad<TW>(slots, P.fr_push16[lb + k - 2], wl, v);
 }
 
 // Phase G of one tile: each wave walks the streams of its words, class by
@@ -298,20 +300,12 @@ __global__ void __launch_bounds__(TW * 32) __attribute__((amdgpu_waves_per_eu(4)
         }
         // phase S
         const cptr<uint32_t> stp = uniform(P.fr_step);
-        uint4 pa = make_uint4(0, 0, 0, 0), pb = pa, pa2 = pa, pb2 = pa;
+        uint4 pa = make_uint4(0, 0, 0, 0), pa2 = pa;
         uint64_t pe[WPW];
         uint32_t pk[WPW];
         auto fetch_records = [&](uint32_t first, uint32_t n) {
-            if (tid < n * QPN) {
-                const uint4 *rec = (const uint4 *)(P.fr_nodes + 8 * (size_t)(first + tid / QPN));
-                pa = rec[0];
-                pb = rec[1];
-            }
-            if (tid + NT < n * QPN) {
-                const uint4 *rec = (const uint4 *)(P.fr_nodes + 8 * (size_t)(first + (tid + NT) / QPN));
-                pa2 = rec[0];
-                pb2 = rec[1];
-            }
+            if (tid < n * QPN) pa = ((const uint4 *)P.fr_nodes16)[first + tid / QPN];
+            if (tid + NT < n * QPN) pa2 = ((const uint4 *)P.fr_nodes16)[first + (tid + NT) / QPN];
         };
         auto fetch_entries = [&](uint32_t c) {
 #pragma unroll
@@ -370,12 +364,12 @@ __global__ void __launch_bounds__(TW * 32) __attribute__((amdgpu_waves_per_eu(4)
             // Take the data fetched for this step before issuing any store: a wait
             // on vector memory covers every operation issued before it, so a load
             // consumed behind fresh stores would wait for the stores as well.
-            const uint4 ra = pa, rb = pb, ra2 = pa2, rb2 = pb2;
+            const uint4 ra = pa, ra2 = pa2;
             if (is_emit) {
                 const uint32_t n = r[2];
                 fetch_records(r[5], r[6]);
-                if (tid < n * QPN) emit_quad<TW>(P, A, ra, rb, tid, wt, full, slots, fl, k0, k1);
-                if (tid + NT < n * QPN) emit_quad<TW>(P, A, ra2, rb2, tid + NT, wt, full, slots, fl, k0, k1);
+                if (tid < n * QPN) emit_quad<TW>(P, A, ra, tid, wt, full, slots, fl, k0, k1);
+                if (tid + NT < n * QPN) emit_quad<TW>(P, A, ra2, tid + NT, wt, full, slots, fl, k0, k1);
             } else {
 #pragma unroll
                 for (uint32_t i = 0; i < WPW; ++i) asm volatile("" : : "v"(pe[i]));
