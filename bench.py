@@ -39,11 +39,15 @@ LDS_BYTES = 160 * 1024
 CSRC = os.path.join(ROOT, "paper_2607_28600_amd", "csrc")
 
 # HBM bytes per launch measured with rocprofv3 (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 KiB, the scales
-# read off a 1 GiB device copy; profiles/ holds the runs), with the SHA-256 of the kernel source they
-# were taken on.  A changed source reports traffic null until it is profiled again.
-# The digest covers the kernel's source file and the headers every kernel includes.
-PROFILED_TRAFFIC = {}
-_HEADERS = ["device_program.hpp", "launch_args.hpp", "philox.hpp", "frame_device.hpp"]
+# read off a 1 GiB device copy; profiles/ holds the runs), keyed by (workload, kernel source), with the
+# first 16 hex digits of the SHA-256 of the sources they were taken on (see _HEADERS).  A changed source
+# reports traffic null until it is profiled again.
+PROFILED_TRAFFIC = {
+    ("surface_d11_r11_p1e-3", "sample_frame.hip"): ("8242dc0860e3a9a8", 14387607861),
+}
+# the kernel sources a traffic figure depends on: the kernel file, the shared headers and the host code that
+# lays out the device program
+_HEADERS = ["device_program.hpp", "launch_args.hpp", "philox.hpp", "frame_device.hpp", "frame_schedule.cpp", "capi.cpp"]
 
 
 def _source_sha(name):
