@@ -154,3 +154,35 @@ def test_schedule_past_both_frame_kernels_runs_on_the_active_kernel():
     oc = OracleCircuit(c)
     print("d19 r3: active kernel", flush=True)
     assert np.array_equal(_gpu(p, 64 * 2 - 9, 11, shot_offset=64 * 7), oc.sample(11, 64 * 2 - 9, shot_begin=64 * 7))
+
+
+def _fanout_circuit(n=24, p=0.05):
+    """An error on the control of a CX fan-out flips every later record: an event of up to n + 1 slot flips
+    (seven packed entries: the record's two, two from the extension, three more from its list)."""
+    from workloads.circuit import Circuit
+    c = Circuit(n)
+    c.append("X_ERROR", [0], arg=p)
+    c.append("DEPOLARIZE1", [0], arg=p)
+    c.append("CX", [q for t in range(1, n) for q in (0, t)])
+    c.append("M", list(range(n)))
+    for i in range(n - 1):
+        c.detector([i, i + 1])
+    c.observable(0, [n - 1])
+    return c
+
+
+@pytest.mark.parametrize("fk", [1, 2])
+@pytest.mark.parametrize("cap", [0, 8])
+def test_events_with_many_flips_bit_exact(fk, cap):
+    c = _fanout_circuit()
+    p = S.Program(c)
+    info = p.info()
+    assert info["k_max"] == 0 and info["frame_slots"] > 16
+    oc = OracleCircuit(c)
+    seed = 0xFA9 + fk
+    n = 64 * 40 + 11
+    print(f"fan-out, frame kernel {fk}, cap {cap}", flush=True)
+    assert np.array_equal(_gpu(p, n, seed, frame_entry_cap=cap, frame_kernel=fk), oc.sample(seed, n))
+    off = 64 * 9
+    assert np.array_equal(_gpu(p, 64 * 3, seed, shot_offset=off, frame_entry_cap=cap, frame_kernel=fk),
+                          oc.sample(seed, 64 * 3, shot_begin=off))
