@@ -133,6 +133,7 @@ __device__ __forceinline__ void word_noise(const DevProg &P, uint64_t seed, uint
     for (uint32_t c = 0; c < P.n_cls; ++c) {
         const uint64_t *Q = P.cls_Q + (size_t)c * 4097;
         const float il = P.cls_invlog2q[c];
+        const GapFast F = P.cls_fast[c];
         const uint32_t coff = P.cls_off[c];
         const uint64_t end = (uint64_t)(P.cls_off[c + 1] - coff) * 64;
         uint64_t pos = 0, ev0 = 0, blk0 = 0;
@@ -143,7 +144,9 @@ __device__ __forceinline__ void word_noise(const DevProg &P, uint64_t seed, uint
             uint32_t inc = 0, evc = 0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                G[i] = gap_of(Q, il, v[i]);
+                // the table-free margins, else the three-read window, else the table search (the same
+                // decision as the pure-frame walks)
+                if (!gap_fast_lean(F, v[i], G[i])) G[i] = v[i] >= F.vwin ? gap_window(Q, v[i], G[i]) : gap_of(Q, il, v[i]);
                 inc += (G[i] == 4096) ? 4096u : (uint32_t)G[i] + 1u;
                 evc += (G[i] < 4096) ? 1u : 0u;
             }
