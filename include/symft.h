@@ -248,11 +248,11 @@ symft_status symft_sample_noalloc(const symft_program *p, const symft_sample_opt
  * shots, here also across programs): a work queue over (program, word range)
  * items ordered by decreasing cost.  records_out[i] (device, n_rows(i) x
  * ceil(shots[i]/64) words) receives program i's rows for shots[i] shots with
- * seeds[i]; precision as in symft_sample_opts.  Threads per shot come from
- * the autotuner, run on first use of each (k_max, precision) on a 256-word
- * sample (a batch member shares the GPU, so its own occupancy matters less
- * than for a single launch; these choices are kept apart from
- * symft_autotune's).  `graph` = 1
+ * seeds[i]; precision as in symft_sample_opts.  Threads per shot follow a
+ * fixed rule, not the autotuner: the members share one LDS size (the largest
+ * member's), so each member takes the most shot groups per 256-thread
+ * workgroup whose vectors fit 64 KB (at most 64 groups), which keeps two
+ * workgroups per CU.  `graph` = 1
  * captures the launch (a counter-reset kernel and the persistent kernel) in
  * a HIP graph on first use and replays it on later calls with identical
  * arguments.  Programs that need their own kernel (pure frame, or vectors
@@ -351,8 +351,9 @@ symft_status symft_sample_counts_batch(const symft_program *const *progs, const 
  * widths 9 .. 12 also 64 .. 256 with vectors in HBM instead of LDS;
  * untuned, those widths run 128 threads per shot in FP32 and 256 in FP64; from
  * width 15 on, 1024 always) and keeps the fastest
- * for the program's (peak active width, precision); later launches with that
- * key use it (sample calls and batches alike).  Records do not depend on the
+ * for the program's (peak active width, precision); later single-program
+ * launches with that key use it (batches use their own rule, see
+ * symft_sample_batch).  Records do not depend on the
  * choice.  Synchronous; allocates a scratch output.  *tps_out (nullable)
  * receives the choice (0 for pure-frame programs, which have one kernel). */
 symft_status symft_autotune(const symft_program *p, uint32_t precision, uint32_t *tps_out);

@@ -475,12 +475,24 @@ struct ActiveConfig {
     size_t lds;
 };
 
-// Threads per shot chosen by the autotuner, per (peak active width, precision,
-// context).  Context 0: a launch that has the GPU to itself (tuned on 4096
-// words, so occupancy weighs in); context 1: a member of a batch, sharing the
-// GPU with the other programs (tuned on 256 words).
+// Threads per shot chosen by the autotuner for launches that have the GPU to
+// themselves, per (peak active width, precision); tuned on 4096 words, so
+// occupancy weighs in.
 static std::mutex g_tune_mu;
-static std::map<std::tuple<uint32_t, bool, int>, uint32_t> g_tune;
+static std::map<std::pair<uint32_t, bool>, uint32_t> g_tune;
+
+// Threads per shot of a batch member.  The members share one workgroup size
+// (256) and the LDS size of the largest member, which sets the occupancy of
+// the whole batch.  On the 128-program batch (widths 1..12, FP32 and FP64),
+// two workgroups per CU with up to 64 KB of vectors each ran every width
+// fastest: G = 64 KB / (2^k amplitudes) shot groups per workgroup (at most
+// 64), 256 / G threads each.  Timing members alone cannot find this: a few
+// hundred words give each CU one workgroup whatever its LDS size.
+static uint32_t batch_tps(uint32_t k, bool fp64) {
+    const uint64_t per_shot = ((uint64_t)1 << k) * (fp64 ? 16u : 8u);
+    const uint64_t G = std::max<uint64_t>(1, std::min<uint64_t>(64, 65536 / per_shot));
+    return (uint32_t)(256 / G);
+}
 
 // Threads per shot before the autotuner has run: about 2^(k-4) amplitudes'
 // worth of threads in FP32 and twice that in FP64, at least 4 (the choices
@@ -508,7 +520,7 @@ static bool hbm_candidate(uint32_t k) { return k >= 9 && k <= 12; }
 
 // count_mode: a workgroup holds one shot group when groups are a wave or
 // more (64 .. 256 threads), so it drops a discarded shot at once.
-ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, int context = 0,
+ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, bool batch = false,
                            bool count_mode = false) {
     ActiveConfig c;
     uint32_t k = P.k_max;
@@ -516,9 +528,10 @@ ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, 
     c.tps = narrow_wide(k) ? (fp64 ? 256u : 128u) : default_tps(k, fp64);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune.find({k, fp64, context});
+        auto it = g_tune.find({k, fp64});
         if (it != g_tune.end()) c.tps = it->second;
     }
+    if (batch && k < 13) c.tps = batch_tps(k, fp64);
     if (force_tps) c.tps = force_tps;
     const bool hbm = (c.tps & kHbmVec) && hbm_candidate(k);
     c.tps &= ~kHbmVec;
@@ -539,7 +552,7 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
                                uint64_t probe_shot0, uint64_t probe_n, uint64_t seed, hipStream_t st,
                                uint32_t force_tps = 0, const CountArgs *cnt = nullptr, double *amp = nullptr,
                                uint32_t amp_k = 0, const FixedScratch *fixed = nullptr) {
-    ActiveConfig c = choose_active(D, fp64, force_tps, 0, cnt != nullptr);
+    ActiveConfig c = choose_active(D, fp64, force_tps, false, cnt != nullptr);
     if (c.lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "program tables exceed the LDS budget of the active kernel");
     int per_cu = active_max_blocks_per_cu(fp64, c.bs, c.lds_vec, c.lds, cnt != nullptr);
     if (per_cu <= 0) per_cu = 1;
@@ -1173,7 +1186,7 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
         }
         if (rc == SYMFT_OK && ms < best) {
             best = ms;
-            best_tps = choose_active(D, fp64, 0, 0, false).tps | kViaRecords;
+            best_tps = choose_active(D, fp64, 0, false, false).tps | kViaRecords;
         }
     }
     (void)hipEventDestroy(e0);
@@ -1281,18 +1294,17 @@ symft_status symft_gap_check(uint64_t p32, const uint32_t *v, int32_t *g_out, ui
 }
 
 // ------------------------------------------------------------ autotune ----
-// Times every threads-per-shot candidate that fits LDS on 4096 words (context
-// 0) or 256 words (context 1) of the program and keeps the fastest for
-// (k_max, precision, context).  Records do not depend on the choice; only
+// Times every threads-per-shot candidate that fits LDS on 4096 words of the
+// program and keeps the fastest for (k_max, precision).  Records do not depend on the choice; only
 // branch-probability rounding does.
-static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, uint32_t *tps_out, int context = 0) {
+static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, uint32_t *tps_out) {
     if ((D.k_max >= 13 && !narrow_wide(D.k_max)) || D.fr_ok) {
         if (tps_out) *tps_out = D.k_max >= 13 ? 1024 : 0;
         return SYMFT_OK;
     }
     // widths 13 and 14 run up to 1024 workgroups: time enough words to fill them
     const bool wide = narrow_wide(D.k_max);
-    const uint64_t words = wide ? 1024 : context != 0 ? 256 : 4096;
+    const uint64_t words = wide ? 1024 : 4096;
     uint64_t *out = nullptr;
     const uint64_t rows = std::max<uint64_t>(1, p->P.n_rows());
     if (hipMalloc(&out, 8 * rows * words) != hipSuccess) return set_err(SYMFT_ENOMEM, "autotune buffer allocation failed");
@@ -1307,7 +1319,7 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
     float best = 1e30f;
     uint32_t best_tps = default_tps(D.k_max, fp64);
     symft_status rc = SYMFT_OK;
-    const bool hbm_try = context == 0 && hbm_candidate(D.k_max);
+    const bool hbm_try = hbm_candidate(D.k_max);
     for (uint32_t cand : {4u, 8u, 16u, 32u, 64u, 128u, 256u, 1024u, 64u | kHbmVec, 128u | kHbmVec, 256u | kHbmVec}) {
         const uint32_t tps = cand & ~kHbmVec;
         if ((cand & kHbmVec) && !hbm_try) continue;
@@ -1335,7 +1347,7 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[{D.k_max, fp64, context}] = best_tps;
+        g_tune[{D.k_max, fp64}] = best_tps;
     }
     if (tps_out) *tps_out = best_tps & ~kHbmVec;
     return SYMFT_OK;
@@ -1440,16 +1452,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         bool mine = shots[i] > 0 && !D.fr_ok;
         ActiveConfig c;
         if (mine) {
-            bool tuned;
-            {
-                std::lock_guard<std::mutex> lk(g_tune_mu);
-                tuned = g_tune.count({D.k_max, fp64, 1}) > 0;
-            }
-            if (!tuned && D.k_max < 13) {
-                rc = tune_program(p, D, fp64, nullptr, 1);
-                if (rc) return rc;
-            }
-            c = choose_active(D, fp64, 0, 1);
+            c = choose_active(D, fp64, 0, true);
             mine = c.bs == 256 && c.lds_vec;
         }
         if (!mine) {
