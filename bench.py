@@ -58,6 +58,16 @@ def _source_sha(name):
     return h.hexdigest()
 
 
+def _flops_per_shot(info):
+    """Algorithmic flops per shot of the representation the program samples with: its product components
+    (merges included) when selected, else the dense vector."""
+    return info["product_flops_per_shot"] if info["product_selected"] else info["dense_flops_per_shot"]
+
+
+def _representation(info):
+    return "product components" if info["product_selected"] else "dense vector"
+
+
 def _traffic(workload, source):
     rec = PROFILED_TRAFFIC.get((workload, source))
     if rec is None or _source_sha(source)[:16] != rec[0]:
@@ -112,13 +122,23 @@ def _c4_comparison(S, stream, steps, prec="fp32"):
             p.sample_into(o, x.shots, x.seed, precision="fp64", stream=stream.cuda_stream)
 
     ms_64, _ = _time_launches(plain_fp64, max(2, steps // 2), 1, stream)
-    flops = sum(p.info()["dense_flops_per_shot"] * s for p, s in zip(progs, shots))
+    flops = sum(_flops_per_shot(p.info()) * s for p, s in zip(progs, shots))
+    # the same batch with every member on the dense vector (symft_compile_opts.components = 1)
+    dense = [S.Program(x.circuit, components="off") for x in ws]
+
+    def batched_dense():
+        S.sample_batch(dense, shots, seeds, outs, precision=prec, graph=True, stream=stream.cuda_stream)
+
+    ms_bd, _ = _time_launches(batched_dense, max(2, steps // 2), 1, stream)
+    n_prod = sum(p.info()["product_selected"] for p in progs)
     return {
         "shots": total, "programs": len(ws),
         f"batched_{prec}": {"ms_per_step": round(ms_b, 3), "shots_per_s": round(total / (ms_b / 1e3), 1),
                             "tflops": round(flops / (ms_b_kernel / 1e3) / 1e12, 3)},
         "per_circuit_fp64_autotuned": {"ms_per_step": round(ms_64, 3), "shots_per_s": round(total / (ms_64 / 1e3), 1)},
         f"batched_{prec}_over_per_circuit_fp64": round(ms_64 / ms_b, 3),
+        "members_on_product_components": n_prod,
+        f"batched_{prec}_dense_vector": {"ms_per_step": round(ms_bd, 3), "shots_per_s": round(total / (ms_bd / 1e3), 1)},
     }, (progs, ws, flops, ms_b_kernel)
 
 
@@ -240,7 +260,8 @@ def run(args):
                                   "frac": round(rec_bytes / (ms_ok / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
                 except S.SymftError as e:  # the schedule does not fit that kernel
                     extra[key] = {"unavailable": str(e)}
-        elif (1 << info["k_max"]) * (8 if prec == "fp32" else 16) > LDS_BYTES and info["k_max"] >= 15:
+        elif (not info["product_selected"] and (1 << info["k_max"]) * (8 if prec == "fp32" else 16) > LDS_BYTES
+              and info["k_max"] >= 15):
             # vectors streamed from HBM scratch far beyond the caches: one read and one write of the live
             # vector per dense instruction
             nbytes = info["dense_bytes_per_shot"] * (1 if prec == "fp32" else 2) * w.shots
@@ -252,8 +273,8 @@ def run(args):
                     "kernel": "active_kernel", "bytes_per_launch": nbytes}
         else:
             # vectors in LDS, or at widths 13 and 14 in scratch that the L2 and the Infinity Cache hold:
-            # priced against the vector ALU
-            flops = info["dense_flops_per_shot"] * w.shots
+            # priced against the vector ALU, with the flops of the representation that runs
+            flops = _flops_per_shot(info) * w.shots
             achieved = flops / (ms_kernel / 1e3) / 1e12
             peak = FP32_PEAK_TFLOPS if prec == "fp32" else FP64_PEAK_TFLOPS
             roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
@@ -263,6 +284,19 @@ def run(args):
                   "precision": prec if info["k_max"] else "n/a (integer path)"}
         if tps:
             config["threads_per_shot"] = tps
+        if info["k_max"]:
+            config["representation"] = _representation(info)
+        if info["k_max"] and info["product_selected"] and args.extras:
+            # the same launch on the dense vector
+            dprog = S.Program(w.circuit, components="off")
+            dprog.autotune(prec)
+
+            def dense_step():
+                dprog.sample_into(out, w.shots, w.seed, precision=prec, stream=stream.cuda_stream)
+            _, ms_d = _time_launches(dense_step, max(2, args.steps // 4), 1, stream)
+            extra["dense_vector"] = {"ms_per_launch": round(ms_d, 4), "dense_over_product": round(ms_d / ms_kernel, 3),
+                                     "dense_flops_per_shot": info["dense_flops_per_shot"],
+                                     "product_flops_per_shot": info["product_flops_per_shot"]}
         if info["k_max"]:
             errors_for = (prog, w)
         n_cpu_words = {"c1": 256, "c2": 24, "c3": 64, "c3fp64": 64, "c5": 8, "c5fp64": 8, "c5k16": 2,
@@ -282,7 +316,8 @@ def run(args):
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None, "kernel": "batch_kernel"}
         dtype = "f32" if prec == "fp32" else "f64"
-        config = {"workload": "batch_128_near_clifford", "shots": cmp["shots"], "programs": len(ws), "precision": prec}
+        config = {"workload": "batch_128_near_clifford", "shots": cmp["shots"], "programs": len(ws), "precision": prec,
+                  "representation": "automatic per member"}
         circ, seed = ws[0].circuit, ws[0].seed
         sample_words = list(range(16))
     elif wl in ("post", "distill"):
@@ -320,8 +355,8 @@ def run(args):
         extra["logical_errors_per_kept_shot"] = round(n_log / max(1, w.shots - n_disc), 6)
         extra["full_records"] = {"shots_per_s": round(w.shots / (ms_rec / 1e3), 1), "ms_per_step": round(ms_rec, 4)}
         extra["counts_over_full_records"] = round(ms_rec / ms_step, 3)
-        # the full dense work of every shot, priced on the records launch, which does all of it
-        flops = info["dense_flops_per_shot"] * w.shots
+        # the full work of every shot, priced on the records launch, which does all of it
+        flops = _flops_per_shot(info) * w.shots
         achieved = flops / (ms_rec_kernel / 1e3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,

@@ -134,6 +134,12 @@ typedef struct {
                                       active kernel */
     uint64_t frame_wave_batches;   /* wave-owned schedule: node batches (one node per lane) */
     uint64_t frame_wave_flushes;   /* wave-owned schedule: staged-row flushes (workgroup barriers) */
+    uint64_t product_selected;     /* 1: sampling runs the product-component stream (symft_compile_opts) */
+    uint64_t product_components;   /* components of that stream: one per PromoteRot and one per merge */
+    uint64_t product_merges;       /* Kronecker merges per shot */
+    uint64_t product_vector_amplitudes; /* its vector buffer per shot (all component regions) */
+    double product_flops_per_shot; /* its algorithmic flops per shot (dense_flops_per_shot's weights on the
+                                      components' widths, plus 4 per merged amplitude) */
 } symft_info;
 
 /* Compile options.  simplify = 1 runs a conservative commutation-aware
@@ -152,7 +158,12 @@ typedef struct {
  * measurement order are unchanged. */
 typedef struct {
     uint32_t simplify;
-    uint32_t reserved[3];          /* 0 */
+    uint32_t components;           /* product components (paper Sec. 6): 0 = automatic (used when they at
+                                      least halve the dense flops per shot, merges counted, with a vector
+                                      buffer no larger than 2^k_max); 1 = never; 2 = always (programs with an
+                                      active state whose buffer fits 2^20 amplitudes).  Records are the same
+                                      up to the rounding of branch probabilities */
+    uint32_t reserved[2];          /* 0 */
 } symft_compile_opts;
 
 /* Compile `ops` (paper Sec. 2 circuit) into a sampling program (Sec. 3-4).

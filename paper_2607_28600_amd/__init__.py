@@ -59,12 +59,14 @@ class symft_info(C.Structure):
         ("frame_steps", C.c_uint64), ("frame_noise_steps", C.c_uint64), ("frame_slots", C.c_uint64),
         ("frame_max_level", C.c_uint64), ("frame_pushes", C.c_uint64), ("frame_noise_consumers", C.c_uint64),
         ("rotations_removed", C.c_uint64), ("frame_kernel", C.c_uint64), ("frame_wave_batches", C.c_uint64),
-        ("frame_wave_flushes", C.c_uint64),
+        ("frame_wave_flushes", C.c_uint64), ("product_selected", C.c_uint64), ("product_components", C.c_uint64),
+        ("product_merges", C.c_uint64), ("product_vector_amplitudes", C.c_uint64),
+        ("product_flops_per_shot", C.c_double),
     ]
 
 
 class symft_compile_opts(C.Structure):
-    _fields_ = [("simplify", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+    _fields_ = [("simplify", C.c_uint32), ("components", C.c_uint32), ("reserved", C.c_uint32 * 2)]
 
 
 class symft_sample_opts(C.Structure):
@@ -180,12 +182,13 @@ def _marshal(circ):
 class Program:
     """A compiled SymFT sampling program (owned by the C library)."""
 
-    def __init__(self, circ, simplify: bool = False):
+    def __init__(self, circ, simplify: bool = False, components: str = "auto"):
         """simplify: fuse and cancel rotations with the same Pauli body across ops on other qubits
-        (symft_compile_opts.simplify)."""
+        (symft_compile_opts.simplify).  components: "auto", "off" or "on" (symft_compile_opts.components,
+        the product-component representation)."""
         arr, keep = _marshal(circ)
         h = C.c_void_p()
-        opts = symft_compile_opts(simplify=1 if simplify else 0)
+        opts = symft_compile_opts(simplify=1 if simplify else 0, components={"auto": 0, "off": 1, "on": 2}[components])
         _check(_lib.symft_compile(circ.n_qubits, arr, len(circ.ops), C.cast(C.pointer(opts), C.c_void_p), C.byref(h)),
                "symft_compile")
         self._h = h

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libsymft.so")
-SOURCES = ["compile.cpp", "frame_schedule.cpp", "capi.cpp", "sample_active.hip", "sample_frame.hip", "sample_frame_wave.hip"]
+SOURCES = ["compile.cpp", "components.cpp", "frame_schedule.cpp", "capi.cpp", "sample_active.hip", "sample_frame.hip", "sample_frame_wave.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -99,7 +99,8 @@ struct HostLayout {
     // offsets of each array inside blob
     size_t o_instr, o_cmeas, o_am, o_rm, o_recmeas, o_detoff, o_detrows, o_obsoff, o_obsrows, o_clsQ, o_clsoff, o_clschan,
         o_chan, o_bmask, o_thr, o_symoff, o_symcons, o_invlog, o_clsfast, o_frstep, o_frnodes, o_frpush, o_frnodes16, o_frpush16, o_frchinfo,
-        o_frrec, o_frfl3, o_frcap, o_frcapoff, o_wvops, o_wvrows, o_wvfl, o_wvsl, o_wvrm, o_wvcap, o_wvcapoff, o_ci32, o_st8, o_q32;
+        o_frrec, o_frfl3, o_frcap, o_frcapoff, o_wvops, o_wvrows, o_wvfl, o_wvsl, o_wvrm, o_wvcap, o_wvcapoff, o_ci32, o_st8, o_q32,
+        o_pinstr, o_merge;
     uint32_t word_entries = 0;  // flip entries per word over all classes (frame kernel scratch)
     uint32_t wv_word_entries = 0;  // slot flips per word over all classes (wave kernel scratch)
     DevProg meta;  // counts only; pointers filled at upload
@@ -118,6 +119,10 @@ struct symft_program {
     Program P;
     HostLayout L;
     FrameSchedule F;
+    ProductPlan PP;
+    uint32_t comp_mode = 0;  // symft_compile_opts.components
+    bool product = false;    // sampling runs the product-component stream
+    uint32_t k_eff = 0;      // its vector buffer holds 2^k_eff amplitudes per shot
     std::mutex mu;
     std::map<int, void *> dev;  // device id -> uploaded blob
     // aggregate-count tables (postselection bits, expected observables, check lists) by (device, content)
@@ -210,6 +215,47 @@ static void lower(symft_program *h) {
             i += 1;
         }
     }
+    // The product-component stream (paper Sec. 6): the same instructions with
+    // the component's region, local width, masks and pivot, the merges before
+    // them, and no fused passes.  Selected when the dense work it saves is
+    // clear: at most half the dense flops, merges counted, and a vector
+    // buffer no larger than the dense one.
+    plan_components(P, h->PP);
+    std::vector<DevInstr> pins = ins;
+    std::vector<DevMerge> pmerge;
+    for (size_t i = 0; i < ins.size(); ++i) {
+        const ProductPlan::PInstr &Q = h->PP.ins[i];
+        DevInstr &D = pins[i];
+        D.fuse = 0;
+        if (Q.kind == RANDOM_MEAS || Q.kind == DET_MEAS) continue;
+        D.kind = Q.kind;
+        D.k_in = Q.k_in;
+        D.h = Q.h;
+        D.a = Q.a;
+        D.b = Q.b;
+        D.base = Q.base;
+        D.mg_off = Q.mg_off;
+        D.mg_len = (uint8_t)Q.mg_len;
+    }
+    for (const ProductPlan::Merge &m : h->PP.merges) {
+        DevMerge d;
+        std::memset(&d, 0, sizeof(d));
+        d.dst = m.dst;
+        d.src1 = m.src1;
+        d.src2 = m.src2;
+        d.w1 = (uint8_t)m.w1;
+        d.w = (uint8_t)m.w;
+        pmerge.push_back(d);
+    }
+    {
+        uint32_t ke = 0;
+        while (((uint64_t)1 << ke) < h->PP.vcap) ++ke;
+        h->k_eff = ke;
+        bool fits = h->PP.valid && P.k_max >= 1 && ke <= 20;
+        for (const ProductPlan::PInstr &Q : h->PP.ins) fits = fits && Q.mg_len < 256;
+        const bool clear = h->PP.work_product + 64.0 * h->PP.n_merges <= 0.5 * h->PP.work_dense && ke <= P.k_max;
+        h->product = fits && (h->comp_mode == 2 || (h->comp_mode == 0 && clear));
+    }
     std::vector<uint32_t> symoff(P.n_noise_sym + 1, 0), symcons;
     for (uint32_t s = 0; s < P.n_noise_sym; ++s) {
         symoff[s] = (uint32_t)symcons.size();
@@ -262,6 +308,8 @@ static void lower(symft_program *h) {
     build_frame_schedule(P, h->F);
     L.blob.clear();
     L.o_instr = put(L.blob, ins);
+    L.o_pinstr = put(L.blob, pins);
+    L.o_merge = put(L.blob, pmerge);
     L.o_cmeas = put(L.blob, cmeas);
     L.o_am = put(L.blob, am);
     L.o_rm = put(L.blob, rm);
@@ -361,7 +409,9 @@ struct FixedScratch {
 
 // upload = false: fail instead of uploading a program that is not resident on
 // the current device (the allocation-free entry point allocates nothing).
-static symft_status device_prog(symft_program *h, DevProg &out, bool upload = true) {
+// dense = true: the dense instruction stream even for a product-component
+// program (the amplitude probe reads the whole vector).
+static symft_status device_prog(symft_program *h, DevProg &out, bool upload = true, bool dense = false) {
     int dev = 0;
     if (const hipError_t e = hipGetDevice(&dev)) return hip_err("hipGetDevice failed", e);
     std::lock_guard<std::mutex> lk(h->mu);
@@ -383,6 +433,11 @@ static symft_status device_prog(symft_program *h, DevProg &out, bool upload = tr
     const HostLayout &L = h->L;
     out = L.meta;
     out.instr = (const DevInstr *)(b + L.o_instr);
+    out.merges = (const DevMerge *)(b + L.o_merge);
+    if (h->product && !dense) {
+        out.instr = (const DevInstr *)(b + L.o_pinstr);
+        out.k_max = h->k_eff;
+    }
     out.cmeas = (const uint32_t *)(b + L.o_cmeas);
     out.am_meas = (const uint32_t *)(b + L.o_am);
     out.rm_list = (const uint32_t *)(b + L.o_rm);
@@ -729,9 +784,11 @@ symft_status symft_compile(uint32_t n_qubits, const symft_op *ops, size_t n_ops,
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *(const symft_compile_opts *)opts;
     if (o.simplify > 1) return set_err(SYMFT_EINVAL, "simplify must be 0 or 1");
+    if (o.components > 2) return set_err(SYMFT_EINVAL, "components must be 0, 1 or 2");
     symft_program *h = nullptr;
     try {
         h = new symft_program();
+        h->comp_mode = o.components;
         std::string err;
         std::vector<symft_op> rewritten;
         uint64_t removed = 0;
@@ -804,6 +861,11 @@ symft_status symft_program_info(const symft_program *p, symft_info *info) {
     info->frame_kernel = p->L.meta.fr_ok ? (frame_lds_bytes(p->L.meta, 16) <= kLdsLimit ? 2u : 1u) : 0u;
     info->frame_wave_batches = p->F.w_n_batches;
     info->frame_wave_flushes = p->F.w_n_flushes;
+    info->product_selected = p->product ? 1u : 0u;
+    info->product_components = p->PP.n_comps;
+    info->product_merges = p->PP.n_merges;
+    info->product_vector_amplitudes = p->PP.vcap;
+    info->product_flops_per_shot = p->PP.work_product;
     for (size_t i = 0; i < p->F.steps.size(); i += FR_STEP_WORDS)
         if (p->F.steps[i] == FR_NOISE) info->frame_noise_steps += 1;
     return SYMFT_OK;
@@ -1250,7 +1312,7 @@ symft_status symft_probe_amplitudes(const symft_program *pc, uint64_t shot_begin
         return SYMFT_OK;
     }
     DevProg D;
-    symft_status rc = device_prog(p, D);
+    symft_status rc = device_prog(p, D, true, true);
     if (rc) return rc;
     const uint64_t w0 = shot_begin / 64, w1 = (shot_begin + n_shots + 63) / 64;
     const uint64_t nw = w1 - w0;

@@ -18,15 +18,26 @@ struct DevInstr {
                                    // (2 and 3 with FP32 vectors in HBM scratch and a coset per thread
                                    // only; otherwise such a pair rotation runs alone, and the middle one
                                    // of 3 carries mark 1)
-    uint8_t pad1;
+    uint8_t mg_len;                // product-component programs: Kronecker merges run before it
     uint32_t a, b;
     int32_t meas;                  // measurement index (measurements)
     uint32_t cm_off, cm_len;       // causal refs of lambda: cm_len (word, mask) pairs from pair cm_off
     uint32_t am_idx;               // active measurements: ordinal among them in stream order
     double c, s;
     float cf, sf;
+    uint32_t base;                 // region of the shot's vector buffer it runs on (0 for dense programs)
+    uint32_t mg_off;               // its first merge in DevProg::merges
 };
-static_assert(sizeof(DevInstr) == 56, "DevInstr layout");
+static_assert(sizeof(DevInstr) == 64, "DevInstr layout");
+
+// A Kronecker merge of two components (paper Sec. 6): dst[x] = src1[x mod
+// 2^w1] * src2[x >> w1] for x < 2^w (offsets in amplitudes of the shot's
+// vector buffer; the three regions do not overlap).
+struct DevMerge {
+    uint32_t dst, src1, src2;
+    uint8_t w1, w, pad[2];
+};
+static_assert(sizeof(DevMerge) == 16, "DevMerge layout");
 
 // Noise channel under the draw contract.
 struct DevChan {
@@ -64,6 +75,7 @@ static_assert(sizeof(GapFast) == 32, "GapFast layout");
 // Pointers into one device allocation (all read-only in the kernels).
 struct DevProg {
     const DevInstr *instr;
+    const DevMerge *merges;      // product-component programs: merges before instructions
     const uint32_t *cmeas;       // causal refs of each lambda: (outcome word, bit mask) pairs
     const uint32_t *am_meas;     // measurement id of every active measurement, in stream order
     const uint32_t *rm_list;     // instructions that are RandomMeas

@@ -17,6 +17,9 @@ enum InstrKind : uint8_t {
     DET_MEAS = 5,
     ACTIVE_DIAG_MEAS = 6,
     ACTIVE_PAIR_MEAS = 7,
+    // product-component streams only: a PromoteRot whose new coordinate starts a
+    // component of its own, written from the amplitude 1 (no source vector)
+    PROMOTE_FRESH = 8,
 };
 
 // Affine Boolean expression over F2 (paper Sec. 3): constant bit, noise
@@ -83,6 +86,33 @@ struct Program {
     std::vector<int8_t> rot_kind;
     uint64_t n_rows() const { return n_rec + n_det + n_obs; }
 };
+
+// The product-component lowering (paper Sec. 6): per dense instruction, the
+// component it runs on (region offset and local width in the shot's vector
+// buffer, masks and pivot in local coordinates) and the Kronecker merges that
+// run before it.  Index-aligned with Program::instrs.
+struct ProductPlan {
+    struct PInstr {
+        uint8_t kind = 0;   // as the dense instruction, PROMOTE_FRESH for a PromoteRot
+        uint8_t k_in = 0;   // local width of the component before the instruction
+        uint8_t h = 0;      // local pivot
+        uint32_t a = 0, b = 0;
+        uint32_t base = 0;  // region offset of the component (amplitudes)
+        uint32_t mg_off = 0, mg_len = 0;
+    };
+    struct Merge {
+        uint32_t dst, src1, src2;  // region offsets
+        uint32_t w1, w;            // width of src1; width of the result (src2 has w - w1)
+    };
+    std::vector<PInstr> ins;
+    std::vector<Merge> merges;
+    bool valid = true;         // the plan followed the dense widths (else only the dense stream runs)
+    uint32_t vcap = 1;         // amplitudes per shot over all regions
+    uint32_t n_comps = 0, n_merges = 0, k_local_max = 0;
+    double work_dense = 0;     // algorithmic flops per shot, dense
+    double work_product = 0;   // the same for the components, merges included
+};
+void plan_components(const Program &P, ProductPlan &out);
 
 // Returns 0 or a negative symft status; err receives the message.
 int compile_program(uint32_t n_qubits, const void *ops, size_t n_ops, Program &out, std::string &err);

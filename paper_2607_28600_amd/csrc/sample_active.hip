@@ -56,7 +56,7 @@ __device__ __forceinline__ DevInstr load_instr(const DevInstr *p, uint32_t i) {
     d.eta = (uint8_t)w1;
     d.lam_c = (uint8_t)(w1 >> 8);
     d.fuse = (uint8_t)(w1 >> 16);
-    d.pad1 = 0;
+    d.mg_len = (uint8_t)(w1 >> 24);
     d.a = q[2];
     d.b = q[3];
     d.meas = (int32_t)q[4];
@@ -67,7 +67,21 @@ __device__ __forceinline__ DevInstr load_instr(const DevInstr *p, uint32_t i) {
     d.s = __hiloint2double((int)q[11], (int)q[10]);
     d.cf = __uint_as_float(q[12]);
     d.sf = __uint_as_float(q[13]);
+    d.base = q[14];
+    d.mg_off = q[15];
     return d;
+}
+
+__device__ __forceinline__ DevMerge load_merge(const DevMerge *p, uint32_t i) {
+    const __attribute__((address_space(4))) uint32_t *q = (const __attribute__((address_space(4))) uint32_t *)(p + i);
+    DevMerge m;
+    m.dst = q[0];
+    m.src1 = q[1];
+    m.src2 = q[2];
+    m.w1 = (uint8_t)q[3];
+    m.w = (uint8_t)(q[3] >> 8);
+    m.pad[0] = m.pad[1] = 0;
+    return m;
 }
 
 // One pair of an ActivePairRot: (va at ya, vb at yb = ya ^ a) become
@@ -370,11 +384,40 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 const T c = sizeof(T) == 8 ? (T)I.c : (T)I.cf;
                 const T s = sizeof(T) == 8 ? (T)I.s : (T)I.sf;
                 uint32_t mbit = 0;  // this instruction's outcome, known to every thread of the group
+                // Product-component programs: the component this instruction runs on,
+                // after the Kronecker merges of the components its masks span
+                V *vb = vec + I.base;
+                for (uint32_t q = 0; q < I.mg_len; ++q) {
+                    const DevMerge M = load_merge(P.merges, I.mg_off + q);
+                    const uint32_t NW = 1u << M.w, m1 = (1u << M.w1) - 1u;
+                    if (live)
+                    for (uint32_t x = (uint32_t)r; x < NW; x += (uint32_t)tps) {
+                        const V u = vec[M.src1 + (x & m1)], w = vec[M.src2 + (x >> M.w1)];
+                        V o;
+                        o.x = u.x * w.x - u.y * w.y;
+                        o.y = u.x * w.y + u.y * w.x;
+                        vec[M.dst + x] = o;
+                    }
+                    gsync();
+                }
                 switch (I.kind) {
+                case 8: {  // PromoteRot that starts a component of its own, from the amplitude 1
+                    const T ss = lam ? -s : s;
+                    if (live && r == 0) {
+                        V lo, hi;
+                        lo.x = c;
+                        lo.y = (T)0;
+                        hi.x = (T)0;
+                        hi.y = -ss;
+                        vb[0] = lo;
+                        vb[1] = hi;
+                    }
+                    break;
+                }
                 case 1: {  // PromoteRot: x0 <- c a_x, x1 <- -i (-1)^lam s a_x
                     const T ss = lam ? -s : s;
                     if (live)
-                    for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) put_promoted(vec, x, N, vec[x], c, ss);
+                    for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) put_promoted(vb, x, N, vb[x], c, ss);
                     break;
                 }
                 case 2: {  // ActiveDiagRot: a_x *= c - i sigma s, sigma = (-1)^lam mu (-1)^(b.x)
@@ -384,12 +427,12 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                     if (live)
                     for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
                         const T sg = (neg ^ parity(I.b & x)) ? -s : s;
-                        V v = vec[x];
+                        V v = vb[x];
                         V o;
                         o.x = c * v.x + sg * v.y;
                         o.y = c * v.y - sg * v.x;
-                        if (I.fuse) put_promoted(vec, x, N, o, pc, pss);
-                        else vec[x] = o;
+                        if (I.fuse) put_promoted(vb, x, N, o, pc, pss);
+                        else vb[x] = o;
                     }
                     if (I.fuse) ++ii;  // the PromoteRot ran in this pass
                     break;
@@ -422,21 +465,21 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                         for (uint32_t z = (uint32_t)r; z < (N >> 2); z += (uint32_t)tps) {
                             const uint32_t y0 = insert_bit(insert_bit(z, plo, 0), phi, 0);
                             const uint32_t y1 = y0 ^ I.a, y2 = y0 ^ I2.a, y3 = y1 ^ I2.a;
-                            V v0 = vec[y0], v1 = vec[y1], v2 = vec[y2], v3 = vec[y3];
+                            V v0 = vb[y0], v1 = vb[y1], v2 = vb[y2], v3 = vb[y3];
                             pair_update(v0, v1, y0, y1, e0, I.b, c, s);
                             pair_update(v2, v3, y2, y3, e0, I.b, c, s);
                             pair_update(v0, v2, y0, y2, e02, I2.b, c2, s2);
                             pair_update(v1, v3, y1, y3, e02, I2.b, c2, s2);
                             if (fz == 3) {
-                                put_promoted(vec, y0, N, v0, pc, pss);
-                                put_promoted(vec, y1, N, v1, pc, pss);
-                                put_promoted(vec, y2, N, v2, pc, pss);
-                                put_promoted(vec, y3, N, v3, pc, pss);
+                                put_promoted(vb, y0, N, v0, pc, pss);
+                                put_promoted(vb, y1, N, v1, pc, pss);
+                                put_promoted(vb, y2, N, v2, pc, pss);
+                                put_promoted(vb, y3, N, v3, pc, pss);
                             } else {
-                                vec[y0] = v0;
-                                vec[y1] = v1;
-                                vec[y2] = v2;
-                                vec[y3] = v3;
+                                vb[y0] = v0;
+                                vb[y1] = v1;
+                                vb[y2] = v2;
+                                vb[y3] = v3;
                             }
                         }
                         ii += fz == 3 ? 2u : 1u;  // the instructions that ran in this pass
@@ -446,7 +489,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                     if (live)
                     for (uint32_t z = (uint32_t)r; z < half; z += (uint32_t)tps) {
                         const uint32_t x0 = insert_bit(z, I.h, 0), x1 = x0 ^ I.a;
-                        V a0 = vec[x0], a1 = vec[x1];
+                        V a0 = vb[x0], a1 = vb[x1];
                         // factor f0 multiplies a1 into x0's update, f1 multiplies a0 into x1's
                         const int q0 = (e0 + 2 * parity(I.b & x1)) & 3;
                         const int q1 = (e0 + 2 * parity(I.b & x0)) & 3;
@@ -460,11 +503,11 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                         n0.x = c * a0.x + s * t0.x; n0.y = c * a0.y + s * t0.y;
                         n1.x = c * a1.x + s * t1.x; n1.y = c * a1.y + s * t1.y;
                         if (fz) {
-                            put_promoted(vec, x0, N, n0, pc, pss);
-                            put_promoted(vec, x1, N, n1, pc, pss);
+                            put_promoted(vb, x0, N, n0, pc, pss);
+                            put_promoted(vb, x1, N, n1, pc, pss);
                         } else {
-                            vec[x0] = n0;
-                            vec[x1] = n1;
+                            vb[x0] = n0;
+                            vb[x1] = n1;
                         }
                     }
                     if (fz) ++ii;  // the PromoteRot ran in this pass
@@ -514,7 +557,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                     if (!live) {
                     } else if (!pair) {
                         for (uint32_t x = (uint32_t)r; x < N; x += (uint32_t)tps) {
-                            V v = vec[x];
+                            V v = vb[x];
                             T m2 = v.x * v.x + v.y * v.y;
                             if (parity(I.b & x)) kahan_add(s1, c1, m2); else kahan_add(s0, c0, m2);
                         }
@@ -522,7 +565,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                         const int mc = (4 - (int)I.mu) & 3;  // conj(mu) = i^mc
                         for (uint32_t z = (uint32_t)r; z < half; z += (uint32_t)tps) {
                             const uint32_t u0 = insert_bit(z, I.h, 0);
-                            V a0 = vec[u0], a1 = vec[u0 ^ I.a];
+                            V a0 = vb[u0], a1 = vb[u0 ^ I.a];
                             const int q = (mc + 2 * parity(I.b & u0)) & 3;
                             T tx = (q == 0) ? a1.x : (q == 1) ? -a1.y : (q == 2) ? -a1.x : a1.y;
                             T ty = (q == 0) ? a1.y : (q == 1) ? a1.x : (q == 2) ? -a1.y : -a1.x;
@@ -561,11 +604,11 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                                 if (!pair) {
                                     const uint32_t uu = insert_bit(z, I.h, (uint32_t)y);
                                     const uint32_t x = uu ^ ((uint32_t)parity(bl & uu) << I.h);
-                                    V v = vec[x];
+                                    V v = vb[x];
                                     vals[e].x = v.x * scale; vals[e].y = v.y * scale;
                                 } else {
                                     const uint32_t u0 = insert_bit(z, I.h, 0);
-                                    V a0 = vec[u0], a1 = vec[u0 ^ I.a];
+                                    V a0 = vb[u0], a1 = vb[u0 ^ I.a];
                                     const int q = (mc + 2 * parity(I.b & u0) + 2 * y) & 3;
                                     T tx = (q == 0) ? a1.x : (q == 1) ? -a1.y : (q == 2) ? -a1.x : a1.y;
                                     T ty = (q == 0) ? a1.y : (q == 1) ? a1.x : (q == 2) ? -a1.y : -a1.x;
@@ -578,7 +621,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const uint32_t z = z0 + (uint32_t)e * (uint32_t)tps + (uint32_t)r;
-                            if (z < half && !dead) vec[z] = vals[e];
+                            if (z < half && !dead) vb[z] = vals[e];
                         }
                         gsync();
                     }

@@ -41,10 +41,12 @@ def c2():
     return w, S.Program(w.circuit), OracleCircuit(w.circuit)
 
 
-@pytest.fixture(scope="module")
-def c3():
+@pytest.fixture(scope="module", params=["auto", "off"])
+def c3(request):
+    """C3 with the automatic representation (product components: its active state is nearly separable) and
+    with the dense vector."""
     w = configs.c3()
-    return w, S.Program(w.circuit), OracleCircuit(w.circuit)
+    return w, S.Program(w.circuit, components=request.param), OracleCircuit(w.circuit)
 
 
 def test_c1_full_bit_exact(c1):
@@ -133,10 +135,11 @@ def test_c3_full_size_sampled_words(c3, prec):
         compare_records(got[:, j:j + 1], want[:, j:j + 1], w.circuit, oc, w.seed, 64 * wd, TOL[prec])
 
 
+@pytest.mark.parametrize("comp", ["auto", "off"])
 @pytest.mark.parametrize("i", [0, 3, 7, 10, 11, 23, 59, 127])
-def test_c4_programs(i):
+def test_c4_programs(i, comp):
     w = configs.c4()[i]
-    p = S.Program(w.circuit)
+    p = S.Program(w.circuit, components=comp)
     oc = OracleCircuit(w.circuit)
     n = 64 * 8
     for prec in ("fp64", "fp32"):
@@ -145,10 +148,11 @@ def test_c4_programs(i):
         compare_records(got, want, w.circuit, oc, w.seed, 0, TOL[prec])
 
 
+@pytest.mark.parametrize("comp", ["auto", "off"])
 @pytest.mark.parametrize("k,prec", [(14, "fp32"), (14, "fp64"), (16, "fp32"), (16, "fp64")])
-def test_c5_large_active_state(k, prec):
+def test_c5_large_active_state(k, prec, comp):
     w = configs.c5(k)
-    p = S.Program(w.circuit)
+    p = S.Program(w.circuit, components=comp)
     assert p.k_max == k
     oc = OracleCircuit(w.circuit)
     n = 64 * 2
@@ -160,9 +164,9 @@ def test_c5_large_active_state(k, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_widest_state_records(prec):
     """Maximum size: a peak active width of 20 (2^20 amplitudes per shot, HBM-resident, 1024 threads per
-    shot), 64 shots against the oracle."""
+    shot; the dense vector), 64 shots against the oracle."""
     c = wide_circuit(18, 7)
-    p = S.Program(c)
+    p = S.Program(c, components="off")
     assert p.k_max == 20
     oc = OracleCircuit(c)
     seed = 4242
@@ -175,13 +179,14 @@ def test_random_small_circuits():
     rng = np.random.default_rng(2024)
     for trial in range(25):
         c = random_circuit(rng, int(rng.integers(2, 8)), int(rng.integers(10, 60)))
-        p = S.Program(c)
         oc = OracleCircuit(c)
         seed = 31337 + trial
-        for prec in ("fp64", "fp32"):
-            got = _gpu(p, 64 * 3, seed, precision=prec)
-            want = oc.sample(seed, 64 * 3)
-            compare_records(got, want, c, oc, seed, 0, TOL[prec])
+        want = oc.sample(seed, 64 * 3)
+        for comp in ("auto", "off"):
+            p = S.Program(c, components=comp)
+            for prec in ("fp64", "fp32"):
+                got = _gpu(p, 64 * 3, seed, precision=prec)
+                compare_records(got, want, c, oc, seed, 0, TOL[prec])
 
 
 def test_zero_shots_is_noop(c1):
