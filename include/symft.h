@@ -260,10 +260,13 @@ symft_status symft_sample_noalloc(const symft_program *p, const symft_sample_opt
  * items ordered by decreasing cost.  records_out[i] (device, n_rows(i) x
  * ceil(shots[i]/64) words) receives program i's rows for shots[i] shots with
  * seeds[i]; precision as in symft_sample_opts.  Threads per shot follow a
- * fixed rule, not the autotuner: the members share one LDS size (the largest
+ * rule, not the autotuner: the members share one LDS size (the largest
  * member's), so each member takes the most shot groups per 256-thread
- * workgroup whose vectors fit 64 KB (at most 64 groups), which keeps two
- * workgroups per CU.  `graph` = 1
+ * workgroup whose vectors fit an LDS budget (at most 64 groups).  The first
+ * call with a new argument set builds the plans for budgets of 64 and 32 KB
+ * and, when they differ, runs each twice on `stream` (writing the batch's own
+ * records, which the call's launch then rewrites) and keeps the faster; that
+ * first call synchronises the stream.  `graph` = 1
  * captures the launch (a counter-reset kernel and the persistent kernel) in
  * a HIP graph on first use and replays it on later calls with identical
  * arguments.  Programs that need their own kernel (pure frame, or vectors

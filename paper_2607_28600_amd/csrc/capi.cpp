@@ -538,14 +538,18 @@ static std::map<std::pair<uint32_t, bool>, uint32_t> g_tune;
 
 // Threads per shot of a batch member.  The members share one workgroup size
 // (256) and the LDS size of the largest member, which sets the occupancy of
-// the whole batch.  On the 128-program batch (widths 1..12, FP32 and FP64),
-// two workgroups per CU with up to 64 KB of vectors each ran every width
-// fastest: G = 64 KB / (2^k amplitudes) shot groups per workgroup (at most
-// 64), 256 / G threads each.  Timing members alone cannot find this: a few
+// the whole batch.  Each member takes G = budget / (2^k amplitudes) shot
+// groups per workgroup (at most 64), 256 / G threads each, for an LDS budget
+// per workgroup that the batch chooses (symft_sample_batch times 32 and 64
+// KB).  On the 128-program batch with dense vectors (widths 1..12), 64 KB, two
+// workgroups per CU, ran every width fastest; with most members on small
+// product components, 32 KB (three per CU) did, one wide member no longer
+// holding the others to two.  Timing members alone cannot find this: a few
 // hundred words give each CU one workgroup whatever its LDS size.
-static uint32_t batch_tps(uint32_t k, bool fp64) {
+static const uint64_t kBatchBudgets[2] = {65536, 32768};
+static uint32_t batch_tps(uint32_t k, bool fp64, uint64_t budget) {
     const uint64_t per_shot = ((uint64_t)1 << k) * (fp64 ? 16u : 8u);
-    const uint64_t G = std::max<uint64_t>(1, std::min<uint64_t>(64, 65536 / per_shot));
+    const uint64_t G = std::max<uint64_t>(1, std::min<uint64_t>(64, budget / per_shot));
     return (uint32_t)(256 / G);
 }
 
@@ -575,7 +579,8 @@ static bool hbm_candidate(uint32_t k) { return k >= 9 && k <= 12; }
 
 // count_mode: a workgroup holds one shot group when groups are a wave or
 // more (64 .. 256 threads), so it drops a discarded shot at once.
-ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, bool batch = false,
+// batch_budget: nonzero for a batch member, the batch's LDS budget per workgroup.
+ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, uint64_t batch_budget = 0,
                            bool count_mode = false) {
     ActiveConfig c;
     uint32_t k = P.k_max;
@@ -586,7 +591,7 @@ ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, 
         auto it = g_tune.find({k, fp64});
         if (it != g_tune.end()) c.tps = it->second;
     }
-    if (batch && k < 13) c.tps = batch_tps(k, fp64);
+    if (batch_budget && k < 13) c.tps = batch_tps(k, fp64, batch_budget);
     if (force_tps) c.tps = force_tps;
     const bool hbm = (c.tps & kHbmVec) && hbm_candidate(k);
     c.tps &= ~kHbmVec;
@@ -607,7 +612,7 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
                                uint64_t probe_shot0, uint64_t probe_n, uint64_t seed, hipStream_t st,
                                uint32_t force_tps = 0, const CountArgs *cnt = nullptr, double *amp = nullptr,
                                uint32_t amp_k = 0, const FixedScratch *fixed = nullptr) {
-    ActiveConfig c = choose_active(D, fp64, force_tps, false, cnt != nullptr);
+    ActiveConfig c = choose_active(D, fp64, force_tps, 0, cnt != nullptr);
     if (c.lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "program tables exceed the LDS budget of the active kernel");
     int per_cu = active_max_blocks_per_cu(fp64, c.bs, c.lds_vec, c.lds, cnt != nullptr);
     if (per_cu <= 0) per_cu = 1;
@@ -1248,7 +1253,7 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
         }
         if (rc == SYMFT_OK && ms < best) {
             best = ms;
-            best_tps = choose_active(D, fp64, 0, false, false).tps | kViaRecords;
+            best_tps = choose_active(D, fp64, 0, 0, false).tps | kViaRecords;
         }
     }
     (void)hipEventDestroy(e0);
@@ -1490,7 +1495,8 @@ static void drop_batch_plans(const symft_program *p) {
 // its first word; outs is then unused.
 static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, const uint64_t *shots,
                                const uint64_t *seeds, uint64_t *const *outs, size_t n, uint32_t precision,
-                               const CountArgs *cnt = nullptr, const uint64_t *word0 = nullptr) {
+                               const CountArgs *cnt = nullptr, const uint64_t *word0 = nullptr,
+                               uint64_t budget = kBatchBudgets[0]) {
     const bool fp64 = precision == 0;
     B.cm = cnt != nullptr;
     B.progs.assign(progs, progs + n);
@@ -1514,7 +1520,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         bool mine = shots[i] > 0 && !D.fr_ok;
         ActiveConfig c;
         if (mine) {
-            c = choose_active(D, fp64, 0, true);
+            c = choose_active(D, fp64, 0, budget);
             mine = c.bs == 256 && c.lds_vec;
         }
         if (!mine) {
@@ -1608,6 +1614,27 @@ static symft_status run_plan(BatchPlan &B, bool fp64, uint32_t graph, hipStream_
     return SYMFT_OK;
 }
 
+// Two direct launches of a plan on stream st; *ms is the second one's time.
+static symft_status time_plan(BatchPlan &B, bool fp64, hipStream_t st, float *ms) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return set_err(SYMFT_EHIP, "event creation failed");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_err(SYMFT_EHIP, "event creation failed");
+    }
+    symft_status rc = run_plan(B, fp64, 0, st);
+    if (rc == SYMFT_OK) (void)hipEventRecord(e0, st);
+    if (rc == SYMFT_OK) rc = run_plan(B, fp64, 0, st);
+    if (rc == SYMFT_OK) {
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            rc = set_err(SYMFT_EHIP, "batch timing failed");
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 // A new plan at the front of the cache, which keeps the four most recent.
 static void keep_plan(BatchPlan *B) {
     g_plans.insert(g_plans.begin(), B);
@@ -1635,12 +1662,49 @@ symft_status symft_sample_batch(const symft_program *const *progs, const uint64_
             break;
         }
     if (!B) {
-        B = new BatchPlan();
-        symft_status rc = build_plan(*B, progs, shots, seeds, records_out, n, precision);
-        if (rc) {
-            B->release();
-            delete B;
-            return rc;
+        // Plans for both LDS budgets; when they differ, each runs twice on the
+        // caller's stream (its records are the batch's own, rewritten by the
+        // launch below) and the faster second run is kept.
+        float best_ms = 0;
+        for (uint64_t budget : kBatchBudgets) {
+            BatchPlan *C = new BatchPlan();
+            symft_status rc = build_plan(*C, progs, shots, seeds, records_out, n, precision, nullptr, nullptr, budget);
+            if (rc || (B && C->lds == B->lds)) {
+                C->release();
+                delete C;
+                if (rc) {
+                    if (B) {
+                        B->release();
+                        delete B;
+                    }
+                    return rc;
+                }
+                continue;
+            }
+            if (B) {
+                if (!best_ms) {
+                    // time the first plan now that there is a second to compare with
+                    rc = time_plan(*B, precision == 0, st, &best_ms);
+                    if (rc) return rc;
+                }
+                float ms = 0;
+                rc = time_plan(*C, precision == 0, st, &ms);
+                if (rc) {
+                    C->release();
+                    delete C;
+                    B->release();
+                    delete B;
+                    return rc;
+                }
+                if (ms < best_ms) {
+                    std::swap(B, C);
+                    best_ms = ms;
+                }
+                C->release();
+                delete C;
+            } else {
+                B = C;
+            }
         }
         keep_plan(B);
     }
