@@ -219,6 +219,12 @@ typedef struct {
                                       (ECAPACITY if it does not fit); 2 = step-synchronous.  A nonzero
                                       frame_tile_words selects the step-synchronous kernel.  Records are
                                       unchanged */
+    uint32_t active_kernel;        /* programs with an active state: 0 = automatic (symft_autotune's choice,
+                                      else the shot-group kernel); 1 = the shot-group kernel (a group of
+                                      threads per shot); 2 = the lane kernel (one wave per 64-shot word, one
+                                      lane per shot, every shot's vector buffer in LDS; ECAPACITY when that
+                                      state passes 64 KB).  Records are the same up to the rounding of branch
+                                      probabilities */
 } symft_sample_opts;
 
 /* Sample `shots` shots (paper Sec. 5) into device buffer records_out
@@ -369,7 +375,9 @@ symft_status symft_sample_counts_batch(const symft_program *const *progs, const 
  * launches with that key use it (batches use their own rule, see
  * symft_sample_batch).  Records do not depend on the
  * choice.  Synchronous; allocates a scratch output.  *tps_out (nullable)
- * receives the choice (0 for pure-frame programs, which have one kernel). */
+ * receives the choice (0 for pure-frame programs, which have one kernel; 1 for
+ * the lane kernel, symft_sample_opts.active_kernel = 2, also a candidate when
+ * its state fits). */
 symft_status symft_autotune(const symft_program *p, uint32_t precision, uint32_t *tps_out);
 
 /* Probe: Pr(m = 0) of every measurement for shots [shot_begin, shot_begin + n_shots)

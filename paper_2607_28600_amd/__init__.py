@@ -72,7 +72,7 @@ class symft_compile_opts(C.Structure):
 class symft_sample_opts(C.Structure):
     _fields_ = [("shot_offset", C.c_uint64), ("precision", C.c_uint32), ("sections", C.c_uint32),
                 ("row_stride_words", C.c_uint64), ("frame_entry_cap", C.c_uint32), ("frame_tile_words", C.c_uint32),
-                ("frame_kernel", C.c_uint32)]
+                ("frame_kernel", C.c_uint32), ("active_kernel", C.c_uint32)]
 
 
 class symft_count_opts(C.Structure):
@@ -248,19 +248,20 @@ class Program:
     # -- sampling (device) ------------------------------------------------
     def sample_into(self, out, shots: int, seed: int, shot_offset: int = 0, precision: str = "fp64",
                     sections: int = 0, row_stride_words: int = 0, stream=None, frame_entry_cap: int = 0,
-                    frame_tile_words: int = 0, frame_kernel: int = 0) -> None:
+                    frame_tile_words: int = 0, frame_kernel: int = 0, active_kernel: int = 0) -> None:
         """out: a device tensor / pointer holding n_rows x stride uint64 words."""
         import torch
         ptr = out.data_ptr() if hasattr(out, "data_ptr") else int(out)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         o = symft_sample_opts(shot_offset, 0 if precision == "fp64" else 1, sections, row_stride_words,
-                              frame_entry_cap, frame_tile_words, frame_kernel)
+                              frame_entry_cap, frame_tile_words, frame_kernel, active_kernel)
         _check(_lib.symft_sample_ex(self._h, C.byref(o), shots, seed, C.c_void_p(ptr), C.c_void_p(stream)),
                "symft_sample_ex")
 
     def sample_noalloc_into(self, out, shots: int, seed: int, shot_offset: int = 0, precision: str = "fp64",
-                            sections: int = 0, row_stride_words: int = 0, stream=None, frame_kernel: int = 0) -> None:
+                            sections: int = 0, row_stride_words: int = 0, stream=None, frame_kernel: int = 0,
+                            active_kernel: int = 0) -> None:
         """symft_sample_noalloc: as sample_into, with the kernels' scratch in the library's fixed device array
         (the program must have been sampled once on this device)."""
         import torch
@@ -268,12 +269,12 @@ class Program:
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         o = symft_sample_opts(shot_offset, 0 if precision == "fp64" else 1, sections, row_stride_words, 0, 0,
-                              frame_kernel)
+                              frame_kernel, active_kernel)
         _check(_lib.symft_sample_noalloc(self._h, C.byref(o), shots, seed, C.c_void_p(ptr), C.c_void_p(stream)),
                "symft_sample_noalloc")
 
     def sample(self, shots: int, seed: int, shot_offset: int = 0, precision: str = "fp64", device="cuda",
-               frame_entry_cap: int = 0, frame_tile_words: int = 0, frame_kernel: int = 0):
+               frame_entry_cap: int = 0, frame_tile_words: int = 0, frame_kernel: int = 0, active_kernel: int = 0):
         """Returns a [n_rows, ceil(shots/64)] int64 tensor on the GPU (uint64 bit patterns)."""
         import torch
         words = (shots + 63) // 64
@@ -281,7 +282,7 @@ class Program:
         if shots:
             self.sample_into(out, shots, seed, shot_offset=shot_offset, precision=precision,
                              frame_entry_cap=frame_entry_cap, frame_tile_words=frame_tile_words,
-                             frame_kernel=frame_kernel)
+                             frame_kernel=frame_kernel, active_kernel=active_kernel)
         return out[: self.n_rows, :words]
 
     def _count_opts(self, post, obs_expected, shot_offset, precision, threads_per_shot, mode=0, frame_kernel=0):

@@ -20,6 +20,9 @@ struct ActiveArgs;
 hipError_t launch_active(const ActiveArgs &A, bool fp64, uint32_t bs, uint32_t grid, hipStream_t st);
 size_t active_lds_bytes(const DevProg &P, uint32_t bs, uint32_t tps, bool lds_vec, bool fp64);
 int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds, bool cm);
+size_t lane_lds_bytes(const DevProg &P, bool fp64);
+int lane_max_blocks_per_cu(bool fp64, size_t lds);
+hipError_t launch_lane(const ActiveArgs &A, bool fp64, uint32_t grid, hipStream_t st);
 struct FrameArgs;
 struct CountArgs;
 hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st, uint32_t tw);
@@ -243,8 +246,7 @@ static void lower(symft_program *h) {
         d.dst = m.dst;
         d.src1 = m.src1;
         d.src2 = m.src2;
-        d.w1 = (uint8_t)m.w1;
-        d.w = (uint8_t)m.w;
+        d.m1w = (m.m1 & 0xFFFFFFu) | (m.w << 24);
         pmerge.push_back(d);
     }
     {
@@ -527,6 +529,7 @@ static int num_cus() {
 struct ActiveConfig {
     uint32_t bs, tps;
     bool lds_vec;
+    bool lane = false;  // the lane kernel: one wave per word, one lane per shot
     size_t lds;
 };
 
@@ -577,6 +580,29 @@ static bool narrow_wide(uint32_t k) { return k >= 13 && k <= 14; }
 static const uint32_t kHbmVec = 1u << 16;
 static bool hbm_candidate(uint32_t k) { return k >= 9 && k <= 12; }
 
+// A tuned (or forced) choice may carry this bit instead: the lane kernel, for
+// programs whose whole per-wave state (64 shots' vector buffers, outcome bits
+// and exogenous words) fits kLaneLds of LDS; records path only, not in batches.
+static const uint32_t kLaneVec = 1u << 17;
+static const size_t kLaneLds = 64 * 1024;
+static bool lane_candidate(const DevProg &P, bool fp64) { return P.k_max >= 1 && lane_lds_bytes(P, fp64) <= kLaneLds; }
+// A forced choice with this bit keeps the tuned thread count but never the lane kernel.
+static const uint32_t kNoLane = 1u << 18;
+
+// force_tps of a sampling call from symft_sample_opts.active_kernel.
+static symft_status active_choice(const DevProg &D, bool fp64, uint32_t sel, uint32_t &force) {
+    force = 0;
+    if (sel == 0) return SYMFT_OK;
+    if (sel == 1) {
+        force = kNoLane;
+        return SYMFT_OK;
+    }
+    if (sel != 2) return set_err(SYMFT_EINVAL, "active_kernel must be 0, 1 or 2");
+    if (!lane_candidate(D, fp64)) return set_err(SYMFT_ECAPACITY, "the lane kernel's state does not fit 64 KB of LDS");
+    force = 1u | kLaneVec;
+    return SYMFT_OK;
+}
+
 // count_mode: a workgroup holds one shot group when groups are a wave or
 // more (64 .. 256 threads), so it drops a discarded shot at once.
 // batch_budget: nonzero for a batch member, the batch's LDS budget per workgroup.
@@ -592,7 +618,18 @@ ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, 
         if (it != g_tune.end()) c.tps = it->second;
     }
     if (batch_budget && k < 13) c.tps = batch_tps(k, fp64, batch_budget);
-    if (force_tps) c.tps = force_tps;
+    if (force_tps & kNoLane) c.tps &= ~kLaneVec;
+    else if (force_tps) c.tps = force_tps;
+    if ((c.tps & kLaneVec) && !batch_budget && !count_mode && lane_candidate(P, fp64)) {
+        c.lane = true;
+        c.bs = 64;
+        c.tps = 1;
+        c.lds = lane_lds_bytes(P, fp64);
+        c.lds_vec = true;
+        return c;
+    }
+    // a lane choice tuned on another program of this width that this one cannot take
+    if (c.tps & kLaneVec) c.tps = default_tps(k, fp64);
     const bool hbm = (c.tps & kHbmVec) && hbm_candidate(k);
     c.tps &= ~kHbmVec;
     if (narrow_wide(k) && c.tps < 64) c.tps = 64;
@@ -614,6 +651,31 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
                                uint32_t amp_k = 0, const FixedScratch *fixed = nullptr) {
     ActiveConfig c = choose_active(D, fp64, force_tps, 0, cnt != nullptr);
     if (c.lds > kLdsLimit) return set_err(SYMFT_ECAPACITY, "program tables exceed the LDS budget of the active kernel");
+    if (c.lane) {
+        ActiveArgs A;
+        std::memset(&A, 0, sizeof(A));
+        A.P = D;
+        A.seed = seed;
+        A.word_begin = word_begin;
+        A.n_words = n_words;
+        A.shots = shots;
+        A.out = out;
+        A.row_stride = stride;
+        A.sections = sections;
+        A.tps = 1;
+        A.p0_out = p0;
+        A.amp_out = amp;
+        A.amp_k = amp_k;
+        A.probe_shot0 = probe_shot0;
+        A.probe_n = probe_n;
+        A.lds_vec = 1;
+        A.lds_bytes = (uint32_t)c.lds;
+        const int per_cu = std::max(1, lane_max_blocks_per_cu(fp64, c.lds));
+        const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_words, (uint64_t)per_cu * num_cus()));
+        const hipError_t e = launch_lane(A, fp64, grid, st);
+        if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("lane kernel launch failed: ") + hipGetErrorString(e));
+        return SYMFT_OK;
+    }
     int per_cu = active_max_blocks_per_cu(fp64, c.bs, c.lds_vec, c.lds, cnt != nullptr);
     if (per_cu <= 0) per_cu = 1;
     uint64_t cap = (uint64_t)per_cu * (uint64_t)num_cus();
@@ -952,7 +1014,11 @@ symft_status symft_sample_ex(const symft_program *pc, const symft_sample_opts *o
     if (D.fr_ok)
         return run_frame(p, D, w0, n_words, shots, records_out, stride, sections, seed, o.frame_entry_cap, st,
                          nullptr, o.frame_tile_words, o.frame_kernel);
-    return run_active(p, D, o.precision == 0, w0, n_words, shots, records_out, stride, sections, nullptr, 0, 0, seed, st);
+    uint32_t force = 0;
+    rc = active_choice(D, o.precision == 0, o.active_kernel, force);
+    if (rc) return rc;
+    return run_active(p, D, o.precision == 0, w0, n_words, shots, records_out, stride, sections, nullptr, 0, 0, seed, st,
+                      force);
 }
 
 symft_status symft_sample(const symft_program *p, uint64_t shots, uint64_t seed, uint64_t *records_out, void *stream) {
@@ -1022,8 +1088,11 @@ symft_status symft_sample_noalloc(const symft_program *pc, const symft_sample_op
     if (D.fr_ok)
         return run_frame(p, D, w0, n_words, shots, records_out, stride, sections, seed, o.frame_entry_cap, st,
                          nullptr, o.frame_tile_words, o.frame_kernel, &fx);
+    uint32_t force = 0;
+    rc = active_choice(D, o.precision == 0, o.active_kernel, force);
+    if (rc) return rc;
     return run_active(p, D, o.precision == 0, w0, n_words, shots, records_out, stride, sections, nullptr, 0, 0, seed,
-                      st, 0, nullptr, nullptr, 0, &fx);
+                      st, force, nullptr, nullptr, 0, &fx);
 }
 
 }  // extern "C"
@@ -1387,12 +1456,17 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
     uint32_t best_tps = default_tps(D.k_max, fp64);
     symft_status rc = SYMFT_OK;
     const bool hbm_try = hbm_candidate(D.k_max);
-    for (uint32_t cand : {4u, 8u, 16u, 32u, 64u, 128u, 256u, 1024u, 64u | kHbmVec, 128u | kHbmVec, 256u | kHbmVec}) {
-        const uint32_t tps = cand & ~kHbmVec;
+    const bool lane_try = lane_candidate(D, fp64);
+    for (uint32_t cand : {4u, 8u, 16u, 32u, 64u, 128u, 256u, 1024u, 64u | kHbmVec, 128u | kHbmVec, 256u | kHbmVec,
+                          1u | kLaneVec}) {
+        const uint32_t tps = cand & ~(kHbmVec | kLaneVec);
         if ((cand & kHbmVec) && !hbm_try) continue;
-        if (wide ? tps < 64 : tps > 256) continue;  // widths 13 and 14: 64 .. 256 threads, or 1024
-        if (((uint32_t)1 << D.k_max) < tps / 4 && tps > 4) continue;  // most lanes would idle
-        if (!wide && !(cand & kHbmVec) && active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
+        if ((cand & kLaneVec) && !lane_try) continue;
+        if (!(cand & kLaneVec)) {
+            if (wide ? tps < 64 : tps > 256) continue;  // widths 13 and 14: 64 .. 256 threads, or 1024
+            if (((uint32_t)1 << D.k_max) < tps / 4 && tps > 4) continue;  // most lanes would idle
+            if (!wide && !(cand & kHbmVec) && active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
+        }
         float ms = 0;
         for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
             (void)hipEventRecord(e0, st);
@@ -1416,7 +1490,7 @@ static symft_status tune_program(symft_program *p, const DevProg &D, bool fp64, 
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[{D.k_max, fp64}] = best_tps;
     }
-    if (tps_out) *tps_out = best_tps & ~kHbmVec;
+    if (tps_out) *tps_out = best_tps & ~(kHbmVec | kLaneVec);
     return SYMFT_OK;
 }
 

@@ -7,7 +7,8 @@
 // couples the coordinates of its masks (X part a, Z part b); when those lie in
 // several components, the components are first merged by an exact Kronecker
 // product and the instruction then runs on the merged component alone, with
-// its masks and pivot renumbered to the component's local coordinates.  An
+// its masks and pivot renumbered to the component's local coordinates (a
+// component's coordinates keep their dense order).  An
 // active measurement removes its pivot coordinate from its component.  A
 // component is never split again.
 //
@@ -59,7 +60,7 @@ void plan_components(const Program &P, ProductPlan &out) {
     std::vector<std::pair<uint32_t, uint32_t>> slot;
     // merges before each instruction, by component id (offsets filled after allocation)
     struct MergeIds {
-        uint32_t dst, src1, src2, w1, w;
+        uint32_t dst, src1, src2, m1, w;
     };
     std::vector<std::vector<MergeIds>> merges(n);
     std::vector<uint32_t> comp_of(n, UINT32_MAX);
@@ -104,12 +105,18 @@ void plan_components(const Program &P, ProductPlan &out) {
             comps[c1].last = std::max(comps[c1].last, t_merge);
             comps[c2].last = std::max(comps[c2].last, t_merge);
             const uint32_t id = (uint32_t)comps.size();
-            merges[i].push_back({id, c1, c2, comps[c1].w, m.w});
-            // x = x1 + 2^w1 x2: the first component's coordinates stay low
-            for (auto &s : slot) {
-                if (s.first == c1) s.first = id;
-                else if (s.first == c2) s = {id, s.second + comps[c1].w};
-            }
+            // The merged coordinates keep their dense order (local index = rank among the
+            // component's dense coordinates), so a pivot that is the highest set bit of a
+            // dense mask stays the highest of the local one, and a measurement's compaction
+            // reads every source at or above the index it writes.  m1 marks the first
+            // component's coordinates among the merged ones.
+            uint32_t m1 = 0, r = 0;
+            for (auto &s : slot)
+                if (s.first == c1 || s.first == c2) {
+                    if (s.first == c1) m1 |= 1u << r;
+                    s = {id, r++};
+                }
+            merges[i].push_back({id, c1, c2, m1, m.w});
             comps.push_back(m);
             out.work_product += 4.0 * std::ldexp(1.0, m.w);  // one complex product per amplitude
             L.erase(L.begin(), L.begin() + 2);
@@ -126,6 +133,14 @@ void plan_components(const Program &P, ProductPlan &out) {
         Q.a = al;
         Q.b = bl;
         Q.h = (uint8_t)slot[I.h].second;
+        // the kernels' pairings and in-place compactions take the pivot as the highest set bit of
+        // the pair mask (a) or, for a diagonal measurement, of b; the dense order inside a
+        // component keeps it so
+        const uint32_t pm = I.kind == ACTIVE_DIAG_MEAS ? bl : al;
+        if (I.kind != ACTIVE_DIAG_ROT && (pm == 0 || 31u - (uint32_t)__builtin_clz(pm) != Q.h)) {
+            out.valid = false;
+            return;
+        }
         Q.k_in = (uint8_t)comps[c].w;
         out.work_product += flops_of(I.kind, std::ldexp(1.0, comps[c].w));
         out.k_local_max = std::max<uint32_t>(out.k_local_max, comps[c].w);
@@ -175,7 +190,7 @@ void plan_components(const Program &P, ProductPlan &out) {
         Q.mg_off = (uint32_t)out.merges.size();
         Q.mg_len = (uint32_t)merges[i].size();
         for (const MergeIds &m : merges[i])
-            out.merges.push_back({comps[m.dst].off, comps[m.src1].off, comps[m.src2].off, m.w1, m.w});
+            out.merges.push_back({comps[m.dst].off, comps[m.src1].off, comps[m.src2].off, m.m1, m.w});
     }
     out.n_merges = (uint32_t)out.merges.size();
 }

@@ -30,12 +30,13 @@ struct DevInstr {
 };
 static_assert(sizeof(DevInstr) == 64, "DevInstr layout");
 
-// A Kronecker merge of two components (paper Sec. 6): dst[x] = src1[x mod
-// 2^w1] * src2[x >> w1] for x < 2^w (offsets in amplitudes of the shot's
-// vector buffer; the three regions do not overlap).
+// A Kronecker merge of two components (paper Sec. 6): for x < 2^w,
+// dst[x] = src1[x1] * src2[x2], where x1 gathers the bits of x at the set bits
+// of m1 and x2 those at the others, each in increasing order (offsets in
+// amplitudes of the shot's vector buffer; the three regions do not overlap).
 struct DevMerge {
     uint32_t dst, src1, src2;
-    uint8_t w1, w, pad[2];
+    uint32_t m1w;  // m1 in bits 0..23, w in bits 24..31
 };
 static_assert(sizeof(DevMerge) == 16, "DevMerge layout");
 

@@ -102,7 +102,7 @@ struct ProductPlan {
     };
     struct Merge {
         uint32_t dst, src1, src2;  // region offsets
-        uint32_t w1, w;            // width of src1; width of the result (src2 has w - w1)
+        uint32_t m1, w;            // the result's coordinates that come from src1 (bit mask); its width
     };
     std::vector<PInstr> ins;
     std::vector<Merge> merges;

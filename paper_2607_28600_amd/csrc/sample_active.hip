@@ -78,10 +78,19 @@ __device__ __forceinline__ DevMerge load_merge(const DevMerge *p, uint32_t i) {
     m.dst = q[0];
     m.src1 = q[1];
     m.src2 = q[2];
-    m.w1 = (uint8_t)q[3];
-    m.w = (uint8_t)(q[3] >> 8);
-    m.pad[0] = m.pad[1] = 0;
+    m.m1w = q[3];
     return m;
+}
+
+// The bits of x at the set bits of m, packed in increasing order (m wave-uniform).
+__device__ __forceinline__ uint32_t gather_bits(uint32_t x, uint32_t m) {
+    uint32_t r = 0, b = 1;
+    while (m) {
+        if (x & m & (0u - m)) r |= b;
+        b <<= 1;
+        m &= m - 1u;
+    }
+    return r;
 }
 
 // One pair of an ActivePairRot: (va at ya, vb at yb = ya ^ a) become
@@ -389,10 +398,10 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 V *vb = vec + I.base;
                 for (uint32_t q = 0; q < I.mg_len; ++q) {
                     const DevMerge M = load_merge(P.merges, I.mg_off + q);
-                    const uint32_t NW = 1u << M.w, m1 = (1u << M.w1) - 1u;
+                    const uint32_t NW = 1u << (M.m1w >> 24), m1 = M.m1w & 0xFFFFFFu, m2 = (NW - 1u) & ~m1;
                     if (live)
                     for (uint32_t x = (uint32_t)r; x < NW; x += (uint32_t)tps) {
-                        const V u = vec[M.src1 + (x & m1)], w = vec[M.src2 + (x >> M.w1)];
+                        const V u = vec[M.src1 + gather_bits(x, m1)], w = vec[M.src2 + gather_bits(x, m2)];
                         V o;
                         o.x = u.x * w.x - u.y * w.y;
                         o.y = u.x * w.y + u.y * w.x;
@@ -767,6 +776,335 @@ __global__ void __launch_bounds__(BS) active_kernel(ActiveArgs A) {
     run_active_words<T, BS, LDSV, CM>(A, blockIdx.x, A.n_words, gridDim.x, blockIdx.x, smem);
 }
 
+// ----------------------------------------------------------------- lane kernel
+// One wave per 64-shot word and one lane per shot, for programs whose vector
+// buffer is small (typically product components, a few amplitudes per shot).
+// Each shot's buffer lives in LDS amplitude-major (amplitude x of lane l at
+// x * 64 + l), and its outcome bits likewise (word j of lane l at j * 64 + l).
+// Every index, pivot and mask parity of an instruction is then the same for
+// all lanes (scalar work shared by the 64 shots); only the sign bits, the
+// branch decisions and the kept class differ per lane.  A measurement's sums,
+// decision and compaction are each lane's own, so the wave needs no shuffles,
+// reductions or barriers; the word's noise and RandomMeas words are drawn by
+// the same wave under the same draw contract (its 64-lane draw rounds take
+// the same sequence of Philox blocks as the shot-group kernel's wider ones).
+
+__device__ __forceinline__ void lane_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The word's noise events, XORed into exo[] (domains 1 and 2 of the draw contract).
+__device__ __forceinline__ void word_noise_wave(const DevProg &P, uint64_t seed, uint64_t w, unsigned long long *exo) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t wlo = (uint32_t)w, whi = (uint32_t)(w >> 32);
+    for (uint32_t c = 0; c < P.n_cls; ++c) {
+        const uint64_t *Q = P.cls_Q + (size_t)c * 4097;
+        const float il = P.cls_invlog2q[c];
+        const GapFast F = P.cls_fast[c];
+        const uint32_t coff = P.cls_off[c];
+        const uint64_t end = (uint64_t)(P.cls_off[c + 1] - coff) * 64;
+        uint64_t pos = 0, ev0 = 0, blk0 = 0;
+        while (pos < end) {
+            const uint4 r = philox4x32_10(make_uint4((uint32_t)(blk0 + lane), wlo, c, (1u << 24) | whi), k0, k1);
+            const uint32_t v[4] = {r.x, r.y, r.z, r.w};
+            int G[4];
+            uint32_t inc = 0, evc = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (!gap_fast_lean(F, v[i], G[i])) G[i] = v[i] >= F.vwin ? gap_window(Q, v[i], G[i]) : gap_of(Q, il, v[i]);
+                inc += (G[i] == 4096) ? 4096u : (uint32_t)G[i] + 1u;
+                evc += (G[i] < 4096) ? 1u : 0u;
+            }
+            const uint64_t mine = ((uint64_t)evc << 40) | inc;
+            uint64_t x = mine;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint64_t y = __shfl_up(x, off, 64);
+                if ((int)lane >= off) x += y;
+            }
+            const uint64_t total = __shfl(x, 63, 64);
+            const uint64_t ex = x - mine;
+            uint64_t p = pos + (ex & ((1ull << 40) - 1));
+            uint64_t e = ev0 + (ex >> 40);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (G[i] < 4096) {
+                    const uint64_t at = p + (uint64_t)G[i];
+                    if (at < end) {
+                        const uint32_t rank = (uint32_t)(at >> 6), sl = (uint32_t)(at & 63);
+                        const DevChan ch = P.chan[P.cls_chan[coff + rank]];
+                        const uint4 br = philox4x32_10(make_uint4((uint32_t)(e >> 2), wlo, c, (2u << 24) | whi), k0, k1);
+                        const uint32_t bv = (e & 3) == 0 ? br.x : (e & 3) == 1 ? br.y : (e & 3) == 2 ? br.z : br.w;
+                        uint32_t j;
+                        if (ch.uniform) {
+                            j = (uint32_t)(((uint64_t)bv * ch.J) >> 32);
+                        } else {
+                            j = ch.J - 1;
+                            for (uint32_t t = 0; t < ch.J; ++t)
+                                if ((uint64_t)bv < P.thr[ch.thr_off + t]) { j = t; break; }
+                        }
+                        uint32_t mask = P.bmask[ch.bm_off + j];
+                        while (mask) {
+                            const uint32_t sym = ch.sym0 + (uint32_t)__ffs(mask) - 1u;
+                            mask &= mask - 1u;
+                            for (uint32_t q = P.sym_off[sym]; q < P.sym_off[sym + 1]; ++q)
+                                atomicXor(&exo[P.sym_cons[q]], 1ull << sl);
+                        }
+                    }
+                    ++e;
+                }
+                p += (G[i] == 4096) ? 4096u : (uint32_t)G[i] + 1u;
+            }
+            pos += total & ((1ull << 40) - 1);
+            ev0 += total >> 40;
+            blk0 += 64;
+        }
+    }
+}
+
+// Parity of the causal part of lambda for this lane's shot.
+__device__ __forceinline__ int lane_parity(const DevProg &P, const DevInstr &I, const uint32_t *mb, uint32_t lane) {
+    const __attribute__((address_space(4))) uint32_t *q =
+        (const __attribute__((address_space(4))) uint32_t *)(P.cmeas + 2 * (size_t)I.cm_off);
+    uint32_t x = 0;
+    for (uint32_t j = 0; j < I.cm_len; ++j) x ^= mb[q[2 * j] * 64u + lane] & q[2 * j + 1];
+    return __popc(x) & 1;
+}
+
+// v * i^q
+template <typename V>
+__device__ __forceinline__ V lane_iq(V v, int q) {
+    V t;
+    t.x = (q == 0) ? v.x : (q == 1) ? -v.y : (q == 2) ? -v.x : v.y;
+    t.y = (q == 0) ? v.y : (q == 1) ? v.x : (q == 2) ? -v.y : -v.x;
+    return t;
+}
+
+// LDS of the lane kernel (one wave): exogenous words, outcome bits, vectors.
+__host__ __device__ inline size_t lane_vec_offset(uint32_t n_instr, uint32_t n_meas) {
+    const size_t mw = (n_meas + 31) / 32;
+    return ((size_t)8 * n_instr + (size_t)256 * mw + 15) & ~(size_t)15;
+}
+
+template <typename T>
+__device__ __forceinline__ void run_lane_words(const ActiveArgs &A, uint64_t wi_begin, uint64_t wi_end, uint64_t wi_step,
+                                               unsigned char *smem) {
+    using V = typename C2<T>::type;
+    const DevProg &P = A.P;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t mw = (P.n_meas + 31) / 32;
+    unsigned long long *exo = (unsigned long long *)smem;  // n_instr
+    uint32_t *mb = (uint32_t *)(exo + P.n_instr);            // [mw][64]
+    V *vec = (V *)(smem + lane_vec_offset(P.n_instr, P.n_meas));  // [2^k_max][64]
+    const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
+    const T rs2 = (T)0.70710678118654752440;
+    for (uint64_t wi = wi_begin; wi < wi_end; wi += wi_step) {
+        const uint64_t w = A.word_begin + wi;
+        const uint64_t shot = w * 64 + lane;
+        for (uint32_t i = lane; i < P.n_instr; i += 64) exo[i] = 0;
+        for (uint32_t j = 0; j < mw; ++j) mb[j * 64u + lane] = 0;
+        {
+            V one;
+            one.x = (T)1;
+            one.y = (T)0;
+            vec[lane] = one;
+        }
+        lane_sync();
+        word_noise_wave(P, A.seed, w, exo);
+        for (uint32_t i = lane; i < P.n_rm; i += 64) {
+            const uint32_t ii = P.rm_list[i];
+            const uint32_t t = (uint32_t)P.instr[ii].meas;
+            const uint4 o = philox4x32_10(make_uint4(t >> 1, (uint32_t)w, 0u, (3u << 24) | (uint32_t)(w >> 32)), k0, k1);
+            exo[ii] = (t & 1) ? ((uint64_t)o.z | ((uint64_t)o.w << 32)) : ((uint64_t)o.x | ((uint64_t)o.y << 32));
+        }
+        lane_sync();
+        const bool probe = shot - A.probe_shot0 < A.probe_n;
+        for (uint32_t ii = 0; ii < P.n_instr; ++ii) {
+            const DevInstr I = load_instr(P.instr, ii);
+            const uint32_t N = 1u << I.k_in;
+            V *vb = vec + (size_t)I.base * 64u;
+            for (uint32_t q = 0; q < I.mg_len; ++q) {
+                const DevMerge M = load_merge(P.merges, I.mg_off + q);
+                const uint32_t NW = 1u << (M.m1w >> 24), m1 = M.m1w & 0xFFFFFFu, m2 = (NW - 1u) & ~m1;
+                for (uint32_t x = 0; x < NW; ++x) {
+                    const V u = vec[(size_t)(M.src1 + gather_bits(x, m1)) * 64u + lane];
+                    const V v = vec[(size_t)(M.src2 + gather_bits(x, m2)) * 64u + lane];
+                    V o;
+                    o.x = u.x * v.x - u.y * v.y;
+                    o.y = u.x * v.y + u.y * v.x;
+                    vec[(size_t)(M.dst + x) * 64u + lane] = o;
+                }
+            }
+            const int lam = (int)I.lam_c ^ (int)((exo[ii] >> lane) & 1ull) ^ lane_parity(P, I, mb, lane);
+            const T c = sizeof(T) == 8 ? (T)I.c : (T)I.cf;
+            const T s = sizeof(T) == 8 ? (T)I.s : (T)I.sf;
+            switch (I.kind) {
+            case 1: {  // PromoteRot: x <- c a_x, x + N <- -i (-1)^lam s a_x
+                const T ss = lam ? -s : s;
+                for (uint32_t x = 0; x < N; ++x) {
+                    V v = vb[x * 64u + lane];
+                    V hi;
+                    hi.x = ss * v.y;
+                    hi.y = -ss * v.x;
+                    vb[(x + N) * 64u + lane] = hi;
+                    v.x *= c;
+                    v.y *= c;
+                    vb[x * 64u + lane] = v;
+                }
+                break;
+            }
+            case 8: {  // PromoteRot starting a component of its own, from the amplitude 1
+                const T ss = lam ? -s : s;
+                V lo, hi;
+                lo.x = c;
+                lo.y = (T)0;
+                hi.x = (T)0;
+                hi.y = -ss;
+                vb[lane] = lo;
+                vb[64u + lane] = hi;
+                break;
+            }
+            case 2: {  // ActiveDiagRot: a_x *= c - i sigma s, sigma = (-1)^lam mu (-1)^(b.x)
+                const int neg = lam ^ (I.mu == 2 ? 1 : 0);
+                for (uint32_t x = 0; x < N; ++x) {
+                    const T sg = (neg ^ parity(I.b & x)) ? -s : s;
+                    const V v = vb[x * 64u + lane];
+                    V o;
+                    o.x = c * v.x + sg * v.y;
+                    o.y = c * v.y - sg * v.x;
+                    vb[x * 64u + lane] = o;
+                }
+                break;
+            }
+            case 3: {  // ActivePairRot on pairs (x0, x0 ^ a), bit h of x0 = 0
+                const int e0 = (int)I.mu + 3 + 2 * lam;
+                for (uint32_t z = 0; z < (N >> 1); ++z) {
+                    const uint32_t x0 = insert_bit(z, I.h, 0), x1 = x0 ^ I.a;
+                    V a0 = vb[x0 * 64u + lane], a1 = vb[x1 * 64u + lane];
+                    pair_update(a0, a1, x0, x1, e0, I.b, c, s);
+                    vb[x0 * 64u + lane] = a0;
+                    vb[x1 * 64u + lane] = a1;
+                }
+                break;
+            }
+            case 4: {  // RandomMeas
+                const uint32_t t = (uint32_t)I.meas;
+                mb[(t >> 5) * 64u + lane] |= (uint32_t)((exo[ii] >> lane) & 1ull) << (t & 31);
+                if (A.p0_out && probe) A.p0_out[(shot - A.probe_shot0) * P.n_meas + t] = 0.5;
+                break;
+            }
+            case 5: {  // DetMeas: m = lambda ^ eta
+                const uint32_t t = (uint32_t)I.meas;
+                mb[(t >> 5) * 64u + lane] |= (uint32_t)(lam ^ I.eta) << (t & 31);
+                if (A.p0_out && probe) A.p0_out[(shot - A.probe_shot0) * P.n_meas + t] = (lam ^ I.eta) ? 0.0 : 1.0;
+                break;
+            }
+            case 6:    // ActiveDiagMeas
+            case 7: {  // ActivePairMeas
+                const bool pair = I.kind == 7;
+                const uint32_t t = (uint32_t)I.meas, half = N >> 1;
+                const uint4 od = philox4x32_10(make_uint4(t, (uint32_t)shot, (uint32_t)(shot >> 32), 4u << 24), k0, k1);
+                const int mc = (4 - (int)I.mu) & 3;  // conj(mu) = i^mc
+                T s0 = 0, s1 = 0, c0 = 0, c1 = 0;
+                if (!pair) {
+                    for (uint32_t x = 0; x < N; ++x) {
+                        const V v = vb[x * 64u + lane];
+                        const T m2 = v.x * v.x + v.y * v.y;
+                        if (parity(I.b & x)) kahan_add(s1, c1, m2); else kahan_add(s0, c0, m2);
+                    }
+                } else {
+                    for (uint32_t z = 0; z < half; ++z) {
+                        const uint32_t u0 = insert_bit(z, I.h, 0);
+                        const V a0 = vb[u0 * 64u + lane];
+                        const V tt = lane_iq(vb[(u0 ^ I.a) * 64u + lane], (mc + 2 * parity(I.b & u0)) & 3);
+                        const T bx = (a0.x + tt.x) * rs2, by = (a0.y + tt.y) * rs2;
+                        const T dx = (a0.x - tt.x) * rs2, dy = (a0.y - tt.y) * rs2;
+                        kahan_add(s0, c0, bx * bx + by * by);
+                        kahan_add(s1, c1, dx * dx + dy * dy);
+                    }
+                }
+                const int flip = pair ? lam : (lam ^ (int)I.eta);
+                const double S0 = (double)s0, S1 = (double)s1;
+                const double p0 = (flip ? S1 : S0) / (S0 + S1);
+                const double u = (double)(((uint64_t)od.x << 21) + (uint64_t)(od.y >> 11)) * 0x1p-53;
+                const int m = (u < p0) ? 0 : 1;
+                const int y = m ^ flip;  // kept class
+                const double Sy = y ? S1 : S0;
+                const T scale = (T)(1.0 / sqrt(Sy > 0x1p-1000 ? Sy : 0x1p-1000));
+                mb[(t >> 5) * 64u + lane] |= (uint32_t)m << (t & 31);
+                if (A.p0_out && probe) A.p0_out[(shot - A.probe_shot0) * P.n_meas + t] = p0;
+                // compaction 2^k -> 2^(k-1) in place: output z's sources lie at indices >= z,
+                // so increasing z never overwrites a source still to be read
+                const uint32_t bl = I.b & ~(1u << I.h);
+                for (uint32_t z = 0; z < half; ++z) {
+                    V o;
+                    if (!pair) {
+                        const uint32_t uu = insert_bit(z, I.h, (uint32_t)y);
+                        const uint32_t x = uu ^ ((uint32_t)parity(bl & uu) << I.h);
+                        const V v = vb[x * 64u + lane];
+                        o.x = v.x * scale;
+                        o.y = v.y * scale;
+                    } else {
+                        const uint32_t u0 = insert_bit(z, I.h, 0);
+                        const V a0 = vb[u0 * 64u + lane];
+                        const V tt = lane_iq(vb[(u0 ^ I.a) * 64u + lane], (mc + 2 * parity(I.b & u0) + 2 * y) & 3);
+                        o.x = (a0.x + tt.x) * rs2 * scale;
+                        o.y = (a0.y + tt.y) * rs2 * scale;
+                    }
+                    vb[z * 64u + lane] = o;
+                }
+                break;
+            }
+            default: break;
+            }
+        }
+        if (A.amp_out && probe) {
+            double *dst = A.amp_out + (shot - A.probe_shot0) * (2ull << A.amp_k);
+            for (uint32_t x = 0; x < (1u << A.amp_k); ++x) {
+                const V v = vec[x * 64u + lane];
+                dst[2 * x] = (double)v.x;
+                dst[2 * x + 1] = (double)v.y;
+            }
+        }
+        // rows: one ballot per row over the word's shots (bits past the call's shots are 0)
+        const bool valid = shot - A.word_begin * 64 < A.shots;
+        const uint64_t col = wi;
+        auto rec_bit = [&](uint32_t row) -> uint32_t {
+            const uint32_t t = P.rec_meas[row];
+            return (mb[(t >> 5) * 64u + lane] >> (t & 31)) & 1u;
+        };
+        if (A.sections & 1u)
+            for (uint32_t row = 0; row < P.n_rec; ++row) {
+                const uint64_t v = __ballot(valid && rec_bit(row));
+                if (lane == 0) A.out[(uint64_t)row * A.row_stride + col] = v;
+            }
+        if (A.sections & 2u)
+            for (uint32_t d = 0; d < P.n_det; ++d) {
+                uint32_t x = 0;
+                for (uint32_t q = P.det_off[d]; q < P.det_off[d + 1]; ++q) x ^= rec_bit(P.det_rows[q]);
+                const uint64_t v = __ballot(valid && x);
+                if (lane == 0) A.out[(uint64_t)(P.n_rec + d) * A.row_stride + col] = v;
+            }
+        if (A.sections & 4u)
+            for (uint32_t b = 0; b < P.n_obs; ++b) {
+                uint32_t x = 0;
+                for (uint32_t q = P.obs_off[b]; q < P.obs_off[b + 1]; ++q) x ^= rec_bit(P.obs_rows[q]);
+                const uint64_t v = __ballot(valid && x);
+                if (lane == 0) A.out[(uint64_t)(P.n_rec + P.n_det + b) * A.row_stride + col] = v;
+            }
+        lane_sync();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) lane_kernel(ActiveArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    run_lane_words<T>(A, blockIdx.x, A.n_words, gridDim.x, smem);
+}
+
 // Persistent work queue over (program, word range) items: every workgroup
 // takes the next item index with a global atomic until the list is exhausted,
 // so every wave reaches the exit.  Items are ordered by decreasing cost.
@@ -921,6 +1259,28 @@ int batch_max_blocks_per_cu(bool fp64, bool cm, size_t lds) {
 
 hipError_t launch_active(const ActiveArgs &A, bool fp64, uint32_t bs, uint32_t grid, hipStream_t st) {
     return dispatch<LaunchOne>(fp64, bs, A.lds_vec != 0, A.cnt.on != 0, A, grid, st);
+}
+
+
+// The lane kernel: LDS bytes per wave (= per workgroup), occupancy and launch.
+size_t lane_lds_bytes(const DevProg &P, bool fp64) {
+    return lane_vec_offset(P.n_instr, P.n_meas) + ((size_t)64 << P.k_max) * (fp64 ? 16 : 8);
+}
+
+int lane_max_blocks_per_cu(bool fp64, size_t lds) {
+    int nb = 0;
+    const void *k = fp64 ? (const void *)lane_kernel<double> : (const void *)lane_kernel<float>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, lds) != hipSuccess) return 1;
+    return nb;
+}
+
+hipError_t launch_lane(const ActiveArgs &A, bool fp64, uint32_t grid, hipStream_t st) {
+    const void *k = fp64 ? (const void *)lane_kernel<double> : (const void *)lane_kernel<float>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds_bytes);
+    if (e != hipSuccess) return e;
+    if (fp64) hipLaunchKernelGGL(lane_kernel<double>, dim3(grid), dim3(64), A.lds_bytes, st, A);
+    else hipLaunchKernelGGL(lane_kernel<float>, dim3(grid), dim3(64), A.lds_bytes, st, A);
+    return hipGetLastError();
 }
 
 }  // namespace symft

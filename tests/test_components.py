@@ -166,6 +166,22 @@ def test_plan_automatic_choice_rule():
     assert seen > 10
 
 
+def test_forced_plan_valid_everywhere():
+    """With components forced on, every program with an active state gets a product plan: the lowering
+    keeps each component's coordinates in dense order, so every pivot stays the highest set bit of its
+    local mask (the lowering falls back to dense otherwise, which this would catch)."""
+    from workloads import configs
+    circs = [configs.c3().circuit, configs.postselect().circuit, configs.distill().circuit,
+             configs.c5(14).circuit, configs.c5(16).circuit] + [w.circuit for w in configs.c4()[::7]]
+    rng = np.random.default_rng(17)
+    circs += [random_circuit(rng, int(rng.integers(3, 10)), int(rng.integers(30, 120))) for _ in range(60)]
+    for c in circs:
+        i = S.Program(c, components="on").info()
+        if i["k_max"] == 0:
+            continue
+        assert i["product_selected"] == 1, (i["k_max"], i["product_merges"], i["product_vector_amplitudes"])
+
+
 def test_compile_option_is_checked():
     c = _rotations([0.5])
     opts = S.symft_compile_opts(components=3)
