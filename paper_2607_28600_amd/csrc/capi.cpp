@@ -23,11 +23,13 @@ int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds, b
 size_t lane_lds_bytes(const DevProg &P, bool fp64);
 int lane_max_blocks_per_cu(bool fp64, size_t lds);
 hipError_t launch_lane(const ActiveArgs &A, bool fp64, uint32_t grid, hipStream_t st);
+int lane_batch_max_blocks_per_cu(bool fp64, size_t lds);
 struct FrameArgs;
 struct CountArgs;
 hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st, uint32_t tw);
 struct BatchArgs;
 hipError_t launch_batch(const BatchArgs &B, bool fp64, bool cm, uint32_t grid, uint32_t lds, hipStream_t st);
+hipError_t launch_lane_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t lds, hipStream_t st);
 int batch_max_blocks_per_cu(bool fp64, bool cm, size_t lds);
 size_t frame_lds_bytes(const DevProg &P, uint32_t tw);
 hipError_t launch_flags_from_rows(const uint64_t *rows, uint64_t n_words, uint64_t shots, uint64_t n_rec,
@@ -1517,6 +1519,11 @@ struct BatchPlan {
     uint32_t *d_counter = nullptr;
     BatchArgs args;
     uint32_t grid = 0, lds = 0;
+    // members on the lane kernel: their own queue (counter d_counter + 16), one-wave workgroups
+    ActiveArgs *d_lcalls = nullptr;
+    BatchItem *d_litems = nullptr;
+    BatchArgs largs;
+    uint32_t lgrid = 0, llds = 0;
     std::vector<size_t> others;  // programs sampled by their own launches
     // aggregate-count plans: the count tables' contents and the counters, compared with sig
     bool cm = false;
@@ -1538,11 +1545,15 @@ struct BatchPlan {
         (void)hipFree(d_calls);
         (void)hipFree(d_items);
         (void)hipFree(d_counter);
+        (void)hipFree(d_lcalls);
+        (void)hipFree(d_litems);
         exec = nullptr;
         graph = nullptr;
         d_calls = nullptr;
         d_items = nullptr;
         d_counter = nullptr;
+        d_lcalls = nullptr;
+        d_litems = nullptr;
     }
 };
 
@@ -1581,10 +1592,10 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
     if (!cnt) B.outs.assign(outs, outs + n);
     B.precision = precision;
     (void)hipGetDevice(&B.device);
-    std::vector<ActiveArgs> calls;
-    std::vector<double> cost;
-    std::vector<uint64_t> words_of;
-    size_t lds = 0;
+    std::vector<ActiveArgs> calls, lcalls;
+    std::vector<double> cost, lcost;
+    std::vector<uint64_t> words_of, lwords_of;
+    size_t lds = 0, llds = 0;
     for (size_t i = 0; i < n; ++i) {
         symft_program *p = const_cast<symft_program *>(progs[i]);
         if (!p || (!cnt && shots[i] && !outs[i])) return set_err(SYMFT_EINVAL, "NULL program or output in batch");
@@ -1592,6 +1603,34 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         symft_status rc = device_prog(p, D);
         if (rc) return rc;
         bool mine = shots[i] > 0 && !D.fr_ok;
+        symft_info info;
+        symft_program_info(p, &info);
+        uint64_t n_instr = 0;
+        for (uint64_t v : info.n_instr) n_instr += v;
+        // estimated cost per word: the representation's flops and a per-instruction share
+        const double wcost =
+            (info.product_selected ? info.product_flops_per_shot : info.dense_flops_per_shot) + 200.0 * (double)n_instr + 64.0;
+        if (mine && !cnt && lane_candidate(D, fp64)) {
+            // the lane kernel, in a queue of its own
+            ActiveArgs A;
+            std::memset(&A, 0, sizeof(A));
+            A.P = D;
+            A.seed = seeds[i];
+            A.word_begin = word0 ? word0[i] : 0;
+            A.n_words = (shots[i] + 63) / 64;
+            A.shots = shots[i];
+            A.out = outs[i];
+            A.row_stride = A.n_words;
+            A.sections = 7u;
+            A.tps = 1;
+            A.lds_vec = 1;
+            A.lds_bytes = (uint32_t)lane_lds_bytes(D, fp64);
+            llds = std::max<size_t>(llds, A.lds_bytes);
+            lcalls.push_back(A);
+            lwords_of.push_back(A.n_words);
+            lcost.push_back(wcost);
+            continue;
+        }
         ActiveConfig c;
         if (mine) {
             c = choose_active(D, fp64, 0, budget);
@@ -1618,9 +1657,42 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         lds = std::max(lds, c.lds);
         calls.push_back(A);
         words_of.push_back(A.n_words);
-        symft_info info;
-        symft_program_info(p, &info);
-        cost.push_back(info.dense_flops_per_shot + 200.0 * (double)info.n_instr[0] + 64.0);
+        cost.push_back(wcost);
+    }
+    if (hipMalloc(&B.d_counter, 256) != hipSuccess) return set_err(SYMFT_ENOMEM, "batch metadata allocation failed");
+    if (!lcalls.empty()) {
+        // items of a few words for one-wave workgroups, by decreasing cost
+        const int per_cu = std::max(1, lane_batch_max_blocks_per_cu(fp64, llds));
+        B.lgrid = (uint32_t)(per_cu * num_cus());
+        uint64_t total_words = 0;
+        for (uint64_t w : lwords_of) total_words += w;
+        const uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(16, total_words / ((uint64_t)B.lgrid * 4) + 1));
+        std::vector<std::pair<double, BatchItem>> tmp;
+        for (size_t ci = 0; ci < lcalls.size(); ++ci)
+            for (uint64_t w0 = 0; w0 < lwords_of[ci]; w0 += chunk) {
+                BatchItem it;
+                it.call = (uint32_t)ci;
+                it.pad = 0;
+                it.w0 = w0;
+                it.w1 = std::min(lwords_of[ci], w0 + chunk);
+                tmp.push_back({lcost[ci] * (double)(it.w1 - it.w0), it});
+            }
+        std::stable_sort(tmp.begin(), tmp.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+        std::vector<BatchItem> litems;
+        for (auto &x : tmp) litems.push_back(x.second);
+        B.lgrid = (uint32_t)std::min<uint64_t>(B.lgrid, litems.size());
+        B.llds = (uint32_t)llds;
+        if (hipMalloc(&B.d_lcalls, sizeof(ActiveArgs) * lcalls.size()) != hipSuccess ||
+            hipMalloc(&B.d_litems, sizeof(BatchItem) * litems.size()) != hipSuccess)
+            return set_err(SYMFT_ENOMEM, "batch metadata allocation failed");
+        if (hipMemcpy(B.d_lcalls, lcalls.data(), sizeof(ActiveArgs) * lcalls.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(B.d_litems, litems.data(), sizeof(BatchItem) * litems.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return set_err(SYMFT_EHIP, "batch metadata upload failed");
+        B.largs.calls = B.d_lcalls;
+        B.largs.items = B.d_litems;
+        B.largs.counter = B.d_counter + 16;
+        B.largs.n_items = (uint32_t)litems.size();
+        B.largs.pad = 0;
     }
     std::vector<BatchItem> items;
     if (!calls.empty()) {
@@ -1645,8 +1717,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         B.grid = (uint32_t)std::min<uint64_t>(B.grid, items.size());
         B.lds = (uint32_t)lds;
         if (hipMalloc(&B.d_calls, sizeof(ActiveArgs) * calls.size()) != hipSuccess ||
-            hipMalloc(&B.d_items, sizeof(BatchItem) * items.size()) != hipSuccess ||
-            hipMalloc(&B.d_counter, 256) != hipSuccess)
+            hipMalloc(&B.d_items, sizeof(BatchItem) * items.size()) != hipSuccess)
             return set_err(SYMFT_ENOMEM, "batch metadata allocation failed");
         if (hipMemcpy(B.d_calls, calls.data(), sizeof(ActiveArgs) * calls.size(), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(B.d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess)
@@ -1662,15 +1733,23 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
 
 // The plan's persistent kernel (after its counter reset), launched directly or
 // through its captured graph.
+// The plan's launches: the lane members' queue, then the shot-group members'.
+static hipError_t launch_plan(BatchPlan &B, bool fp64, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    if (B.largs.n_items) e = launch_lane_batch(B.largs, fp64, B.lgrid, B.llds, st);
+    if (e == hipSuccess && B.args.n_items) e = launch_batch(B.args, fp64, B.cm, B.grid, B.lds, st);
+    return e;
+}
+
 static symft_status run_plan(BatchPlan &B, bool fp64, uint32_t graph, hipStream_t st) {
-    if (!B.args.n_items) return SYMFT_OK;
+    if (!B.args.n_items && !B.largs.n_items) return SYMFT_OK;
     if (graph) {
         if (!B.exec) {
-            // capture [counter reset, persistent kernel] once on a private stream
+            // capture [counter resets, persistent kernels] once on a private stream
             hipStream_t cs;
             if (hipStreamCreate(&cs) != hipSuccess) return set_err(SYMFT_EHIP, "stream creation failed");
             hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) e = launch_batch(B.args, fp64, B.cm, B.grid, B.lds, cs);
+            if (e == hipSuccess) e = launch_plan(B, fp64, cs);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(cs, &g);
             if (e == hipSuccess) e = e2;
@@ -1682,7 +1761,7 @@ static symft_status run_plan(BatchPlan &B, bool fp64, uint32_t graph, hipStream_
         hipError_t e = hipGraphLaunch(B.exec, st);
         if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("batch graph launch failed: ") + hipGetErrorString(e));
     } else {
-        hipError_t e = launch_batch(B.args, fp64, B.cm, B.grid, B.lds, st);
+        hipError_t e = launch_plan(B, fp64, st);
         if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("batch kernel launch failed: ") + hipGetErrorString(e));
     }
     return SYMFT_OK;

@@ -1105,6 +1105,22 @@ __global__ void __launch_bounds__(64) lane_kernel(ActiveArgs A) {
     run_lane_words<T>(A, blockIdx.x, A.n_words, gridDim.x, smem);
 }
 
+// The lane kernel behind a persistent queue of (program, word range) items:
+// each one-wave workgroup takes the next item with a global atomic until the
+// list is exhausted.
+template <typename T>
+__global__ void __launch_bounds__(64) lane_batch_kernel(BatchArgs B) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    while (true) {
+        uint32_t idx = 0;
+        if ((threadIdx.x & 63u) == 0) idx = atomicAdd(B.counter, 1u);
+        idx = (uint32_t)__shfl((int)idx, 0, 64);
+        if (idx >= B.n_items) break;
+        const BatchItem it = B.items[idx];
+        run_lane_words<T>(B.calls[it.call], it.w0, it.w1, 1, smem);
+    }
+}
+
 // Persistent work queue over (program, word range) items: every workgroup
 // takes the next item index with a global atomic until the list is exhausted,
 // so every wave reaches the exit.  Items are ordered by decreasing cost.
@@ -1272,6 +1288,23 @@ int lane_max_blocks_per_cu(bool fp64, size_t lds) {
     const void *k = fp64 ? (const void *)lane_kernel<double> : (const void *)lane_kernel<float>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, lds) != hipSuccess) return 1;
     return nb;
+}
+
+int lane_batch_max_blocks_per_cu(bool fp64, size_t lds) {
+    int nb = 0;
+    const void *k = fp64 ? (const void *)lane_batch_kernel<double> : (const void *)lane_batch_kernel<float>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, lds) != hipSuccess) return 1;
+    return nb;
+}
+
+hipError_t launch_lane_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t lds, hipStream_t st) {
+    const void *k = fp64 ? (const void *)lane_batch_kernel<double> : (const void *)lane_batch_kernel<float>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, B.counter);
+    if (fp64) hipLaunchKernelGGL(lane_batch_kernel<double>, dim3(grid), dim3(64), lds, st, B);
+    else hipLaunchKernelGGL(lane_batch_kernel<float>, dim3(grid), dim3(64), lds, st, B);
+    return hipGetLastError();
 }
 
 hipError_t launch_lane(const ActiveArgs &A, bool fp64, uint32_t grid, hipStream_t st) {
