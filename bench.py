@@ -278,8 +278,8 @@ def run(args):
             achieved = flops / (ms_kernel / 1e3) / 1e12
             peak = FP32_PEAK_TFLOPS if prec == "fp32" else FP64_PEAK_TFLOPS
             roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved / peak, 4), "traffic": None, "kernel": "active_kernel",
-                    "flops_per_launch": flops}
+                    "frac": round(achieved / peak, 4), "traffic": None,
+                    "kernel": "lane_kernel" if tps == 1 else "active_kernel", "flops_per_launch": flops}
         config = {"workload": w.name, "shots": w.shots, "rows": prog.n_rows, "k_max": info["k_max"],
                   "precision": prec if info["k_max"] else "n/a (integer path)"}
         if tps:
@@ -314,7 +314,8 @@ def run(args):
         achieved = flops / (ms_kernel / 1e3) / 1e12
         peak = FP32_PEAK_TFLOPS if prec == "fp32" else FP64_PEAK_TFLOPS
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": "batch_kernel"}
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "lane_batch_kernel + batch_kernel (one graph)"}
         dtype = "f32" if prec == "fp32" else "f64"
         config = {"workload": "batch_128_near_clifford", "shots": cmp["shots"], "programs": len(ws), "precision": prec,
                   "representation": "automatic per member"}
@@ -360,7 +361,8 @@ def run(args):
         achieved = flops / (ms_rec_kernel / 1e3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": "active_kernel (full-records launch)", "flops_per_launch": flops}
+                "kernel": ("lane_kernel" if tps == 1 else "active_kernel") + " (full-records launch)",
+                "flops_per_launch": flops}
         dtype = "f32"
         config = {"workload": w.name, "shots": w.shots, "rows": prog.n_rows, "k_max": info["k_max"],
                   "precision": prec, "threads_per_shot": tps_counts, "threads_per_shot_full_records": tps,
