@@ -142,3 +142,47 @@ def test_too_large_is_refused():
     p = S.Program(w.circuit, components="off")  # 256 amplitudes x 64 shots: past 64 KB
     with pytest.raises(S.SymftError):
         p.sample(64, w.seed, active_kernel=2)
+
+
+def test_probes_after_the_autotuner_picks_it():
+    """Once the autotuner has chosen the lane kernel (reported as 1 thread per shot), the probes run on it:
+    branch probabilities against the oracle (C3 on components, FP64 1e-12) and the final vector of a dense
+    width-4 program against the oracle's up to the Pauli frame."""
+    import oracle as O
+    from tests.parity_util import frame_relation
+    w = configs.c3()
+    p = S.Program(w.circuit)
+    tps = p.autotune("fp64")
+    print(f"c3 fp64 autotune: {tps}", flush=True)
+    if tps != 1:
+        pytest.skip("the autotuner kept the shot-group kernel on this box")
+    oc = OracleCircuit(w.circuit)
+    shots = list(range(64 * 3, 64 * 3 + 20))
+    p0 = p.probe(shots[0], len(shots), w.seed, precision="fp64")
+    worst = 0.0
+    for i, s in enumerate(shots):
+        tr = oc.trace(w.seed, s)
+        for t in np.flatnonzero(tr["meas_kind"] >= 2):
+            worst = max(worst, abs(p0[i, t] - tr["p0"][t]))
+            if abs(O.active_u(w.seed, int(t), s) - tr["p0"][t]) < TOL["fp64"]:
+                break
+    assert worst < 1e-12, worst
+    x = [x for x in configs.c4() if S.Program(x.circuit, components="off").k_max == 4][0]
+    q = S.Program(x.circuit, components="off")
+    if q.autotune("fp64") != 1:
+        pytest.skip("the autotuner kept the shot-group kernel for the width-4 program")
+    n = 32
+    amp = q.probe_amplitudes(0, n, x.seed, precision="fp64")
+    rec = S.bits_to_numpy(q.sample(n, x.seed, precision="fp64"))
+    ox = OracleCircuit(x.circuit)
+    want = ox.sample(x.seed, n)
+    checked = 0
+    for shot in range(n):
+        bit = np.uint64(shot % 64)
+        if not np.array_equal((rec[:, shot // 64] >> bit) & np.uint64(1), (want[:, shot // 64] >> bit) & np.uint64(1)):
+            continue
+        fs = ox.final_state(x.seed, shot)
+        assert amp.shape[1] == 1 << fs["k"]
+        assert frame_relation(amp[shot], fs["alpha"], 1e-9) is not None, shot
+        checked += 1
+    assert checked >= n - 2

@@ -71,11 +71,11 @@ def test_noalloc_rejects_a_program_not_resident_here():
 
 
 def test_noalloc_rejects_a_workgroup_past_the_fixed_scratch():
-    """A width-23 state in FP64 needs 128 MiB of vector scratch for its one shot group: ECAPACITY, raised
-    before any launch."""
+    """A width-23 state in FP64 (the dense vector) needs 128 MiB of vector scratch for its one shot group:
+    ECAPACITY, raised before any launch."""
     from tests.randcirc import wide_circuit
     c = wide_circuit(19, 7)
-    p = S.Program(c)
+    p = S.Program(c, components="off")
     assert p.k_max == 23
     # the autotuner uploads the program (and times nothing at widths past 14)
     p.autotune("fp64")
