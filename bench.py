@@ -303,6 +303,30 @@ def run(args):
                        "c5k16fp64": 2}[wl]
         sample_words = [int(i * words / n_cpu_words) for i in range(n_cpu_words)]
         circ, seed = w.circuit, w.seed
+        if wl == "c1" and args.extras:
+            # the launch-latency-bound case: the same call eager, through the allocation-free entry point,
+            # and captured once in a HIP graph and replayed (that entry point allocates nothing, so it can be
+            # captured); every replay's records equal the eager call's
+            eager = out.clone()
+            prog.sample_noalloc_into(out, w.shots, w.seed, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager)
+
+            def noalloc():
+                prog.sample_noalloc_into(out, w.shots, w.seed, stream=stream.cuda_stream)
+            ms_na, _ = _time_launches(noalloc, args.steps, args.warmup, stream)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, capture_error_mode="thread_local"):
+                prog.sample_noalloc_into(out, w.shots, w.seed)
+            out.fill_(-1)
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager), "graph replay differs from the eager call"
+            ms_g, _ = _time_launches(graph.replay, args.steps, args.warmup, stream)
+            extra["c1_launch_latency"] = {"eager_us_per_call": round(ms_step * 1e3, 2),
+                                          "noalloc_us_per_call": round(ms_na * 1e3, 2),
+                                          "graph_replay_us_per_call": round(ms_g * 1e3, 2),
+                                          "kernel_us": round(ms_kernel * 1e3, 2)}
         if wl == "c2" and args.extras:
             extra["c4_batch"], _ = _c4_comparison(S, stream, 6)
     elif wl in ("c4", "c4fp64"):
