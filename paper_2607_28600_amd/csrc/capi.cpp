@@ -438,9 +438,11 @@ static symft_status device_prog(symft_program *h, DevProg &out, bool upload = tr
     out = L.meta;
     out.instr = (const DevInstr *)(b + L.o_instr);
     out.merges = (const DevMerge *)(b + L.o_merge);
+    out.vcap = 1u << out.k_max;
     if (h->product && !dense) {
         out.instr = (const DevInstr *)(b + L.o_pinstr);
         out.k_max = h->k_eff;
+        out.vcap = h->PP.vcap;
     }
     out.cmeas = (const uint32_t *)(b + L.o_cmeas);
     out.am_meas = (const uint32_t *)(b + L.o_am);
@@ -588,6 +590,11 @@ static bool hbm_candidate(uint32_t k) { return k >= 9 && k <= 12; }
 static const uint32_t kLaneVec = 1u << 17;
 static const size_t kLaneLds = 64 * 1024;
 static bool lane_candidate(const DevProg &P, bool fp64) { return P.k_max >= 1 && lane_lds_bytes(P, fp64) <= kLaneLds; }
+// In a batch the lane queue's LDS size is its largest member's, which sets the
+// occupancy of all of them: members above kLaneBatchLds stay in the
+// shot-group queue (on C4, admitting members up to 64 KB took the FP32 batch
+// from 5.3 to 6.6 ms).
+static const size_t kLaneBatchLds = 40 * 1024;
 // A forced choice with this bit keeps the tuned thread count but never the lane kernel.
 static const uint32_t kNoLane = 1u << 18;
 
@@ -1610,7 +1617,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         // estimated cost per word: the representation's flops and a per-instruction share
         const double wcost =
             (info.product_selected ? info.product_flops_per_shot : info.dense_flops_per_shot) + 200.0 * (double)n_instr + 64.0;
-        if (mine && !cnt && lane_candidate(D, fp64)) {
+        if (mine && !cnt && lane_candidate(D, fp64) && lane_lds_bytes(D, fp64) <= kLaneBatchLds) {
             // the lane kernel, in a queue of its own
             ActiveArgs A;
             std::memset(&A, 0, sizeof(A));

@@ -122,6 +122,7 @@ struct DevProg {
     uint32_t fr_n_steps, fr_n_slots, n_sym, fr_ok;   // fr_ok: the pure-frame kernel can run the program
     uint32_t fr_first_emit, fr_first_emit_n, fr_first_noise_cls, n_am;
     uint32_t wv_n_ops, wv_n_rm, wv_first_noise_cls, wv_first_batch, wv_first_batch_n, wv_ok;
+    uint32_t vcap, vcap_pad;     // amplitudes per shot the instruction stream touches (<= 2^k_max)
     uint32_t fr_n_cch;           // entries of fr_ci32 / fr_st8: channels over all classes, padded to a multiple of 16
     uint32_t fr_ltab;            // nonzero: phase G copies fr_ci32, fr_st8 and cls_Q32 into LDS
     uint32_t fr_rec_ok;          // nonzero: slots below 2^12, as the step-synchronous kernel's entries need

@@ -898,7 +898,7 @@ __device__ __forceinline__ void run_lane_words(const ActiveArgs &A, uint64_t wi_
     const uint32_t mw = (P.n_meas + 31) / 32;
     unsigned long long *exo = (unsigned long long *)smem;  // n_instr
     uint32_t *mb = (uint32_t *)(exo + P.n_instr);            // [mw][64]
-    V *vec = (V *)(smem + lane_vec_offset(P.n_instr, P.n_meas));  // [2^k_max][64]
+    V *vec = (V *)(smem + lane_vec_offset(P.n_instr, P.n_meas));  // [vcap][64]
     const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
     const T rs2 = (T)0.70710678118654752440;
     for (uint64_t wi = wi_begin; wi < wi_end; wi += wi_step) {
@@ -1280,7 +1280,7 @@ hipError_t launch_active(const ActiveArgs &A, bool fp64, uint32_t bs, uint32_t g
 
 // The lane kernel: LDS bytes per wave (= per workgroup), occupancy and launch.
 size_t lane_lds_bytes(const DevProg &P, bool fp64) {
-    return lane_vec_offset(P.n_instr, P.n_meas) + ((size_t)64 << P.k_max) * (fp64 ? 16 : 8);
+    return lane_vec_offset(P.n_instr, P.n_meas) + (size_t)64 * P.vcap * (fp64 ? 16 : 8);
 }
 
 int lane_max_blocks_per_cu(bool fp64, size_t lds) {

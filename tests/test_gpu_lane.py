@@ -29,12 +29,10 @@ def _lane(prog, shots, seed, **kw):
 def _fits(prog, prec):
     """The lane kernel's per-wave state (exogenous words, outcome bits, 64 vector buffers) within 64 KB."""
     i = prog.info()
-    k = i["k_max"]
-    if i["product_selected"]:
-        k = int(np.ceil(np.log2(max(1, i["product_vector_amplitudes"]))))
+    amps = i["product_vector_amplitudes"] if i["product_selected"] else 1 << i["k_max"]
     n_instr = sum(i["n_instr"].values())
     head = (8 * n_instr + 256 * ((i["n_measurements"] + 31) // 32) + 15) // 16 * 16
-    return head + 64 * (1 << k) * (16 if prec == "fp64" else 8) <= 65536
+    return head + 64 * amps * (16 if prec == "fp64" else 8) <= 65536
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
