@@ -1526,11 +1526,15 @@ struct BatchPlan {
     uint32_t *d_counter = nullptr;
     BatchArgs args;
     uint32_t grid = 0, lds = 0;
-    // members on the lane kernel: their own queue (counter d_counter + 16), one-wave workgroups
-    ActiveArgs *d_lcalls = nullptr;
-    BatchItem *d_litems = nullptr;
-    BatchArgs largs;
-    uint32_t lgrid = 0, llds = 0;
+    // members on the lane kernel: queues of one-wave workgroups by LDS class (queue q counts at
+    // d_counter + 16 (q + 1))
+    struct LaneQueue {
+        ActiveArgs *d_calls = nullptr;
+        BatchItem *d_items = nullptr;
+        BatchArgs args;
+        uint32_t grid = 0, lds = 0;
+    };
+    std::vector<LaneQueue> lq;
     std::vector<size_t> others;  // programs sampled by their own launches
     // aggregate-count plans: the count tables' contents and the counters, compared with sig
     bool cm = false;
@@ -1552,15 +1556,17 @@ struct BatchPlan {
         (void)hipFree(d_calls);
         (void)hipFree(d_items);
         (void)hipFree(d_counter);
-        (void)hipFree(d_lcalls);
-        (void)hipFree(d_litems);
+        for (LaneQueue &q : lq) {
+            (void)hipFree(q.d_calls);
+            (void)hipFree(q.d_items);
+        }
+        lq.clear();
         exec = nullptr;
         graph = nullptr;
         d_calls = nullptr;
         d_items = nullptr;
         d_counter = nullptr;
-        d_lcalls = nullptr;
-        d_litems = nullptr;
+
     }
 };
 
@@ -1599,10 +1605,17 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
     if (!cnt) B.outs.assign(outs, outs + n);
     B.precision = precision;
     (void)hipGetDevice(&B.device);
-    std::vector<ActiveArgs> calls, lcalls;
-    std::vector<double> cost, lcost;
-    std::vector<uint64_t> words_of, lwords_of;
-    size_t lds = 0, llds = 0;
+    std::vector<ActiveArgs> calls;
+    std::vector<double> cost;
+    std::vector<uint64_t> words_of;
+    size_t lds = 0;
+    // lane members by LDS class: the queue's LDS is its largest member's, which sets its occupancy
+    constexpr int kClasses = 4;
+    static const size_t kLaneClass[kClasses] = {8 * 1024, 16 * 1024, 24 * 1024, kLaneBatchLds};
+    std::vector<ActiveArgs> lcalls[kClasses];
+    std::vector<double> lcost[kClasses];
+    std::vector<uint64_t> lwords_of[kClasses];
+    size_t llds[kClasses] = {0, 0, 0, 0};
     for (size_t i = 0; i < n; ++i) {
         symft_program *p = const_cast<symft_program *>(progs[i]);
         if (!p || (!cnt && shots[i] && !outs[i])) return set_err(SYMFT_EINVAL, "NULL program or output in batch");
@@ -1632,10 +1645,12 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
             A.tps = 1;
             A.lds_vec = 1;
             A.lds_bytes = (uint32_t)lane_lds_bytes(D, fp64);
-            llds = std::max<size_t>(llds, A.lds_bytes);
-            lcalls.push_back(A);
-            lwords_of.push_back(A.n_words);
-            lcost.push_back(wcost);
+            int q = 0;
+            while (A.lds_bytes > kLaneClass[q]) ++q;
+            llds[q] = std::max<size_t>(llds[q], A.lds_bytes);
+            lcalls[q].push_back(A);
+            lwords_of[q].push_back(A.n_words);
+            lcost[q].push_back(wcost);
             continue;
         }
         ActiveConfig c;
@@ -1667,39 +1682,43 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         cost.push_back(wcost);
     }
     if (hipMalloc(&B.d_counter, 256) != hipSuccess) return set_err(SYMFT_ENOMEM, "batch metadata allocation failed");
-    if (!lcalls.empty()) {
+    for (int q = 0; q < kClasses; ++q) {
+        if (lcalls[q].empty()) continue;
         // items of a few words for one-wave workgroups, by decreasing cost
-        const int per_cu = std::max(1, lane_batch_max_blocks_per_cu(fp64, llds));
-        B.lgrid = (uint32_t)(per_cu * num_cus());
+        BatchPlan::LaneQueue Q;
+        const int per_cu = std::max(1, lane_batch_max_blocks_per_cu(fp64, llds[q]));
+        Q.grid = (uint32_t)(per_cu * num_cus());
         uint64_t total_words = 0;
-        for (uint64_t w : lwords_of) total_words += w;
-        const uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(16, total_words / ((uint64_t)B.lgrid * 4) + 1));
+        for (uint64_t w : lwords_of[q]) total_words += w;
+        const uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(16, total_words / ((uint64_t)Q.grid * 4) + 1));
         std::vector<std::pair<double, BatchItem>> tmp;
-        for (size_t ci = 0; ci < lcalls.size(); ++ci)
-            for (uint64_t w0 = 0; w0 < lwords_of[ci]; w0 += chunk) {
+        for (size_t ci = 0; ci < lcalls[q].size(); ++ci)
+            for (uint64_t w0 = 0; w0 < lwords_of[q][ci]; w0 += chunk) {
                 BatchItem it;
                 it.call = (uint32_t)ci;
                 it.pad = 0;
                 it.w0 = w0;
-                it.w1 = std::min(lwords_of[ci], w0 + chunk);
-                tmp.push_back({lcost[ci] * (double)(it.w1 - it.w0), it});
+                it.w1 = std::min(lwords_of[q][ci], w0 + chunk);
+                tmp.push_back({lcost[q][ci] * (double)(it.w1 - it.w0), it});
             }
         std::stable_sort(tmp.begin(), tmp.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
         std::vector<BatchItem> litems;
         for (auto &x : tmp) litems.push_back(x.second);
-        B.lgrid = (uint32_t)std::min<uint64_t>(B.lgrid, litems.size());
-        B.llds = (uint32_t)llds;
-        if (hipMalloc(&B.d_lcalls, sizeof(ActiveArgs) * lcalls.size()) != hipSuccess ||
-            hipMalloc(&B.d_litems, sizeof(BatchItem) * litems.size()) != hipSuccess)
+        Q.grid = (uint32_t)std::min<uint64_t>(Q.grid, litems.size());
+        Q.lds = (uint32_t)llds[q];
+        B.lq.push_back(Q);
+        BatchPlan::LaneQueue &R = B.lq.back();
+        if (hipMalloc(&R.d_calls, sizeof(ActiveArgs) * lcalls[q].size()) != hipSuccess ||
+            hipMalloc(&R.d_items, sizeof(BatchItem) * litems.size()) != hipSuccess)
             return set_err(SYMFT_ENOMEM, "batch metadata allocation failed");
-        if (hipMemcpy(B.d_lcalls, lcalls.data(), sizeof(ActiveArgs) * lcalls.size(), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(B.d_litems, litems.data(), sizeof(BatchItem) * litems.size(), hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpy(R.d_calls, lcalls[q].data(), sizeof(ActiveArgs) * lcalls[q].size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(R.d_items, litems.data(), sizeof(BatchItem) * litems.size(), hipMemcpyHostToDevice) != hipSuccess)
             return set_err(SYMFT_EHIP, "batch metadata upload failed");
-        B.largs.calls = B.d_lcalls;
-        B.largs.items = B.d_litems;
-        B.largs.counter = B.d_counter + 16;
-        B.largs.n_items = (uint32_t)litems.size();
-        B.largs.pad = 0;
+        R.args.calls = R.d_calls;
+        R.args.items = R.d_items;
+        R.args.counter = B.d_counter + 16 * B.lq.size();
+        R.args.n_items = (uint32_t)litems.size();
+        R.args.pad = 0;
     }
     std::vector<BatchItem> items;
     if (!calls.empty()) {
@@ -1740,16 +1759,17 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
 
 // The plan's persistent kernel (after its counter reset), launched directly or
 // through its captured graph.
-// The plan's launches: the lane members' queue, then the shot-group members'.
+// The plan's launches: the lane members' queues (by LDS class), then the shot-group members'.
 static hipError_t launch_plan(BatchPlan &B, bool fp64, hipStream_t st) {
     hipError_t e = hipSuccess;
-    if (B.largs.n_items) e = launch_lane_batch(B.largs, fp64, B.lgrid, B.llds, st);
+    for (const BatchPlan::LaneQueue &q : B.lq)
+        if (e == hipSuccess && q.args.n_items) e = launch_lane_batch(q.args, fp64, q.grid, q.lds, st);
     if (e == hipSuccess && B.args.n_items) e = launch_batch(B.args, fp64, B.cm, B.grid, B.lds, st);
     return e;
 }
 
 static symft_status run_plan(BatchPlan &B, bool fp64, uint32_t graph, hipStream_t st) {
-    if (!B.args.n_items && !B.largs.n_items) return SYMFT_OK;
+    if (!B.args.n_items && B.lq.empty()) return SYMFT_OK;
     if (graph) {
         if (!B.exec) {
             // capture [counter resets, persistent kernels] once on a private stream
