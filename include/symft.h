@@ -300,7 +300,10 @@ typedef struct {
                                       choice below); otherwise 4 .. 256, a power of two, or 1024 at peak
                                       width >= 13 (peak widths 13 and 14 run 64 .. 256 with vectors in HBM,
                                       values below 64 as 64; width 15 and above always uses 1024).  From 64
-                                      on a workgroup holds one shot group.  Flags do not depend on it */
+                                      on a workgroup holds one shot group.  1 = the lane kernel (one lane per
+                                      shot; a wave leaves the stream once all its shots are discarded;
+                                      ECAPACITY when its state passes 64 KB), also a candidate of
+                                      symft_autotune_counts.  Flags do not depend on it */
     uint32_t mode;                 /* programs with a dense active vector: 0 = automatic (the path
                                       symft_autotune_counts timed faster, else 1); 1 = the count kernel, which
                                       stops a rejected shot's dense work; 2 = detector and observable rows

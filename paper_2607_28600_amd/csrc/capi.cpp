@@ -21,15 +21,15 @@ hipError_t launch_active(const ActiveArgs &A, bool fp64, uint32_t bs, uint32_t g
 size_t active_lds_bytes(const DevProg &P, uint32_t bs, uint32_t tps, bool lds_vec, bool fp64);
 int active_max_blocks_per_cu(bool fp64, uint32_t bs, bool lds_vec, size_t lds, bool cm);
 size_t lane_lds_bytes(const DevProg &P, bool fp64);
-int lane_max_blocks_per_cu(bool fp64, size_t lds);
+int lane_max_blocks_per_cu(bool fp64, size_t lds, bool cm);
 hipError_t launch_lane(const ActiveArgs &A, bool fp64, uint32_t grid, hipStream_t st);
-int lane_batch_max_blocks_per_cu(bool fp64, size_t lds);
+int lane_batch_max_blocks_per_cu(bool fp64, size_t lds, bool cm);
 struct FrameArgs;
 struct CountArgs;
 hipError_t launch_frame(const FrameArgs &A, uint32_t grid, hipStream_t st, uint32_t tw);
 struct BatchArgs;
 hipError_t launch_batch(const BatchArgs &B, bool fp64, bool cm, uint32_t grid, uint32_t lds, hipStream_t st);
-hipError_t launch_lane_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t lds, hipStream_t st);
+hipError_t launch_lane_batch(const BatchArgs &B, bool fp64, bool cm, uint32_t grid, uint32_t lds, hipStream_t st);
 int batch_max_blocks_per_cu(bool fp64, bool cm, size_t lds);
 size_t frame_lds_bytes(const DevProg &P, uint32_t tw);
 hipError_t launch_flags_from_rows(const uint64_t *rows, uint64_t n_words, uint64_t shots, uint64_t n_rec,
@@ -629,7 +629,7 @@ ActiveConfig choose_active(const DevProg &P, bool fp64, uint32_t force_tps = 0, 
     if (batch_budget && k < 13) c.tps = batch_tps(k, fp64, batch_budget);
     if (force_tps & kNoLane) c.tps &= ~kLaneVec;
     else if (force_tps) c.tps = force_tps;
-    if ((c.tps & kLaneVec) && !batch_budget && !count_mode && lane_candidate(P, fp64)) {
+    if ((c.tps & kLaneVec) && !batch_budget && lane_candidate(P, fp64)) {
         c.lane = true;
         c.bs = 64;
         c.tps = 1;
@@ -679,7 +679,8 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
         A.probe_n = probe_n;
         A.lds_vec = 1;
         A.lds_bytes = (uint32_t)c.lds;
-        const int per_cu = std::max(1, lane_max_blocks_per_cu(fp64, c.lds));
+        if (cnt) A.cnt = *cnt;
+        const int per_cu = std::max(1, lane_max_blocks_per_cu(fp64, c.lds, cnt != nullptr));
         const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_words, (uint64_t)per_cu * num_cus()));
         const hipError_t e = launch_lane(A, fp64, grid, st);
         if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("lane kernel launch failed: ") + hipGetErrorString(e));
@@ -1227,8 +1228,9 @@ symft_status symft_sample_counts(const symft_program *pc, const symft_count_opts
     if (o.n_post && !o.post) return set_err(SYMFT_EINVAL, "post is NULL");
     if (o.threads_per_shot && (o.threads_per_shot & (o.threads_per_shot - 1)))
         return set_err(SYMFT_EINVAL, "threads_per_shot must be a power of two");
-    if (o.threads_per_shot && (o.threads_per_shot < 4 || (o.threads_per_shot > 256 && o.threads_per_shot != 1024)))
-        return set_err(SYMFT_EINVAL, "threads_per_shot must be 4 .. 256 (or 1024 at peak width >= 13)");
+    if (o.threads_per_shot && o.threads_per_shot != 1 &&
+        (o.threads_per_shot < 4 || (o.threads_per_shot > 256 && o.threads_per_shot != 1024)))
+        return set_err(SYMFT_EINVAL, "threads_per_shot must be 1 (the lane kernel), 4 .. 256, or 1024 at peak width >= 13");
     if (o.mode > 2) return set_err(SYMFT_EINVAL, "mode must be 0, 1 or 2");
     CountArgs C;
     std::memset(&C, 0, sizeof(C));
@@ -1248,6 +1250,11 @@ symft_status symft_sample_counts(const symft_program *pc, const symft_count_opts
     if (D.k_max < 13 && o.threads_per_shot > 256)
         return set_err(SYMFT_EINVAL, "threads_per_shot above 256 needs peak width >= 13");
     uint32_t tps = o.threads_per_shot;
+    if (tps == 1) {
+        // the lane kernel
+        if (!lane_candidate(D, fp64)) return set_err(SYMFT_ECAPACITY, "the lane kernel's state does not fit 64 KB of LDS");
+        tps = 1u | kLaneVec;
+    }
     uint32_t tuned = 0;
     {
         std::lock_guard<std::mutex> lk(p->mu);
@@ -1299,12 +1306,16 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
     (void)hipEventCreate(&e1);
     float best = 1e30f;
     uint32_t best_tps = 0;
-    for (uint32_t cand : {4u, 8u, 16u, 32u, 64u, 128u, 256u, 1024u, 64u | kHbmVec, 128u | kHbmVec, 256u | kHbmVec}) {
-        const uint32_t tps = cand & ~kHbmVec;
+    for (uint32_t cand : {4u, 8u, 16u, 32u, 64u, 128u, 256u, 1024u, 64u | kHbmVec, 128u | kHbmVec, 256u | kHbmVec,
+                          1u | kLaneVec}) {
+        const uint32_t tps = cand & ~(kHbmVec | kLaneVec);
         if ((cand & kHbmVec) && !hbm_candidate(D.k_max)) continue;
-        if (wide ? tps < 64 : tps > 256) continue;  // widths 13 and 14: 64 .. 256 threads, or 1024
-        if (((uint32_t)1 << D.k_max) < tps / 4 && tps > 4) continue;  // most lanes would idle
-        if (!wide && !(cand & kHbmVec) && active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
+        if ((cand & kLaneVec) && !lane_candidate(D, fp64)) continue;
+        if (!(cand & kLaneVec)) {
+            if (wide ? tps < 64 : tps > 256) continue;  // widths 13 and 14: 64 .. 256 threads, or 1024
+            if (((uint32_t)1 << D.k_max) < tps / 4 && tps > 4) continue;  // most lanes would idle
+            if (!wide && !(cand & kHbmVec) && active_lds_bytes(D, 256, tps, true, fp64) > kLdsLimit) continue;
+        }
         float ms = 0;
         for (int rep = 0; rep < 2 && rc == SYMFT_OK; ++rep) {
             (void)hipEventRecord(e0, st);
@@ -1343,7 +1354,7 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
         std::lock_guard<std::mutex> lk(p->mu);
         p->count_tune[{key, fp64}] = best_tps;
     }
-    if (tps_out) *tps_out = best_tps & ~(kHbmVec | kViaRecords);
+    if (tps_out) *tps_out = best_tps & ~(kHbmVec | kLaneVec | kViaRecords);
     return SYMFT_OK;
 }
 
@@ -1630,7 +1641,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         // estimated cost per word: the representation's flops and a per-instruction share
         const double wcost =
             (info.product_selected ? info.product_flops_per_shot : info.dense_flops_per_shot) + 200.0 * (double)n_instr + 64.0;
-        if (mine && !cnt && lane_candidate(D, fp64) && lane_lds_bytes(D, fp64) <= kLaneBatchLds) {
+        if (mine && lane_candidate(D, fp64) && lane_lds_bytes(D, fp64) <= kLaneBatchLds) {
             // the lane kernel, in a queue of its own
             ActiveArgs A;
             std::memset(&A, 0, sizeof(A));
@@ -1639,9 +1650,10 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
             A.word_begin = word0 ? word0[i] : 0;
             A.n_words = (shots[i] + 63) / 64;
             A.shots = shots[i];
-            A.out = outs[i];
+            A.out = cnt ? nullptr : outs[i];
             A.row_stride = A.n_words;
-            A.sections = 7u;
+            A.sections = cnt ? 0u : 7u;
+            if (cnt) A.cnt = cnt[i];
             A.tps = 1;
             A.lds_vec = 1;
             A.lds_bytes = (uint32_t)lane_lds_bytes(D, fp64);
@@ -1686,7 +1698,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         if (lcalls[q].empty()) continue;
         // items of a few words for one-wave workgroups, by decreasing cost
         BatchPlan::LaneQueue Q;
-        const int per_cu = std::max(1, lane_batch_max_blocks_per_cu(fp64, llds[q]));
+        const int per_cu = std::max(1, lane_batch_max_blocks_per_cu(fp64, llds[q], B.cm));
         Q.grid = (uint32_t)(per_cu * num_cus());
         uint64_t total_words = 0;
         for (uint64_t w : lwords_of[q]) total_words += w;
@@ -1763,7 +1775,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
 static hipError_t launch_plan(BatchPlan &B, bool fp64, hipStream_t st) {
     hipError_t e = hipSuccess;
     for (const BatchPlan::LaneQueue &q : B.lq)
-        if (e == hipSuccess && q.args.n_items) e = launch_lane_batch(q.args, fp64, q.grid, q.lds, st);
+        if (e == hipSuccess && q.args.n_items) e = launch_lane_batch(q.args, fp64, B.cm, q.grid, q.lds, st);
     if (e == hipSuccess && B.args.n_items) e = launch_batch(B.args, fp64, B.cm, B.grid, B.lds, st);
     return e;
 }

@@ -889,7 +889,12 @@ __host__ __device__ inline size_t lane_vec_offset(uint32_t n_instr, uint32_t n_m
     return ((size_t)8 * n_instr + (size_t)256 * mw + 15) & ~(size_t)15;
 }
 
-template <typename T>
+// CM: count mode (paper Sec. 6, detector postselection): each lane's shot is
+// discarded once a postselected detector whose last record an instruction
+// makes is 1; the wave leaves the instruction stream when every live shot of
+// its word is discarded (a live-shot mask over the 64 lanes).  The word's two
+// flag words and the totals are written instead of rows.
+template <typename T, bool CM>
 __device__ __forceinline__ void run_lane_words(const ActiveArgs &A, uint64_t wi_begin, uint64_t wi_end, uint64_t wi_step,
                                                unsigned char *smem) {
     using V = typename C2<T>::type;
@@ -901,9 +906,12 @@ __device__ __forceinline__ void run_lane_words(const ActiveArgs &A, uint64_t wi_
     V *vec = (V *)(smem + lane_vec_offset(P.n_instr, P.n_meas));  // [vcap][64]
     const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
     const T rs2 = (T)0.70710678118654752440;
+    unsigned long long n_disc = 0, n_logic = 0;  // count mode: this wave's totals
     for (uint64_t wi = wi_begin; wi < wi_end; wi += wi_step) {
         const uint64_t w = A.word_begin + wi;
         const uint64_t shot = w * 64 + lane;
+        const bool valid = shot - A.word_begin * 64 < A.shots;
+        bool dead = false;
         for (uint32_t i = lane; i < P.n_instr; i += 64) exo[i] = 0;
         for (uint32_t j = 0; j < mw; ++j) mb[j * 64u + lane] = 0;
         {
@@ -1060,6 +1068,25 @@ __device__ __forceinline__ void run_lane_words(const ActiveArgs &A, uint64_t wi_
             }
             default: break;
             }
+            if (CM) {
+                // postselected detectors whose last record this instruction made (scalar offsets)
+                const __attribute__((address_space(4))) uint32_t *co =
+                    (const __attribute__((address_space(4))) uint32_t *)A.cnt.chk_off;
+                const uint32_t c0 = co[ii], c1 = co[ii + 1];
+                if (c0 < c1) {
+                    uint32_t fired = 0;
+                    for (uint32_t q = c0; q < c1; ++q) {
+                        uint32_t x = 0;
+                        for (uint32_t e = A.cnt.chk_mo[q]; e < A.cnt.chk_mo[q + 1]; ++e) {
+                            const uint32_t t = A.cnt.chk_meas[e];
+                            x ^= (mb[(t >> 5) * 64u + lane] >> (t & 31)) & 1u;
+                        }
+                        fired |= x;
+                    }
+                    dead = dead || fired != 0;
+                    if (__ballot(valid && !dead) == 0) break;  // every shot of the word discarded
+                }
+            }
         }
         if (A.amp_out && probe) {
             double *dst = A.amp_out + (shot - A.probe_shot0) * (2ull << A.amp_k);
@@ -1069,9 +1096,31 @@ __device__ __forceinline__ void run_lane_words(const ActiveArgs &A, uint64_t wi_
                 dst[2 * x + 1] = (double)v.y;
             }
         }
-        // rows: one ballot per row over the word's shots (bits past the call's shots are 0)
-        const bool valid = shot - A.word_begin * 64 < A.shots;
         const uint64_t col = wi;
+        if (CM) {
+            // the word's flags: discarded; kept with an observable off its expected value
+            uint32_t le = 0;
+            for (uint32_t b = 0; b < P.n_obs; ++b) {
+                uint32_t x = (A.cnt.obs_exp[b >> 5] >> (b & 31)) & 1u;
+                for (uint32_t q = P.obs_off[b]; q < P.obs_off[b + 1]; ++q) {
+                    const uint32_t t = P.rec_meas[P.obs_rows[q]];
+                    x ^= (mb[(t >> 5) * 64u + lane] >> (t & 31)) & 1u;
+                }
+                le |= x;
+            }
+            const uint64_t d = __ballot(valid && dead), l = __ballot(valid && !dead && le != 0);
+            if (lane == 0) {
+                if (A.cnt.flags) {
+                    A.cnt.flags[col] = d;
+                    A.cnt.flags[A.n_words + col] = l;
+                }
+                n_disc += (unsigned long long)__popcll(d);
+                n_logic += (unsigned long long)__popcll(l);
+            }
+            lane_sync();
+            continue;
+        }
+        // rows: one ballot per row over the word's shots (bits past the call's shots are 0)
         auto rec_bit = [&](uint32_t row) -> uint32_t {
             const uint32_t t = P.rec_meas[row];
             return (mb[(t >> 5) * 64u + lane] >> (t & 31)) & 1u;
@@ -1097,18 +1146,22 @@ __device__ __forceinline__ void run_lane_words(const ActiveArgs &A, uint64_t wi_
             }
         lane_sync();
     }
+    if (CM && A.cnt.counts && lane == 0) {
+        if (n_disc) atomicAdd(&A.cnt.counts[0], n_disc);
+        if (n_logic) atomicAdd(&A.cnt.counts[1], n_logic);
+    }
 }
 
-template <typename T>
+template <typename T, bool CM>
 __global__ void __launch_bounds__(64) lane_kernel(ActiveArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
-    run_lane_words<T>(A, blockIdx.x, A.n_words, gridDim.x, smem);
+    run_lane_words<T, CM>(A, blockIdx.x, A.n_words, gridDim.x, smem);
 }
 
 // The lane kernel behind a persistent queue of (program, word range) items:
 // each one-wave workgroup takes the next item with a global atomic until the
 // list is exhausted.
-template <typename T>
+template <typename T, bool CM>
 __global__ void __launch_bounds__(64) lane_batch_kernel(BatchArgs B) {
     extern __shared__ __align__(16) unsigned char smem[];
     while (true) {
@@ -1117,7 +1170,7 @@ __global__ void __launch_bounds__(64) lane_batch_kernel(BatchArgs B) {
         idx = (uint32_t)__shfl((int)idx, 0, 64);
         if (idx >= B.n_items) break;
         const BatchItem it = B.items[idx];
-        run_lane_words<T>(B.calls[it.call], it.w0, it.w1, 1, smem);
+        run_lane_words<T, CM>(B.calls[it.call], it.w0, it.w1, 1, smem);
     }
 }
 
@@ -1283,37 +1336,54 @@ size_t lane_lds_bytes(const DevProg &P, bool fp64) {
     return lane_vec_offset(P.n_instr, P.n_meas) + (size_t)64 * P.vcap * (fp64 ? 16 : 8);
 }
 
-int lane_max_blocks_per_cu(bool fp64, size_t lds) {
+static const void *lane_kfn(bool fp64, bool cm) {
+    if (fp64) return cm ? (const void *)lane_kernel<double, true> : (const void *)lane_kernel<double, false>;
+    return cm ? (const void *)lane_kernel<float, true> : (const void *)lane_kernel<float, false>;
+}
+
+static const void *lane_batch_kfn(bool fp64, bool cm) {
+    if (fp64) return cm ? (const void *)lane_batch_kernel<double, true> : (const void *)lane_batch_kernel<double, false>;
+    return cm ? (const void *)lane_batch_kernel<float, true> : (const void *)lane_batch_kernel<float, false>;
+}
+
+int lane_max_blocks_per_cu(bool fp64, size_t lds, bool cm) {
     int nb = 0;
-    const void *k = fp64 ? (const void *)lane_kernel<double> : (const void *)lane_kernel<float>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, lds) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kfn(fp64, cm), 64, lds) != hipSuccess) return 1;
     return nb;
 }
 
-int lane_batch_max_blocks_per_cu(bool fp64, size_t lds) {
+int lane_batch_max_blocks_per_cu(bool fp64, size_t lds, bool cm) {
     int nb = 0;
-    const void *k = fp64 ? (const void *)lane_batch_kernel<double> : (const void *)lane_batch_kernel<float>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, lds) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_batch_kfn(fp64, cm), 64, lds) != hipSuccess) return 1;
     return nb;
 }
 
-hipError_t launch_lane_batch(const BatchArgs &B, bool fp64, uint32_t grid, uint32_t lds, hipStream_t st) {
-    const void *k = fp64 ? (const void *)lane_batch_kernel<double> : (const void *)lane_batch_kernel<float>;
-    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+template <typename T, bool CM>
+static hipError_t launch_lane_batch_t(const BatchArgs &B, uint32_t grid, uint32_t lds, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void *)lane_batch_kernel<T, CM>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, B.counter);
-    if (fp64) hipLaunchKernelGGL(lane_batch_kernel<double>, dim3(grid), dim3(64), lds, st, B);
-    else hipLaunchKernelGGL(lane_batch_kernel<float>, dim3(grid), dim3(64), lds, st, B);
+    hipLaunchKernelGGL((lane_batch_kernel<T, CM>), dim3(grid), dim3(64), lds, st, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_lane_batch(const BatchArgs &B, bool fp64, bool cm, uint32_t grid, uint32_t lds, hipStream_t st) {
+    if (cm) return fp64 ? launch_lane_batch_t<double, true>(B, grid, lds, st) : launch_lane_batch_t<float, true>(B, grid, lds, st);
+    return fp64 ? launch_lane_batch_t<double, false>(B, grid, lds, st) : launch_lane_batch_t<float, false>(B, grid, lds, st);
+}
+
+template <typename T, bool CM>
+static hipError_t launch_lane_t(const ActiveArgs &A, uint32_t grid, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void *)lane_kernel<T, CM>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((lane_kernel<T, CM>), dim3(grid), dim3(64), A.lds_bytes, st, A);
     return hipGetLastError();
 }
 
 hipError_t launch_lane(const ActiveArgs &A, bool fp64, uint32_t grid, hipStream_t st) {
-    const void *k = fp64 ? (const void *)lane_kernel<double> : (const void *)lane_kernel<float>;
-    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds_bytes);
-    if (e != hipSuccess) return e;
-    if (fp64) hipLaunchKernelGGL(lane_kernel<double>, dim3(grid), dim3(64), A.lds_bytes, st, A);
-    else hipLaunchKernelGGL(lane_kernel<float>, dim3(grid), dim3(64), A.lds_bytes, st, A);
-    return hipGetLastError();
+    const bool cm = A.cnt.on != 0;
+    if (cm) return fp64 ? launch_lane_t<double, true>(A, grid, st) : launch_lane_t<float, true>(A, grid, st);
+    return fp64 ? launch_lane_t<double, false>(A, grid, st) : launch_lane_t<float, false>(A, grid, st);
 }
 
 }  // namespace symft

@@ -166,7 +166,7 @@ def test_counts_do_not_depend_on_threads_per_shot_and_autotune():
         assert torch.equal(f, ref_f), tps
         assert torch.equal(n, ref_c), tps
     tps = p.autotune_counts(post, precision="fp32")
-    assert tps in (4, 8, 16, 32, 64, 128, 256)
+    assert tps in (1, 4, 8, 16, 32, 64, 128, 256)  # 1: the lane kernel
     f, n = p.sample_counts(64 * 5 + 9, 0x5EED0C06, post=post, precision="fp32")
     assert torch.equal(f, ref_f) and torch.equal(n, ref_c)
 

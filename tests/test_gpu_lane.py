@@ -184,3 +184,60 @@ def test_probes_after_the_autotuner_picks_it():
         assert frame_relation(amp[shot], fs["alpha"], 1e-9) is not None, shot
         checked += 1
     assert checked >= n - 2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_count_mode(prec):
+    """Count mode on the lane kernel (threads_per_shot = 1): flags equal those derived from the same kernel's
+    full records (a discarded shot's early exit changes no kept shot), counters their popcounts, on a coherent
+    distance-3 code with every detector postselected (most shots discarded) and on C3 with a random subset of
+    observables' expected values; offsets and a ragged last word."""
+    from oracle.counts import count_flags
+    from workloads.surface import rotated_memory_z
+
+    def popcount(a):
+        return int(sum(bin(int(x)).count("1") for x in np.asarray(a, dtype=np.uint64).reshape(-1)))
+
+    cases = [(rotated_memory_z(3, 3, 1e-3, coherent=0.3), 77), (rotated_memory_z(3, 2, 2e-2, coherent=0.2), 78)]
+    for c, seed in cases:
+        p = S.Program(c)
+        assert _fits(p, prec)
+        n, off = 64 * 11 + 37, 64 * 5
+        post = list(range(c.num_detectors))
+        exp = [1] * c.num_observables
+        f, cnt = p.sample_counts(n, seed, post=post, obs_expected=exp, shot_offset=off, precision=prec,
+                                 threads_per_shot=1)
+        flags = S.bits_to_numpy(f)
+        rec = _lane(p, n, seed, shot_offset=off, precision=prec)
+        own, own_c = count_flags(rec, c.num_records, c.num_detectors, c.num_observables, n, post, exp)
+        assert np.array_equal(flags, own)
+        assert list(cnt.cpu().numpy()) == [popcount(flags[0]), popcount(flags[1])] == list(own_c)
+        assert popcount(flags[0]) > n // 4  # many discarded: early exits happen
+        oc = OracleCircuit(c)
+        compare_records(rec, oc.sample(seed, n, shot_begin=off), c, oc, seed, off, TOL[prec])
+
+
+def test_count_batch_lane_queue():
+    """Count mode inside the batched queue: lane-eligible members run the lane queue in count mode; flags equal
+    the ones from the same batch's records."""
+    from oracle.counts import count_flags
+    from workloads.surface import rotated_memory_z
+    circs = [rotated_memory_z(3, 3, 1e-3, coherent=0.3), configs.c3(shots=64 * 4).circuit,
+             configs.c4()[4].circuit, configs.c4()[17].circuit]
+    progs = [S.Program(c) for c in circs]
+    shots = [64 * 3 + 11, 64 * 4, 64 * 2 + 1, 64 * 5]
+    seeds = [101, 102, 103, 104]
+    posts = [list(range(c.num_detectors)) for c in circs]
+    flags = [torch.full((2, (s + 63) // 64), -1, dtype=torch.int64, device="cuda") for s in shots]
+    counts = torch.zeros(2 * len(progs), dtype=torch.int64, device="cuda")
+    S.sample_counts_batch(progs, shots, seeds, posts, flags, counts, precision="fp64")
+    outs = [torch.zeros((p.n_rows, (s + 63) // 64), dtype=torch.int64, device="cuda") for p, s in zip(progs, shots)]
+    S.sample_batch(progs, shots, seeds, outs, precision="fp64", graph=False)
+    torch.cuda.synchronize()
+    cnt = counts.cpu().numpy()
+    for i, c in enumerate(circs):
+        got = S.bits_to_numpy(flags[i])
+        own, own_c = count_flags(S.bits_to_numpy(outs[i]), c.num_records, c.num_detectors, c.num_observables,
+                                 shots[i], posts[i], None)
+        assert np.array_equal(got, own), i
+        assert list(cnt[2 * i:2 * i + 2]) == list(own_c), i
