@@ -827,36 +827,61 @@ __device__ __forceinline__ void word_noise_wave(const DevProg &P, uint64_t seed,
             }
             const uint64_t total = __shfl(x, 63, 64);
             const uint64_t ex = x - mine;
+            // this lane's events (at most four): position, event index
             uint64_t p = pos + (ex & ((1ull << 40) - 1));
             uint64_t e = ev0 + (ex >> 40);
+            uint64_t at[4], ee[4];
+            bool has[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                if (G[i] < 4096) {
-                    const uint64_t at = p + (uint64_t)G[i];
-                    if (at < end) {
-                        const uint32_t rank = (uint32_t)(at >> 6), sl = (uint32_t)(at & 63);
-                        const DevChan ch = P.chan[P.cls_chan[coff + rank]];
-                        const uint4 br = philox4x32_10(make_uint4((uint32_t)(e >> 2), wlo, c, (2u << 24) | whi), k0, k1);
-                        const uint32_t bv = (e & 3) == 0 ? br.x : (e & 3) == 1 ? br.y : (e & 3) == 2 ? br.z : br.w;
-                        uint32_t j;
-                        if (ch.uniform) {
-                            j = (uint32_t)(((uint64_t)bv * ch.J) >> 32);
-                        } else {
-                            j = ch.J - 1;
-                            for (uint32_t t = 0; t < ch.J; ++t)
-                                if ((uint64_t)bv < P.thr[ch.thr_off + t]) { j = t; break; }
-                        }
-                        uint32_t mask = P.bmask[ch.bm_off + j];
-                        while (mask) {
-                            const uint32_t sym = ch.sym0 + (uint32_t)__ffs(mask) - 1u;
-                            mask &= mask - 1u;
-                            for (uint32_t q = P.sym_off[sym]; q < P.sym_off[sym + 1]; ++q)
-                                atomicXor(&exo[P.sym_cons[q]], 1ull << sl);
-                        }
-                    }
-                    ++e;
-                }
+                at[i] = p + (uint64_t)G[i];
+                ee[i] = e;
+                has[i] = G[i] < 4096 && at[i] < end;
+                if (G[i] < 4096) ++e;
                 p += (G[i] == 4096) ? 4096u : (uint32_t)G[i] + 1u;
+            }
+            // The events' loads are issued together (channel descriptors, then branch masks), so a lane
+            // with several events waits for one chain of dependent loads, not one per event.
+            uint32_t chid[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) chid[i] = has[i] ? P.cls_chan[coff + (uint32_t)(at[i] >> 6)] : 0u;
+            DevChan ch[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (has[i]) ch[i] = P.chan[chid[i]];
+            uint32_t mask[4];
+            uint4 br = make_uint4(0, 0, 0, 0);
+            uint64_t brb = ~0ull;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                mask[i] = 0;
+                if (!has[i]) continue;
+                if ((ee[i] >> 2) != brb) {  // four consecutive events share a branch block
+                    brb = ee[i] >> 2;
+                    br = philox4x32_10(make_uint4((uint32_t)brb, wlo, c, (2u << 24) | whi), k0, k1);
+                }
+                const uint32_t q = (uint32_t)(ee[i] & 3);
+                const uint32_t bv = q == 0 ? br.x : q == 1 ? br.y : q == 2 ? br.z : br.w;
+                uint32_t j;
+                if (ch[i].uniform) {
+                    j = (uint32_t)(((uint64_t)bv * ch[i].J) >> 32);
+                } else {
+                    j = ch[i].J - 1;
+                    for (uint32_t t = 0; t < ch[i].J; ++t)
+                        if ((uint64_t)bv < P.thr[ch[i].thr_off + t]) { j = t; break; }
+                }
+                mask[i] = P.bmask[ch[i].bm_off + j];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t sl = (uint32_t)(at[i] & 63);
+                uint32_t m = mask[i];
+                while (m) {
+                    const uint32_t sym = ch[i].sym0 + (uint32_t)__ffs(m) - 1u;
+                    m &= m - 1u;
+                    for (uint32_t q = P.sym_off[sym]; q < P.sym_off[sym + 1]; ++q)
+                        atomicXor(&exo[P.sym_cons[q]], 1ull << sl);
+                }
             }
             pos += total & ((1ull << 40) - 1);
             ev0 += total >> 40;
@@ -1167,7 +1192,8 @@ __global__ void __launch_bounds__(64) lane_batch_kernel(BatchArgs B) {
     while (true) {
         uint32_t idx = 0;
         if ((threadIdx.x & 63u) == 0) idx = atomicAdd(B.counter, 1u);
-        idx = (uint32_t)__shfl((int)idx, 0, 64);
+        // a wave-uniform index: the item and its argument block come by scalar loads
+        idx = __builtin_amdgcn_readfirstlane((uint32_t)__shfl((int)idx, 0, 64));
         if (idx >= B.n_items) break;
         const BatchItem it = B.items[idx];
         run_lane_words<T, CM>(B.calls[it.call], it.w0, it.w1, 1, smem);
