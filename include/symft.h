@@ -304,8 +304,9 @@ typedef struct {
                                       shot; a wave leaves the stream once all its shots are discarded;
                                       ECAPACITY when its state passes 64 KB), also a candidate of
                                       symft_autotune_counts.  Flags do not depend on it */
-    uint32_t mode;                 /* programs with a dense active vector: 0 = automatic (the path
-                                      symft_autotune_counts timed faster, else 1); 1 = the count kernel, which
+    uint32_t mode;                 /* programs with a dense active vector: 0 = automatic (with threads_per_shot
+                                      0, the path symft_autotune_counts timed faster, else 1; with a nonzero
+                                      threads_per_shot, 1); 1 = the count kernel, which
                                       stops a rejected shot's dense work; 2 = detector and observable rows
                                       written to scratch by the record kernel, then reduced to the flags (for
                                       programs that reject few shots).  Flags do not depend on it.  Pure-frame
@@ -336,8 +337,8 @@ symft_status symft_sample_counts(const symft_program *p, const symft_count_opts 
 /* Autotuner of the aggregate-count mode: times each threads-per-shot
  * configuration (4 .. 256 that fits LDS; at widths 9 .. 12 also 64 .. 256 with
  * vectors in HBM; at peak widths 13 and 14, 64 .. 256 with vectors in HBM and
- * 1024) on 4096 words of this program (1024 at widths
- * 13 and 14) with opts' postselection set and precision (opts->threads_per_shot
+ * 1024; the lane kernel; rows written by the record kernel, then reduced) on
+ * 16384 words of this program (1024 at widths 13 and 14) with opts' postselection set and precision (opts->threads_per_shot
  * and shot_offset are ignored) and keeps the fastest for later
  * symft_sample_counts calls with the same program, set and precision.
  * Fewer shot groups per workgroup let rejected shots end sooner; more keep

@@ -1357,25 +1357,14 @@ hipError_t launch_active(const ActiveArgs &A, bool fp64, uint32_t bs, uint32_t g
 }
 
 
-// The lane kernel: LDS bytes per wave (= per workgroup), occupancy and launch.
+// The lane kernel: LDS bytes per wave (= per workgroup), the batch queue's occupancy, and launch.
 size_t lane_lds_bytes(const DevProg &P, bool fp64) {
     return lane_vec_offset(P.n_instr, P.n_meas) + (size_t)64 * P.vcap * (fp64 ? 16 : 8);
-}
-
-static const void *lane_kfn(bool fp64, bool cm) {
-    if (fp64) return cm ? (const void *)lane_kernel<double, true> : (const void *)lane_kernel<double, false>;
-    return cm ? (const void *)lane_kernel<float, true> : (const void *)lane_kernel<float, false>;
 }
 
 static const void *lane_batch_kfn(bool fp64, bool cm) {
     if (fp64) return cm ? (const void *)lane_batch_kernel<double, true> : (const void *)lane_batch_kernel<double, false>;
     return cm ? (const void *)lane_batch_kernel<float, true> : (const void *)lane_batch_kernel<float, false>;
-}
-
-int lane_max_blocks_per_cu(bool fp64, size_t lds, bool cm) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kfn(fp64, cm), 64, lds) != hipSuccess) return 1;
-    return nb;
 }
 
 int lane_batch_max_blocks_per_cu(bool fp64, size_t lds, bool cm) {
