@@ -57,7 +57,7 @@ def test_branch_probabilities_match_oracle(name, prec):
     assert worst < P0_TOL[prec], worst
 
 
-@pytest.mark.parametrize("k,prec", [(14, "fp32"), (14, "fp64"), (16, "fp32")])
+@pytest.mark.parametrize("k,prec", [(14, "fp32"), (14, "fp64"), (16, "fp32"), (16, "fp64")])
 def test_c5_full_launch_sampled_words(k, prec):
     """The benchmark's launch: all 2^16 shots in one call (up to about a thousand shot groups, each with
     its vector slice in HBM scratch, and a grid-stride loop over words where the grid is smaller than
