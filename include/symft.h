@@ -327,7 +327,9 @@ typedef struct {
  *               shot ranges accumulate; zero it before the first).
  * On programs with a dense active vector a postselected detector is checked
  * right after the instruction that makes its last record, and a rejected
- * shot does no further dense work.  Flags equal those computed from the full
+ * shot does no further dense work; with one shot group per workgroup the
+ * workgroups take 4-shot units of the words as they free up, so the
+ * rejected shots' uneven work balances over the launch.  Flags equal those computed from the full
  * records of symft_sample_ex with the same seed and shot range.
  * Errors: EINVAL (null program, detector index out of range, expected value
  * not 0/1, bad offset), ECAPACITY, ENOMEM, EHIP.  shots == 0 is a no-op. */
@@ -338,7 +340,8 @@ symft_status symft_sample_counts(const symft_program *p, const symft_count_opts 
  * configuration (4 .. 256 that fits LDS; at widths 9 .. 12 also 64 .. 256 with
  * vectors in HBM; at peak widths 13 and 14, 64 .. 256 with vectors in HBM and
  * 1024; the lane kernel; rows written by the record kernel, then reduced) on
- * 16384 words of this program (1024 at widths 13 and 14) with opts' postselection set and precision (opts->threads_per_shot
+ * 16384 words of this program up to peak width 8, 4096 at widths 9 .. 12 and 1024 at 13 and 14,
+ * with opts' postselection set and precision (opts->threads_per_shot
  * and shot_offset are ignored) and keeps the fastest for later
  * symft_sample_counts calls with the same program, set and precision.
  * Fewer shot groups per workgroup let rejected shots end sooner; more keep

@@ -596,8 +596,10 @@ static bool lane_candidate(const DevProg &P, bool fp64) { return P.k_max >= 1 &&
 static const size_t kLaneBatchLds = 40 * 1024;
 // A forced choice with this bit keeps the tuned thread count but never the lane kernel.
 static const uint32_t kNoLane = 1u << 18;
-// Lane-kernel grid cap; above it each workgroup strides over several words.
-static const uint64_t kMaxLaneGrid = (uint64_t)1 << 30;
+// Grid cap of the launches of one workgroup per work unit; above it workgroups stride over units.
+static const uint64_t kMaxGrid = (uint64_t)1 << 30;
+// Count mode with one shot group per workgroup: words split into 2^kCountPartLog2 work units (1 .. 6).
+static const uint32_t kCountPartLog2 = 4;
 
 // force_tps of a sampling call from symft_sample_opts.active_kernel.
 static symft_status active_choice(const DevProg &D, bool fp64, uint32_t sel, uint32_t &force) {
@@ -684,7 +686,7 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
         // One workgroup per word, left to the hardware dispatcher: a persistent grid sized by the
         // occupancy query ran the C3 FP64 stream 1.5x slower (the query admitted one more 15.5 KB
         // workgroup per CU than ran at once, so a tenth of the workgroups waited for a whole pass).
-        const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_words, kMaxLaneGrid));
+        const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_words, kMaxGrid));
         const hipError_t e = launch_lane(A, fp64, grid, st);
         if (e != hipSuccess) return set_err(SYMFT_EHIP, std::string("lane kernel launch failed: ") + hipGetErrorString(e));
         return SYMFT_OK;
@@ -694,17 +696,29 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
     uint64_t cap = (uint64_t)per_cu * (uint64_t)num_cus();
     // HBM-resident vectors: about 1024 threads of shot groups per CU
     if (!c.lds_vec) cap = std::min<uint64_t>(cap, (uint64_t)num_cus() * std::max<uint32_t>(2u, 1024u / c.bs));
+    // Count mode with one shot group per workgroup: work units of 4 shots (a sixteenth of a word).  A
+    // rejected shot ends its work early, so the units' costs differ; whole words assigned one per
+    // workgroup left the launch waiting for its costliest words (POST: 33.4 ms with whole words, 31.1
+    // with 16-shot units, 29.8 with 8, 28.9 with 4, 28.8 with 2).  With LDS vectors each unit is its own workgroup (the
+    // dispatcher balances them); with HBM vectors, whose slices are per workgroup, resident workgroups
+    // take units from a counter at the head of the scratch.
+    const uint32_t part_log2 = (cnt && c.bs == c.tps && n_words < ((uint64_t)1 << (31 - kCountPartLog2))) ? kCountPartLog2 : 0u;
+    const uint64_t units = n_words << part_log2;
+    const bool queue = part_log2 && !c.lds_vec;
+    const uint64_t qhdr = queue ? 256 : 0;
     if (fixed && !c.lds_vec) {
-        // the vector slices of every workgroup must fit the caller's scratch
+        // the vector slices of every workgroup (and the unit counter) must fit the caller's scratch
         const uint64_t per_wg = (uint64_t)(c.bs / c.tps) * ((uint64_t)1 << D.k_max) * (fp64 ? 16 : 8);
-        if (per_wg > fixed->bytes)
+        if (per_wg + qhdr > fixed->bytes)
             return set_err(SYMFT_ECAPACITY, "one workgroup's vector scratch exceeds the fixed scratch (" +
-                                                std::to_string(per_wg) + " > " + std::to_string(fixed->bytes) + " bytes)");
-        cap = std::min<uint64_t>(cap, fixed->bytes / per_wg);
+                                                std::to_string(per_wg + qhdr) + " > " + std::to_string(fixed->bytes) + " bytes)");
+        cap = std::min<uint64_t>(cap, (fixed->bytes - qhdr) / per_wg);
     }
-    uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_words, cap));
+    uint32_t grid = (uint32_t)std::max<uint64_t>(
+        1, (part_log2 && c.lds_vec) ? std::min<uint64_t>(units, kMaxGrid) : std::min<uint64_t>(units, cap));
     ActiveArgs A;
     std::memset(&A, 0, sizeof(A));
+    A.part_log2 = part_log2;
     A.P = D;
     A.seed = seed;
     A.word_begin = word_begin;
@@ -726,13 +740,16 @@ static symft_status run_active(symft_program *h, const DevProg &D, bool fp64, ui
     if (!c.lds_vec) {
         const uint32_t G = c.bs / c.tps;
         A.scratch_stride = (uint64_t)1 << D.k_max;
-        size_t bytes = (size_t)grid * G * A.scratch_stride * (fp64 ? 16 : 8);
+        size_t bytes = qhdr + (size_t)grid * G * A.scratch_stride * (fp64 ? 16 : 8);
+        unsigned char *base = nullptr;
         if (fixed) {
-            A.scratch = fixed->ptr;
+            base = (unsigned char *)fixed->ptr;
         } else {
             if (pool_alloc(&scratch, bytes, st) != hipSuccess) return set_err(SYMFT_ENOMEM, "vector scratch allocation failed");
-            A.scratch = scratch;
+            base = (unsigned char *)scratch;
         }
+        A.scratch = base + qhdr;
+        if (queue) A.unit_counter = (uint32_t *)base;
     }
     hipError_t e = launch_active(A, fp64, c.bs, grid, st);
     if (scratch) (void)hipFreeAsync(scratch, st);
@@ -1295,11 +1312,11 @@ symft_status symft_autotune_counts(const symft_program *pc, const symft_count_op
         if (tps_out) *tps_out = D.fr_ok ? 0 : 1024;
         return SYMFT_OK;
     }
-    // 16384 words: on 4096 a lane candidate whose count-mode LDS admits fewer workgroups per CU than
-    // the record kernel's ran two passes to the records' one, and the records route won on the sample
-    // while losing at full size
+    // 16384 words up to width 8: on 4096 a lane candidate whose count-mode LDS admits fewer workgroups
+    // per CU than the record kernel's ran two passes to the records' one, and the records route won on
+    // the sample while losing at full size
     const bool wide = narrow_wide(D.k_max);
-    const uint64_t words = wide ? 1024 : 16384;
+    const uint64_t words = wide ? 1024 : D.k_max <= 8 ? 16384 : 4096;
     unsigned long long *cnt = nullptr;
     if (hipMalloc(&cnt, 16) != hipSuccess) return set_err(SYMFT_ENOMEM, "autotune buffer allocation failed");
     C.counts = cnt;

@@ -41,9 +41,12 @@ struct ActiveArgs {
     double *p0_out;           // probe: [shot][n_meas] or nullptr
     double *amp_out;          // probe: final active vector [shot][2^amp_k] as (re, im) FP64 pairs, or nullptr
     uint64_t probe_shot0, probe_n;
-    uint32_t amp_k, pad_a;
+    uint32_t amp_k;
+    uint32_t part_log2;       // count mode: each word split into 2^part_log2 work units of consecutive shots
     uint32_t lds_vec;         // 1: vectors in LDS
     uint32_t lds_bytes;
+    uint32_t *unit_counter;   // count mode: workgroups take units from this counter (zeroed before the
+                              // launch); nullptr: workgroup b takes units b, b + grid, ...
     CountArgs cnt;
 };
 

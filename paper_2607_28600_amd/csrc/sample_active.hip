@@ -322,7 +322,12 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
         tot[1] = 0ull;
     }
 
-    for (uint64_t wi = wi_begin; wi < wi_end; wi += wi_step) {
+    // Work units: whole words, or in count mode 2^part_log2 parts of a word (consecutive shots).  A part
+    // recomputes its word's draws and owns its shots' flag bits.
+    const uint32_t pl = CM ? A.part_log2 : 0u;
+    for (uint64_t ui = wi_begin; ui < wi_end; ui += wi_step) {
+        const uint64_t wi = ui >> pl;
+        const int lane0 = (int)((uint32_t)(ui & ((1u << pl) - 1u)) << (6u - pl)), lane1 = lane0 + (64 >> pl);
         const uint64_t w = A.word_begin + wi;
         for (uint32_t i = threadIdx.x; i < P.n_instr; i += BS) exo[i] = 0;
         for (uint32_t i = threadIdx.x; i < P.n_rec; i += BS) recw[i] = 0;
@@ -355,7 +360,7 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
                 __syncthreads();
             }
         };
-        for (int base = 0; base < 64; base += G) {
+        for (int base = lane0; base < lane1; base += G) {
             const int lane = base + g;
             const uint64_t shot = w * 64 + (uint64_t)lane;
             for (uint32_t i = (uint32_t)r; i < mw; i += (uint32_t)tps) mb[i] = 0;
@@ -735,11 +740,32 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
         if (cm) {
             if (threadIdx.x == 0) {
                 const uint64_t s0 = wi * 64;
-                const unsigned long long m = s0 + 64 <= A.shots ? ~0ull : (1ull << (A.shots - s0)) - 1ull;
+                unsigned long long m = s0 + 64 <= A.shots ? ~0ull : (1ull << (A.shots - s0)) - 1ull;
+                const unsigned long long pm = (~0ull >> (64 - (64 >> pl))) << lane0;  // this unit's bits
+                m &= pm;
                 const unsigned long long d = *fdisc & m, l = *flogic & ~d & m;
                 if (A.cnt.flags) {
-                    A.cnt.flags[col] = d;
-                    A.cnt.flags[A.n_words + col] = l;
+                    if (pl == 0) {
+                        A.cnt.flags[col] = d;
+                        A.cnt.flags[A.n_words + col] = l;
+                    } else if (pl == 1) {  // this part's 32 bits of the two flag words
+                        ((uint32_t *)(A.cnt.flags + col))[lane0 >> 5] = (uint32_t)(d >> lane0);
+                        ((uint32_t *)(A.cnt.flags + A.n_words + col))[lane0 >> 5] = (uint32_t)(l >> lane0);
+                    } else if (pl == 2) {  // 16 bits
+                        ((uint16_t *)(A.cnt.flags + col))[lane0 >> 4] = (uint16_t)(d >> lane0);
+                        ((uint16_t *)(A.cnt.flags + A.n_words + col))[lane0 >> 4] = (uint16_t)(l >> lane0);
+                    } else if (pl == 3) {  // 8 bits
+                        ((uint8_t *)(A.cnt.flags + col))[lane0 >> 3] = (uint8_t)(d >> lane0);
+                        ((uint8_t *)(A.cnt.flags + A.n_words + col))[lane0 >> 3] = (uint8_t)(l >> lane0);
+                    } else {  // parts below a byte: clear and set this part's bits (padding included),
+                              // which no other unit touches
+                        unsigned long long *f0 = (unsigned long long *)(A.cnt.flags + col);
+                        unsigned long long *f1 = (unsigned long long *)(A.cnt.flags + A.n_words + col);
+                        atomicAnd(f0, ~pm);
+                        atomicOr(f0, d);
+                        atomicAnd(f1, ~pm);
+                        atomicOr(f1, l);
+                    }
                 }
                 tot[0] += (unsigned long long)__popcll(d);
                 tot[1] += (unsigned long long)__popcll(l);
@@ -773,7 +799,22 @@ __device__ __forceinline__ void run_active_words(const ActiveArgs &A, uint64_t w
 template <typename T, int BS, bool LDSV, bool CM>
 __global__ void __launch_bounds__(BS) active_kernel(ActiveArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
-    run_active_words<T, BS, LDSV, CM>(A, blockIdx.x, A.n_words, gridDim.x, blockIdx.x, smem);
+    const uint64_t n_units = CM ? A.n_words << A.part_log2 : A.n_words;
+    if (CM && A.unit_counter) {
+        // count mode: units from a global counter, so that workgroups whose shots were rejected early
+        // take more of them; every workgroup leaves once the counter passes the last unit
+        __shared__ uint32_t s_u;
+        while (true) {
+            __syncthreads();  // the previous unit's reads of s_u are done
+            if (threadIdx.x == 0) s_u = atomicAdd(A.unit_counter, 1u);
+            __syncthreads();
+            const uint32_t u = s_u;
+            if (u >= n_units) break;
+            run_active_words<T, BS, LDSV, CM>(A, u, (uint64_t)u + 1, 1, blockIdx.x, smem);
+        }
+        return;
+    }
+    run_active_words<T, BS, LDSV, CM>(A, blockIdx.x, n_units, gridDim.x, blockIdx.x, smem);
 }
 
 // ----------------------------------------------------------------- lane kernel
@@ -1273,6 +1314,7 @@ static hipError_t launch_one(const ActiveArgs &A, uint32_t grid, hipStream_t st)
     auto kfn = active_kernel<T, BS, LDSV, CM>;
     hipError_t e = hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)A.lds_bytes);
     if (e != hipSuccess) return e;
+    if (A.unit_counter) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, A.unit_counter);
     hipLaunchKernelGGL(kfn, dim3(grid), dim3(BS), A.lds_bytes, st, A);
     return hipGetLastError();
 }

@@ -235,3 +235,29 @@ def test_count_paths_agree_over_several_chunks(prec):
     own, own_c = count_flags(rec, c.num_records, c.num_detectors, c.num_observables, shots, post, None)
     assert np.array_equal(a1, own)
     assert list(c1.cpu().numpy()) == list(own_c)
+
+
+@pytest.mark.parametrize("prec,tps", [("fp32", 64), ("fp32", 256), ("fp64", 64), ("fp64", 256)])
+def test_counts_sub_word_units(prec, tps):
+    """One shot group per workgroup: the count launch splits each word into units of 4 shots (LDS vectors:
+    one workgroup per unit; HBM vectors, as FP64 at width 12: resident workgroups take units from a
+    counter).  On a flag buffer that starts as all ones, every unit must write exactly its shots' bits:
+    the flags equal those derived from the same kernels' full records, padding bits included, over a
+    ragged range at an offset."""
+    w = configs.postselect()
+    c = w.circuit
+    p = S.Program(c)
+    assert p.k_max == 12
+    post = list(range(c.num_detectors))
+    shots, off = 64 * 37 + 13, 64 * 11
+    words = (shots + 63) // 64
+    print(f"sub-word units: {prec} tps={tps}", flush=True)
+    flags = torch.full((2, words), -1, dtype=torch.int64, device="cuda")
+    counts = torch.zeros(2, dtype=torch.int64, device="cuda")
+    p.sample_counts_into(flags, counts, shots, w.seed, post=post, shot_offset=off, precision=prec, threads_per_shot=tps)
+    rec = S.bits_to_numpy(p.sample(shots, w.seed, shot_offset=off, precision=prec))
+    own_f, _ = count_flags(rec, c.num_records, c.num_detectors, c.num_observables, shots, post, None)
+    got = S.bits_to_numpy(flags)
+    assert np.array_equal(got, own_f)
+    assert list(counts.cpu().numpy()) == [_popcount(own_f[0]), _popcount(own_f[1])]
+    assert 0 < _popcount(own_f[0]) < shots
