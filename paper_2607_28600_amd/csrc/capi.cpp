@@ -590,10 +590,11 @@ static const uint32_t kLaneVec = 1u << 17;
 static const size_t kLaneLds = 64 * 1024;
 static bool lane_candidate(const DevProg &P, bool fp64) { return P.k_max >= 1 && lane_lds_bytes(P, fp64) <= kLaneLds; }
 // In a batch the lane queue's LDS size is its largest member's, which sets the
-// occupancy of all of them: members above kLaneBatchLds stay in the
-// shot-group queue (on C4, admitting members up to 64 KB took the FP32 batch
-// from 5.3 to 6.6 ms).
-static const size_t kLaneBatchLds = 40 * 1024;
+// occupancy of all of them: members above the cap stay in the shot-group queue
+// (on C4, admitting members up to 64 KB took the FP32 batch from 5.3 to 6.6
+// ms).  Measured on C4 with the caps 24 / 32 / 40 KB: FP32 3.91 / 3.02 / 3.36
+// ms, FP64 6.77 / 5.97 / 5.76 ms.
+static size_t lane_batch_cap(bool fp64) { return fp64 ? 40 * 1024 : 32 * 1024; }
 // A forced choice with this bit keeps the tuned thread count but never the lane kernel.
 static const uint32_t kNoLane = 1u << 18;
 // Grid cap of the launches of one workgroup per work unit; above it workgroups stride over units.
@@ -1655,7 +1656,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
     size_t lds = 0;
     // lane members by LDS class: the queue's LDS is its largest member's, which sets its occupancy
     constexpr int kClasses = 4;
-    static const size_t kLaneClass[kClasses] = {8 * 1024, 16 * 1024, 24 * 1024, kLaneBatchLds};
+    const size_t kLaneClass[kClasses] = {8 * 1024, 16 * 1024, 24 * 1024, lane_batch_cap(fp64)};
     std::vector<ActiveArgs> lcalls[kClasses];
     std::vector<double> lcost[kClasses];
     std::vector<uint64_t> lwords_of[kClasses];
@@ -1674,7 +1675,7 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         // estimated cost per word: the representation's flops and a per-instruction share
         const double wcost =
             (info.product_selected ? info.product_flops_per_shot : info.dense_flops_per_shot) + 200.0 * (double)n_instr + 64.0;
-        if (mine && lane_candidate(D, fp64) && lane_lds_bytes(D, fp64) <= kLaneBatchLds) {
+        if (mine && lane_candidate(D, fp64) && lane_lds_bytes(D, fp64) <= lane_batch_cap(fp64)) {
             // the lane kernel, in a queue of its own
             ActiveArgs A;
             std::memset(&A, 0, sizeof(A));
