@@ -1727,7 +1727,9 @@ static symft_status build_plan(BatchPlan &B, const symft_program *const *progs, 
         words_of.push_back(A.n_words);
         cost.push_back(wcost);
     }
-    if (hipMalloc(&B.d_counter, 256) != hipSuccess) return set_err(SYMFT_ENOMEM, "batch metadata allocation failed");
+    // the shot-group queue's counter and one per lane class, 64 bytes apart
+    if (hipMalloc(&B.d_counter, sizeof(uint32_t) * 16 * (kClasses + 1)) != hipSuccess)
+        return set_err(SYMFT_ENOMEM, "batch metadata allocation failed");
     for (int q = 0; q < kClasses; ++q) {
         if (lcalls[q].empty()) continue;
         // items of a few words for one-wave workgroups, by decreasing cost
