@@ -3,7 +3,7 @@ branch probabilities against the oracle on every active workload, full-size
 launches of the HBM-resident widths and of the
 batched queue (sampled words), and batch plans across freed programs.
 
-Tolerances are those of the scope (the benchmark spec): records bit-exact outside
+Tolerances: records bit-exact outside
 the threshold exclusion (1e-9 FP64, 1e-5 FP32), Pr(m = 0) within 1e-12 (FP64)
 or 1e-5 (FP32) of the oracle's.
 """
