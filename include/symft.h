@@ -129,9 +129,9 @@ typedef struct {
     uint64_t frame_pushes;         /* record-to-consumer XORs over the schedule */
     uint64_t frame_noise_consumers;/* noise-symbol-to-consumer XORs, summed over symbols */
     uint64_t rotations_removed;    /* rotations fused into an earlier one or cancelled (symft_compile_opts) */
-    uint64_t frame_kernel;         /* pure-frame kernel of the automatic choice: 2 step-synchronous, 1 wave-owned
-                                      (schedules whose slots fit only its LDS); 0 when the program runs on the
-                                      active kernel */
+    uint64_t frame_kernel;         /* pure-frame kernel of the automatic choice for calls of more than
+                                      frame_small_words words: 2 step-synchronous, 1 wave-owned (schedules whose
+                                      slots fit only its LDS); 0 when the program runs on the active kernel */
     uint64_t frame_wave_batches;   /* wave-owned schedule: node batches (one node per lane) */
     uint64_t frame_wave_flushes;   /* wave-owned schedule: staged-row flushes (workgroup barriers) */
     uint64_t product_selected;     /* 1: sampling runs the product-component stream (symft_compile_opts) */
@@ -140,6 +140,9 @@ typedef struct {
     uint64_t product_vector_amplitudes; /* its vector buffer per shot (all component regions) */
     double product_flops_per_shot; /* its algorithmic flops per shot (dense_flops_per_shot's weights on the
                                       components' widths, plus 4 per merged amplitude) */
+    uint64_t frame_small_words;    /* pure-frame programs whose automatic kernel is the step-synchronous one:
+                                      calls of at most this many 64-shot words take the wave-owned kernel
+                                      instead (small schedules, where it is faster); 0 when none do */
 } symft_info;
 
 /* Compile options.  simplify = 1 runs a conservative commutation-aware
@@ -215,7 +218,9 @@ typedef struct {
                                       (ECAPACITY if it does not fit; records are unchanged) */
     uint32_t frame_kernel;         /* pure-frame programs: 0 = automatic (the step-synchronous kernel when its
                                       LDS fits, else the wave-owned kernel, in which each wave of a 16-wave
-                                      workgroup owns one 64-shot word for the whole schedule); 1 = wave-owned
+                                      workgroup owns one 64-shot word for the whole schedule; the wave-owned
+                                      one also for calls of at most symft_info.frame_small_words words);
+                                      1 = wave-owned
                                       (ECAPACITY if it does not fit); 2 = step-synchronous.  A nonzero
                                       frame_tile_words selects the step-synchronous kernel.  Records are
                                       unchanged */

@@ -61,7 +61,7 @@ class symft_info(C.Structure):
         ("rotations_removed", C.c_uint64), ("frame_kernel", C.c_uint64), ("frame_wave_batches", C.c_uint64),
         ("frame_wave_flushes", C.c_uint64), ("product_selected", C.c_uint64), ("product_components", C.c_uint64),
         ("product_merges", C.c_uint64), ("product_vector_amplitudes", C.c_uint64),
-        ("product_flops_per_shot", C.c_double),
+        ("product_flops_per_shot", C.c_double), ("frame_small_words", C.c_uint64),
     ]
 
 

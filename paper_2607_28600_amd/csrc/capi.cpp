@@ -809,6 +809,16 @@ static symft_status run_frame_wave(symft_program *h, const DevProg &D, uint64_t 
 // frame_kernel: 0 automatic (the step-synchronous kernel when its LDS fits,
 // else the wave-owned one), 1 wave-owned, 2 step-synchronous (tile_words 16 /
 // 32 or 0 = automatic); tile_words != 0 implies the step-synchronous kernel.
+// Small calls of small schedules take the wave-owned kernel: it has no workgroup barriers, and at a few
+// tiles per CU the step kernel's chain of barrier steps is the whole launch.  Measured per call, 16 to
+// 4,096 words: d = 3 surface code (58 rows) 26-30 us against 31-34 us, d = 5 (266 rows) 35-40 against
+// 39-43 us; at d = 11 (2,762 rows) the step kernel is faster at every size, and at 16,384 words for all
+// three.
+static const uint64_t kSmallFrameWords = 4096;
+static bool frame_small_program(const DevProg &D) {
+    return D.wv_ok && (uint64_t)D.n_rec + D.n_det + D.n_obs <= 512;
+}
+
 static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_begin, uint64_t n_words, uint64_t shots,
                               uint64_t *out, uint64_t stride, uint32_t sections, uint64_t seed, uint32_t cap_override,
                               hipStream_t st, const CountArgs *cnt = nullptr, uint32_t tile_words = 0,
@@ -820,7 +830,8 @@ static symft_status run_frame(symft_program *h, const DevProg &D, uint64_t word_
     if (frame_kernel == 1 && !D.wv_ok)
         return set_err(SYMFT_ECAPACITY, "the wave-owned frame kernel cannot run this schedule (LDS)");
     const bool step_fits = frame_lds_bytes(D, 16) <= kLdsLimit;
-    if (frame_kernel == 1 || (frame_kernel == 0 && !tile_words && !step_fits && D.wv_ok))
+    const bool small = n_words <= kSmallFrameWords && frame_small_program(D);
+    if (frame_kernel == 1 || (frame_kernel == 0 && !tile_words && D.wv_ok && (!step_fits || small)))
         return run_frame_wave(h, D, word_begin, n_words, shots, out, stride, sections, seed, cap_override, st, cnt,
                               fixed);
     // 32-word tiles halve the barrier steps per word; they need the slots of
@@ -959,6 +970,8 @@ symft_status symft_program_info(const symft_program *p, symft_info *info) {
     info->frame_kernel = p->L.meta.fr_ok ? (frame_lds_bytes(p->L.meta, 16) <= kLdsLimit ? 2u : 1u) : 0u;
     info->frame_wave_batches = p->F.w_n_batches;
     info->frame_wave_flushes = p->F.w_n_flushes;
+    info->frame_small_words =
+        p->L.meta.fr_ok && info->frame_kernel == 2 && frame_small_program(p->L.meta) ? kSmallFrameWords : 0u;
     info->product_selected = p->product ? 1u : 0u;
     info->product_components = p->PP.n_comps;
     info->product_merges = p->PP.n_merges;

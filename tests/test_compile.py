@@ -162,6 +162,18 @@ def test_frame_schedule_folds_same_level_dependencies():
     assert info["frame_steps"] == 2
 
 
+def test_small_frame_calls_report_the_wave_owned_kernel():
+    """The automatic pure-frame choice: small calls (up to 4,096 words) of schedules of at most 512 rows take
+    the wave-owned kernel; larger schedules and active programs report no such range."""
+    from workloads.surface import rotated_memory_z
+    for c, small in ((configs.c1().circuit, 4096), (rotated_memory_z(5, 5, 1e-3), 4096),
+                     (rotated_memory_z(7, 7, 1e-3), 0), (configs.c2().circuit, 0), (configs.c3().circuit, 0)):
+        i = S.Program(c).info()
+        assert i["frame_small_words"] == small, (i["n_rows"], i["frame_small_words"])
+        if small:
+            assert i["n_rows"] <= 512 and i["frame_kernel"] == 2
+
+
 def test_frame_relation_accepts_frame_maps_and_rejects_other_states():
     from tests.parity_util import frame_relation
     rng = np.random.default_rng(3)
