@@ -167,9 +167,12 @@ __device__ __forceinline__ void emit_quad(const DevProg &P, const FrameArgs &A, 
         const uint64_t wi = wt + wl;
         unsigned long long *dst = (unsigned long long *)A.out + (uint64_t)ra.y * A.row_stride + wi;
         if (full) {
-            // every word of the tile is whole and 16-byte stores are allowed
-            ((ulonglong2 *)dst)[0] = make_ulonglong2(v[0], v[1]);
-            ((ulonglong2 *)dst)[1] = make_ulonglong2(v[2], v[3]);
+            // every word of the tile is whole and 16-byte stores are allowed; the rows are not read again,
+            // so they are stored non-temporally and leave the L2 to the flip records and entries (C2: 5.48
+            // against 5.61 ms)
+            typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+            __builtin_nontemporal_store((u64x2){v[0], v[1]}, (u64x2 *)dst);
+            __builtin_nontemporal_store((u64x2){v[2], v[3]}, (u64x2 *)dst + 1);
         } else {
 #pragma unroll
             for (uint32_t h = 0; h < 2; ++h) {
